@@ -1,0 +1,168 @@
+/*
+ * tapt.h -- C ABI of the MI355X (gfx950) TAPT hot-path library, libtapt.so.
+ *
+ * Transformer-Augmented Parallel Tempering (arXiv:2509.23043, Algorithm 1):
+ * replicas of a sparse Ising problem on a fixed inverse-temperature ladder
+ * run graph-colored single-spin Monte Carlo sweeps, accept pre-generated
+ * global proposals with the Delta-E-only rule (Eq. 2) and exchange states
+ * between neighbouring temperatures with alternating parity (Eq. 1).
+ *
+ * Conventions used by every entry point:
+ *   - spins are int8 in {-1, +1}; configurations are [n] arrays in site order;
+ *     replica arrays are [R][n], row r = beta slot r, slot 0 the hottest.
+ *   - energy E(m) = -sum_{i<j} J_ij m_i m_j - sum_i h_i m_i (Supp. S4), int32.
+ *   - "host pointer" arguments are caller-owned host memory, read or written
+ *     during the call only. "device pointer" arguments are device memory of
+ *     the context's GPU (e.g. a torch tensor's data_ptr()), used on the
+ *     context's stream and complete when the call returns.
+ *   - every call returns PT_OK (0) or a negative PT_E* code; on error
+ *     pt_last_error() returns a message (thread-local) and no state changed,
+ *     except PT_EDEVICE, after which the context is unusable.
+ *   - a context is used by one host thread at a time; different contexts may
+ *     be used concurrently.
+ *
+ * Random numbers follow a fixed counter-based contract (Philox4x32-10 keyed
+ * by pt_opts.seed, counters from site, sweep, beta slot and a stream tag), so
+ * results do not depend on tiling, batching or co-tenancy: the same problem,
+ * ladder, options and seed give bit-identical chains on every path.
+ */
+#ifndef TAPT_H
+#define TAPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PT_OK 0
+#define PT_EINVAL (-1)        /* bad argument */
+#define PT_ENOMEM (-2)        /* device or host allocation failed, or over budget */
+#define PT_EDEVICE (-3)       /* HIP error; the context is unusable afterwards */
+#define PT_ESTATE (-4)        /* call not valid in the current state */
+#define PT_EUNSUPPORTED (-5)  /* problem shape not supported by the kernels */
+#define PT_ETIMEOUT (-6)      /* a cross-workgroup wait exceeded its bound */
+
+#define PT_METROPOLIS 0       /* flip with min(1, exp(-beta dE)) */
+#define PT_GIBBS 1            /* heat bath, Methods Eq. 5: flip with 1/(1+exp(beta dE)) */
+
+typedef struct pt_ctx pt_ctx;
+typedef struct pt_batch pt_batch;
+typedef struct pt_server pt_server;
+
+/* A sparse Ising problem (Methods, Eq. 4; Supp. S4). All pointers are host
+ * pointers, copied by pt_create.
+ *   lattice_L > 0: periodic L^3 cubic lattice, n = L^3, even L >= 4,
+ *     site i = x + L*(y + L*z); J holds 3n bond couplings, J[d*n + i] for
+ *     the bond from i to its +x (d=0), +y (1), +z (2) neighbour. row_ptr and
+ *     col are ignored; colors are the checkerboard (x+y+z) mod 2.
+ *   lattice_L == 0: general graph in CSR form with both directions of every
+ *     edge stored, symmetric values, no self loops; J[nnz] couplings.
+ *   h: [n] fields or NULL (all 0). clamp: [n] 0 = free, +-1 = fixed, or NULL.
+ *   color: [n] proper coloring with colors 0..C-1 (C <= 64) for CSR graphs,
+ *     required there (sites of a color are updated in parallel, colors in
+ *     increasing order -- Methods, Graph coloring).
+ * Limits: |J| <= 127, |h| <= 32767, n <= 32768, lattice L <= 32. */
+typedef struct {
+    int32_t n;
+    int32_t lattice_L;
+    int32_t nnz;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const int32_t *J;
+    const int32_t *h;
+    const int8_t *clamp;
+    const int32_t *color;
+} pt_graph;
+
+/* Run options (Algorithm 1 inputs). prop_period = 0 disables proposals;
+ * otherwise a proposal stage runs at the end of sweep t when t >= prop_start,
+ * (t - prop_start) % prop_period == 0 and (prop_stop < 0 or t <= prop_stop);
+ * prop_start and prop_period must be multiples of sweeps_per_cycle.
+ * target: first_hit records the first sweep with min_r E_r <= target. */
+typedef struct {
+    int32_t rule;              /* PT_METROPOLIS or PT_GIBBS */
+    int32_t sweeps_per_cycle;  /* M >= 1: sweeps between swap stages */
+    int64_t prop_start;
+    int64_t prop_period;
+    int64_t prop_stop;
+    uint64_t seed;
+    int32_t has_target;
+    int32_t target;
+} pt_opts;
+
+/* Accept / attempt counters and best-energy record of a context. */
+typedef struct {
+    uint64_t t;                 /* completed sweeps */
+    int32_t best_energy;        /* lowest min_r E_r seen (after init included) */
+    int64_t best_t;             /* sweep when best_energy was first reached */
+    int32_t best_slot;          /* lowest slot holding it at best_t */
+    int64_t first_hit;          /* first sweep with min_r E_r <= target, or -1 */
+} pt_summary;
+
+/* Create a context: validate and copy the problem, build the uint32
+ * acceptance tables on the host in FP64 (Eqs. 1, 2, 5), allocate device
+ * state and initialise the replicas randomly (Algorithm 1, first line).
+ * betas: host [R], strictly increasing, > 0 (slot 0 hottest). R in 2..1024. */
+int pt_create(const pt_graph *g, const double *betas, int32_t R, const pt_opts *o, pt_ctx **out);
+int pt_destroy(pt_ctx *c);
+
+/* Install (or replace) the proposal bank of the slot whose beta equals
+ * ``beta`` exactly; n_configs = 0 clears it. configs: host pointer to
+ * [n_configs][n] spins; every entry must be +-1 and match the clamps.
+ * Entry energies are computed once on the device; the slot's cursor starts
+ * at the contract's seeded offset and advances by one per proposal. */
+int pt_propose(pt_ctx *c, double beta, const int8_t *configs, int32_t n_configs);
+/* Same with configs in device memory (not validated entry by entry). */
+int pt_propose_device(pt_ctx *c, double beta, const int8_t *configs_dev, int32_t n_configs);
+
+/* Plain path: run n_sweeps sweeps of Algorithm 1 on this context alone with
+ * one launch sequence per cycle (sweep kernel, cycle-end kernel). */
+int pt_sweep(pt_ctx *c, uint64_t n_sweeps);
+
+/* Current replica energies by slot: host [R]. */
+int pt_energies(pt_ctx *c, int32_t *out);
+/* Current spins by slot: host [R][n]; sweep counter to *t if non-NULL. */
+int pt_state(pt_ctx *c, int8_t *spins, uint64_t *t);
+/* Same into device memory [R][n]. */
+int pt_state_device(pt_ctx *c, int8_t *spins_dev);
+/* Replace the state (resume): host [R][n] spins and sweep counter t. The
+ * counters restart at zero; energies are recomputed. */
+int pt_set_state(pt_ctx *c, const int8_t *spins, uint64_t t);
+
+/* Summary and counters. swap_att/swap_acc: host [R-1] per pair (r, r+1);
+ * prop_att/prop_acc/flips: host [R]; any may be NULL. best_spins: host [n]
+ * or NULL. */
+int pt_summary_get(pt_ctx *c, pt_summary *s, int8_t *best_spins);
+int pt_counters(pt_ctx *c, uint64_t *swap_att, uint64_t *swap_acc, uint64_t *prop_att,
+                uint64_t *prop_acc, uint64_t *flips);
+
+/* Energies of configurations under the context's problem: device pointers,
+ * configs [k][n] -> energies [k] (the full-recompute reduction kernel). */
+int pt_energy_device(pt_ctx *c, const int8_t *configs_dev, int32_t k, int32_t *energies_dev);
+
+/* Use a HIP stream (hipStream_t passed as void*, e.g. torch's current
+ * stream) for this context's work; NULL = the library's own stream. */
+int pt_set_stream(pt_ctx *c, void *stream);
+
+/* ---- batched path: many contexts in one persistent launch per chunk ---- */
+typedef struct {
+    int32_t replicas_per_wg;     /* slots per workgroup (0 = choose) */
+    int32_t replicas_per_thread; /* 1, 2 or 4 (0 = choose) */
+    int32_t chunk_sweeps;        /* sweeps per persistent launch (0 = 1000) */
+    int32_t use_graph;           /* 1: replay the chunk launches as a hipGraph */
+} pt_batch_opts;
+
+/* Group contexts for batched execution. The contexts stay owned by the
+ * caller and must outlive the batch; they may differ in size, ladder and
+ * options. Results are bit-identical to running each context alone. */
+int pt_batch_create(pt_ctx *const *ctxs, int32_t k, const pt_batch_opts *o, pt_batch **out);
+int pt_batch_sweep(pt_batch *b, uint64_t n_sweeps);
+int pt_batch_destroy(pt_batch *b);
+
+const char *pt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TAPT_H */

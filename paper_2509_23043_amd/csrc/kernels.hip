@@ -1,0 +1,987 @@
+// HIP kernels of the TAPT hot path for gfx950 (MI355X).
+//
+// Algorithm 1 of arXiv:2509.23043: replicas sweep their spins with a
+// single-spin rule (Methods, Eqs. 4-5) over color classes of the coupling
+// graph (Methods, Graph coloring); at the end of each cycle of M sweeps the
+// proposal-enabled replicas test a pre-generated configuration with the
+// Delta-E-only rule (Eq. 2) and neighbouring replicas exchange states with
+// alternating parity (Eq. 1).
+//
+// Everything on the device is integer: int8 spins and couplings, int32
+// energies, uint32 uniforms from Philox4x32-10 compared with uint32 threshold
+// tables that the host built in FP64. No step is a dense contraction, so no
+// MFMA is used; the sweep is bound by LDS instruction issue and VALU.
+//
+// Persistent chunk kernel: each workgroup owns G consecutive beta slots of one
+// instance and keeps their spins in LDS for K sweeps. Swaps between slots of
+// the same workgroup exchange labels (slot <-> storage maps in LDS); swaps
+// across a workgroup boundary copy the boundary state through a global
+// exchange buffer with release/acquire flags. All random numbers are keyed by
+// (seed, site, sweep, slot, stream tag), never by thread or storage, so the
+// chain is the same for every tiling, batch and launch sequence.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tapt_dev.h"
+
+namespace tapt {
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). The 32x32->64 products
+// compile to v_mad_u64_u32; the key schedule is wave-uniform (SGPRs).
+struct P4 {
+    uint32_t v[4];
+};
+
+__host__ __device__ __forceinline__ P4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t a = (uint64_t)c0 * 0xD2511F53u;
+        uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
+        uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+        uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)b;
+        c3 = (uint32_t)a;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    P4 o;
+    o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+    return o;
+}
+
+__host__ __device__ __forceinline__ uint32_t philox_word0(uint32_t c0, uint32_t c1, uint32_t c3,
+                                                          uint32_t k0, uint32_t k1)
+{
+    return philox(c0, c1, 0, c3, k0, k1).v[0];
+}
+
+// accept iff T == ALWAYS or u < T, with u = (hi << 16) | lo and the low half
+// drawn only when the high half leaves the decision open.
+__device__ __forceinline__ bool coarse_accept(uint32_t T, uint32_t hs, bool &maybe)
+{
+    bool acc = (hs | 0xFFFFu) < T;
+    maybe = !acc && hs < T;
+    return acc;
+}
+
+__device__ __forceinline__ bool any_lane(bool p) { return __any(p); }
+
+// ---------------------------------------------------------------------------
+// Sweepers. Each provides: storage size and LDS index of a site, per-thread
+// setup, and one sweep of every storage of the workgroup (all threads call it;
+// it contains the workgroup barriers between color classes).
+
+// Periodic L^3 cubic lattice, checkerboard colors (x+y+z) mod 2, even L.
+// Thread (group g, call q) owns sites 8q..8q+7 -- the 8 sites whose uniforms
+// come from Philox call q -- of RPT storages. Every such call holds exactly 4
+// sites of each color (a row has even length and calls start at even x), so a
+// thread updates 4 sites per color phase. Neighbour LDS addresses and packed
+// couplings of those 8 sites are computed once and stay in VGPRs.
+// LDS layout of a storage: site i at byte (i & 7) * (N/8) + (i >> 3), so
+// lanes (consecutive q) touch consecutive bytes for every neighbour direction.
+template <int L, int RPT>
+struct LatSweep {
+    static constexpr int N = L * L * L;
+    static constexpr int NC = N / 8;
+    static_assert(L % 2 == 0 && L >= 4, "even L >= 4");
+    static constexpr int SB = N;   // bytes per storage
+    static constexpr int MAXT = 512;  // block limit: leaves up to 256 VGPRs per lane
+
+    __host__ __device__ static constexpr int lidx(int i) { return (i & 7) * NC + (i >> 3); }
+    static int threads(int G) { return ((G + RPT - 1) / RPT) * NC; }
+
+    int q, grp;
+    bool active;
+    int own[2][4];
+    int nb[2][4][6];
+    short2v J[2][4][3];
+    int sh[2][4];
+
+    __device__ static int site(int x, int y, int z)
+    {
+        x = (x + L) % L; y = (y + L) % L; z = (z + L) % L;
+        return x + L * (y + L * z);
+    }
+
+    __device__ void setup(const InstDev &I, int G)
+    {
+        int tid = threadIdx.x;
+        grp = tid / NC;
+        q = tid % NC;
+        active = grp < (G + RPT - 1) / RPT;
+        const int8_t *J3 = I.J3;
+        for (int c = 0; c < 2; ++c) {
+            for (int s = 0; s < 4; ++s) {
+                int i0 = 8 * q + 2 * s;
+                int x = i0 % L, y = (i0 / L) % L, z = i0 / (L * L);
+                int p = (((x + y + z) & 1) == c) ? 0 : 1;
+                int i = i0 + p;
+                x = i % L;
+                int nbs[6] = {site(x + 1, y, z), site(x - 1, y, z), site(x, y + 1, z),
+                              site(x, y - 1, z), site(x, y, z + 1), site(x, y, z - 1)};
+                int jj[6] = {J3[i], J3[nbs[1]], J3[N + i], J3[N + nbs[3]], J3[2 * N + i], J3[2 * N + nbs[5]]};
+                own[c][s] = lidx(i) + grp * RPT * SB;
+                for (int d = 0; d < 6; ++d) nb[c][s][d] = lidx(nbs[d]) + grp * RPT * SB;
+                for (int d = 0; d < 3; ++d) {
+                    short2v v;
+                    v.x = (short)jj[2 * d];
+                    v.y = (short)jj[2 * d + 1];
+                    J[c][s][d] = v;
+                }
+                sh[c][s] = 16 * p;
+            }
+        }
+    }
+
+    // One sweep at sweep index t of every storage this workgroup holds.
+    // slot_of: storage -> local slot; global slot = s0 + local slot.
+    __device__ void sweep(const InstDev &I, int G, int s0, uint32_t t, const int *slot_of, int8_t *sp,
+                          const uint32_t *tab, int stride, int *Elds, unsigned *flips_lds)
+    {
+        uint32_t w[RPT][4];
+        int sl[RPT], dE[RPT], nf[RPT];
+        bool ok[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            int stor = grp * RPT + k;
+            ok[k] = active && stor < G;
+            sl[k] = ok[k] ? slot_of[stor] : 0;
+            P4 r = philox((uint32_t)q, t, (uint32_t)(s0 + sl[k]), TAG_SWEEP, I.seed_lo, I.seed_hi);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) w[k][j] = r.v[j];
+            dE[k] = 0;
+            nf[k] = 0;
+        }
+        const int D = I.D;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+                if (ok[k]) {
+                    const uint32_t *trow = tab + sl[k] * stride + D;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        int m = sp[own[c][s] + k * SB];
+                        short2v m01, m23, m45;
+                        m01.x = sp[nb[c][s][0] + k * SB];
+                        m01.y = sp[nb[c][s][1] + k * SB];
+                        m23.x = sp[nb[c][s][2] + k * SB];
+                        m23.y = sp[nb[c][s][3] + k * SB];
+                        m45.x = sp[nb[c][s][4] + k * SB];
+                        m45.y = sp[nb[c][s][5] + k * SB];
+                        int f = __builtin_amdgcn_sdot2(m01, J[c][s][0], 0, false);
+                        f = __builtin_amdgcn_sdot2(m23, J[c][s][1], f, false);
+                        f = __builtin_amdgcn_sdot2(m45, J[c][s][2], f, false);
+                        int d = m * f;                      // dE / 2
+                        uint32_t T = trow[d];
+                        uint32_t hs = (w[k][s] >> sh[c][s]) << 16;
+                        bool maybe;
+                        bool acc = coarse_accept(T, hs, maybe);
+                        if (any_lane(maybe)) {
+                            P4 r2 = philox((uint32_t)q, t, (uint32_t)(s0 + sl[k]), TAG_REFINE, I.seed_lo, I.seed_hi);
+                            uint32_t lo = (r2.v[s] >> sh[c][s]) & 0xFFFFu;
+                            acc = acc || (maybe && (T == ALWAYS || (hs | lo) < T));
+                        }
+                        if (acc) {
+                            sp[own[c][s] + k * SB] = (int8_t)(-m);
+                            dE[k] += 2 * d;
+                            nf[k] += 1;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // per-storage energy change and flip count
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            int e = dE[k], f = nf[k];
+            if constexpr (NC % 64 == 0) {
+                // a wave belongs to one storage group
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    e += __shfl_xor(e, off);
+                    f += __shfl_xor(f, off);
+                }
+                if (ok[k] && (threadIdx.x & 63) == 0) {
+                    atomicAdd(&Elds[grp * RPT + k], e);
+                    atomicAdd(&flips_lds[sl[k]], (unsigned)f);
+                }
+            } else {
+                if (ok[k] && (e != 0 || f != 0)) {
+                    atomicAdd(&Elds[grp * RPT + k], e);
+                    atomicAdd(&flips_lds[sl[k]], (unsigned)f);
+                }
+            }
+        }
+    }
+};
+
+// General sparse graph (CSR, any proper coloring, clamps, fields). Random
+// halves for every site of every storage are staged in LDS at the start of
+// the sweep (one Philox call per 8 sites), then each color class is spread
+// over all threads of the workgroup.
+struct CsrSweep {
+    static constexpr int RPTV = 1;
+    static constexpr int MAXT = 1024;
+    int n, SB, nr;
+
+    __host__ __device__ static int storage_bytes(int n) { return (n + 15) & ~15; }
+    __device__ int lidx(int i) const { return i; }
+
+    __device__ void setup(const InstDev &I, int G)
+    {
+        (void)G;
+        n = I.n;
+        SB = storage_bytes(n);
+        nr = (n + 7) & ~7;
+    }
+
+    __device__ void sweep(const InstDev &I, int G, int s0, uint32_t t, const int *slot_of, int8_t *sp,
+                          const uint32_t *tab, int stride, int *Elds, unsigned *flips_lds, uint16_t *rnd)
+    {
+        const int tid = threadIdx.x, bs = blockDim.x;
+        const int ncall = nr >> 3;
+        for (int idx = tid; idx < G * ncall; idx += bs) {
+            int k = idx / ncall, q = idx - k * ncall;
+            P4 r = philox((uint32_t)q, t, (uint32_t)(s0 + slot_of[k]), TAG_SWEEP, I.seed_lo, I.seed_hi);
+            uint4 v = make_uint4(r.v[0], r.v[1], r.v[2], r.v[3]);
+            *(uint4 *)(rnd + (size_t)k * nr + 8 * q) = v;
+        }
+        __syncthreads();
+        const int D = I.D;
+        for (int c = 0; c < I.ncolors; ++c) {
+            int off = I.color_off[c], cnt = I.color_off[c + 1] - off;
+            for (int idx = tid; idx < G * cnt; idx += bs) {
+                int k = idx / cnt;
+                int i = I.color_sites[off + idx - k * cnt];
+                int8_t *m_k = sp + k * SB;
+                int f = I.h[i];
+                for (int e = I.row_ptr[i]; e < I.row_ptr[i + 1]; ++e) f += (int)I.Jc[e] * (int)m_k[I.col[e]];
+                int m = m_k[i];
+                int d = m * f;
+                int sl = slot_of[k];
+                uint32_t T = tab[sl * stride + D + d];
+                uint32_t hs = (uint32_t)rnd[(size_t)k * nr + i] << 16;
+                bool maybe;
+                bool acc = coarse_accept(T, hs, maybe);
+                if (any_lane(maybe)) {
+                    if (maybe) {
+                        P4 r2 = philox((uint32_t)(i >> 3), t, (uint32_t)(s0 + sl), TAG_REFINE, I.seed_lo, I.seed_hi);
+                        uint32_t wd = r2.v[(i & 7) >> 1];
+                        uint32_t lo = ((i & 1) ? (wd >> 16) : wd) & 0xFFFFu;
+                        acc = (T == ALWAYS) || ((hs | lo) < T);
+                    }
+                }
+                if (acc) {
+                    m_k[i] = (int8_t)(-m);
+                    atomicAdd(&Elds[k], 2 * d);
+                    atomicAdd(&flips_lds[sl], 1u);
+                }
+            }
+            __syncthreads();
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// LDS carve-up shared by the persistent kernel and the host's size query.
+struct ChunkLds {
+    int8_t *sp;
+    uint32_t *tab;
+    int *slot_of, *stor_of, *Elds;
+    unsigned *flips, *satt, *sacc;
+    int *misc;
+    long long *src;
+    uint16_t *rnd;
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+__host__ __device__ inline size_t chunk_lds_layout(int G, int SB, int stride, int nr_csr, unsigned char *base,
+                                                   ChunkLds *out)
+{
+    size_t o = 0;
+    size_t sp = o; o = align16(o + (size_t)G * SB);
+    size_t tab = o; o = align16(o + (size_t)G * stride * 4);
+    size_t ints = o; o = align16(o + (size_t)G * 4 * 7 + 64);
+    size_t src = o; o = align16(o + (size_t)G * 8);
+    size_t rnd = o; o = align16(o + (size_t)G * nr_csr * 2);
+    if (out) {
+        out->sp = (int8_t *)(base + sp);
+        out->tab = (uint32_t *)(base + tab);
+        int *ib = (int *)(base + ints);
+        out->slot_of = ib;
+        out->stor_of = ib + G;
+        out->Elds = ib + 2 * G;
+        out->flips = (unsigned *)(ib + 3 * G);
+        out->satt = (unsigned *)(ib + 4 * G);
+        out->sacc = (unsigned *)(ib + 5 * G);
+        out->misc = ib + 7 * G;    // 16 ints of flags
+        out->src = (long long *)(base + src);
+        out->rnd = (uint16_t *)(base + rnd);
+    }
+    return o;
+}
+
+__device__ inline bool is_prop_sweep(const InstDev &I, uint64_t t)
+{
+    if (I.prop_period <= 0) return false;
+    if ((int64_t)t < I.prop_start) return false;
+    if (I.prop_stop >= 0 && (int64_t)t > I.prop_stop) return false;
+    return (((int64_t)t - I.prop_start) % I.prop_period) == 0;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent chunk kernel: K sweeps (and the cycle-end stages they reach) of
+// the slots [s0, s0+G) of one instance per workgroup.
+template <class Sw>
+struct SweepCall;
+
+template <int L, int RPT>
+struct SweepCall<LatSweep<L, RPT>> {
+    static __device__ void run(LatSweep<L, RPT> &sw, const InstDev &I, int G, int s0, uint32_t t, ChunkLds &c,
+                               int stride)
+    {
+        sw.sweep(I, G, s0, t, c.slot_of, c.sp, c.tab, stride, c.Elds, c.flips);
+    }
+    static __device__ int SB(const LatSweep<L, RPT> &) { return LatSweep<L, RPT>::SB; }
+    static __device__ int lidx(const LatSweep<L, RPT> &, int i) { return LatSweep<L, RPT>::lidx(i); }
+};
+
+template <>
+struct SweepCall<CsrSweep> {
+    static __device__ void run(CsrSweep &sw, const InstDev &I, int G, int s0, uint32_t t, ChunkLds &c, int stride)
+    {
+        sw.sweep(I, G, s0, t, c.slot_of, c.sp, c.tab, stride, c.Elds, c.flips, c.rnd);
+    }
+    static __device__ int SB(const CsrSweep &s) { return s.SB; }
+    static __device__ int lidx(const CsrSweep &, int i) { return i; }
+};
+
+template <class Sw>
+__global__ void __launch_bounds__(Sw::MAXT) chunk_kernel(ChunkArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int item = a.order[blockIdx.x];
+    if (item < 0) return;   // padding block that keeps the XCD placement aligned
+    const WorkItem it = a.items[item];
+    const InstDev &I = *it.inst;
+    const int G = it.G, s0 = it.s0, n = I.n;
+    const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63;
+    const uint64_t t0 = *I.t;
+    const uint64_t tend = (t0 + a.K < I.sweep_cap) ? t0 + a.K : I.sweep_cap;
+    if (t0 >= tend) return;
+
+    Sw sw;
+    sw.setup(I, G);
+    const int SB = SweepCall<Sw>::SB(sw);
+    const int stride = I.tflip_stride;
+    ChunkLds c;
+    chunk_lds_layout(G, SB, stride, (n + 7) & ~7, lds_raw, &c);
+
+    // stage tables and state
+    for (int x = tid; x < G * stride; x += bs) c.tab[x] = I.tflip[(size_t)s0 * stride + x];
+    for (int x = tid; x < G * n; x += bs) {
+        int l = x / n, i = x - l * n;
+        c.sp[l * SB + SweepCall<Sw>::lidx(sw, i)] = I.spins[(size_t)(s0 + l) * n + i];
+    }
+    for (int l = tid; l < G; l += bs) {
+        c.slot_of[l] = l;
+        c.stor_of[l] = l;
+        c.Elds[l] = I.E[s0 + l];
+        c.flips[l] = 0;
+        c.satt[l] = 0;
+        c.sacc[l] = 0;
+    }
+    if (tid < 16) c.misc[tid] = 0;
+    // best-energy bookkeeping lives in registers of wave 0, lane 0
+    int bestE = I.best->E;
+    int64_t bestT = -1;
+    int bestSlot = -1;
+    int64_t hit = I.best->first_hit;
+    const int64_t hit0 = hit;
+    const uint32_t k0 = I.seed_lo, k1 = I.seed_hi;
+    const unsigned long long tagbase = ((unsigned long long)I.epoch) << 32;
+    __syncthreads();
+
+    bool failed = false;
+    for (uint64_t t = t0 + 1; t <= tend && !failed; ++t) {
+        SweepCall<Sw>::run(sw, I, G, s0, (uint32_t)t, c, stride);
+        __syncthreads();
+        if (t % (uint64_t)I.M == 0) {
+            const uint32_t cyc = (uint32_t)(t / (uint64_t)I.M);
+            // ---- proposals (Eq. 2), slots in increasing order ----
+            if (is_prop_sweep(I, t)) {
+                if (tid < 64) {
+                    for (int l = lane; l < G; l += 64) {
+                        int r = s0 + l;
+                        c.src[l] = 0;
+                        int B = I.bank_n[r];
+                        if (B > 0) {
+                            int k = I.cursor[r];
+                            I.cursor[r] = (k + 1 == B) ? 0 : k + 1;
+                            int ET = I.bankE[r][k];
+                            int st = c.stor_of[l];
+                            long long dd = (long long)ET - (long long)c.Elds[st];
+                            uint32_t T;
+                            if (dd <= 0) T = ALWAYS;
+                            else if (dd <= I.tprop_len[r]) T = I.tprop[I.tprop_off[r] + (int)dd - 1];
+                            else T = 0;
+                            uint32_t u = philox_word0((uint32_t)r, cyc, TAG_PROPOSE, k0, k1);
+                            I.prop_att[r] += 1;
+                            if (T == ALWAYS || u < T) {
+                                c.Elds[st] = ET;
+                                c.src[l] = (long long)(I.bank[r] + (size_t)k * n);
+                                I.prop_acc[r] += 1;
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                for (int l = 0; l < G; ++l) {
+                    const int8_t *src = (const int8_t *)c.src[l];
+                    if (src) {
+                        int8_t *dst = c.sp + c.stor_of[l] * SB;
+                        for (int i = tid; i < n; i += bs) dst[SweepCall<Sw>::lidx(sw, i)] = src[i];
+                    }
+                }
+                __syncthreads();
+            }
+            // ---- replica exchange (Eq. 1), alternating parity ----
+            const int first = (cyc & 1) ? 0 : 1;
+            if (tid < 64) {
+                // pairs inside this workgroup: exchange labels
+                for (int l = lane; l + 1 < G; l += 64) {
+                    int r = s0 + l;
+                    if (((r - first) & 1) != 0) continue;
+                    int sa = c.stor_of[l], sb = c.stor_of[l + 1];
+                    int dE = c.Elds[sb] - c.Elds[sa];
+                    uint32_t T;
+                    if (dE >= 0) T = ALWAYS;
+                    else if (-dE <= I.tswap_len[r]) T = I.tswap[I.tswap_off[r] - dE - 1];
+                    else T = 0;
+                    uint32_t u = philox_word0((uint32_t)r, cyc, TAG_SWAP, k0, k1);
+                    c.satt[l] += 1;
+                    if (T == ALWAYS || u < T) {
+                        c.sacc[l] += 1;
+                        c.stor_of[l] = sb;
+                        c.stor_of[l + 1] = sa;
+                        c.slot_of[sb] = l;
+                        c.slot_of[sa] = l + 1;
+                    }
+                }
+            }
+            // pairs across a workgroup boundary: copy states through global memory
+            const bool down = it.w > 0 && (((s0 - 1 - first) & 1) == 0);
+            const bool up = it.w + 1 < it.W && (((s0 + G - 1 - first) & 1) == 0);
+            if ((down || up) && tid < 64) {
+                const int buf = (cyc >> 1) & 1;
+                const unsigned long long tag = tagbase | cyc;
+                // publish my boundary states (side 0 = my lowest slot, 1 = my highest)
+                for (int side = 0; side < 2; ++side) {
+                    if (!(side == 0 ? down : up)) continue;
+                    int l = side == 0 ? 0 : G - 1;
+                    int st = c.stor_of[l];
+                    int8_t *out = it.xbuf + ((size_t)(it.w * 2 + side) * 2 + buf) * it.xstride;
+                    for (int i = lane; i < n; i += 64) out[i] = c.sp[st * SB + SweepCall<Sw>::lidx(sw, i)];
+                    if (lane == 0) *(int *)(out + it.xstride - 16) = c.Elds[st];
+                }
+                __threadfence();
+                if (lane == 0) {
+                    if (down) __hip_atomic_store(&it.flags[it.w * 2 + 0], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (up) __hip_atomic_store(&it.flags[it.w * 2 + 1], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                // wait for the partners' states
+                int timeout = 0;
+                if (lane == 0) {
+                    for (int side = 0; side < 2 && !timeout; ++side) {
+                        if (!(side == 0 ? down : up)) continue;
+                        int pw = side == 0 ? it.w - 1 : it.w + 1;
+                        unsigned long long *fl = &it.flags[pw * 2 + (side == 0 ? 1 : 0)];
+                        uint32_t polls = 0;
+                        while (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tag) {
+                            __builtin_amdgcn_s_sleep(2);
+                            if (++polls > a.spin_limit) { timeout = 1; break; }
+                        }
+                    }
+                }
+                timeout = __shfl(timeout, 0);
+                __threadfence();
+                if (timeout) {
+                    if (lane == 0) { c.misc[0] = 1; atomicExch(a.err, 1); }
+                } else {
+                    for (int side = 0; side < 2; ++side) {
+                        if (!(side == 0 ? down : up)) continue;
+                        int pw = side == 0 ? it.w - 1 : it.w + 1;
+                        const int8_t *in = it.xbuf + ((size_t)(pw * 2 + (side == 0 ? 1 : 0)) * 2 + buf) * it.xstride;
+                        int pE = *(const int *)(in + it.xstride - 16);
+                        int l = side == 0 ? 0 : G - 1;
+                        int st = c.stor_of[l];
+                        int myE = c.Elds[st];
+                        int r = side == 0 ? s0 - 1 : s0 + G - 1;     // lower slot of the pair
+                        int dE = side == 0 ? myE - pE : pE - myE;    // E_{r+1} - E_r
+                        uint32_t T;
+                        if (dE >= 0) T = ALWAYS;
+                        else if (-dE <= I.tswap_len[r]) T = I.tswap[I.tswap_off[r] - dE - 1];
+                        else T = 0;
+                        uint32_t u = philox_word0((uint32_t)r, cyc, TAG_SWAP, k0, k1);
+                        bool acc = (T == ALWAYS || u < T);
+                        if (side == 1 && lane == 0) {         // the lower workgroup owns the pair's counters
+                            c.satt[G - 1] += 1;
+                            if (acc) c.sacc[G - 1] += 1;
+                        }
+                        if (acc) {
+                            for (int i = lane; i < n; i += 64) c.sp[st * SB + SweepCall<Sw>::lidx(sw, i)] = in[i];
+                            if (lane == 0) c.Elds[st] = pE;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            failed = c.misc[0] != 0;
+        }
+        // ---- best energy and first hit (wave 0) ----
+        if (tid < 64) {
+            int e = 0x7FFFFFFF, ls = 0x7FFFFFFF;
+            for (int l = lane; l < G; l += 64) {
+                int v = c.Elds[c.stor_of[l]];
+                if (v < e) { e = v; ls = l; }
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                int e2 = __shfl_xor(e, off), l2 = __shfl_xor(ls, off);
+                if (e2 < e || (e2 == e && l2 < ls)) { e = e2; ls = l2; }
+            }
+            if (I.has_target && hit < 0 && e <= I.target) hit = (int64_t)t;
+            if (e < bestE) {
+                bestE = e;
+                bestT = (int64_t)t;
+                bestSlot = s0 + ls;
+                int st = c.stor_of[ls];
+                for (int i = lane; i < n; i += 64) it.best_spins[i] = c.sp[st * SB + SweepCall<Sw>::lidx(sw, i)];
+            }
+        }
+        __syncthreads();
+    }
+
+    // write the state back by slot
+    for (int x = tid; x < G * n; x += bs) {
+        int l = x / n, i = x - l * n;
+        I.spins[(size_t)(s0 + l) * n + i] = c.sp[c.stor_of[l] * SB + SweepCall<Sw>::lidx(sw, i)];
+    }
+    for (int l = tid; l < G; l += bs) {
+        I.E[s0 + l] = c.Elds[c.stor_of[l]];
+        I.flips[s0 + l] += c.flips[l];
+        if (s0 + l + 1 < I.R) {
+            I.swap_att[s0 + l] += c.satt[l];
+            I.swap_acc[s0 + l] += c.sacc[l];
+        }
+    }
+    if (tid == 0) {
+        BestRec b;
+        b.E = bestT >= 0 ? bestE : 0x7FFFFFFF;
+        b.slot = bestSlot;
+        b.t = bestT;
+        b.first_hit = (hit0 < 0) ? hit : -1;
+        b.pad = 0;
+        *it.best = b;
+    }
+}
+
+// Merge the per-workgroup best records of one instance into its canonical
+// record, and advance its sweep counter. One workgroup per instance.
+__global__ void finish_kernel(const WorkItem *items, const int *first_item, int n_inst, uint32_t K)
+{
+    int inst = blockIdx.x;
+    if (inst >= n_inst) return;
+    const WorkItem *its = items + first_item[inst];
+    const InstDev &I = *its[0].inst;
+    const int W = its[0].W;
+    __shared__ int win;
+    if (threadIdx.x == 0) {
+        BestRec cb = *I.best;
+        int wbest = -1;
+        long long hit = -1;
+        for (int w = 0; w < W; ++w) {
+            BestRec b = *its[w].best;
+            if (b.first_hit >= 0 && (hit < 0 || b.first_hit < hit)) hit = b.first_hit;
+            if (b.t < 0) continue;
+            if (b.E < cb.E || (b.E == cb.E && (b.t < cb.t || (b.t == cb.t && b.slot < cb.slot)))) {
+                cb.E = b.E;
+                cb.t = b.t;
+                cb.slot = b.slot;
+                wbest = w;
+            }
+        }
+        if (cb.first_hit < 0 && hit >= 0) cb.first_hit = hit;
+        *I.best = cb;
+        win = wbest;
+        uint64_t t0 = *I.t;
+        uint64_t t1 = t0 + K < I.sweep_cap ? t0 + K : I.sweep_cap;
+        if (t0 < t1) *I.t = t1;
+    }
+    __syncthreads();
+    if (win >= 0)
+        for (int i = threadIdx.x; i < I.n; i += blockDim.x) I.best_spins[i] = its[win].best_spins[i];
+}
+
+// ---------------------------------------------------------------------------
+// Plain path: one launch per sweep (every replica, one workgroup each), then a
+// one-workgroup tail launch for the cycle-end stages and best tracking.
+template <class Sw>
+__global__ void __launch_bounds__(Sw::MAXT) plain_sweep_kernel(const InstDev *Ip, uint32_t t)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const InstDev &I = *Ip;
+    const int r = blockIdx.x, n = I.n, tid = threadIdx.x, bs = blockDim.x;
+    Sw sw;
+    sw.setup(I, 1);
+    const int SB = SweepCall<Sw>::SB(sw);
+    const int stride = I.tflip_stride;
+    ChunkLds c;
+    chunk_lds_layout(1, SB, stride, (n + 7) & ~7, lds_raw, &c);
+    for (int x = tid; x < stride; x += bs) c.tab[x] = I.tflip[(size_t)r * stride + x];
+    for (int i = tid; i < n; i += bs) c.sp[SweepCall<Sw>::lidx(sw, i)] = I.spins[(size_t)r * n + i];
+    if (tid == 0) {
+        c.slot_of[0] = 0;
+        c.stor_of[0] = 0;
+        c.Elds[0] = 0;
+        c.flips[0] = 0;
+    }
+    __syncthreads();
+    SweepCall<Sw>::run(sw, I, 1, r, t, c, stride);
+    __syncthreads();
+    for (int i = tid; i < n; i += bs) I.spins[(size_t)r * n + i] = c.sp[SweepCall<Sw>::lidx(sw, i)];
+    if (tid == 0) {
+        I.E[r] += c.Elds[0];
+        I.flips[r] += c.flips[0];
+    }
+}
+
+__global__ void __launch_bounds__(256) plain_tail_kernel(const InstDev *Ip, uint32_t t)
+{
+    const InstDev &I = *Ip;
+    const int n = I.n, R = I.R, tid = threadIdx.x, bs = blockDim.x;
+    const uint32_t k0 = I.seed_lo, k1 = I.seed_hi;
+    __shared__ int acc_s[1024];
+    __shared__ int bank_k[1024];
+    if (t % (uint32_t)I.M == 0) {
+        const uint32_t cyc = t / (uint32_t)I.M;
+        if (is_prop_sweep(I, t)) {
+            for (int r = tid; r < R; r += bs) {
+                acc_s[r] = 0;
+                int B = I.bank_n[r];
+                if (B <= 0) continue;
+                int k = I.cursor[r];
+                I.cursor[r] = (k + 1 == B) ? 0 : k + 1;
+                int ET = I.bankE[r][k];
+                long long dd = (long long)ET - (long long)I.E[r];
+                uint32_t T;
+                if (dd <= 0) T = ALWAYS;
+                else if (dd <= I.tprop_len[r]) T = I.tprop[I.tprop_off[r] + (int)dd - 1];
+                else T = 0;
+                uint32_t u = philox_word0((uint32_t)r, cyc, TAG_PROPOSE, k0, k1);
+                I.prop_att[r] += 1;
+                if (T == ALWAYS || u < T) {
+                    acc_s[r] = 1;
+                    bank_k[r] = k;
+                    I.E[r] = ET;
+                    I.prop_acc[r] += 1;
+                }
+            }
+            __syncthreads();
+            for (int r = 0; r < R; ++r) {
+                if (!acc_s[r]) continue;
+                const int8_t *src = I.bank[r] + (size_t)bank_k[r] * n;
+                for (int i = tid; i < n; i += bs) I.spins[(size_t)r * n + i] = src[i];
+            }
+            __syncthreads();
+        }
+        const int first = (cyc & 1) ? 0 : 1;
+        for (int r = tid; r + 1 < R; r += bs) {
+            acc_s[r] = 0;
+            if (((r - first) & 1) != 0) continue;
+            int dE = I.E[r + 1] - I.E[r];
+            uint32_t T;
+            if (dE >= 0) T = ALWAYS;
+            else if (-dE <= I.tswap_len[r]) T = I.tswap[I.tswap_off[r] - dE - 1];
+            else T = 0;
+            uint32_t u = philox_word0((uint32_t)r, cyc, TAG_SWAP, k0, k1);
+            I.swap_att[r] += 1;
+            if (T == ALWAYS || u < T) {
+                acc_s[r] = 1;
+                I.swap_acc[r] += 1;
+                int e = I.E[r];
+                I.E[r] = I.E[r + 1];
+                I.E[r + 1] = e;
+            }
+        }
+        __syncthreads();
+        for (int r = 0; r + 1 < R; ++r) {
+            if (!acc_s[r]) continue;
+            int8_t *a = I.spins + (size_t)r * n, *b = I.spins + (size_t)(r + 1) * n;
+            for (int i = tid; i < n; i += bs) {
+                int8_t x = a[i];
+                a[i] = b[i];
+                b[i] = x;
+            }
+        }
+        __syncthreads();
+    }
+    // best energy and first hit
+    __shared__ int be[256], bl[256];
+    int e = 0x7FFFFFFF, ls = 0x7FFFFFFF;
+    for (int r = tid; r < R; r += bs) {
+        int v = I.E[r];
+        if (v < e) { e = v; ls = r; }
+    }
+    be[tid] = e;
+    bl[tid] = ls;
+    __syncthreads();
+    for (int off = bs / 2; off > 0; off >>= 1) {
+        if (tid < off) {
+            int e2 = be[tid + off], l2 = bl[tid + off];
+            if (e2 < be[tid] || (e2 == be[tid] && l2 < bl[tid])) { be[tid] = e2; bl[tid] = l2; }
+        }
+        __syncthreads();
+    }
+    __shared__ int better_s;
+    if (tid == 0) {
+        BestRec b = *I.best;
+        if (I.has_target && b.first_hit < 0 && be[0] <= I.target) b.first_hit = t;
+        better_s = be[0] < b.E;
+        if (better_s) {
+            b.E = be[0];
+            b.t = t;
+            b.slot = bl[0];
+        }
+        *I.best = b;
+        *I.t = t;
+    }
+    __syncthreads();
+    if (better_s)
+        for (int i = tid; i < n; i += bs) I.best_spins[i] = I.spins[(size_t)bl[0] * n + i];
+}
+
+// ---------------------------------------------------------------------------
+// Initialization ("Initialize replica states randomly", Algorithm 1): spin i
+// of slot r is +1 iff word (i & 3) of Philox(i >> 2, 0, r, INIT) >= 2^31;
+// clamped sites take their clamp value.
+__global__ void init_kernel(const InstDev *Ip)
+{
+    const InstDev &I = *Ip;
+    const int n = I.n;
+    const int ng = (n + 3) >> 2;
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= ng * I.R) return;
+    int r = gid / ng, g = gid - r * ng;
+    P4 w = philox((uint32_t)g, 0, (uint32_t)r, TAG_INIT, I.seed_lo, I.seed_hi);
+    for (int j = 0; j < 4; ++j) {
+        int i = 4 * g + j;
+        if (i >= n) break;
+        int cl = I.clamp[i];
+        I.spins[(size_t)r * n + i] = cl ? (int8_t)cl : (int8_t)(w.v[j] >= 0x80000000u ? 1 : -1);
+    }
+}
+
+// Full energy E(m) = -sum_{i<j} J_ij m_i m_j - sum_i h_i m_i (Supp. S4) of k
+// configurations: one workgroup per configuration, lane partial sums reduced
+// across the wavefront and then through LDS.
+__global__ void __launch_bounds__(256) energy_kernel(const InstDev *Ip, const int8_t *cfg, int k, int32_t *out)
+{
+    const InstDev &I = *Ip;
+    const int b = blockIdx.x;
+    if (b >= k) return;
+    const int n = I.n;
+    const int8_t *m = cfg + (size_t)b * n;
+    int e = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        int mi = m[i];
+        int f = I.h[i];
+        if (I.kind == KIND_LATTICE) {
+            int L = I.L;
+            int x = i % L, y = (i / L) % L, z = i / (L * L);
+            int jx = x + 1 == L ? i - (L - 1) : i + 1;
+            int jy = y + 1 == L ? i - (L - 1) * L : i + L;
+            int jz = z + 1 == L ? i - (L - 1) * L * L : i + L * L;
+            f = f + I.J3[i] * m[jx] + I.J3[n + i] * m[jy] + I.J3[2 * n + i] * m[jz];
+        } else {
+            for (int q = I.row_ptr[i]; q < I.row_ptr[i + 1]; ++q) {
+                int j = I.col[q];
+                if (j > i) f += (int)I.Jc[q] * (int)m[j];
+            }
+        }
+        e -= mi * f;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+    __shared__ int part[16];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) s += part[w];
+        out[b] = s;
+    }
+}
+
+// Record the state right after initialization as the first best (t = 0).
+__global__ void init_best_kernel(const InstDev *Ip)
+{
+    const InstDev &I = *Ip;
+    __shared__ int slot_s;
+    if (threadIdx.x == 0) {
+        int e = 0x7FFFFFFF, ls = 0;
+        for (int r = 0; r < I.R; ++r)
+            if (I.E[r] < e) { e = I.E[r]; ls = r; }
+        BestRec b;
+        b.E = e;
+        b.slot = ls;
+        b.t = 0;
+        b.first_hit = (I.has_target && e <= I.target) ? 0 : -1;
+        b.pad = 0;
+        *I.best = b;
+        slot_s = ls;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < I.n; i += blockDim.x) I.best_spins[i] = I.spins[(size_t)slot_s * I.n + i];
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (C++ linkage, used by the runtime in host.cpp).
+
+#define TAPT_LATTICE_LIST(X) X(4) X(6) X(8) X(10) X(12) X(14) X(16)
+
+bool lattice_supported(int L) { return L >= 4 && L <= 16 && L % 2 == 0; }
+
+int lattice_max_threads() { return 512; }
+
+int lattice_threads(int L, int G, int rpt) { return ((G + rpt - 1) / rpt) * (L * L * L / 8); }
+
+size_t chunk_lds_bytes(int kind, int n, int G, int stride)
+{
+    int SB = kind == KIND_LATTICE ? n : CsrSweep::storage_bytes(n);
+    int nr = kind == KIND_LATTICE ? 0 : ((n + 7) & ~7);
+    return chunk_lds_layout(G, SB, stride, nr, nullptr, nullptr);
+}
+
+template <class K>
+static hipError_t set_lds(K kern, size_t lds)
+{
+    return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+// The dynamic-LDS attribute is set by chunk_occupancy, which the runtime calls
+// before the first launch, so nothing here is illegal under stream capture.
+template <class Sw>
+static hipError_t launch_chunk_t(const ChunkArgs &a, int block, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL(chunk_kernel<Sw>, dim3(a.n_items), dim3(block), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk(int kind, int L, int rpt, const ChunkArgs &a, int block, size_t lds, hipStream_t s)
+{
+    if (kind == KIND_CSR) return launch_chunk_t<CsrSweep>(a, block, lds, s);
+#define X(LL)                                                                         \
+    if (L == LL) {                                                                    \
+        if (rpt == 1) return launch_chunk_t<LatSweep<LL, 1>>(a, block, lds, s);       \
+        if (rpt == 2) return launch_chunk_t<LatSweep<LL, 2>>(a, block, lds, s);       \
+        if (rpt == 4) return launch_chunk_t<LatSweep<LL, 4>>(a, block, lds, s);       \
+    }
+    TAPT_LATTICE_LIST(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+template <class Sw>
+static hipError_t occupancy_t(int block, size_t lds, int *blocks_per_cu)
+{
+    hipError_t e = set_lds(chunk_kernel<Sw>, lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, chunk_kernel<Sw>, block, lds);
+}
+
+hipError_t chunk_occupancy(int kind, int L, int rpt, int block, size_t lds, int *blocks_per_cu)
+{
+    if (kind == KIND_CSR) return occupancy_t<CsrSweep>(block, lds, blocks_per_cu);
+#define X(LL)                                                                      \
+    if (L == LL) {                                                                 \
+        if (rpt == 1) return occupancy_t<LatSweep<LL, 1>>(block, lds, blocks_per_cu); \
+        if (rpt == 2) return occupancy_t<LatSweep<LL, 2>>(block, lds, blocks_per_cu); \
+        if (rpt == 4) return occupancy_t<LatSweep<LL, 4>>(block, lds, blocks_per_cu); \
+    }
+    TAPT_LATTICE_LIST(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_finish(const WorkItem *items, const int *first_item, int n_inst, uint32_t K, hipStream_t s)
+{
+    hipLaunchKernelGGL(finish_kernel, dim3(n_inst), dim3(256), 0, s, items, first_item, n_inst, K);
+    return hipGetLastError();
+}
+
+template <class Sw>
+static hipError_t launch_plain_sweep_t(const InstDev *dI, int R, int block, size_t lds, uint32_t t, hipStream_t s)
+{
+    hipError_t e = set_lds(plain_sweep_kernel<Sw>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(plain_sweep_kernel<Sw>, dim3(R), dim3(block), lds, s, dI, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain(int kind, int L, const InstDev *dI, int R, int n, int stride, uint32_t t, hipStream_t s)
+{
+    size_t lds = chunk_lds_bytes(kind, n, 1, stride);
+    hipError_t e;
+    if (kind == KIND_CSR) {
+        e = launch_plain_sweep_t<CsrSweep>(dI, R, 256, lds, t, s);
+    } else {
+        e = hipErrorInvalidValue;
+        int block = (lattice_threads(L, 1, 1) + 63) & ~63;
+#define X(LL) \
+        if (L == LL) e = launch_plain_sweep_t<LatSweep<LL, 1>>(dI, R, block, lds, t, s);
+        TAPT_LATTICE_LIST(X)
+#undef X
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(plain_tail_kernel, dim3(1), dim3(256), 0, s, dI, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const InstDev *dI, int R, int n, hipStream_t s)
+{
+    int ng = (n + 3) >> 2;
+    int total = ng * R;
+    hipLaunchKernelGGL(init_kernel, dim3((total + 255) / 256), dim3(256), 0, s, dI);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy(const InstDev *dI, const int8_t *cfg, int k, int32_t *out, hipStream_t s)
+{
+    if (k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(energy_kernel, dim3(k), dim3(256), 0, s, dI, cfg, k, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_best(const InstDev *dI, hipStream_t s)
+{
+    hipLaunchKernelGGL(init_best_kernel, dim3(1), dim3(256), 0, s, dI);
+    return hipGetLastError();
+}
+
+uint32_t host_philox_word0(uint32_t c0, uint32_t c1, uint32_t c3, uint32_t k0, uint32_t k1)
+{
+    return philox_word0(c0, c1, c3, k0, k1);
+}
+
+} // namespace tapt

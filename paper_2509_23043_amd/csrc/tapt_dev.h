@@ -1,0 +1,91 @@
+// Device-side descriptors shared by the HIP kernels and the host runtime of
+// libtapt. Everything the kernels read about a problem instance lives in one
+// InstDev struct in device memory; a persistent launch is a list of WorkItems,
+// one per workgroup.
+#pragma once
+#include <stdint.h>
+
+namespace tapt {
+
+enum : int32_t { KIND_LATTICE = 0, KIND_CSR = 1 };
+enum : uint32_t { TAG_INIT = 1, TAG_SWEEP = 2, TAG_REFINE = 3, TAG_PROPOSE = 4, TAG_SWAP = 5, TAG_BANK = 6 };
+constexpr uint32_t ALWAYS = 0xFFFFFFFFu;   // threshold meaning "accept unconditionally"
+constexpr int MAX_COLORS = 64;
+
+struct BestRec {          // best min_r E_r seen; ordered by (E, t, slot)
+    int32_t E;
+    int32_t slot;
+    int64_t t;
+    int64_t first_hit;    // -1: target not reached
+    int64_t pad;
+};
+
+struct InstDev {
+    int32_t n, L, R, kind;
+    int32_t rule, M, D, tflip_stride;       // flip table: index d + D, d = m_i I_i in [-D, D]
+    int32_t has_target, target, ncolors, nfree;
+    int32_t nnz, pad0;
+    uint32_t seed_lo, seed_hi;
+    uint32_t epoch, pad1;                   // bumps when the state is replaced
+    int64_t prop_start, prop_period, prop_stop;
+    uint64_t sweep_cap;                     // batched runs stop at this sweep count
+
+    // problem
+    const int8_t *J3;          // lattice: [3][n] +x,+y,+z bond couplings
+    const int32_t *row_ptr;    // CSR [n+1]
+    const int16_t *col;        // CSR [nnz]
+    const int8_t *Jc;          // CSR [nnz]
+    const int16_t *h;          // [n]
+    const int8_t *clamp;       // [n]
+    const int16_t *color_sites;// CSR: free sites sorted by (color, index) [nfree]
+    const int32_t *color_off;  // [ncolors + 1]
+
+    // acceptance tables (uint32 thresholds, built on the host in FP64)
+    const uint32_t *tflip;     // [R][tflip_stride]
+    const uint32_t *tprop;     // row r: entries for d = 1..tprop_len[r] at tprop_off[r]
+    const int32_t *tprop_off, *tprop_len;
+    const uint32_t *tswap;     // pair r: entries for d = 1..tswap_len[r] at tswap_off[r]
+    const int32_t *tswap_off, *tswap_len;
+
+    // state (slot order)
+    int8_t *spins;             // [R][n]
+    int32_t *E;                // [R]
+    unsigned long long *t;     // completed sweeps
+    int32_t *cursor;           // [R]
+
+    // proposal banks
+    const int8_t *const *bank; // [R] device pointers, null = slot not proposal-enabled
+    const int32_t *const *bankE;
+    const int32_t *bank_n;     // [R]
+
+    // counters
+    unsigned long long *swap_att, *swap_acc;   // [R-1]
+    unsigned long long *prop_att, *prop_acc;   // [R]
+    unsigned long long *flips;                 // [R]
+
+    BestRec *best;             // canonical record
+    int8_t *best_spins;        // [n]
+};
+
+struct WorkItem {              // one workgroup of a persistent chunk launch
+    const InstDev *inst;
+    int32_t s0, G;             // beta slots [s0, s0 + G) held by this workgroup
+    int32_t w, W;              // index of this workgroup in the instance's ladder split
+    BestRec *best;             // this workgroup's record for the chunk
+    int8_t *best_spins;        // [n]
+    int8_t *xbuf;              // instance exchange area: [W][2 sides][2 buffers][xstride]
+    unsigned long long *flags; // instance flags [W][2 sides]
+    int32_t xstride;           // bytes per exchange buffer (n spins + energy, padded)
+    int32_t pad;
+};
+
+struct ChunkArgs {
+    const WorkItem *items;
+    const int32_t *order;      // blockIdx -> item index (XCD-aware placement)
+    int32_t n_items;
+    uint32_t K;                // sweeps per launch
+    int32_t *err;              // set to 1 when a cross-workgroup wait times out
+    uint32_t spin_limit;       // polls before a wait gives up
+};
+
+} // namespace tapt

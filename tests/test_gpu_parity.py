@@ -1,0 +1,186 @@
+"""GPU vs oracle parity: the HIP path must realise the same chain bit for bit
+(spins, integer energies, counters, best record) for the same seeds."""
+import numpy as np
+import pytest
+
+from paper_2509_23043_amd import binding, inputs
+from tests.gpu_util import announce, compare, make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _cfg1():
+    return inputs.ea_lattice(4, 1), inputs.geometric_ladder(16)
+
+
+def test_plain_path_cfg1():
+    announce("plain path, EA L=4 R=16, 200 sweeps")
+    g, b = _cfg1()
+    ctx, ref = make_pair(g, b, seed=1001)
+    ctx.sweep(200)
+    ref.run(200)
+    compare(ctx, ref)
+
+
+@pytest.mark.parametrize("G,rpt,K", [(16, 1, 1000), (16, 2, 64), (5, 1, 37), (4, 2, 200), (3, 4, 50), (1, 1, 100)])
+def test_batched_tilings_cfg1(G, rpt, K):
+    announce(f"batched EA L=4 R=16, G={G} rpt={rpt} K={K}, 300 sweeps")
+    g, b = _cfg1()
+    ctx, ref = make_pair(g, b, seed=1001)
+    bt = binding.Batch([ctx], replicas_per_wg=G, replicas_per_thread=rpt, chunk_sweeps=K)
+    bt.sweep(300)
+    ref.run(300)
+    compare(ctx, ref)
+
+
+def test_cfg1_full_1000_sweeps_graph():
+    announce("batched EA L=4 R=16, 1000 sweeps, hipGraph replay")
+    g, b = _cfg1()
+    ctx, ref = make_pair(g, b, seed=1001, target=-100)
+    bt = binding.Batch([ctx], chunk_sweeps=128, use_graph=True)
+    bt.sweep(1000)
+    ref.run(1000)
+    compare(ctx, ref)
+
+
+@pytest.mark.parametrize("path", ["plain", "batched", "split"])
+def test_proposals(path):
+    announce(f"proposals, {path}")
+    g, b = _cfg1()
+    banks = {r: inputs.random_bank(64, 9, seed=200 + r) for r in range(14)}
+    ctx, ref = make_pair(g, b, seed=77, banks=banks, prop_start=4, prop_period=6, prop_stop=150)
+    if path == "plain":
+        ctx.sweep(180)
+    else:
+        bt = binding.Batch([ctx], replicas_per_wg=16 if path == "batched" else 6, chunk_sweeps=45)
+        bt.sweep(180)
+    ref.run(180)
+    compare(ctx, ref)
+
+
+@pytest.mark.parametrize("rule,M", [("gibbs", 1), ("metropolis", 3), ("gibbs", 4)])
+def test_rules_and_cycle_length(rule, M):
+    announce(f"rule={rule} M={M}")
+    g, b = _cfg1()
+    banks = {r: inputs.random_bank(64, 5, seed=300 + r) for r in range(0, 12, 2)}
+    kw = dict(rule=rule, M=M, prop_start=2 * M, prop_period=2 * M)
+    ctx, ref = make_pair(g, b, seed=5, banks=banks, **kw)
+    ctx2, _ = make_pair(g, b, seed=5, banks=banks, **kw)
+    ctx.sweep(121)
+    bt = binding.Batch([ctx2], replicas_per_wg=5, chunk_sweeps=40)
+    bt.sweep(121)
+    ref.run(121)
+    compare(ctx, ref)
+    compare(ctx2, ref)
+
+
+@pytest.mark.parametrize("L,R", [(6, 8), (8, 12), (10, 6), (12, 4), (14, 3), (16, 4)])
+def test_lattice_sizes(L, R):
+    announce(f"lattice L={L} R={R}")
+    g = inputs.ea_lattice(L, 10 + L)
+    b = inputs.geometric_ladder(R)
+    ctx, ref = make_pair(g, b, seed=L)
+    ctx2, _ = make_pair(g, b, seed=L)
+    bt = binding.Batch([ctx2], chunk_sweeps=25)
+    bt.sweep(60)
+    ctx.sweep(60)
+    ref.run(60)
+    compare(ctx, ref)
+    compare(ctx2, ref)
+
+
+@pytest.mark.parametrize("m", [3, 4, 6])
+def test_factorization_csr(m):
+    announce(f"multiplier m={m} (CSR kernel, clamps, DSATUR colors)")
+    ps = inputs.primes_in(1 << (m - 1), 1 << m)
+    C = ps[0] * ps[-1]
+    g = inputs.multiplier(m, C)
+    b = inputs.geometric_ladder(12)
+    egnd = -3 * m * m - 4 * m * (m - 1)
+    banks = {r: np.stack([inputs.multiplier_assignment(g, ps[0], ps[-1])] * 2 + [inputs.random_bank(g["n"], 1, seed=r, clamp=g["clamp"])[0]])
+             for r in range(3)}
+    ctx, ref = make_pair(g, b, seed=m, banks=banks, prop_start=20, prop_period=20, target=egnd)
+    ctx2, _ = make_pair(g, b, seed=m, banks=banks, prop_start=20, prop_period=20, target=egnd)
+    ctx.sweep(100)
+    bt = binding.Batch([ctx2], replicas_per_wg=5, chunk_sweeps=30)
+    bt.sweep(100)
+    ref.run(100)
+    compare(ctx, ref)
+    compare(ctx2, ref)
+
+
+def test_gadget_sequential_colors():
+    announce("full adder, one color per spin (sequential sweep)")
+    g = inputs.gadget_graph("fa")
+    b = np.array([0.5, 1.7, 4.6])
+    ctx, ref = make_pair(g, b, seed=3, rule="gibbs")
+    ctx.sweep(500)
+    ref.run(500)
+    compare(ctx, ref)
+
+
+def test_mixed_batch_and_switching_paths():
+    announce("mixed batch (lattices of 3 sizes + CSR), then plain, then batched again")
+    probs = [(inputs.ea_lattice(4, 2), inputs.geometric_ladder(7)),
+             (inputs.ea_lattice(6, 3), inputs.geometric_ladder(9)),
+             (inputs.ea_lattice(8, 4), inputs.geometric_ladder(10)),
+             (inputs.multiplier(4, 11 * 13), inputs.geometric_ladder(8))]
+    pairs = [make_pair(g, b, seed=40 + k) for k, (g, b) in enumerate(probs)]
+    bt = binding.Batch([p[0] for p in pairs], replicas_per_wg=4, chunk_sweeps=33)
+    bt.sweep(70)
+    for ctx, _ in pairs:
+        ctx.sweep(11)
+    bt.sweep(40)
+    for ctx, ref in pairs:
+        ref.run(121)
+        compare(ctx, ref)
+
+
+def test_resume_from_saved_state():
+    announce("save / restore / continue")
+    g, b = _cfg1()
+    ctx, ref = make_pair(g, b, seed=9)
+    ctx.sweep(50)
+    spins, t = ctx.state()
+    ctx2 = binding.Context(g, b, seed=9)
+    ctx2.set_state(spins, t)
+    bt = binding.Batch([ctx2], replicas_per_wg=8, chunk_sweeps=20)
+    bt.sweep(70)
+    ref.run(120)
+    s2, t2 = ctx2.state()
+    assert t2 == 120
+    assert np.array_equal(s2, ref.spins)
+    assert np.array_equal(ctx2.energies(), ref.E)
+
+
+def test_bank_energies_and_energy_kernel():
+    announce("energy kernel vs oracle energy")
+    import torch
+    import oracle
+    g = inputs.ea_lattice(8, 5)
+    ctx = binding.Context(g, inputs.geometric_ladder(4), seed=1)
+    cfg = inputs.random_bank(512, 33, seed=9)
+    dev = torch.from_numpy(cfg).cuda()
+    out = torch.zeros(33, dtype=torch.int32, device="cuda")
+    ctx.energy_device(dev.data_ptr(), 33, out.data_ptr())
+    torch.cuda.synchronize()
+    run = oracle.Run(g, [1.0], seed=0)
+    want = np.array([run.energy(c) for c in cfg])
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
+def test_invalid_inputs_rejected():
+    announce("argument validation")
+    g, b = _cfg1()
+    with pytest.raises(binding.TaptError):
+        binding.Context(g, b[::-1], seed=1)
+    ctx = binding.Context(g, b, seed=1)
+    bad = np.zeros((2, 64), np.int8)
+    with pytest.raises(binding.TaptError):
+        ctx.propose(0, bad)
+    m = inputs.multiplier(3, 35)
+    ctxm = binding.Context(m, b[:4], seed=1)
+    wrong = inputs.random_bank(m["n"], 2, seed=1)          # ignores the clamps
+    if np.any((m["clamp"] != 0) & (wrong[0] != m["clamp"])):
+        with pytest.raises(binding.TaptError):
+            ctxm.propose(0, wrong)
