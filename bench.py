@@ -1,0 +1,306 @@
+#!/usr/bin/env python3
+"""Benchmark of the TAPT hot path on one MI355X.
+
+Workload: 64 synthetic 3D Edwards-Anderson +-J instances, L = 8 periodic
+(512 int8 spins), 32 replicas on a geometric beta ladder 0.2..3.0, Metropolis,
+one sweep per swap stage, proposals every 100 sweeps on the 30 hottest slots
+from per-slot banks of 256 configurations produced by plain-PT runs of the same
+instance. One step = 10^4 sweeps of the whole batch (every step of
+Algorithm 1: sweeps, proposal stages, swap stages, best tracking); the default
+10 timed steps are the 10^5-sweep run.
+
+Prints one JSON line: batched attempts/ns (value), the plain
+one-instance-per-launch path on the same chain (bit-identical final state),
+the ALU roofline of the chunk kernel from HIP events, and the CPU oracle
+baseline on this host.
+"""
+import argparse
+import hashlib
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spin-flip attempts/ns (batched vs plain) + p50/p99 time-to-target per request"
+# algorithmic integer operations per single-spin attempt on the +-J cubic lattice:
+# 6 multiply-accumulates for the local field, 2 for dE/2 = m I and the table
+# index, 7.5 for one eighth of a Philox4x32-10 call (10 rounds of two 32x32->64
+# multiplies and four XORs, 8 uniforms per call), 3 for compare, flip, energy.
+OPS_PER_ATTEMPT = 6 + 2 + 7.5 + 3
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12       # int32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+LDS_BYTES_PER_ATTEMPT = 14                       # 6 neighbour spins + 6 couplings + own spin read + write
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12          # 128 B/clk/CU
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sweeps-per-step", type=int, default=10_000)
+    ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--L", type=int, default=8)
+    ap.add_argument("--R", type=int, default=32)
+    ap.add_argument("--bank", type=int, default=256)
+    ap.add_argument("--tiling", default="auto", help="'auto' or G,rpt (slots per workgroup, per thread)")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=1500)
+    ap.add_argument("--calib-copy", action="store_true", help="also run a 256 MiB device copy (PMC scaling)")
+    ap.add_argument("--bank-cache", default=None,
+                    help="file to save the generated banks to, or load them from when it exists")
+    return ap.parse_args()
+
+
+def problems(n_inst, L, R):
+    from paper_2509_23043_amd import inputs
+    probs = [inputs.ea_lattice(L, 2000 + i) for i in range(n_inst)]
+    betas = inputs.geometric_ladder(R)
+    return probs, betas
+
+
+def make_banks(probs, betas, B, n_prop_slots, log):
+    """Per-slot banks from plain-PT runs (no proposals) of each instance:
+    10^4 burn-in sweeps, then one sample of every slot every 100 sweeps."""
+    import torch
+    from paper_2509_23043_amd import binding
+    n = probs[0]["n"]
+    R = len(betas)
+    gens = [binding.Context(p, betas, seed=1_000_000 + i) for i, p in enumerate(probs)]
+    bt = binding.Batch(gens, chunk_sweeps=2000)
+    bt.sweep(10_000)
+    bank = torch.empty((len(probs), n_prop_slots, B, n), dtype=torch.int8, device="cuda")
+    tmp = torch.empty((R, n), dtype=torch.int8, device="cuda")
+    for k in range(B):
+        bt.sweep(100)
+        for i, g in enumerate(gens):
+            g.state_device(tmp.data_ptr())
+            bank[i, :, k, :] = tmp[:n_prop_slots]
+        if (k + 1) % 64 == 0:
+            log(f"bank samples {k + 1}/{B}")
+    torch.cuda.synchronize()
+    log(f"banks: {len(probs)} x {n_prop_slots} slots x {B} configs")
+    bt.close()
+    for g in gens:
+        g.close()
+    return bank
+
+
+def build_contexts(probs, betas, bank, seeds):
+    from paper_2509_23043_amd import binding
+    ctxs = []
+    for i, p in enumerate(probs):
+        c = binding.Context(p, betas, seed=seeds[i], prop_start=100, prop_period=100)
+        for r in range(bank.shape[1]):
+            c.propose_device(r, bank[i, r].data_ptr(), bank.shape[2])
+        ctxs.append(c)
+    return ctxs
+
+
+def scan_tilings(probs, betas, bank, L, R, log):
+    """Time a short run of each candidate tiling on scratch contexts. Results
+    are bit-identical for every tiling, so only speed is compared."""
+    from paper_2509_23043_amd import binding
+    import torch
+    nc = L ** 3 // 8
+    cands = []
+    for G in (32, 16, 8, 4, 2):
+        for rpt in (4, 2, 1):
+            if G < rpt or G > R:
+                continue
+            if ((G + rpt - 1) // rpt) * nc > 512:
+                continue
+            cands.append((G, rpt))
+    ctxs = build_contexts(probs, betas, bank, [7 + i for i in range(len(probs))])
+    res = []
+    for G, rpt in cands:
+        try:
+            bt = binding.Batch(ctxs, replicas_per_wg=G, replicas_per_thread=rpt, chunk_sweeps=500)
+        except binding.TaptError as e:
+            log(f"tiling G={G} rpt={rpt}: {e}")
+            continue
+        bt.sweep(500)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bt.sweep(1500)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rate = 1500 * len(probs) * R * L ** 3 / dt / 1e9
+        res.append((rate, G, rpt))
+        log(f"tiling G={G:2d} rpt={rpt}: {rate:8.1f} attempts/ns")
+        bt.close()
+    for c in ctxs:
+        c.close()
+    res.sort(reverse=True)
+    return res
+
+
+def _cpu_worker(args):
+    idx, L, R, seed, bank, sweeps = args
+    import oracle
+    from paper_2509_23043_amd import inputs
+    p = inputs.ea_lattice(L, 2000 + idx)
+    betas = inputs.geometric_ladder(R)
+    banks = {r: bank[r] for r in range(bank.shape[0])}
+    run = oracle.Run(p, betas, seed=seed, banks=banks, prop_start=100, prop_period=100, check_energy=False)
+    t0 = time.perf_counter()
+    run.run(sweeps)
+    return time.perf_counter() - t0, sweeps * R * L ** 3
+
+
+def cpu_baseline(bank_host, L, R, sweeps, log):
+    workers = max(1, min(16, os.cpu_count() or 1, len(bank_host)))
+    jobs = [(i, L, R, 3000 + i, bank_host[i], sweeps) for i in range(workers)]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        out = pool.map(_cpu_worker, jobs)
+    wall = time.perf_counter() - t0
+    attempts = sum(a for _, a in out)
+    single = np.mean([a / t for t, a in out]) / 1e9
+    rate = attempts / max(t for t, _ in out) / 1e9
+    log(f"cpu oracle: {workers} processes, {attempts:.3g} attempts, {wall:.1f} s wall, "
+        f"{rate:.4f} attempts/ns ({single:.4f} per core)")
+    return dict(value=round(rate, 5), unit="attempts/ns", cores=workers, kind="oracle",
+                single_core_value=round(single, 5),
+                sample=f"{workers} instances (one per process) of the same workload, {sweeps} sweeps each "
+                       f"with proposals every 100 sweeps, banks as on the GPU")
+
+
+def traffic_from_profiles(launch_sweeps, kern_hash):
+    path = os.path.join(ROOT, "profiles", "traffic_chunk_kernel_ea_l8_r32_x64.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256") != kern_hash or d.get("sweeps_per_launch") != launch_sweeps:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); instances would shard "
+              f"across GPUs with no communication, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2509_23043_amd import binding
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    binding.lib()
+    L, R, NI, S = args.L, args.R, args.instances, args.sweeps_per_step
+    n = L ** 3
+    n_prop = R - 2
+    probs, betas = problems(NI, L, R)
+    t0 = time.perf_counter()
+    if args.bank_cache and os.path.exists(args.bank_cache):
+        bank = torch.load(args.bank_cache, weights_only=True).cuda()
+        assert tuple(bank.shape) == (NI, n_prop, args.bank, n), bank.shape
+        log(f"banks loaded from {args.bank_cache}")
+    else:
+        bank = make_banks(probs, betas, args.bank, n_prop, log)
+        log(f"bank generation {time.perf_counter() - t0:.1f} s")
+        if args.bank_cache:
+            torch.save(bank.cpu(), args.bank_cache)
+
+    if args.tiling == "auto":
+        scan = scan_tilings(probs, betas, bank, L, R, log)
+        _, G, rpt = scan[0]
+    else:
+        G, rpt = (int(x) for x in args.tiling.split(","))
+        scan = []
+    log(f"tiling: {G} slots per workgroup, {rpt} per thread")
+
+    seeds = [3000 + i for i in range(NI)]
+    ctxs = build_contexts(probs, betas, bank, seeds)
+    bt = binding.Batch(ctxs, replicas_per_wg=G, replicas_per_thread=rpt, chunk_sweeps=S)
+    for _ in range(args.warmup):
+        bt.sweep(S)
+    torch.cuda.synchronize()
+    bt.kernel_time()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bt.sweep(S)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms, launches = bt.kernel_time()
+    attempts = args.steps * S * NI * R * n
+    value = attempts / dt / 1e9
+    ms_step = dt * 1e3 / args.steps
+    log(f"batched: {value:.1f} attempts/ns, {ms_step:.2f} ms/step, chunk kernel {kern_ms / max(launches, 1):.3f} ms avg")
+
+    # the plain path on instance 0, same seed and bank: same chain, compared bit for bit
+    plain = None
+    if not args.no_plain:
+        p_ctx = build_contexts(probs[:1], betas, bank[:1], seeds[:1])[0]
+        total = (args.warmup + args.steps) * S
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p_ctx.sweep(total)
+        torch.cuda.synchronize()
+        pdt = time.perf_counter() - t0
+        p_att = total * R * n
+        s_plain, _ = p_ctx.state()
+        s_batch, _ = ctxs[0].state()
+        same = bool(np.array_equal(s_plain, s_batch) and np.array_equal(p_ctx.energies(), ctxs[0].energies()))
+        res_b = ctxs[0].summary()["best"]
+        plain = dict(value=round(p_att / pdt / 1e9, 4), unit="attempts/ns", sweeps=total,
+                     instances=1, identical_final_state=same, best_energy=int(p_ctx.summary()["best"]),
+                     best_energy_batched=int(res_b))
+        log(f"plain: {plain['value']} attempts/ns over {total} sweeps, identical={same}")
+        if not same:
+            log("ERROR: plain and batched chains differ")
+            sys.exit(1)
+        plain["speedup"] = round(value / plain["value"], 1)
+
+    if args.calib_copy:
+        a = torch.ones(1 << 28, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    # roofline of the chunk kernel from its own HIP events
+    avg_ms = kern_ms / max(launches, 1)
+    att_launch = attempts / max(launches, 1)
+    achieved = OPS_PER_ATTEMPT * att_launch / (avg_ms * 1e-3) / 1e12
+    kern_src = open(os.path.join(ROOT, "paper_2509_23043_amd", "csrc", "kernels.hip"), "rb").read()
+    kern_hash = hashlib.sha256(kern_src).hexdigest()
+    roof = dict(bound="alu", achieved=round(achieved, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TOP/s",
+                frac=round(achieved / VALU_PEAK_TOPS, 4), traffic=traffic_from_profiles(S, kern_hash),
+                kernel="chunk_kernel<LatSweep<8,*>>", avg_launch_ms=round(avg_ms, 4), launches=launches,
+                ops_per_attempt=OPS_PER_ATTEMPT,
+                lds=dict(bytes_per_attempt=LDS_BYTES_PER_ATTEMPT,
+                         achieved_TBps=round(LDS_BYTES_PER_ATTEMPT * att_launch / (avg_ms * 1e-3) / 1e12, 3),
+                         peak_TBps=round(LDS_PEAK_TBS, 1),
+                         frac=round(LDS_BYTES_PER_ATTEMPT * att_launch / (avg_ms * 1e-3) / 1e12 / LDS_PEAK_TBS, 4)))
+
+    cpu = None
+    if not args.no_cpu:
+        bank_host = bank[:16].cpu().numpy()
+        cpu = cpu_baseline(bank_host, L, R, args.cpu_sweeps, log)
+
+    out = dict(metric=METRIC, value=round(value, 2), unit="attempts/ns", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(ms_step, 3), higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="int8", data="synthetic",
+               config=dict(workload="3D EA +-J L=8 (512 spins) x 64 instances, 32 replicas beta 0.2..3.0 "
+                                    "geometric, Metropolis, M=1, proposals every 100 sweeps from 256-entry "
+                                    "plain-PT banks on 30 slots; 10^4 sweeps per step",
+                           instances=NI, L=L, replicas=R, sweeps_per_step=S, bank=args.bank,
+                           tiling=dict(replicas_per_wg=G, replicas_per_thread=rpt)),
+               plain=plain, roofline=roof, cpu_baseline=cpu,
+               tiling_scan=[dict(G=g, rpt=r, attempts_per_ns=round(v, 1)) for v, g, r in scan])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

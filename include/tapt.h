@@ -159,6 +159,14 @@ typedef struct {
 int pt_batch_create(pt_ctx *const *ctxs, int32_t k, const pt_batch_opts *o, pt_batch **out);
 int pt_batch_sweep(pt_batch *b, uint64_t n_sweeps);
 int pt_batch_destroy(pt_batch *b);
+/* Launch the batch's work on ``stream`` (hipStream_t as void*, e.g. torch's
+ * current stream); NULL restores the batch's own stream. */
+int pt_batch_set_stream(pt_batch *b, void *stream);
+/* Total device time of the persistent chunk-kernel launches since the last
+ * call, measured with HIP events recorded around each launch on the batch's
+ * stream (launches replayed from a hipGraph are not timed), and their count.
+ * Resets both. */
+int pt_batch_kernel_time(pt_batch *b, double *ms, uint64_t *launches);
 
 const char *pt_last_error(void);
 

@@ -48,7 +48,7 @@ class _BatchOpts(C.Structure):
 EXPORTS = ["pt_create", "pt_destroy", "pt_propose", "pt_propose_device", "pt_sweep", "pt_energies",
            "pt_state", "pt_state_device", "pt_set_state", "pt_summary_get", "pt_counters",
            "pt_energy_device", "pt_set_stream", "pt_batch_create", "pt_batch_sweep", "pt_batch_destroy",
-           "pt_last_error"]
+           "pt_batch_set_stream", "pt_batch_kernel_time", "pt_last_error"]
 
 _lib = None
 
@@ -82,6 +82,8 @@ def lib():
     L.pt_batch_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(_BatchOpts), C.POINTER(vp)]
     L.pt_batch_sweep.argtypes = [vp, C.c_uint64]
     L.pt_batch_destroy.argtypes = [vp]
+    L.pt_batch_set_stream.argtypes = [vp, vp]
+    L.pt_batch_kernel_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
     L.pt_last_error.restype = C.c_char_p
     for name in EXPORTS:
         if name != "pt_last_error":
@@ -221,6 +223,15 @@ class Batch:
 
     def sweep(self, n):
         _check(lib().pt_batch_sweep(self.h, int(n)))
+
+    def set_stream(self, stream_ptr):
+        _check(lib().pt_batch_set_stream(self.h, C.c_void_p(stream_ptr)))
+
+    def kernel_time(self):
+        """(ms, launches) of the chunk-kernel launches since the last call."""
+        ms, n = C.c_double(), C.c_uint64()
+        _check(lib().pt_batch_kernel_time(self.h, C.byref(ms), C.byref(n)))
+        return float(ms.value), int(n.value)
 
     def close(self):
         if getattr(self, "h", None):

@@ -18,14 +18,14 @@
 #include <string>
 #include <vector>
 
-#include "../../include/tapt.h"
+#include "tapt.h"
 #include "tapt_dev.h"
 
 namespace tapt {
 bool lattice_supported(int L);
 int lattice_max_threads();
 int lattice_threads(int L, int G, int rpt);
-size_t chunk_lds_bytes(int kind, int n, int G, int stride);
+size_t chunk_lds_bytes(int kind, int n, int G, int stride, int tsw_entries);
 hipError_t launch_chunk(int kind, int L, int rpt, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t chunk_occupancy(int kind, int L, int rpt, int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_finish(const WorkItem *items, const int *first_item, int n_inst, uint32_t K, hipStream_t s);
@@ -125,6 +125,7 @@ struct pt_ctx {
     // problem (host copies)
     int32_t n = 0, L = 0, R = 0, kind = KIND_CSR, D = 0, ncolors = 0;
     std::vector<double> betas;
+    std::vector<int32_t> h_tswap_len; // host copy: swap-table length per pair
     pt_opts opts{};
     std::vector<int8_t> clamp;
     int64_t nfree = 0;
@@ -431,6 +432,7 @@ extern "C" int pt_create(const pt_graph *g, const double *betas, int32_t R, cons
     if (tprop.empty()) tprop.push_back(0);
     if (tswap.empty()) tswap.push_back(0);
 
+    c->h_tswap_len.assign(tswap_len.begin(), tswap_len.begin() + std::max(R - 1, 0));
     std::vector<int16_t> colsites = P.color_sites;
     hipError_t e = hipSuccess;
 #define UP(buf, vec) if (e == hipSuccess) e = upload(c->buf, vec, s)
@@ -726,11 +728,13 @@ extern "C" int pt_energy_device(pt_ctx *c, const int8_t *configs_dev, int32_t k,
 // batched path
 
 struct LaunchGroup {
-    int kind, L, rpt, block, grid = 0;
+    int kind, L, rpt, block, grid = 0, tsw_entries = 0;
     size_t lds;
     std::vector<pt_ctx *> ctxs;
     std::vector<int> Gs;              // per context: slots per workgroup (max)
-    DevBuf items, order, first_item, best, best_spins, xbuf, flags;
+    DevBuf items, order, first_item, best, best_spins, xbuf;
+    std::vector<size_t> x_off, x_bytes;   // per context: its exchange words
+    std::vector<uint32_t> x_epoch;        // epoch the exchange words were cleared for
     int n_items = 0;
 };
 
@@ -745,12 +749,18 @@ struct pt_batch {
     uint32_t graph_K = 0;
     int device = 0;
     int cus = 0;
+    hipStream_t own_stream = nullptr;
+    std::vector<hipEvent_t> ev_pool;  // start/stop pairs of timed launches
+    size_t ev_used = 0;
+    double kernel_ms = 0.0;
+    uint64_t kernel_launches = 0;
     ~pt_batch()
     {
+        for (auto e : ev_pool) (void)hipEventDestroy(e);
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         for (auto *g : groups) delete g;
-        if (stream) (void)hipStreamDestroy(stream);
+        if (own_stream) (void)hipStreamDestroy(own_stream);
     }
 };
 
@@ -759,12 +769,13 @@ static void choose_tiling(const pt_ctx *c, const pt_batch_opts &o, int &G, int &
 {
     const int R = c->R;
     rpt = o.replicas_per_thread > 0 ? o.replicas_per_thread : 0;
-    G = o.replicas_per_wg > 0 ? std::min(o.replicas_per_wg, R) : 0;
+    G = o.replicas_per_wg > 0 ? std::min(std::min(o.replicas_per_wg, R), 64) : 0;
     if (c->kind == KIND_CSR) {
         rpt = 1;
         if (!G) G = std::min(R, 32);
         return;
     }
+    // the cycle-end stages keep one slot per lane of a wavefront: G <= 64
     const int NC = c->n / 8;
     const int maxt = lattice_max_threads();
     if (!rpt) rpt = 2;
@@ -773,6 +784,7 @@ static void choose_tiling(const pt_ctx *c, const pt_batch_opts &o, int &G, int &
         int maxg = (maxt / NC) * rpt;
         G = std::min(R, std::max(rpt, maxg));
     }
+    G = std::min(G, 64);
     while (((G + rpt - 1) / rpt) * NC > maxt && G > 1) --G;
 }
 
@@ -783,14 +795,14 @@ static int build_group(pt_batch *b, LaunchGroup *g)
     std::vector<WorkItem> items;
     std::vector<int> first;
     int maxG = 1;
-    size_t nbest = 0, nbs = 0, nx = 0, nflags = 0;
-    struct Pend { int first, W, n, xstride; size_t bs_off, x_off, f_off; };
+    size_t nbest = 0, nbs = 0, nx = 0;
+    struct Pend { int first, W, n, xwords; size_t bs_off, x_off; };
     std::vector<Pend> pend;
     for (size_t k = 0; k < g->ctxs.size(); ++k) {
         pt_ctx *c = g->ctxs[k];
         int R = c->R, W = (R + g->Gs[k] - 1) / g->Gs[k];
-        int xstride = (int)(((size_t)c->n + 16 + 63) & ~(size_t)63);
-        pend.push_back({(int)items.size(), W, c->n, xstride, nbs, nx, nflags});
+        int xwords = (((c->n + 31) >> 5) + 1 + 7) & ~7;
+        pend.push_back({(int)items.size(), W, c->n, xwords, nbs, nx});
         first.push_back((int)items.size());
         int base = R / W, extra = R % W, s0 = 0;
         for (int w = 0; w < W; ++w) {
@@ -801,21 +813,19 @@ static int build_group(pt_batch *b, LaunchGroup *g)
             it.G = G;
             it.w = w;
             it.W = W;
-            it.xstride = xstride;
+            it.xwords = xwords;
             items.push_back(it);
             maxG = std::max(maxG, G);
             s0 += G;
             nbs += (size_t)((c->n + 15) & ~15);
         }
         nbest += W;
-        nx += (size_t)W * 4 * xstride;
-        nflags += (size_t)W * 2;
+        nx += (size_t)W * 4 * xwords * 8;
     }
     HIPCHK(g->best.alloc(nbest * sizeof(BestRec)));
     HIPCHK(g->best_spins.alloc(nbs));
     HIPCHK(g->xbuf.alloc(nx));
-    HIPCHK(g->flags.alloc(nflags * 8));
-    HIPCHK(hipMemsetAsync(g->flags.p, 0, nflags * 8, s));
+    HIPCHK(hipMemsetAsync(g->xbuf.p, 0, nx, s));
     size_t bi = 0;
     for (size_t k = 0; k < g->ctxs.size(); ++k) {
         const Pend &p = pend[k];
@@ -825,9 +835,11 @@ static int build_group(pt_batch *b, LaunchGroup *g)
             it.best = g->best.as<BestRec>() + bi++;
             it.best_spins = g->best_spins.as<int8_t>() + bs_off;
             bs_off += (size_t)((p.n + 15) & ~15);
-            it.xbuf = g->xbuf.as<int8_t>() + p.x_off;
-            it.flags = g->flags.as<unsigned long long>() + p.f_off;
+            it.xbuf = (unsigned long long *)(g->xbuf.as<int8_t>() + p.x_off);
         }
+        g->x_off.push_back(p.x_off);
+        g->x_bytes.push_back((size_t)p.W * 4 * p.xwords * 8);
+        g->x_epoch.push_back(g->ctxs[k]->hI.epoch);
     }
     g->n_items = (int)items.size();
     // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
@@ -854,7 +866,21 @@ static int build_group(pt_batch *b, LaunchGroup *g)
         n = nmax;
         g->block = 256;
     }
-    g->lds = chunk_lds_bytes(g->kind, n, maxG, stride_max);
+    // LDS swap-table rows: pairs s0-1 .. s0+G-1 of each workgroup
+    int tsw_max = 0;
+    for (size_t k = 0; k < g->ctxs.size(); ++k) {
+        const Pend &p = pend[k];
+        pt_ctx *c = g->ctxs[k];
+        for (int w = 0; w < p.W; ++w) {
+            const WorkItem &it = items[p.first + w];
+            int tot = 0;
+            for (int r = it.s0 - 1; r <= it.s0 + it.G - 1; ++r)
+                if (r >= 0 && r + 1 < c->R) tot += c->h_tswap_len[r];
+            tsw_max = std::max(tsw_max, tot);
+        }
+    }
+    g->tsw_entries = tsw_max;
+    g->lds = chunk_lds_bytes(g->kind, n, maxG, stride_max, tsw_max);
     if (g->lds > 160 * 1024) return fail(PT_EUNSUPPORTED, "tiling needs %zu B of LDS per workgroup", g->lds);
     int per_cu = 0;
     HIPCHK(chunk_occupancy(g->kind, g->L, g->rpt, g->block, g->lds, &per_cu));
@@ -891,8 +917,9 @@ extern "C" int pt_batch_create(pt_ctx *const *ctxs, int32_t k, const pt_batch_op
     b->cus = prop.multiProcessorCount;
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(PT_EDEVICE, "stream creation failed"));
-    if (b->err.alloc(4) != hipSuccess) return bail(fail(PT_ENOMEM, "error flag"));
-    if (hipMemset(b->err.p, 0, 4) != hipSuccess) return bail(fail(PT_EDEVICE, "memset"));
+    b->own_stream = b->stream;
+    if (b->err.alloc(32) != hipSuccess) return bail(fail(PT_ENOMEM, "error flag"));
+    if (hipMemset(b->err.p, 0, 32) != hipSuccess) return bail(fail(PT_EDEVICE, "memset"));
     // group contexts by kernel instantiation
     std::map<std::tuple<int, int, int>, LaunchGroup *> gm;
     for (pt_ctx *c : b->ctxs) {
@@ -918,9 +945,22 @@ extern "C" int pt_batch_create(pt_ctx *const *ctxs, int32_t k, const pt_batch_op
     return PT_OK;
 }
 
-static hipError_t enqueue_round(pt_batch *b, uint32_t K)
+static hipError_t enqueue_round(pt_batch *b, uint32_t K, bool timed)
 {
     for (auto *g : b->groups) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed) {
+            while (b->ev_pool.size() < b->ev_used + 2) {
+                hipEvent_t ev;
+                hipError_t ee = hipEventCreate(&ev);
+                if (ee != hipSuccess) return ee;
+                b->ev_pool.push_back(ev);
+            }
+            e0 = b->ev_pool[b->ev_used++];
+            e1 = b->ev_pool[b->ev_used++];
+            hipError_t ee = hipEventRecord(e0, b->stream);
+            if (ee != hipSuccess) return ee;
+        }
         ChunkArgs a{};
         a.items = g->items.as<WorkItem>();
         a.order = g->order.as<int32_t>();
@@ -928,8 +968,13 @@ static hipError_t enqueue_round(pt_batch *b, uint32_t K)
         a.K = K;
         a.err = b->err.as<int32_t>();
         a.spin_limit = 1u << 22;
+        a.tsw_entries = g->tsw_entries;
         hipError_t e = launch_chunk(g->kind, g->L, g->rpt, a, g->block, g->lds, b->stream);
         if (e != hipSuccess) return e;
+        if (timed) {
+            e = hipEventRecord(e1, b->stream);
+            if (e != hipSuccess) return e;
+        }
         e = launch_finish(g->items.as<WorkItem>(), g->first_item.as<int>(), (int)g->ctxs.size(), K, b->stream);
         if (e != hipSuccess) return e;
     }
@@ -949,6 +994,13 @@ extern "C" int pt_batch_sweep(pt_batch *b, uint64_t n_sweeps)
         c->hI.sweep_cap = c->t_host + n_sweeps;
         HIPCHK(hipMemcpyAsync(c->inst.p, &c->hI, sizeof(InstDev), hipMemcpyHostToDevice, b->stream));
     }
+    // a replaced state restarts the cycle count: clear that instance's exchange words
+    for (auto *g : b->groups)
+        for (size_t k = 0; k < g->ctxs.size(); ++k)
+            if (g->x_epoch[k] != g->ctxs[k]->hI.epoch) {
+                HIPCHK(hipMemsetAsync(g->xbuf.as<int8_t>() + g->x_off[k], 0, g->x_bytes[k], b->stream));
+                g->x_epoch[k] = g->ctxs[k]->hI.epoch;
+            }
     const uint32_t K = (uint32_t)b->opts.chunk_sweeps;
     uint64_t rounds = (n_sweeps + K - 1) / K;
     if (b->opts.use_graph) {
@@ -962,7 +1014,7 @@ extern "C" int pt_batch_sweep(pt_batch *b, uint64_t n_sweeps)
                 b->graph = nullptr;
             }
             HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-            hipError_t e = enqueue_round(b, K);
+            hipError_t e = enqueue_round(b, K, false);
             hipGraph_t gr = nullptr;
             hipError_t e2 = hipStreamEndCapture(b->stream, &gr);
             if (e != hipSuccess) return fail(PT_EDEVICE, "capture: %s", hipGetErrorString(e));
@@ -973,23 +1025,61 @@ extern "C" int pt_batch_sweep(pt_batch *b, uint64_t n_sweeps)
         }
         for (uint64_t k = 0; k < rounds; ++k) HIPCHK(hipGraphLaunch(b->gexec, b->stream));
     } else {
+        b->ev_used = 0;
         for (uint64_t k = 0; k < rounds; ++k) {
-            hipError_t e = enqueue_round(b, K);
+            hipError_t e = enqueue_round(b, K, true);
             if (e != hipSuccess) return fail(PT_EDEVICE, "chunk launch: %s", hipGetErrorString(e));
         }
     }
-    int err = 0;
-    HIPCHK(hipMemcpyAsync(&err, b->err.p, 4, hipMemcpyDeviceToHost, b->stream));
+    int err[8] = {0};
+    HIPCHK(hipMemcpyAsync(err, b->err.p, 32, hipMemcpyDeviceToHost, b->stream));
     hipError_t e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         for (pt_ctx *c : b->ctxs) c->broken = true;
         return fail(PT_EDEVICE, "batched sweep: %s", hipGetErrorString(e));
     }
-    for (pt_ctx *c : b->ctxs) c->t_host += n_sweeps;
-    if (err) {
-        for (pt_ctx *c : b->ctxs) c->broken = true;
-        return fail(PT_ETIMEOUT, "a cross-workgroup exchange timed out (workgroups not co-resident?)");
+    for (size_t k = 0; k + 1 < b->ev_used; k += 2) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, b->ev_pool[k], b->ev_pool[k + 1]));
+        b->kernel_ms += ms;
+        b->kernel_launches += 1;
     }
+    b->ev_used = 0;
+    for (pt_ctx *c : b->ctxs) c->t_host += n_sweeps;
+    if (err[0]) {
+        for (pt_ctx *c : b->ctxs) c->broken = true;
+        return fail(PT_ETIMEOUT,
+                    "cross-workgroup exchange timed out: item %d (workgroup %d of its instance) waiting on side %d "
+                    "at cycle %d saw word %08x:%08x, epoch %d",
+                    err[1], err[2], err[3], err[4], (unsigned)err[6], (unsigned)err[5], err[7]);
+    }
+    return PT_OK;
+}
+
+extern "C" int pt_batch_set_stream(pt_batch *b, void *stream)
+{
+    if (!b) return fail(PT_EINVAL, "null batch");
+    HIPCHK(hipSetDevice(b->device));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->stream = stream ? (hipStream_t)stream : b->own_stream;
+    if (b->gexec) {
+        HIPCHK(hipGraphExecDestroy(b->gexec));
+        b->gexec = nullptr;
+    }
+    if (b->graph) {
+        HIPCHK(hipGraphDestroy(b->graph));
+        b->graph = nullptr;
+    }
+    return PT_OK;
+}
+
+extern "C" int pt_batch_kernel_time(pt_batch *b, double *ms, uint64_t *launches)
+{
+    if (!b) return fail(PT_EINVAL, "null batch");
+    if (ms) *ms = b->kernel_ms;
+    if (launches) *launches = b->kernel_launches;
+    b->kernel_ms = 0.0;
+    b->kernel_launches = 0;
     return PT_OK;
 }
 

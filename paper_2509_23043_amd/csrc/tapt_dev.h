@@ -73,9 +73,8 @@ struct WorkItem {              // one workgroup of a persistent chunk launch
     int32_t w, W;              // index of this workgroup in the instance's ladder split
     BestRec *best;             // this workgroup's record for the chunk
     int8_t *best_spins;        // [n]
-    int8_t *xbuf;              // instance exchange area: [W][2 sides][2 buffers][xstride]
-    unsigned long long *flags; // instance flags [W][2 sides]
-    int32_t xstride;           // bytes per exchange buffer (n spins + energy, padded)
+    unsigned long long *xbuf;  // instance exchange area: [W][2 sides][2 buffers][xwords]
+    int32_t xwords;            // 64-bit words per buffer: ceil(n/32) spin words + energy, padded
     int32_t pad;
 };
 
@@ -84,8 +83,10 @@ struct ChunkArgs {
     const int32_t *order;      // blockIdx -> item index (XCD-aware placement)
     int32_t n_items;
     uint32_t K;                // sweeps per launch
-    int32_t *err;              // set to 1 when a cross-workgroup wait times out
+    int32_t *err;              // [8]: err[0] = 1 when a cross-workgroup wait timed out,
+                               // err[1..7] = item, w, side, cycle, seen tag lo/hi, epoch
     uint32_t spin_limit;       // polls before a wait gives up
+    int32_t tsw_entries;       // LDS swap-table capacity (entries) of every workgroup
 };
 
 } // namespace tapt

@@ -184,3 +184,30 @@ def test_invalid_inputs_rejected():
     if np.any((m["clamp"] != 0) & (wrong[0] != m["clamp"])):
         with pytest.raises(binding.TaptError):
             ctxm.propose(0, wrong)
+
+
+@pytest.mark.parametrize("G,rpt", [(4, 4), (4, 1), (2, 1)])
+def test_many_instances_split_ladders(G, rpt):
+    """64 EA L=8 instances with R=32 split into 32/G workgroups each, several
+    launches; sampled instances checked against the oracle."""
+    announce(f"64 instances, L=8 R=32, G={G} rpt={rpt}, 3 launches of 40 sweeps")
+    from tests.gpu_util import make_pair
+    betas = inputs.geometric_ladder(32)
+    pairs = []
+    for i in range(64):
+        g = inputs.ea_lattice(8, 2000 + i)
+        banks = {r: inputs.random_bank(512, 4, seed=7000 + 64 * i + r) for r in range(0, 30, 7)} if i % 8 == 0 else None
+        kw = dict(prop_start=20, prop_period=20) if banks else {}
+        ctx = binding.Context(g, betas, seed=3000 + i, **kw)
+        if banks:
+            for r, b in banks.items():
+                ctx.propose(r, b)
+        pairs.append((ctx, g, banks, kw))
+    bt = binding.Batch([p[0] for p in pairs], replicas_per_wg=G, replicas_per_thread=rpt, chunk_sweeps=40)
+    bt.sweep(120)
+    import oracle
+    for i in (0, 8, 37, 63):
+        ctx, g, banks, kw = pairs[i]
+        ref = oracle.Run(g, betas, seed=3000 + i, banks=banks, **kw)
+        ref.run(120)
+        compare(ctx, ref)
