@@ -168,6 +168,91 @@ int pt_batch_set_stream(pt_batch *b, void *stream);
  * Resets both. */
 int pt_batch_kernel_time(pt_batch *b, double *ms, uint64_t *launches);
 
+/* ---- serving: continuous batching of solve requests ----
+ *
+ * A server owns a worker thread and a stream. Callers register problems
+ * (a context created with pt_create, with its proposal banks installed by
+ * pt_propose: the paper reuses one bank across runs, Supp. S6) and submit
+ * solve requests against them from any thread. A request is a fresh set of
+ * replicas of a registered problem with its own seed, energy target and sweep
+ * cap. It shares the problem's couplings, tables and banks in device memory
+ * and owns only its replica state, which stays resident until it finishes.
+ *
+ * The worker runs rounds. Each round is one persistent launch of
+ * chunk_sweeps sweeps over every admitted request (they overlap on the
+ * device). Between rounds it retires the requests that reached their target or
+ * their cap and admits waiting ones, first come first served, while their
+ * state fits the device-memory budget and every workgroup of the next launch
+ * can be co-resident.
+ *
+ * Results do not depend on co-tenants or arrival times. A request admitted at
+ * sweep 0 stops at the first multiple of chunk_sweeps at or after its first
+ * hit, or at its cap. All its random numbers are keyed by its seed (the
+ * contract of pt_create). So first_hit, the best energy, the best
+ * configuration and the sweep count equal those of the same context run
+ * alone. */
+typedef struct {
+    uint64_t mem_budget;         /* device bytes for request state (0 = 1 GiB) */
+    int32_t chunk_sweeps;        /* sweeps per round (0 = 500) */
+    int32_t max_active;          /* cap on concurrent requests (0 = none) */
+    int32_t replicas_per_wg;     /* tiling as in pt_batch_opts (0 = choose) */
+    int32_t replicas_per_thread;
+} pt_serve_opts;
+
+typedef struct {
+    int32_t problem;             /* id from pt_serve_register */
+    int32_t has_target;
+    int32_t target;              /* done when min_r E_r <= target */
+    int32_t pad;
+    uint64_t seed;               /* Philox key of this request's chain */
+    uint64_t sweep_cap;          /* done after this many sweeps in any case (>= 1) */
+    int8_t *best_out;            /* host [n] or NULL: receives the best configuration
+                                    before the result is published; caller-owned,
+                                    must stay valid until the result is polled */
+    uint64_t user_tag;
+} pt_request;
+
+typedef struct {
+    uint64_t id;                 /* from pt_serve_submit */
+    uint64_t user_tag;
+    int32_t status;              /* PT_OK, or the PT_E* code that rejected it */
+    int32_t hit;                 /* 1 if the target was reached */
+    int64_t first_hit;           /* sweep of the first hit, or -1 */
+    int32_t best_energy;
+    int32_t best_slot;
+    int64_t best_t;
+    uint64_t sweeps;             /* sweeps run */
+    double t_submit, t_admit, t_done;  /* seconds on the server clock (pt_serve_clock) */
+} pt_result;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, rejected;
+    uint64_t rounds;
+    double busy_s;               /* wall time of the rounds (launch to results) */
+    double attempts;             /* spin-flip attempts run for requests */
+    int32_t active, waiting, peak_active;
+    int32_t pad;
+    uint64_t mem_used, mem_peak;
+} pt_serve_stats;
+
+int pt_serve_start(const pt_serve_opts *o, pt_server **out);
+/* Register a problem: the server keeps a pointer to ctx (it must outlive the
+ * server and not be used by the caller while the server runs). Its banks,
+ * ladder and options (rule, sweeps_per_cycle, proposal schedule) apply to
+ * every request on it. */
+int pt_serve_register(pt_server *s, pt_ctx *ctx, int32_t *problem);
+/* Queue a request (thread-safe; copies *rq). */
+int pt_serve_submit(pt_server *s, const pt_request *rq, uint64_t *id);
+/* Move up to max finished results into out; wait up to wait_ms for the
+ * first one (0 = do not wait). *n_out receives the count. */
+int pt_serve_poll(pt_server *s, pt_result *out, int32_t max, int32_t wait_ms, int32_t *n_out);
+int pt_serve_stats_get(pt_server *s, pt_serve_stats *st);
+/* Seconds since the server started (the clock of pt_result). */
+double pt_serve_clock(pt_server *s);
+/* Finish every queued and running request, then stop the worker and free
+ * the server. Results not polled are dropped. */
+int pt_serve_stop(pt_server *s);
+
 const char *pt_last_error(void);
 
 #ifdef __cplusplus

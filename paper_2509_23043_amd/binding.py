@@ -45,10 +45,38 @@ class _BatchOpts(C.Structure):
                 ("chunk_sweeps", C.c_int32), ("use_graph", C.c_int32)]
 
 
+class _ServeOpts(C.Structure):
+    _fields_ = [("mem_budget", C.c_uint64), ("chunk_sweeps", C.c_int32), ("max_active", C.c_int32),
+                ("replicas_per_wg", C.c_int32), ("replicas_per_thread", C.c_int32)]
+
+
+class _Request(C.Structure):
+    _fields_ = [("problem", C.c_int32), ("has_target", C.c_int32), ("target", C.c_int32), ("pad", C.c_int32),
+                ("seed", C.c_uint64), ("sweep_cap", C.c_uint64), ("best_out", C.c_void_p),
+                ("user_tag", C.c_uint64)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("user_tag", C.c_uint64), ("status", C.c_int32), ("hit", C.c_int32),
+                ("first_hit", C.c_int64), ("best_energy", C.c_int32), ("best_slot", C.c_int32),
+                ("best_t", C.c_int64), ("sweeps", C.c_uint64), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+class _ServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("completed", C.c_uint64),
+                ("rejected", C.c_uint64), ("rounds", C.c_uint64), ("busy_s", C.c_double),
+                ("attempts", C.c_double), ("active", C.c_int32), ("waiting", C.c_int32),
+                ("peak_active", C.c_int32), ("pad", C.c_int32), ("mem_used", C.c_uint64),
+                ("mem_peak", C.c_uint64)]
+
+
 EXPORTS = ["pt_create", "pt_destroy", "pt_propose", "pt_propose_device", "pt_sweep", "pt_energies",
            "pt_state", "pt_state_device", "pt_set_state", "pt_summary_get", "pt_counters",
            "pt_energy_device", "pt_set_stream", "pt_batch_create", "pt_batch_sweep", "pt_batch_destroy",
-           "pt_batch_set_stream", "pt_batch_kernel_time", "pt_last_error"]
+           "pt_batch_set_stream", "pt_batch_kernel_time", "pt_serve_start", "pt_serve_register",
+           "pt_serve_submit", "pt_serve_poll", "pt_serve_stats_get", "pt_serve_clock", "pt_serve_stop",
+           "pt_last_error"]
 
 _lib = None
 
@@ -84,10 +112,18 @@ def lib():
     L.pt_batch_destroy.argtypes = [vp]
     L.pt_batch_set_stream.argtypes = [vp, vp]
     L.pt_batch_kernel_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
+    L.pt_serve_start.argtypes = [C.POINTER(_ServeOpts), C.POINTER(vp)]
+    L.pt_serve_register.argtypes = [vp, vp, C.POINTER(C.c_int32)]
+    L.pt_serve_submit.argtypes = [vp, C.POINTER(_Request), C.POINTER(C.c_uint64)]
+    L.pt_serve_poll.argtypes = [vp, C.POINTER(_Result), C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+    L.pt_serve_stats_get.argtypes = [vp, C.POINTER(_ServeStats)]
+    L.pt_serve_clock.argtypes = [vp]
+    L.pt_serve_stop.argtypes = [vp]
     L.pt_last_error.restype = C.c_char_p
     for name in EXPORTS:
-        if name != "pt_last_error":
+        if name not in ("pt_last_error", "pt_serve_clock"):
             getattr(L, name).restype = C.c_int
+    L.pt_serve_clock.restype = C.c_double
     _lib = L
     return L
 
@@ -241,5 +277,77 @@ class Batch:
     def __del__(self):
         try:
             self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching solve server (pt_serve_*). Problems are Contexts
+    with their banks installed; requests are (problem, seed, target, cap)."""
+
+    def __init__(self, mem_budget=0, chunk_sweeps=0, max_active=0, replicas_per_wg=0, replicas_per_thread=0):
+        o = _ServeOpts(int(mem_budget), int(chunk_sweeps), int(max_active), int(replicas_per_wg),
+                       int(replicas_per_thread))
+        h = C.c_void_p()
+        _check(lib().pt_serve_start(C.byref(o), C.byref(h)))
+        self.h = h
+        self.problems = []
+        self._best = {}
+
+    def register(self, ctx):
+        """Register a Context as a problem; returns its id. The context must
+        stay alive and untouched until the server stops."""
+        pid = C.c_int32()
+        _check(lib().pt_serve_register(self.h, ctx.h, C.byref(pid)))
+        self.problems.append(ctx)
+        return int(pid.value)
+
+    def submit(self, problem, seed, sweep_cap, target=None, want_best=True, user_tag=0):
+        rq = _Request()
+        rq.problem = int(problem)
+        rq.has_target = 0 if target is None else 1
+        rq.target = 0 if target is None else int(target)
+        rq.seed = int(seed)
+        rq.sweep_cap = int(sweep_cap)
+        rq.user_tag = int(user_tag)
+        buf = None
+        if want_best:
+            buf = np.zeros(self.problems[problem].n, np.int8)
+            rq.best_out = buf.ctypes.data
+        rid = C.c_uint64()
+        _check(lib().pt_serve_submit(self.h, C.byref(rq), C.byref(rid)))
+        if buf is not None:
+            self._best[int(rid.value)] = buf
+        return int(rid.value)
+
+    def poll(self, max_results=256, wait_ms=0):
+        """Finished requests as dicts (best_spins included when requested)."""
+        arr = (_Result * max_results)()
+        n = C.c_int32()
+        _check(lib().pt_serve_poll(self.h, arr, int(max_results), int(wait_ms), C.byref(n)))
+        out = []
+        for k in range(n.value):
+            r = arr[k]
+            d = {f: getattr(r, f) for f, _ in _Result._fields_}
+            d["best_spins"] = self._best.pop(int(r.id), None)
+            out.append(d)
+        return out
+
+    def stats(self):
+        st = _ServeStats()
+        _check(lib().pt_serve_stats_get(self.h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in _ServeStats._fields_ if f != "pad"}
+
+    def clock(self):
+        return float(lib().pt_serve_clock(self.h))
+
+    def stop(self):
+        if getattr(self, "h", None):
+            _check(lib().pt_serve_stop(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.stop()
         except Exception:
             pass

@@ -9,12 +9,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -28,7 +34,12 @@ int lattice_threads(int L, int G, int rpt);
 size_t chunk_lds_bytes(int kind, int n, int G, int stride, int tsw_entries);
 hipError_t launch_chunk(int kind, int L, int rpt, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t chunk_occupancy(int kind, int L, int rpt, int block, size_t lds, int *blocks_per_cu);
-hipError_t launch_finish(const WorkItem *items, const int *first_item, int n_inst, uint32_t K, hipStream_t s);
+hipError_t launch_finish(const WorkItem *items, const int *first_item, int n_inst, uint32_t K, InstStatus *status,
+                         hipStream_t s);
+int mixed_max_threads();
+int mixed_variant_of(int kind, int L, int rpt);
+hipError_t launch_chunk_mixed(const ChunkArgs &a, int block, size_t lds, hipStream_t s);
+hipError_t chunk_occupancy_mixed(int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_plain(int kind, int L, const InstDev *dI, int R, int n, int stride, uint32_t t, hipStream_t s);
 hipError_t launch_init(const InstDev *dI, int R, int n, hipStream_t s);
 hipError_t launch_energy(const InstDev *dI, const int8_t *cfg, int k, int32_t *out, hipStream_t s);
@@ -100,18 +111,36 @@ static void tail_table(double a, std::vector<uint32_t> &out)
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool owned = true;                // false: a view of memory owned elsewhere
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), owned(o.owned)
+    {
+        o.p = nullptr;
+        o.bytes = 0;
+        o.owned = true;
+    }
     ~DevBuf() { release(); }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p && owned) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        owned = true;
     }
     hipError_t alloc(size_t b)
     {
         release();
         bytes = b;
         return hipMalloc(&p, b ? b : 16);
+    }
+    void view(void *q, size_t b)
+    {
+        release();
+        p = q;
+        bytes = b;
+        owned = false;
     }
     template <class T> T *as() const { return (T *)p; }
 };
@@ -147,6 +176,7 @@ struct pt_ctx {
     bool broken = false;
     uint64_t t_host = 0;
     int device = 0;
+    DevBuf arena;                     // a served request's state, carved into the views above
 };
 
 static int push_inst(pt_ctx *c)
@@ -729,10 +759,12 @@ extern "C" int pt_energy_device(pt_ctx *c, const int8_t *configs_dev, int32_t k,
 
 struct LaunchGroup {
     int kind, L, rpt, block, grid = 0, tsw_entries = 0;
+    bool mixed = false;               // one launch of chunk_kernel_mixed for several sweepers
     size_t lds;
     std::vector<pt_ctx *> ctxs;
     std::vector<int> Gs;              // per context: slots per workgroup (max)
-    DevBuf items, order, first_item, best, best_spins, xbuf;
+    std::vector<int> rpts;            // per context: slots per thread
+    DevBuf items, order, first_item, best, best_spins, xbuf, status;
     std::vector<size_t> x_off, x_bytes;   // per context: its exchange words
     std::vector<uint32_t> x_epoch;        // epoch the exchange words were cleared for
     int n_items = 0;
@@ -764,8 +796,9 @@ struct pt_batch {
     }
 };
 
-// Choose (slots per workgroup, slots per thread) for a context.
-static void choose_tiling(const pt_ctx *c, const pt_batch_opts &o, int &G, int &rpt)
+// Choose (slots per workgroup, slots per thread) for a context. A mixed
+// launch takes at most two slots per thread (its block limit is the same).
+static void choose_tiling(const pt_ctx *c, const pt_batch_opts &o, bool mixed, int &G, int &rpt)
 {
     const int R = c->R;
     rpt = o.replicas_per_thread > 0 ? o.replicas_per_thread : 0;
@@ -775,9 +808,10 @@ static void choose_tiling(const pt_ctx *c, const pt_batch_opts &o, int &G, int &
         if (!G) G = std::min(R, 32);
         return;
     }
+    if (mixed && rpt > 2) rpt = 2;
     // the cycle-end stages keep one slot per lane of a wavefront: G <= 64
     const int NC = c->n / 8;
-    const int maxt = lattice_max_threads();
+    const int maxt = mixed ? mixed_max_threads() : lattice_max_threads();
     if (!rpt) rpt = 2;
     if (!G) {
         // whole ladder in one workgroup when it fits the block limit, else split
@@ -788,22 +822,27 @@ static void choose_tiling(const pt_ctx *c, const pt_batch_opts &o, int &G, int &
     while (((G + rpt - 1) / rpt) * NC > maxt && G > 1) --G;
 }
 
-static int build_group(pt_batch *b, LaunchGroup *g)
-{
-    hipStream_t s = b->stream;
-    // items: per context, W workgroups with near-equal slot counts
+// Host-side layout of one launch: the work items (one workgroup each, with
+// near-equal slot counts per instance), the XCD-aware block order, the block
+// size, the LDS carve-up, and whether every workgroup can be co-resident.
+struct GroupPlan {
     std::vector<WorkItem> items;
     std::vector<int> first;
-    int maxG = 1;
-    size_t nbest = 0, nbs = 0, nx = 0;
-    struct Pend { int first, W, n, xwords; size_t bs_off, x_off; };
-    std::vector<Pend> pend;
+    std::vector<int32_t> order;
+    struct Ctx { int first, W, n, xwords, gmax; size_t bs_off, x_off; };
+    std::vector<Ctx> ctx;
+    size_t nbest = 0, nbs = 0, nx = 0, lds = 0;
+    int block = 64, grid = 0, tsw_max = 0, per_cu = 0;
+};
+
+static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
+{
     for (size_t k = 0; k < g->ctxs.size(); ++k) {
         pt_ctx *c = g->ctxs[k];
         int R = c->R, W = (R + g->Gs[k] - 1) / g->Gs[k];
         int xwords = (((c->n + 31) >> 5) + 1 + 7) & ~7;
-        pend.push_back({(int)items.size(), W, c->n, xwords, nbs, nx});
-        first.push_back((int)items.size());
+        P.ctx.push_back({(int)P.items.size(), W, c->n, xwords, (R + W - 1) / W, P.nbs, P.nx});
+        P.first.push_back((int)P.items.size());
         int base = R / W, extra = R % W, s0 = 0;
         for (int w = 0; w < W; ++w) {
             int G = base + (w < extra ? 1 : 0);
@@ -814,24 +853,71 @@ static int build_group(pt_batch *b, LaunchGroup *g)
             it.w = w;
             it.W = W;
             it.xwords = xwords;
-            items.push_back(it);
-            maxG = std::max(maxG, G);
+            it.variant = mixed_variant_of(c->kind, c->L, g->rpts[k]);
+            P.items.push_back(it);
             s0 += G;
-            nbs += (size_t)((c->n + 15) & ~15);
+            P.nbs += (size_t)((c->n + 15) & ~15);
         }
-        nbest += W;
-        nx += (size_t)W * 4 * xwords * 8;
+        P.nbest += W;
+        P.nx += (size_t)W * 4 * xwords * 8;
+        // LDS swap-table rows: pairs s0-1 .. s0+G-1 of each workgroup
+        for (int w = 0; w < W; ++w) {
+            const WorkItem &it = P.items[P.ctx[k].first + w];
+            int tot = 0;
+            for (int r = it.s0 - 1; r <= it.s0 + it.G - 1; ++r)
+                if (r >= 0 && r + 1 < c->R) tot += c->h_tswap_len[r];
+            P.tsw_max = std::max(P.tsw_max, tot);
+        }
+        // a block covers the largest item's threads
+        int need = c->kind == KIND_LATTICE ? lattice_threads(c->L, P.ctx[k].gmax, g->rpts[k]) : 256;
+        P.block = std::max(P.block, (need + 63) & ~63);
     }
-    HIPCHK(g->best.alloc(nbest * sizeof(BestRec)));
-    HIPCHK(g->best_spins.alloc(nbs));
-    HIPCHK(g->xbuf.alloc(nx));
-    HIPCHK(hipMemsetAsync(g->xbuf.p, 0, nx, s));
+    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
+    // so blockIdx b runs on XCD b % 8. Each XCD gets a contiguous run of the
+    // instance-ordered items (so the workgroups of one instance share an L2);
+    // blocks past the end of a run are padding that exits at once.
+    const int nx8 = 8, n_items = (int)P.items.size();
+    int per = (n_items + nx8 - 1) / nx8;
+    P.order.assign((size_t)per * nx8, -1);
+    for (int idx = 0; idx < n_items; ++idx) P.order[(size_t)(idx % per) * nx8 + idx / per] = idx;
+    P.grid = per * nx8;
+    // LDS: the largest carve-up over the items (every item lays out its own
+    // region with the common swap-table capacity)
+    for (size_t k = 0; k < g->ctxs.size(); ++k) {
+        pt_ctx *c = g->ctxs[k];
+        P.lds = std::max(P.lds, chunk_lds_bytes(c->kind, c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max));
+    }
+    if (P.lds > 160 * 1024) return fail(PT_EUNSUPPORTED, "tiling needs %zu B of LDS per workgroup", P.lds);
+    if (g->mixed)
+        HIPCHK(chunk_occupancy_mixed(P.block, P.lds, &P.per_cu));
+    else
+        HIPCHK(chunk_occupancy(g->kind, g->L, g->rpt, P.block, P.lds, &P.per_cu));
+    if (P.per_cu < 1) return fail(PT_EUNSUPPORTED, "kernel cannot run with block %d, LDS %zu", P.block, P.lds);
+    // the cross-workgroup waits need every workgroup of the launch resident
+    // (counted with the padding blocks, so that every XCD's share fits its CUs)
+    if ((long long)P.per_cu * b->cus < (long long)P.grid)
+        return fail(PT_EUNSUPPORTED, "%d workgroups exceed the %d that can be co-resident; use fewer contexts per batch",
+                    P.grid, P.per_cu * b->cus);
+    return PT_OK;
+}
+
+static int build_group(pt_batch *b, LaunchGroup *g)
+{
+    hipStream_t s = b->stream;
+    GroupPlan P;
+    int rc = plan_group(b, g, P);
+    if (rc) return rc;
+    HIPCHK(g->status.alloc(g->ctxs.size() * sizeof(InstStatus)));
+    HIPCHK(g->best.alloc(P.nbest * sizeof(BestRec)));
+    HIPCHK(g->best_spins.alloc(P.nbs));
+    HIPCHK(g->xbuf.alloc(P.nx));
+    HIPCHK(hipMemsetAsync(g->xbuf.p, 0, P.nx, s));
     size_t bi = 0;
     for (size_t k = 0; k < g->ctxs.size(); ++k) {
-        const Pend &p = pend[k];
+        const GroupPlan::Ctx &p = P.ctx[k];
         size_t bs_off = p.bs_off;
         for (int w = 0; w < p.W; ++w) {
-            WorkItem &it = items[p.first + w];
+            WorkItem &it = P.items[p.first + w];
             it.best = g->best.as<BestRec>() + bi++;
             it.best_spins = g->best_spins.as<int8_t>() + bs_off;
             bs_off += (size_t)((p.n + 15) & ~15);
@@ -841,54 +927,93 @@ static int build_group(pt_batch *b, LaunchGroup *g)
         g->x_bytes.push_back((size_t)p.W * 4 * p.xwords * 8);
         g->x_epoch.push_back(g->ctxs[k]->hI.epoch);
     }
-    g->n_items = (int)items.size();
-    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
-    // so blockIdx b runs on XCD b % 8. Each XCD gets a contiguous run of the
-    // instance-ordered items (so the workgroups of one instance share an L2);
-    // blocks past the end of a run are padding that exits at once.
-    const int nx8 = 8;
-    int per = (g->n_items + nx8 - 1) / nx8;
-    std::vector<int32_t> order((size_t)per * nx8, -1);
-    for (int idx = 0; idx < g->n_items; ++idx) order[(size_t)(idx % per) * nx8 + idx / per] = idx;
-    g->grid = per * nx8;
-    HIPCHK(upload(g->items, items, s));
-    HIPCHK(upload(g->order, order, s));
-    HIPCHK(upload(g->first_item, first, s));
-    // launch shape
-    int stride_max = 1;
-    for (auto *c : g->ctxs) stride_max = std::max(stride_max, 2 * c->D + 1);
-    int n = g->ctxs[0]->n;
-    if (g->kind == KIND_LATTICE) {
-        g->block = (lattice_threads(g->L, maxG, g->rpt) + 63) & ~63;
-    } else {
-        int nmax = 0;
-        for (auto *c : g->ctxs) nmax = std::max(nmax, c->n);
-        n = nmax;
-        g->block = 256;
-    }
-    // LDS swap-table rows: pairs s0-1 .. s0+G-1 of each workgroup
-    int tsw_max = 0;
-    for (size_t k = 0; k < g->ctxs.size(); ++k) {
-        const Pend &p = pend[k];
-        pt_ctx *c = g->ctxs[k];
-        for (int w = 0; w < p.W; ++w) {
-            const WorkItem &it = items[p.first + w];
-            int tot = 0;
-            for (int r = it.s0 - 1; r <= it.s0 + it.G - 1; ++r)
-                if (r >= 0 && r + 1 < c->R) tot += c->h_tswap_len[r];
-            tsw_max = std::max(tsw_max, tot);
-        }
-    }
-    g->tsw_entries = tsw_max;
-    g->lds = chunk_lds_bytes(g->kind, n, maxG, stride_max, tsw_max);
-    if (g->lds > 160 * 1024) return fail(PT_EUNSUPPORTED, "tiling needs %zu B of LDS per workgroup", g->lds);
-    int per_cu = 0;
-    HIPCHK(chunk_occupancy(g->kind, g->L, g->rpt, g->block, g->lds, &per_cu));
-    if (per_cu < 1) return fail(PT_EUNSUPPORTED, "kernel cannot run with block %d, LDS %zu", g->block, g->lds);
-    if ((long long)per_cu * b->cus < g->grid)
-        return fail(PT_EUNSUPPORTED, "%d workgroups exceed the %d that can be co-resident; use fewer contexts per batch",
-                    g->grid, per_cu * b->cus);
+    g->n_items = (int)P.items.size();
+    g->grid = P.grid;
+    g->block = P.block;
+    g->lds = P.lds;
+    g->tsw_entries = P.tsw_max;
+    HIPCHK(upload(g->items, P.items, s));
+    HIPCHK(upload(g->order, P.order, s));
+    HIPCHK(upload(g->first_item, P.first, s));
     HIPCHK(hipStreamSynchronize(s));
+    return PT_OK;
+}
+
+static void clear_groups(pt_batch *b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    for (auto *g : b->groups) delete g;
+    b->groups.clear();
+    b->ctxs.clear();
+}
+
+// The launch group for a set of contexts (host fields only). Contexts that
+// share one sweeper instantiation run in the specialised kernel; a set that
+// needs several sweepers runs as a single launch of the mixed kernel.
+static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx *> &ctxs)
+{
+    std::map<std::tuple<int, int, int>, int> keys;
+    for (pt_ctx *c : ctxs) {
+        int G, rpt;
+        choose_tiling(c, o, false, G, rpt);
+        keys[std::make_tuple(c->kind, c->kind == KIND_LATTICE ? c->L : 0, rpt)] += 1;
+    }
+    LaunchGroup *g = new LaunchGroup();
+    g->mixed = keys.size() > 1;
+    g->kind = ctxs[0]->kind;
+    g->L = g->kind == KIND_LATTICE ? ctxs[0]->L : 0;
+    for (pt_ctx *c : ctxs) {
+        int G, rpt;
+        choose_tiling(c, o, g->mixed, G, rpt);
+        g->rpt = rpt;
+        g->ctxs.push_back(c);
+        g->Gs.push_back(G);
+        g->rpts.push_back(rpt);
+    }
+    return g;
+}
+
+// (Re)build the launch group of a batch for the contexts ctxs[0..k).
+static int batch_set_contexts(pt_batch *b, pt_ctx *const *ctxs, int32_t k)
+{
+    clear_groups(b);
+    for (int i = 0; i < k; ++i) {
+        if (!ctxs[i] || ctxs[i]->broken) return fail(PT_EINVAL, "context %d missing or unusable", i);
+        if (ctxs[i]->device != b->device) return fail(PT_EINVAL, "context %d lives on another device", i);
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(PT_EINVAL, "context %d appears twice", i);
+        b->ctxs.push_back(ctxs[i]);
+    }
+    LaunchGroup *g = make_group(b->opts, b->ctxs);
+    b->groups.push_back(g);
+    return build_group(b, g);
+}
+
+// PT_OK if the contexts could run in one launch of this batch (no allocation).
+static int batch_fits(const pt_batch *b, const std::vector<pt_ctx *> &ctxs)
+{
+    LaunchGroup *g = make_group(b->opts, ctxs);
+    GroupPlan P;
+    int rc = plan_group(b, g, P);
+    delete g;
+    return rc;
+}
+
+static int batch_init(pt_batch *b, int device)
+{
+    b->device = device;
+    if (hipSetDevice(b->device) != hipSuccess) return fail(PT_EDEVICE, "hipSetDevice");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) return fail(PT_EDEVICE, "device properties");
+    b->cus = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(PT_EDEVICE, "stream creation failed");
+    b->own_stream = b->stream;
+    if (b->err.alloc(32) != hipSuccess) return fail(PT_ENOMEM, "error flag");
+    if (hipMemset(b->err.p, 0, 32) != hipSuccess) return fail(PT_EDEVICE, "memset");
     return PT_OK;
 }
 
@@ -897,49 +1022,15 @@ extern "C" int pt_batch_create(pt_ctx *const *ctxs, int32_t k, const pt_batch_op
     if (!out) return fail(PT_EINVAL, "null output pointer");
     *out = nullptr;
     if (!ctxs || k < 1) return fail(PT_EINVAL, "need at least one context");
+    if (!ctxs[0]) return fail(PT_EINVAL, "context 0 missing");
     pt_batch *b = new pt_batch();
     if (o) b->opts = *o;
     if (b->opts.chunk_sweeps <= 0) b->opts.chunk_sweeps = 1000;
-    auto bail = [&](int code) {
+    int rc = batch_init(b, ctxs[0]->device);
+    if (!rc) rc = batch_set_contexts(b, ctxs, k);
+    if (rc) {
         delete b;
-        return code;
-    };
-    for (int i = 0; i < k; ++i) {
-        if (!ctxs[i] || ctxs[i]->broken) return bail(fail(PT_EINVAL, "context %d missing or unusable", i));
-        for (int j = 0; j < i; ++j)
-            if (ctxs[j] == ctxs[i]) return bail(fail(PT_EINVAL, "context %d appears twice", i));
-        b->ctxs.push_back(ctxs[i]);
-    }
-    b->device = ctxs[0]->device;
-    if (hipSetDevice(b->device) != hipSuccess) return bail(fail(PT_EDEVICE, "hipSetDevice"));
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) return bail(fail(PT_EDEVICE, "device properties"));
-    b->cus = prop.multiProcessorCount;
-    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
-        return bail(fail(PT_EDEVICE, "stream creation failed"));
-    b->own_stream = b->stream;
-    if (b->err.alloc(32) != hipSuccess) return bail(fail(PT_ENOMEM, "error flag"));
-    if (hipMemset(b->err.p, 0, 32) != hipSuccess) return bail(fail(PT_EDEVICE, "memset"));
-    // group contexts by kernel instantiation
-    std::map<std::tuple<int, int, int>, LaunchGroup *> gm;
-    for (pt_ctx *c : b->ctxs) {
-        int G, rpt;
-        choose_tiling(c, b->opts, G, rpt);
-        auto key = std::make_tuple(c->kind, c->kind == KIND_LATTICE ? c->L : 0, rpt);
-        LaunchGroup *&g = gm[key];
-        if (!g) {
-            g = new LaunchGroup();
-            g->kind = c->kind;
-            g->L = c->kind == KIND_LATTICE ? c->L : 0;
-            g->rpt = rpt;
-            b->groups.push_back(g);
-        }
-        g->ctxs.push_back(c);
-        g->Gs.push_back(G);
-    }
-    for (auto *g : b->groups) {
-        int rc = build_group(b, g);
-        if (rc) return bail(rc);
+        return rc;
     }
     *out = b;
     return PT_OK;
@@ -969,13 +1060,15 @@ static hipError_t enqueue_round(pt_batch *b, uint32_t K, bool timed)
         a.err = b->err.as<int32_t>();
         a.spin_limit = 1u << 22;
         a.tsw_entries = g->tsw_entries;
-        hipError_t e = launch_chunk(g->kind, g->L, g->rpt, a, g->block, g->lds, b->stream);
+        hipError_t e = g->mixed ? launch_chunk_mixed(a, g->block, g->lds, b->stream)
+                                : launch_chunk(g->kind, g->L, g->rpt, a, g->block, g->lds, b->stream);
         if (e != hipSuccess) return e;
         if (timed) {
             e = hipEventRecord(e1, b->stream);
             if (e != hipSuccess) return e;
         }
-        e = launch_finish(g->items.as<WorkItem>(), g->first_item.as<int>(), (int)g->ctxs.size(), K, b->stream);
+        e = launch_finish(g->items.as<WorkItem>(), g->first_item.as<int>(), (int)g->ctxs.size(), K,
+                          g->status.as<InstStatus>(), b->stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1089,5 +1182,449 @@ extern "C" int pt_batch_destroy(pt_batch *b)
     (void)hipSetDevice(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     delete b;
+    return PT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// serving: continuous batching of solve requests
+
+namespace {
+
+// One allocation holds a served request's state; the parts are 256-byte aligned.
+struct ArenaLayout {
+    size_t spins, E, t, cursor, bank_ptrs, bankE_ptrs, bank_n, swap_att, swap_acc, prop_att, prop_acc, flips, best,
+        best_spins, inst, total;
+};
+
+ArenaLayout arena_layout(int R, int n)
+{
+    ArenaLayout A;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = (o + bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    const size_t P = (size_t)std::max(R - 1, 1);
+    A.spins = take((size_t)R * n);
+    A.E = take((size_t)R * 4);
+    A.t = take(8);
+    A.cursor = take((size_t)R * 4);
+    A.bank_ptrs = take((size_t)R * 8);
+    A.bankE_ptrs = take((size_t)R * 8);
+    A.bank_n = take((size_t)R * 4);
+    A.swap_att = take(P * 8);
+    A.swap_acc = take(P * 8);
+    A.prop_att = take((size_t)R * 8);
+    A.prop_acc = take((size_t)R * 8);
+    A.flips = take((size_t)R * 8);
+    A.best = take(sizeof(BestRec));
+    A.best_spins = take((size_t)n);
+    A.inst = take(sizeof(InstDev));
+    A.total = o;
+    return A;
+}
+
+// A context that reads the problem, tables and banks of `tm` (device data the
+// template owns) and owns only its replica state, on stream s.
+int clone_ctx(const pt_ctx *tm, uint64_t seed, int has_target, int32_t target, uint64_t cap, hipStream_t s,
+              pt_ctx **out)
+{
+    *out = nullptr;
+    pt_ctx *c = new pt_ctx();
+    c->n = tm->n;
+    c->L = tm->L;
+    c->R = tm->R;
+    c->kind = tm->kind;
+    c->D = tm->D;
+    c->ncolors = tm->ncolors;
+    c->betas = tm->betas;
+    c->h_tswap_len = tm->h_tswap_len;
+    c->opts = tm->opts;
+    c->opts.seed = seed;
+    c->opts.has_target = has_target;
+    c->opts.target = target;
+    c->clamp = tm->clamp;
+    c->nfree = tm->nfree;
+    c->device = tm->device;
+    c->stream = s;
+    c->own_stream = false;
+#define VIEW(f) c->f.view(tm->f.p, tm->f.bytes)
+    VIEW(J3); VIEW(row_ptr); VIEW(col); VIEW(Jc); VIEW(h); VIEW(clampd); VIEW(color_sites); VIEW(color_off);
+    VIEW(tflip); VIEW(tprop); VIEW(tprop_off); VIEW(tprop_len); VIEW(tswap); VIEW(tswap_off); VIEW(tswap_len);
+#undef VIEW
+    const int R = c->R, n = c->n;
+    const ArenaLayout A = arena_layout(R, n);
+    hipError_t e = c->arena.alloc(A.total);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(e == hipErrorOutOfMemory ? PT_ENOMEM : PT_EDEVICE, "request state: %s", hipGetErrorString(e));
+    }
+    char *base = c->arena.as<char>();
+    const size_t P = (size_t)std::max(R - 1, 1);
+    c->spins.view(base + A.spins, (size_t)R * n);
+    c->E.view(base + A.E, (size_t)R * 4);
+    c->t.view(base + A.t, 8);
+    c->cursor.view(base + A.cursor, (size_t)R * 4);
+    c->bank_ptrs.view(base + A.bank_ptrs, (size_t)R * 8);
+    c->bankE_ptrs.view(base + A.bankE_ptrs, (size_t)R * 8);
+    c->bank_n.view(base + A.bank_n, (size_t)R * 4);
+    c->swap_att.view(base + A.swap_att, P * 8);
+    c->swap_acc.view(base + A.swap_acc, P * 8);
+    c->prop_att.view(base + A.prop_att, (size_t)R * 8);
+    c->prop_acc.view(base + A.prop_acc, (size_t)R * 8);
+    c->flips.view(base + A.flips, (size_t)R * 8);
+    c->best.view(base + A.best, sizeof(BestRec));
+    c->best_spins.view(base + A.best_spins, (size_t)n);
+    c->inst.view(base + A.inst, sizeof(InstDev));
+    c->banks.resize(R);
+    c->h_bank_ptrs = tm->h_bank_ptrs;
+    c->h_bankE_ptrs = tm->h_bankE_ptrs;
+    c->h_bank_n = tm->h_bank_n;
+    c->hI = tm->hI;
+    c->hI.seed_lo = (uint32_t)seed;
+    c->hI.seed_hi = (uint32_t)(seed >> 32);
+    c->hI.has_target = has_target ? 1 : 0;
+    c->hI.target = target;
+    c->hI.sweep_cap = cap;
+    c->hI.epoch = 0;
+    fill_inst_pointers(c);
+    // the request's bank cursors start at its own seeded offsets
+    std::vector<int32_t> cur(R, 0);
+    for (int r = 0; r < R; ++r)
+        if (c->h_bank_n[r] > 0)
+            cur[r] = (int32_t)(host_philox_word0((uint32_t)r, 0, TAG_BANK, c->hI.seed_lo, c->hI.seed_hi) %
+                               (uint32_t)c->h_bank_n[r]);
+    auto bail = [&](hipError_t ee) {
+        delete c;
+        return fail(PT_EDEVICE, "request setup: %s", hipGetErrorString(ee));
+    };
+    if ((e = hipMemcpyAsync(c->bank_ptrs.p, c->h_bank_ptrs.data(), (size_t)R * 8, hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(c->bankE_ptrs.p, c->h_bankE_ptrs.data(), (size_t)R * 8, hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(c->bank_n.p, c->h_bank_n.data(), (size_t)R * 4, hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(c->cursor.p, cur.data(), (size_t)R * 4, hipMemcpyHostToDevice, s)))
+        return bail(e);
+    int rc = reset_state(c, nullptr, 0);   // ends with a stream synchronisation
+    if (rc) {
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return PT_OK;
+}
+
+double seconds_since(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+struct SrvReq {
+    uint64_t id;
+    pt_request rq;
+    double t_submit;
+};
+
+struct SrvActive {
+    SrvReq r;
+    pt_ctx *c;
+    size_t bytes;
+    double t_admit;
+    uint64_t t_last;
+};
+
+} // namespace
+
+struct pt_server {
+    pt_serve_opts opts{};
+    int device = 0;
+    std::chrono::steady_clock::time_point t0;
+    std::vector<pt_ctx *> problems;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<SrvReq> pending;
+    std::deque<pt_result> done;
+    bool stopping = false;
+    uint64_t next_id = 1;
+    pt_serve_stats st{};
+    std::thread worker;
+    // worker-only
+    pt_batch *batch = nullptr;
+    std::vector<SrvActive> active;
+    std::vector<InstStatus> status;
+};
+
+static void serve_publish(pt_server *S, std::vector<pt_result> &res)
+{
+    if (res.empty()) return;
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (auto &r : res) S->done.push_back(r);
+    res.clear();
+    S->cv_done.notify_all();
+}
+
+static pt_result serve_result(const SrvReq &r, int status, double t_admit, double t_done)
+{
+    pt_result o{};
+    o.id = r.id;
+    o.user_tag = r.rq.user_tag;
+    o.status = status;
+    o.first_hit = -1;
+    o.best_energy = 0x7FFFFFFF;
+    o.best_slot = -1;
+    o.best_t = -1;
+    o.t_submit = r.t_submit;
+    o.t_admit = t_admit;
+    o.t_done = t_done;
+    return o;
+}
+
+// Admit waiting requests, first come first served, while they fit.
+static void serve_admit(pt_server *S, bool &dirty, std::vector<pt_result> &out)
+{
+    for (;;) {
+        SrvReq r;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (S->pending.empty()) return;
+            r = S->pending.front();
+        }
+        if (S->opts.max_active > 0 && (int)S->active.size() >= S->opts.max_active) return;
+        pt_ctx *tm = S->problems[r.rq.problem];
+        const size_t need = arena_layout(tm->R, tm->n).total;
+        int rc = PT_OK;
+        if (S->st.mem_used + need > S->opts.mem_budget) {
+            rc = fail(PT_ENOMEM, "request state of %zu bytes exceeds the memory budget", need);
+        } else {
+            // the template has the clone's shape: plan the next launch with it
+            std::vector<pt_ctx *> set;
+            for (auto &a : S->active) set.push_back(a.c);
+            set.push_back(tm);
+            rc = batch_fits(S->batch, set);
+        }
+        if (rc && !S->active.empty()) return;   // wait for running requests to finish
+        pt_ctx *c = nullptr;
+        if (!rc) rc = clone_ctx(tm, r.rq.seed, r.rq.has_target, r.rq.target, r.rq.sweep_cap, S->batch->stream, &c);
+        const double now = seconds_since(S->t0);
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->pending.pop_front();
+            S->st.waiting = (int32_t)S->pending.size();
+            if (rc) {
+                S->st.rejected += 1;
+            } else {
+                S->st.admitted += 1;
+                S->st.mem_used += need;
+                S->st.mem_peak = std::max(S->st.mem_peak, S->st.mem_used);
+                S->st.active = (int32_t)S->active.size() + 1;
+                S->st.peak_active = std::max(S->st.peak_active, S->st.active);
+            }
+        }
+        if (rc) {
+            out.push_back(serve_result(r, rc, now, now));
+            continue;
+        }
+        S->active.push_back({r, c, need, now, 0});
+        dirty = true;
+    }
+}
+
+// One round: a persistent launch of chunk_sweeps sweeps over every active
+// request, then retire the ones that are done.
+static int serve_round(pt_server *S, bool &dirty, std::vector<pt_result> &out)
+{
+    pt_batch *b = S->batch;
+    if (dirty) {
+        std::vector<pt_ctx *> set;
+        for (auto &a : S->active) set.push_back(a.c);
+        int rc = batch_set_contexts(b, set.data(), (int32_t)set.size());
+        if (rc) return rc;
+        dirty = false;
+    }
+    const double ta = seconds_since(S->t0);
+    const uint32_t K = (uint32_t)S->opts.chunk_sweeps;
+    hipError_t e = enqueue_round(b, K, false);
+    if (e != hipSuccess) return fail(PT_EDEVICE, "serving round: %s", hipGetErrorString(e));
+    LaunchGroup *g = b->groups[0];
+    S->status.resize(g->ctxs.size());
+    int err[8] = {0};
+    HIPCHK(hipMemcpyAsync(S->status.data(), g->status.p, S->status.size() * sizeof(InstStatus),
+                          hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(err, b->err.p, 32, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    if (err[0]) return fail(PT_ETIMEOUT, "cross-workgroup exchange timed out in a serving round");
+    double attempts = 0.0;
+    std::vector<SrvActive> keep;
+    for (size_t k = 0; k < S->active.size(); ++k) {
+        SrvActive &a = S->active[k];
+        const InstStatus &st = S->status[k];
+        const uint64_t t = (uint64_t)st.t;
+        attempts += (double)(t - a.t_last) * (double)a.c->R * (double)a.c->nfree;
+        a.t_last = t;
+        const bool hit = a.r.rq.has_target && st.first_hit >= 0;
+        if (!hit && t < a.r.rq.sweep_cap) {
+            keep.push_back(a);
+            continue;
+        }
+        if (a.r.rq.best_out)
+            HIPCHK(hipMemcpy(a.r.rq.best_out, a.c->best_spins.p, (size_t)a.c->n, hipMemcpyDeviceToHost));
+        pt_result o = serve_result(a.r, PT_OK, a.t_admit, seconds_since(S->t0));
+        o.hit = hit ? 1 : 0;
+        o.first_hit = st.first_hit;
+        o.best_energy = st.best_E;
+        o.best_slot = st.best_slot;
+        o.best_t = st.best_t;
+        o.sweeps = t;
+        out.push_back(o);
+        pt_destroy(a.c);
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->st.mem_used -= a.bytes;
+            S->st.completed += 1;
+        }
+        dirty = true;
+    }
+    S->active.swap(keep);
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->st.rounds += 1;
+    S->st.busy_s += seconds_since(S->t0) - ta;
+    S->st.attempts += attempts;
+    S->st.active = (int32_t)S->active.size();
+    return PT_OK;
+}
+
+static void serve_worker(pt_server *S)
+{
+    (void)hipSetDevice(S->device);
+    bool dirty = true;
+    std::vector<pt_result> out;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (S->active.empty() && S->pending.empty()) {
+                if (S->stopping) break;
+                S->cv_work.wait(lk, [&] { return S->stopping || !S->pending.empty(); });
+                continue;
+            }
+        }
+        serve_admit(S, dirty, out);
+        serve_publish(S, out);
+        if (S->active.empty()) continue;
+        int rc = serve_round(S, dirty, out);
+        if (rc) {
+            // a failed round fails every request in it; the device state of
+            // the launch is unknown, so the server takes no more work
+            const double now = seconds_since(S->t0);
+            for (auto &a : S->active) {
+                out.push_back(serve_result(a.r, rc, a.t_admit, now));
+                a.c->broken = true;
+                pt_destroy(a.c);
+            }
+            S->active.clear();
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (auto &r : S->pending) out.push_back(serve_result(r, rc, now, now));
+            S->st.rejected += S->pending.size();
+            S->pending.clear();
+            S->stopping = true;
+        }
+        serve_publish(S, out);
+    }
+}
+
+extern "C" int pt_serve_start(const pt_serve_opts *o, pt_server **out)
+{
+    if (!out) return fail(PT_EINVAL, "null output pointer");
+    *out = nullptr;
+    pt_server *S = new pt_server();
+    if (o) S->opts = *o;
+    if (S->opts.mem_budget == 0) S->opts.mem_budget = 1ull << 30;
+    if (S->opts.chunk_sweeps <= 0) S->opts.chunk_sweeps = 500;
+    if (hipGetDevice(&S->device) != hipSuccess) {
+        delete S;
+        return fail(PT_EDEVICE, "no HIP device");
+    }
+    S->batch = new pt_batch();
+    S->batch->opts.replicas_per_wg = S->opts.replicas_per_wg;
+    S->batch->opts.replicas_per_thread = S->opts.replicas_per_thread;
+    S->batch->opts.chunk_sweeps = S->opts.chunk_sweeps;
+    int rc = batch_init(S->batch, S->device);
+    if (rc) {
+        delete S->batch;
+        delete S;
+        return rc;
+    }
+    S->t0 = std::chrono::steady_clock::now();
+    S->worker = std::thread(serve_worker, S);
+    *out = S;
+    return PT_OK;
+}
+
+extern "C" int pt_serve_register(pt_server *s, pt_ctx *ctx, int32_t *problem)
+{
+    if (!s || !ctx || !problem) return fail(PT_EINVAL, "null argument");
+    if (ctx->broken) return fail(PT_ESTATE, "context is unusable");
+    if (ctx->device != s->device) return fail(PT_EINVAL, "context lives on another device");
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->problems.push_back(ctx);
+    *problem = (int32_t)s->problems.size() - 1;
+    return PT_OK;
+}
+
+extern "C" int pt_serve_submit(pt_server *s, const pt_request *rq, uint64_t *id)
+{
+    if (!s || !rq) return fail(PT_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) return fail(PT_ESTATE, "server is stopping");
+    if (rq->problem < 0 || rq->problem >= (int32_t)s->problems.size()) return fail(PT_EINVAL, "unknown problem %d", rq->problem);
+    if (rq->sweep_cap < 1 || rq->sweep_cap > 0xFFFFFFFFull) return fail(PT_EINVAL, "sweep_cap must be in 1..2^32-1");
+    SrvReq r;
+    r.id = s->next_id++;
+    r.rq = *rq;
+    r.t_submit = seconds_since(s->t0);
+    s->pending.push_back(r);
+    s->st.submitted += 1;
+    s->st.waiting = (int32_t)s->pending.size();
+    if (id) *id = r.id;
+    s->cv_work.notify_one();
+    return PT_OK;
+}
+
+extern "C" int pt_serve_poll(pt_server *s, pt_result *out, int32_t max, int32_t wait_ms, int32_t *n_out)
+{
+    if (!s || !n_out || (max > 0 && !out)) return fail(PT_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (wait_ms > 0 && s->done.empty())
+        s->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), [&] { return !s->done.empty(); });
+    int n = 0;
+    while (n < max && !s->done.empty()) {
+        out[n++] = s->done.front();
+        s->done.pop_front();
+    }
+    *n_out = n;
+    return PT_OK;
+}
+
+extern "C" int pt_serve_stats_get(pt_server *s, pt_serve_stats *st)
+{
+    if (!s || !st) return fail(PT_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *st = s->st;
+    return PT_OK;
+}
+
+extern "C" double pt_serve_clock(pt_server *s) { return s ? seconds_since(s->t0) : 0.0; }
+
+extern "C" int pt_serve_stop(pt_server *s)
+{
+    if (!s) return PT_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+        s->cv_work.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    for (auto &a : s->active) pt_destroy(a.c);
+    pt_batch_destroy(s->batch);
+    delete s;
     return PT_OK;
 }

@@ -20,777 +20,23 @@
 // maintenance on the critical path). All random numbers are keyed by
 // (seed, site, sweep, slot, stream tag), never by thread or storage, so the
 // chain is the same for every tiling, batch and launch sequence.
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-
-#include "tapt_dev.h"
+#include "sweep.h"
 
 namespace tapt {
-
-typedef short short2v __attribute__((ext_vector_type(2)));
-
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). The 32x32->64 products
-// compile to v_mad_u64_u32; the key schedule is wave-uniform (SGPRs).
-struct P4 {
-    uint32_t v[4];
-};
-
-__host__ __device__ __forceinline__ P4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                              uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        uint64_t a = (uint64_t)c0 * 0xD2511F53u;
-        uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
-        uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
-        uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
-        c1 = (uint32_t)b;
-        c3 = (uint32_t)a;
-        c0 = n0;
-        c2 = n2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    P4 o;
-    o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
-    return o;
-}
-
-__host__ __device__ __forceinline__ uint32_t philox_word0(uint32_t c0, uint32_t c1, uint32_t c3,
-                                                          uint32_t k0, uint32_t k1)
-{
-    return philox(c0, c1, 0, c3, k0, k1).v[0];
-}
-
-// accept iff T == ALWAYS or u < T, with u = (hi << 16) | lo and the low half
-// drawn only when the high half leaves the decision open.
-__device__ __forceinline__ bool coarse_accept(uint32_t T, uint32_t hs, bool &maybe)
-{
-    bool acc = (hs | 0xFFFFu) < T;
-    maybe = !acc && hs < T;
-    return acc;
-}
-
-__device__ __forceinline__ bool any_lane(bool p) { return __any(p); }
-
-// Minimum of x over the 64 lanes of a wavefront with DPP row shifts and row
-// broadcasts (no LDS round trips); every lane receives the result.
-__device__ __forceinline__ int wave_min(int x)
-{
-    const int id = 0x7FFFFFFF;
-    x = min(x, __builtin_amdgcn_update_dpp(id, x, 0x111, 0xf, 0xf, false));   // row_shr:1
-    x = min(x, __builtin_amdgcn_update_dpp(id, x, 0x112, 0xf, 0xf, false));   // row_shr:2
-    x = min(x, __builtin_amdgcn_update_dpp(id, x, 0x114, 0xf, 0xf, false));   // row_shr:4
-    x = min(x, __builtin_amdgcn_update_dpp(id, x, 0x118, 0xf, 0xf, false));   // row_shr:8
-    x = min(x, __builtin_amdgcn_update_dpp(id, x, 0x142, 0xa, 0xf, false));   // row_bcast:15
-    x = min(x, __builtin_amdgcn_update_dpp(id, x, 0x143, 0xc, 0xf, false));   // row_bcast:31
-    return __builtin_amdgcn_readlane(x, 63);
-}
-
-// ---------------------------------------------------------------------------
-// Sweepers. Each provides: storage size and LDS index of a site, per-thread
-// setup, and one sweep of every storage of the workgroup (all threads call it;
-// it contains the workgroup barriers between color classes).
-
-// Periodic L^3 cubic lattice, checkerboard colors (x+y+z) mod 2, even L.
-// Thread (group g, call q) owns sites 8q..8q+7 -- the 8 sites whose uniforms
-// come from Philox call q -- of RPT storages. Every such call holds exactly 4
-// sites of each color (a row has even length and calls start at even x), so a
-// thread updates 4 sites per color phase. Neighbour LDS addresses and packed
-// couplings of those 8 sites are computed once and stay in VGPRs.
-// LDS layout of a storage: site i at byte (i & 7) * (N/8) + (i >> 3), so
-// lanes (consecutive q) touch consecutive bytes for every neighbour direction.
-template <int L, int RPT>
-struct LatSweep {
-    static constexpr int N = L * L * L;
-    static constexpr int NC = N / 8;
-    static_assert(L % 2 == 0 && L >= 4, "even L >= 4");
-    static constexpr int SB = N;   // bytes per storage
-    static constexpr int MAXT = 512;  // block limit: leaves up to 256 VGPRs per lane
-    static constexpr bool RND = false;  // no staged random halves
-
-    __host__ __device__ static constexpr int lidx(int i) { return (i & 7) * NC + (i >> 3); }
-    static int threads(int G) { return ((G + RPT - 1) / RPT) * NC; }
-
-    int q, grp;
-    bool active;
-    int own[2][4];
-    int nb[2][4][6];
-    short2v J[2][4][3];
-    int sh[2][4];
-
-    __device__ static int site(int x, int y, int z)
-    {
-        x = (x + L) % L; y = (y + L) % L; z = (z + L) % L;
-        return x + L * (y + L * z);
-    }
-
-    __device__ __forceinline__ void setup(const InstDev &I, int G)
-    {
-        int tid = threadIdx.x;
-        grp = tid / NC;
-        q = tid % NC;
-        active = grp < (G + RPT - 1) / RPT;
-        const int8_t *J3 = I.J3;
-        for (int c = 0; c < 2; ++c) {
-            for (int s = 0; s < 4; ++s) {
-                int i0 = 8 * q + 2 * s;
-                int x = i0 % L, y = (i0 / L) % L, z = i0 / (L * L);
-                int p = (((x + y + z) & 1) == c) ? 0 : 1;
-                int i = i0 + p;
-                x = i % L;
-                int nbs[6] = {site(x + 1, y, z), site(x - 1, y, z), site(x, y + 1, z),
-                              site(x, y - 1, z), site(x, y, z + 1), site(x, y, z - 1)};
-                int jj[6] = {J3[i], J3[nbs[1]], J3[N + i], J3[N + nbs[3]], J3[2 * N + i], J3[2 * N + nbs[5]]};
-                own[c][s] = lidx(i) + grp * RPT * SB;
-                for (int d = 0; d < 6; ++d) nb[c][s][d] = lidx(nbs[d]) + grp * RPT * SB;
-                for (int d = 0; d < 3; ++d) {
-                    short2v v;
-                    v.x = (short)jj[2 * d];
-                    v.y = (short)jj[2 * d + 1];
-                    J[c][s][d] = v;
-                }
-                sh[c][s] = 16 * p;
-            }
-        }
-    }
-
-    // One sweep at sweep index t of every storage this workgroup holds.
-    // slot_of: storage -> local slot; global slot = s0 + local slot.
-    __device__ __forceinline__ void sweep(const InstDev &I, int G, int s0, uint32_t t, const int *slot_of,
-                                          int8_t *sp, const uint32_t *tab, int stride, int *Elds,
-                                          unsigned *flips_lds)
-    {
-        uint32_t w[RPT][4];
-        int sl[RPT], dE[RPT], nf[RPT];
-        bool ok[RPT];
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            int stor = grp * RPT + k;
-            ok[k] = active && stor < G;
-            sl[k] = ok[k] ? slot_of[stor] : 0;
-            P4 r = philox((uint32_t)q, t, (uint32_t)(s0 + sl[k]), TAG_SWEEP, I.seed_lo, I.seed_hi);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) w[k][j] = r.v[j];
-            dE[k] = 0;
-            nf[k] = 0;
-        }
-        const int D = I.D;
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-#pragma unroll
-            for (int k = 0; k < RPT; ++k) {
-                if (ok[k]) {
-                    // the 4 same-color sites are independent: decide all, then flip
-                    const uint32_t *trow = tab + sl[k] * stride + D;
-                    int mm[4], dd[4];
-                    uint32_t TT[4], hs[4];
-                    bool acc[4], maybe[4];
-                    bool any_maybe = false;
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        int m = sp[own[c][s] + k * SB];
-                        short2v m01, m23, m45;
-                        m01.x = sp[nb[c][s][0] + k * SB];
-                        m01.y = sp[nb[c][s][1] + k * SB];
-                        m23.x = sp[nb[c][s][2] + k * SB];
-                        m23.y = sp[nb[c][s][3] + k * SB];
-                        m45.x = sp[nb[c][s][4] + k * SB];
-                        m45.y = sp[nb[c][s][5] + k * SB];
-                        int f = __builtin_amdgcn_sdot2(m01, J[c][s][0], 0, false);
-                        f = __builtin_amdgcn_sdot2(m23, J[c][s][1], f, false);
-                        f = __builtin_amdgcn_sdot2(m45, J[c][s][2], f, false);
-                        mm[s] = m;
-                        dd[s] = m * f;                      // dE / 2
-                        TT[s] = trow[dd[s]];
-                        hs[s] = (w[k][s] >> sh[c][s]) << 16;
-                        acc[s] = coarse_accept(TT[s], hs[s], maybe[s]);
-                        any_maybe |= maybe[s];
-                    }
-                    if (any_lane(any_maybe)) {
-                        P4 r2 = philox((uint32_t)q, t, (uint32_t)(s0 + sl[k]), TAG_REFINE, I.seed_lo, I.seed_hi);
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) {
-                            uint32_t lo = (r2.v[s] >> sh[c][s]) & 0xFFFFu;
-                            if (maybe[s]) acc[s] = (TT[s] == ALWAYS) || ((hs[s] | lo) < TT[s]);
-                        }
-                    }
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        if (acc[s]) {
-                            sp[own[c][s] + k * SB] = (int8_t)(-mm[s]);
-                            dE[k] += 2 * dd[s];
-                            nf[k] += 1;
-                        }
-                    }
-                }
-            }
-            if (c == 0) __syncthreads();
-        }
-        // per-storage energy change and flip count, then the barrier that
-        // ends the sweep (Elds is final after it)
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            int e = dE[k], f = nf[k];
-            if constexpr (NC % 64 == 0) {
-                // a wave belongs to one storage group
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-                    e += __shfl_xor(e, off);
-                    f += __shfl_xor(f, off);
-                }
-                if (ok[k] && (threadIdx.x & 63) == 0) {
-                    atomicAdd(&Elds[grp * RPT + k], e);
-                    atomicAdd(&flips_lds[sl[k]], (unsigned)f);
-                }
-            } else {
-                if (ok[k] && (e != 0 || f != 0)) {
-                    atomicAdd(&Elds[grp * RPT + k], e);
-                    atomicAdd(&flips_lds[sl[k]], (unsigned)f);
-                }
-            }
-        }
-        __syncthreads();
-    }
-};
-
-// General sparse graph (CSR, any proper coloring, clamps, fields). Random
-// halves for every site of every storage are staged in LDS at the start of
-// the sweep (one Philox call per 8 sites), then each color class is spread
-// over all threads of the workgroup.
-struct CsrSweep {
-    static constexpr int RPTV = 1;
-    static constexpr int MAXT = 1024;
-    static constexpr bool RND = true;   // random halves staged in LDS
-    int n, SB, nr;
-
-    __host__ __device__ static int storage_bytes(int n) { return (n + 15) & ~15; }
-    __device__ int lidx(int i) const { return i; }
-
-    __device__ void setup(const InstDev &I, int G)
-    {
-        (void)G;
-        n = I.n;
-        SB = storage_bytes(n);
-        nr = (n + 7) & ~7;
-    }
-
-    __device__ __forceinline__ void sweep(const InstDev &I, int G, int s0, uint32_t t, const int *slot_of,
-                                          int8_t *sp, const uint32_t *tab, int stride, int *Elds,
-                                          unsigned *flips_lds, uint16_t *rnd)
-    {
-        const int tid = threadIdx.x, bs = blockDim.x;
-        const int ncall = nr >> 3;
-        for (int idx = tid; idx < G * ncall; idx += bs) {
-            int k = idx / ncall, q = idx - k * ncall;
-            P4 r = philox((uint32_t)q, t, (uint32_t)(s0 + slot_of[k]), TAG_SWEEP, I.seed_lo, I.seed_hi);
-            uint4 v = make_uint4(r.v[0], r.v[1], r.v[2], r.v[3]);
-            *(uint4 *)(rnd + (size_t)k * nr + 8 * q) = v;
-        }
-        __syncthreads();
-        const int D = I.D;
-        for (int c = 0; c < I.ncolors; ++c) {
-            int off = I.color_off[c], cnt = I.color_off[c + 1] - off;
-            for (int idx = tid; idx < G * cnt; idx += bs) {
-                int k = idx / cnt;
-                int i = I.color_sites[off + idx - k * cnt];
-                int8_t *m_k = sp + k * SB;
-                int f = I.h[i];
-                for (int e = I.row_ptr[i]; e < I.row_ptr[i + 1]; ++e) f += (int)I.Jc[e] * (int)m_k[I.col[e]];
-                int m = m_k[i];
-                int d = m * f;
-                int sl = slot_of[k];
-                uint32_t T = tab[sl * stride + D + d];
-                uint32_t hs = (uint32_t)rnd[(size_t)k * nr + i] << 16;
-                bool maybe;
-                bool acc = coarse_accept(T, hs, maybe);
-                if (any_lane(maybe)) {
-                    if (maybe) {
-                        P4 r2 = philox((uint32_t)(i >> 3), t, (uint32_t)(s0 + sl), TAG_REFINE, I.seed_lo, I.seed_hi);
-                        uint32_t wd = r2.v[(i & 7) >> 1];
-                        uint32_t lo = ((i & 1) ? (wd >> 16) : wd) & 0xFFFFu;
-                        acc = (T == ALWAYS) || ((hs | lo) < T);
-                    }
-                }
-                if (acc) {
-                    m_k[i] = (int8_t)(-m);
-                    atomicAdd(&Elds[k], 2 * d);
-                    atomicAdd(&flips_lds[sl], 1u);
-                }
-            }
-            __syncthreads();
-        }
-    }
-};
-
-// ---------------------------------------------------------------------------
-// LDS carve-up shared by the persistent kernel and the host's size query.
-// tsw: swap-threshold rows of the pairs a workgroup decides, pair slot p for
-// global pair r = s0 - 1 + p (p = 0 and p = G are the cross-workgroup pairs).
-struct ChunkLds {
-    int8_t *sp;
-    uint32_t *tab;
-    int *slot_of, *stor_of, *Elds;
-    unsigned *flips, *satt, *sacc;
-    int *misc;
-    long long *src;
-    uint16_t *rnd;
-    int *tsw_off;              // [G + 2]: row p spans [tsw_off[p], tsw_off[p+1])
-    uint32_t *tsw;
-    uint32_t *xstage;          // [2][ceil(n/32) + 1] validated exchange words
-    uint32_t *usw;             // [2][65] swap uniforms by cycle parity (lane l: pair s0+l; 64: pair s0-1)
-};
-
-struct ChunkOff {
-    size_t sp, tab, ints, src, rnd, toff, tsw, xst, usw, total;
-};
-
-__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
-
-__host__ __device__ __forceinline__ ChunkOff chunk_lds_offsets(int G, int SB, int stride, int nr_csr, int tsw_entries,
-                                                                int n)
-{
-    ChunkOff f;
-    size_t o = 0;
-    f.sp = o; o = align16(o + (size_t)G * SB);
-    f.tab = o; o = align16(o + (size_t)G * stride * 4);
-    f.ints = o; o = align16(o + (size_t)G * 4 * 7 + 64);
-    f.src = o; o = align16(o + (size_t)G * 8);
-    f.rnd = o; o = align16(o + (size_t)G * nr_csr * 2);
-    f.toff = o; o = align16(o + (size_t)(G + 2) * 4);
-    f.tsw = o; o = align16(o + (size_t)tsw_entries * 4);
-    f.xst = o; o = align16(o + (size_t)2 * (((n + 31) >> 5) + 1) * 4);
-    f.usw = o; o = align16(o + (size_t)2 * 65 * 4);
-    f.total = o;
-    return f;
-}
-
-// Pointers into the dynamic LDS block, built from the kernel's own
-// __shared__ array so that every access compiles to ds_* instructions.
-#define CHUNK_LDS_POINTERS(c, f, G, base)                         \
-    ChunkLds c;                                                   \
-    c.sp = (int8_t *)((base) + (f).sp);                           \
-    c.tab = (uint32_t *)((base) + (f).tab);                       \
-    c.slot_of = (int *)((base) + (f).ints);                       \
-    c.stor_of = c.slot_of + (G);                                  \
-    c.Elds = c.slot_of + 2 * (G);                                 \
-    c.flips = (unsigned *)(c.slot_of + 3 * (G));                  \
-    c.satt = (unsigned *)(c.slot_of + 4 * (G));                   \
-    c.sacc = (unsigned *)(c.slot_of + 5 * (G));                   \
-    c.misc = c.slot_of + 7 * (G);                                 \
-    c.src = (long long *)((base) + (f).src);                      \
-    c.rnd = (uint16_t *)((base) + (f).rnd);                       \
-    c.tsw_off = (int *)((base) + (f).toff);                       \
-    c.tsw = (uint32_t *)((base) + (f).tsw);                       \
-    c.xstage = (uint32_t *)((base) + (f).xst);                    \
-    c.usw = (uint32_t *)((base) + (f).usw)
-
-// Run parameters of one instance, read once per launch (kept in SGPRs).
-struct RunParams {
-    int n, R, M, D, stride, has_target, target;
-    uint32_t k0, k1;
-    int64_t prop_start, prop_period, prop_stop;
-    __device__ __forceinline__ void load(const InstDev &I)
-    {
-        n = I.n; R = I.R; M = I.M; D = I.D; stride = I.tflip_stride;
-        has_target = I.has_target; target = I.target;
-        k0 = I.seed_lo; k1 = I.seed_hi;
-        prop_start = I.prop_start; prop_period = I.prop_period; prop_stop = I.prop_stop;
-    }
-    __device__ __forceinline__ bool prop_sweep(uint64_t t) const
-    {
-        if (prop_period <= 0) return false;
-        if ((int64_t)t < prop_start) return false;
-        if (prop_stop >= 0 && (int64_t)t > prop_stop) return false;
-        return (((int64_t)t - prop_start) % prop_period) == 0;
-    }
-};
-
-__device__ inline bool is_prop_sweep(const InstDev &I, uint64_t t)
-{
-    if (I.prop_period <= 0) return false;
-    if ((int64_t)t < I.prop_start) return false;
-    if (I.prop_stop >= 0 && (int64_t)t > I.prop_stop) return false;
-    return (((int64_t)t - I.prop_start) % I.prop_period) == 0;
-}
-
-// swap threshold for pair r and dE = E_{r+1} - E_r from an LDS row
-__device__ __forceinline__ uint32_t swap_threshold(const ChunkLds &c, int p, int dE)
-{
-    if (dE >= 0) return ALWAYS;
-    int d = -dE, lo = c.tsw_off[p], len = c.tsw_off[p + 1] - lo;
-    return d <= len ? c.tsw[lo + d - 1] : 0u;
-}
-
-// ---------------------------------------------------------------------------
-// Persistent chunk kernel: K sweeps (and the cycle-end stages they reach) of
-// the slots [s0, s0+G) of one instance per workgroup.
-template <class Sw>
-struct SweepCall;
-
-template <int L, int RPT>
-struct SweepCall<LatSweep<L, RPT>> {
-    static __device__ __forceinline__ void run(LatSweep<L, RPT> &sw, const InstDev &I, int G, int s0, uint32_t t, ChunkLds &c,
-                               int stride)
-    {
-        sw.sweep(I, G, s0, t, c.slot_of, c.sp, c.tab, stride, c.Elds, c.flips);
-    }
-    static __device__ int SB(const LatSweep<L, RPT> &) { return LatSweep<L, RPT>::SB; }
-    static __device__ int lidx(const LatSweep<L, RPT> &, int i) { return LatSweep<L, RPT>::lidx(i); }
-};
-
-template <>
-struct SweepCall<CsrSweep> {
-    static __device__ __forceinline__ void run(CsrSweep &sw, const InstDev &I, int G, int s0, uint32_t t, ChunkLds &c, int stride)
-    {
-        sw.sweep(I, G, s0, t, c.slot_of, c.sp, c.tab, stride, c.Elds, c.flips, c.rnd);
-    }
-    static __device__ int SB(const CsrSweep &s) { return s.SB; }
-    static __device__ int lidx(const CsrSweep &, int i) { return i; }
-};
-
 
 template <class Sw>
 __global__ void __launch_bounds__(Sw::MAXT) chunk_kernel(ChunkArgs a)
 {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
     const int item = a.order[blockIdx.x];
     if (item < 0) return;   // padding block that keeps the XCD placement aligned
-    const WorkItem it = a.items[item];
-    const InstDev &I = *it.inst;
-    RunParams P;
-    P.load(I);
-    const int G = it.G, s0 = it.s0, n = P.n;
-    const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63;
-    const uint64_t t0 = *I.t;
-    const uint64_t cap = I.sweep_cap;
-    const uint64_t tend = (t0 + a.K < cap) ? t0 + a.K : cap;
-    if (t0 >= tend) return;
-
-    Sw sw;
-    sw.setup(I, G);
-    const int SB = SweepCall<Sw>::SB(sw);
-    const int stride = P.stride;
-    const ChunkOff lof = chunk_lds_offsets(G, SB, stride, Sw::RND ? ((n + 7) & ~7) : 0, a.tsw_entries, n);
-    CHUNK_LDS_POINTERS(c, lof, G, lds_raw);
-
-    // stage tables and state
-    for (int x = tid; x < G * stride; x += bs) c.tab[x] = I.tflip[(size_t)s0 * stride + x];
-    for (int x = tid; x < G * n; x += bs) {
-        int l = x / n, i = x - l * n;
-        c.sp[l * SB + SweepCall<Sw>::lidx(sw, i)] = I.spins[(size_t)(s0 + l) * n + i];
-    }
-    if (tid == 0) {
-        int o = 0;
-        for (int p = 0; p <= G; ++p) {
-            c.tsw_off[p] = o;
-            int r = s0 - 1 + p;
-            if (r >= 0 && r + 1 < P.R) o += I.tswap_len[r];
-        }
-        c.tsw_off[G + 1] = o;
-    }
-    for (int l = tid; l < G; l += bs) {
-        c.slot_of[l] = l;
-        c.stor_of[l] = l;
-        c.Elds[l] = I.E[s0 + l];
-        c.flips[l] = 0;
-        c.satt[l] = 0;
-        c.sacc[l] = 0;
-    }
-    if (tid < 16) c.misc[tid] = 0;
-    __syncthreads();
-    for (int p = 0; p <= G; ++p) {
-        int r = s0 - 1 + p;
-        if (r < 0 || r + 1 >= P.R) continue;
-        int lo = c.tsw_off[p], len = c.tsw_off[p + 1] - lo;
-        for (int x = tid; x < len; x += bs) c.tsw[lo + x] = I.tswap[I.tswap_off[r] + x];
-    }
-    // best-energy bookkeeping lives in registers of wave 0
-    int bestE = I.best->E;
-    int64_t bestT = -1;
-    int bestSlot = -1;
-    int64_t hit = I.best->first_hit;
-    const int64_t hit0 = hit;
-    const bool has_down = it.w > 0, has_up = it.w + 1 < it.W;
-    __syncthreads();
-
-    // Wave-0 registers for the cycle-end stages (G <= 64): lane l is local
-    // slot l; my_st is the storage holding it; (row_off, row_len) is the LDS
-    // swap-threshold row of pair (s0+l, s0+l+1) -- for l = G-1 that is the
-    // pair across the upper boundary; (dn_off, dn_len) the one across the lower.
-    int my_st = lane, row_off = 0, row_len = 0, dn_off = 0, dn_len = 0;
-    unsigned my_att = 0, my_acc = 0;
-    if (tid < 64) {
-        if (lane < G) {
-            row_off = c.tsw_off[lane + 1];
-            row_len = c.tsw_off[lane + 2] - row_off;
-        }
-        dn_off = c.tsw_off[0];
-        dn_len = c.tsw_off[1] - dn_off;
-    }
-    const int nw = (n + 31) >> 5;
-    if (tid < 64) {   // swap uniforms of the first cycle end of this launch
-        const uint32_t c1 = (uint32_t)((t0 + (uint64_t)P.M) / (uint64_t)P.M);
-        c.usw[(c1 & 1) * 65 + lane] = philox_word0((uint32_t)(s0 + lane), c1, TAG_SWAP, P.k0, P.k1);
-        if (lane == 0 && has_down) c.usw[(c1 & 1) * 65 + 64] = philox_word0((uint32_t)(s0 - 1), c1, TAG_SWAP, P.k0, P.k1);
-    }
-    __syncthreads();
-
-    bool failed = false;
-    for (uint64_t t = t0 + 1; t <= tend && !failed; ++t) {
-        const bool cyc_end = (t % (uint64_t)P.M) == 0;
-        const uint32_t cyc = (uint32_t)(t / (uint64_t)P.M);
-        SweepCall<Sw>::run(sw, I, G, s0, (uint32_t)t, c, stride);   // ends with a barrier
-        // ---- proposals (Eq. 2), slots in increasing order ----
-        if (cyc_end && P.prop_sweep(t)) {
-            if (tid < 64) {
-                for (int l = lane; l < G; l += 64) {
-                    int r = s0 + l;
-                    c.src[l] = 0;
-                    int B = I.bank_n[r];
-                    if (B > 0) {
-                        int k = I.cursor[r];
-                        I.cursor[r] = (k + 1 == B) ? 0 : k + 1;
-                        int ET = I.bankE[r][k];
-                        int st = c.stor_of[l];
-                        long long dd = (long long)ET - (long long)c.Elds[st];
-                        uint32_t T;
-                        if (dd <= 0) T = ALWAYS;
-                        else if (dd <= I.tprop_len[r]) T = I.tprop[I.tprop_off[r] + (int)dd - 1];
-                        else T = 0;
-                        uint32_t u = philox_word0((uint32_t)r, cyc, TAG_PROPOSE, P.k0, P.k1);
-                        I.prop_att[r] += 1;
-                        if (T == ALWAYS || u < T) {
-                            c.Elds[st] = ET;
-                            c.src[l] = (long long)(I.bank[r] + (size_t)k * n);
-                            I.prop_acc[r] += 1;
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-            for (int l = 0; l < G; ++l) {
-                const int8_t *src = (const int8_t *)c.src[l];
-                if (src) {
-                    int8_t *dst = c.sp + c.stor_of[l] * SB;
-                    for (int i = tid; i < n; i += bs) dst[SweepCall<Sw>::lidx(sw, i)] = src[i];
-                }
-            }
-            __syncthreads();
-        }
-        if (tid >= 64 && tid < 128 && cyc_end) {
-            // wave 1 draws the next cycle's swap uniforms while wave 0 works
-            const uint32_t nx = cyc + 1;
-            c.usw[(nx & 1) * 65 + lane] = philox_word0((uint32_t)(s0 + lane), nx, TAG_SWAP, P.k0, P.k1);
-            if (lane == 0 && has_down) c.usw[(nx & 1) * 65 + 64] = philox_word0((uint32_t)(s0 - 1), nx, TAG_SWAP, P.k0, P.k1);
-        }
-        if (tid < 64) {
-            int e = lane < G ? c.Elds[my_st] : 0x7FFFFFFF;
-            if (cyc_end) {
-                const uint32_t u_pair = c.usw[(cyc & 1) * 65 + lane];
-                const uint32_t u_dn = c.usw[(cyc & 1) * 65 + 64];
-                // ---- replica exchange (Eq. 1), alternating parity ----
-                const int first = (cyc & 1) ? 0 : 1;
-                const bool down = has_down && (((s0 - 1 - first) & 1) == 0);
-                const bool up = has_up && (((s0 + G - 1 - first) & 1) == 0);
-                const int buf = (cyc >> 1) & 1;
-                const unsigned long long tag = (unsigned long long)cyc << 32;
-                // (1) publish the boundary states first. A boundary slot in a cross
-                // pair is in no local pair this cycle. Every 64-bit word carries 32
-                // spin bits (or the energy) and the cycle number, written with relaxed
-                // device-scope atomics; the reader accepts a word only when its tag is
-                // this cycle, so no fence or flag is needed. Buffers alternate with the
-                // cycle parity: a partner is at most one exchange ahead.
-                for (int side = 0; side < 2; ++side) {
-                    if (!(side == 0 ? down : up)) continue;
-                    const int st = __shfl(my_st, side == 0 ? 0 : G - 1);
-                    const int eb = __shfl(e, side == 0 ? 0 : G - 1);
-                    const int8_t *stor = c.sp + st * SB;
-                    unsigned long long *out = it.xbuf + ((size_t)(it.w * 2 + side) * 2 + buf) * it.xwords;
-                    const int nch = (n + 63) >> 6;
-                    for (int k0 = 0; k0 < nch; k0 += 8) {
-                        int8_t v[8];
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) {   // unconditional reads: one LDS round trip
-                            const int i = 64 * (k0 + j) + lane;
-                            v[j] = stor[SweepCall<Sw>::lidx(sw, i < n ? i : n - 1)];
-                        }
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) {
-                            const unsigned long long m = __ballot(64 * (k0 + j) + lane < n && v[j] > 0);
-                            const int wd = 2 * (k0 + j) + lane;
-                            if (lane < 2 && wd < nw)
-                                __hip_atomic_store(out + wd, tag | (lane ? (m >> 32) : (m & 0xFFFFFFFFull)),
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        }
-                    }
-                    if (lane == 0)
-                        __hip_atomic_store(out + nw, tag | (uint32_t)eb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-                // (2) pairs inside the workgroup: exchange labels (lane l decides (l, l+1))
-                const int e_nx = __shfl_down(e, 1), st_nx = __shfl_down(my_st, 1);
-                const bool act = lane + 1 < G && (((s0 + lane - first) & 1) == 0);
-                bool acc = false;
-                if (act) {
-                    const int dE = e_nx - e;
-                    const uint32_t T = dE >= 0 ? ALWAYS : (-dE <= row_len ? c.tsw[row_off - dE - 1] : 0u);
-                    acc = T == ALWAYS || u_pair < T;
-                    my_att += 1;
-                    my_acc += acc ? 1u : 0u;
-                }
-                const bool acc_pv = (__shfl_up((int)acc, 1) != 0) && lane > 0;
-                const int st_pv = __shfl_up(my_st, 1), e_pv = __shfl_up(e, 1);
-                if (acc) {
-                    my_st = st_nx;
-                    e = e_nx;
-                } else if (acc_pv) {
-                    my_st = st_pv;
-                    e = e_pv;
-                }
-                if ((acc || acc_pv) && lane < G) {
-                    c.stor_of[lane] = my_st;
-                    c.slot_of[my_st] = lane;
-                }
-                // (3) pairs across a workgroup boundary: the partner's words, the
-                // decision (both sides draw the same uniform), and a state copy
-                if (down || up) {
-                    int timeout = 0;
-                    for (int side = 0; side < 2 && !timeout; ++side) {
-                        if (!(side == 0 ? down : up)) continue;
-                        const int pw = side == 0 ? it.w - 1 : it.w + 1;
-                        const unsigned long long *in =
-                            it.xbuf + ((size_t)(pw * 2 + (side == 0 ? 1 : 0)) * 2 + buf) * it.xwords;
-                        uint32_t *stage = c.xstage + side * (nw + 1);
-                        uint32_t polls = 0;
-                        for (;;) {
-                            bool ok = true;
-                            unsigned long long bad = 0;
-                            for (int wd = lane; wd <= nw; wd += 64) {
-                                unsigned long long v = __hip_atomic_load(in + wd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                if ((uint32_t)(v >> 32) == cyc) {
-                                    stage[wd] = (uint32_t)v;
-                                } else {
-                                    ok = false;
-                                    bad = v;
-                                }
-                            }
-                            if (__all(ok)) break;
-                            __builtin_amdgcn_s_sleep(1);
-                            if (++polls > a.spin_limit) {
-                                timeout = 1;
-                                if (!ok && atomicCAS(a.err, 0, 1) == 0) {
-                                    a.err[1] = item;
-                                    a.err[2] = it.w;
-                                    a.err[3] = side;
-                                    a.err[4] = (int)cyc;
-                                    a.err[5] = (int)(bad & 0xFFFFFFFFu);
-                                    a.err[6] = (int)(bad >> 32);
-                                    a.err[7] = (int)I.epoch;
-                                }
-                                break;
-                            }
-                        }
-                    }
-                    timeout = __shfl(timeout, 0);
-                    if (timeout) {
-                        if (lane == 0) c.misc[0] = 1;
-                    } else {
-                        for (int side = 0; side < 2; ++side) {
-                            if (!(side == 0 ? down : up)) continue;
-                            const uint32_t *stage = c.xstage + side * (nw + 1);
-                            const int pE = (int)stage[nw];
-                            const int bl = side == 0 ? 0 : G - 1;            // my boundary slot
-                            const int st = __shfl(my_st, bl);
-                            const int myE = __shfl(e, bl);
-                            const int dE = side == 0 ? myE - pE : pE - myE; // E_{r+1} - E_r
-                            const int off = side == 0 ? dn_off : __shfl(row_off, G - 1);
-                            const int len = side == 0 ? dn_len : __shfl(row_len, G - 1);
-                            const uint32_t T = dE >= 0 ? ALWAYS : (-dE <= len ? c.tsw[off - dE - 1] : 0u);
-                            const uint32_t u = side == 0 ? u_dn : __shfl(u_pair, G - 1);
-                            const bool sacc = (T == ALWAYS || u < T);
-                            if (side == 1 && lane == G - 1) {   // the lower workgroup owns the pair's counters
-                                my_att += 1;
-                                my_acc += sacc ? 1u : 0u;
-                            }
-                            if (sacc) {
-                                int8_t *stor = c.sp + st * SB;
-                                for (int i0 = 0; i0 < n; i0 += 512) {
-                                    uint32_t wd[8];
-#pragma unroll
-                                    for (int j = 0; j < 8; ++j) {   // all stage reads first
-                                        const int i = i0 + 64 * j + lane;
-                                        wd[j] = stage[(i < n ? i : n - 1) >> 5];
-                                    }
-#pragma unroll
-                                    for (int j = 0; j < 8; ++j) {
-                                        const int i = i0 + 64 * j + lane;
-                                        if (i < n) stor[SweepCall<Sw>::lidx(sw, i)] = ((wd[j] >> (i & 31)) & 1u) ? 1 : -1;
-                                    }
-                                }
-                                if (lane == bl) {
-                                    e = pE;
-                                    c.Elds[st] = pE;
-                                }
-                            }
-                        }
-                    }
-                }
-            }
-            if (cyc_end && bs <= 64) {   // a one-wave workgroup draws the next uniforms itself
-                const uint32_t nx = cyc + 1;
-                c.usw[(nx & 1) * 65 + lane] = philox_word0((uint32_t)(s0 + lane), nx, TAG_SWAP, P.k0, P.k1);
-                if (lane == 0 && has_down) c.usw[(nx & 1) * 65 + 64] = philox_word0((uint32_t)(s0 - 1), nx, TAG_SWAP, P.k0, P.k1);
-            }
-            // ---- best energy and first hit, after every stage of this sweep ----
-            // key e*64 + lane orders by energy, then by slot (|E| < 2^24)
-            const int key = wave_min(lane < G ? e * 64 + lane : 0x7FFFFFFF);
-            const int em = key >> 6, lm = key & 63;
-            if (P.has_target && hit < 0 && em <= P.target) hit = (int64_t)t;
-            if (em < bestE) {
-                bestE = em;
-                bestT = (int64_t)t;
-                bestSlot = s0 + lm;
-                const int st = __shfl(my_st, lm);
-                for (int i = lane; i < n; i += 64) it.best_spins[i] = c.sp[st * SB + SweepCall<Sw>::lidx(sw, i)];
-            }
-        }
-        __syncthreads();
-        if (cyc_end && (has_down || has_up)) failed = c.misc[0] != 0;
-    }
-    if (tid < 64 && lane < G) {
-        c.satt[lane] = my_att;
-        c.sacc[lane] = my_acc;
-    }
-    __syncthreads();
-
-    // write the state back by slot
-    for (int x = tid; x < G * n; x += bs) {
-        int l = x / n, i = x - l * n;
-        I.spins[(size_t)(s0 + l) * n + i] = c.sp[c.stor_of[l] * SB + SweepCall<Sw>::lidx(sw, i)];
-    }
-    for (int l = tid; l < G; l += bs) {
-        I.E[s0 + l] = c.Elds[c.stor_of[l]];
-        I.flips[s0 + l] += c.flips[l];
-        if (s0 + l + 1 < P.R) {
-            I.swap_att[s0 + l] += c.satt[l];
-            I.swap_acc[s0 + l] += c.sacc[l];
-        }
-    }
-    if (tid == 0) {
-        BestRec b;
-        b.E = bestT >= 0 ? bestE : 0x7FFFFFFF;
-        b.slot = bestSlot;
-        b.t = bestT;
-        b.first_hit = (hit0 < 0) ? hit : -1;
-        b.pad = 0;
-        *it.best = b;
-    }
+    chunk_body<Sw>(a, item);
 }
+
 
 // Merge the per-workgroup best records of one instance into its canonical
 // record, and advance its sweep counter. One workgroup per instance.
-__global__ void finish_kernel(const WorkItem *items, const int *first_item, int n_inst, uint32_t K)
+__global__ void finish_kernel(const WorkItem *items, const int *first_item, int n_inst, uint32_t K,
+                              InstStatus *status)
 {
     int inst = blockIdx.x;
     if (inst >= n_inst) return;
@@ -819,6 +65,15 @@ __global__ void finish_kernel(const WorkItem *items, const int *first_item, int 
         uint64_t t0 = *I.t;
         uint64_t t1 = t0 + K < I.sweep_cap ? t0 + K : I.sweep_cap;
         if (t0 < t1) *I.t = t1;
+        if (status) {
+            InstStatus st;
+            st.t = (int64_t)(t0 < t1 ? t1 : t0);
+            st.best_t = cb.t;
+            st.first_hit = cb.first_hit;
+            st.best_E = cb.E;
+            st.best_slot = cb.slot;
+            status[inst] = st;
+        }
     }
     __syncthreads();
     if (win >= 0)
@@ -831,7 +86,6 @@ __global__ void finish_kernel(const WorkItem *items, const int *first_item, int 
 template <class Sw>
 __global__ void __launch_bounds__(Sw::MAXT) plain_sweep_kernel(const InstDev *Ip, uint32_t t)
 {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
     const InstDev &I = *Ip;
     const int r = blockIdx.x, n = I.n, tid = threadIdx.x, bs = blockDim.x;
     Sw sw;
@@ -1050,8 +304,6 @@ __global__ void init_best_kernel(const InstDev *Ip)
 // ---------------------------------------------------------------------------
 // Host-side launchers (C++ linkage, used by the runtime in host.cpp).
 
-#define TAPT_LATTICE_LIST(X) X(4) X(6) X(8) X(10) X(12) X(14) X(16)
-
 bool lattice_supported(int L) { return L >= 4 && L <= 16 && L % 2 == 0; }
 
 int lattice_max_threads() { return 512; }
@@ -1116,11 +368,13 @@ hipError_t chunk_occupancy(int kind, int L, int rpt, int block, size_t lds, int 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_finish(const WorkItem *items, const int *first_item, int n_inst, uint32_t K, hipStream_t s)
+hipError_t launch_finish(const WorkItem *items, const int *first_item, int n_inst, uint32_t K, InstStatus *status,
+                         hipStream_t s)
 {
-    hipLaunchKernelGGL(finish_kernel, dim3(n_inst), dim3(256), 0, s, items, first_item, n_inst, K);
+    hipLaunchKernelGGL(finish_kernel, dim3(n_inst), dim3(256), 0, s, items, first_item, n_inst, K, status);
     return hipGetLastError();
 }
+
 
 template <class Sw>
 static hipError_t launch_plain_sweep_t(const InstDev *dI, int R, int block, size_t lds, uint32_t t, hipStream_t s)

@@ -75,7 +75,15 @@ struct WorkItem {              // one workgroup of a persistent chunk launch
     int8_t *best_spins;        // [n]
     unsigned long long *xbuf;  // instance exchange area: [W][2 sides][2 buffers][xwords]
     int32_t xwords;            // 64-bit words per buffer: ceil(n/32) spin words + energy, padded
-    int32_t pad;
+    int32_t variant;           // sweeper of the item in a mixed launch (chunk_kernel_mixed)
+};
+
+struct InstStatus {            // per-instance progress written after every chunk
+    int64_t t;                 // completed sweeps
+    int64_t best_t;
+    int64_t first_hit;
+    int32_t best_E;
+    int32_t best_slot;
 };
 
 struct ChunkArgs {

@@ -211,3 +211,30 @@ def test_many_instances_split_ladders(G, rpt):
         ref = oracle.Run(g, betas, seed=3000 + i, banks=banks, **kw)
         ref.run(120)
         compare(ctx, ref)
+
+
+def test_mixed_sizes_one_launch():
+    """Lattices L = 6..16 with ladders of 24..48 slots and a multiplier, all in
+    one launch of the mixed kernel; every instance checked against the oracle."""
+    announce("mixed sizes L=6,8,10,12,16 (R=24..48) + 5-bit multiplier, one mixed launch, 60 sweeps")
+    sizes = [(6, 24), (8, 30), (10, 36), (12, 42), (16, 48)]
+    cases = []
+    for k, (L, R) in enumerate(sizes):
+        g = inputs.ea_lattice(L, 3000 + k)
+        banks = {r: inputs.random_bank(g["n"], 3, seed=8000 + 64 * k + r) for r in range(0, R - 2, 5)}
+        cases.append((g, inputs.geometric_ladder(R), banks, dict(prop_start=20, prop_period=20), 3000 + k))
+    m = inputs.multiplier(5, 17 * 29)
+    cases.append((m, inputs.geometric_ladder(16), None, {}, 99))
+    ctxs = []
+    for g, b, banks, kw, seed in cases:
+        ctx = binding.Context(g, b, seed=seed, **kw)
+        for r, bank in (banks or {}).items():
+            ctx.propose(r, bank)
+        ctxs.append(ctx)
+    bt = binding.Batch(ctxs, chunk_sweeps=25)
+    bt.sweep(60)
+    import oracle
+    for ctx, (g, b, banks, kw, seed) in zip(ctxs, cases):
+        ref = oracle.Run(g, b, seed=seed, banks=banks, **kw)
+        ref.run(60)
+        compare(ctx, ref)
