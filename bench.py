@@ -53,6 +53,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=1500)
     ap.add_argument("--calib-copy", action="store_true", help="also run a 256 MiB device copy (PMC scaling)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rates", default="10,30,100,300,1000", help="Poisson arrival rates, req/s")
+    ap.add_argument("--serve-requests", default="30,60,150,300,500", help="requests per rate")
+    ap.add_argument("--serve-cap", type=int, default=20_000, help="sweep cap per request")
+    ap.add_argument("--serve-chunk", type=int, default=250, help="sweeps per serving round")
     ap.add_argument("--bank-cache", default=None,
                     help="file to save the generated banks to, or load them from when it exists")
     return ap.parse_args()
@@ -103,41 +108,15 @@ def build_contexts(probs, betas, bank, seeds):
     return ctxs
 
 
-def scan_tilings(probs, betas, bank, L, R, log):
-    """Time a short run of each candidate tiling on scratch contexts. Results
-    are bit-identical for every tiling, so only speed is compared."""
-    from paper_2509_23043_amd import binding
-    import torch
-    nc = L ** 3 // 8
-    cands = []
-    for G in (32, 16, 8, 4, 2):
-        for rpt in (4, 2, 1):
-            if G < rpt or G > R:
-                continue
-            if ((G + rpt - 1) // rpt) * nc > 512:
-                continue
-            cands.append((G, rpt))
-    ctxs = build_contexts(probs, betas, bank, [7 + i for i in range(len(probs))])
-    res = []
-    for G, rpt in cands:
-        try:
-            bt = binding.Batch(ctxs, replicas_per_wg=G, replicas_per_thread=rpt, chunk_sweeps=500)
-        except binding.TaptError as e:
-            log(f"tiling G={G} rpt={rpt}: {e}")
-            continue
-        bt.sweep(500)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        bt.sweep(1500)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        rate = 1500 * len(probs) * R * L ** 3 / dt / 1e9
-        res.append((rate, G, rpt))
-        log(f"tiling G={G:2d} rpt={rpt}: {rate:8.1f} attempts/ns")
-        bt.close()
-    for c in ctxs:
-        c.close()
-    res.sort(reverse=True)
+def tune_tiling(probs, betas, bank, log):
+    """The autotuner's choice of tiling on scratch contexts of the same batch
+    (M stays 1: the workload fixes one sweep per swap stage)."""
+    from paper_2509_23043_amd import autotune
+
+    def make(M):
+        return build_contexts(probs, betas, bank, [7 + i for i in range(len(probs))])
+
+    res = autotune.tune(make, Ms=(1,), warm=300, timed=1500, log=log)
     return res
 
 
@@ -173,6 +152,14 @@ def cpu_baseline(bank_host, L, R, sweeps, log):
                        f"with proposals every 100 sweeps, banks as on the GPU")
 
 
+def kernel_source_hash():
+    """Hash of the sources of the chunk kernel (body and specialisations)."""
+    h = hashlib.sha256()
+    for f in ("sweep.h", "kernels.hip", "tapt_dev.h"):
+        h.update(open(os.path.join(ROOT, "paper_2509_23043_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def traffic_from_profiles(launch_sweeps, kern_hash):
     path = os.path.join(ROOT, "profiles", "traffic_chunk_kernel_ea_l8_r32_x64.json")
     try:
@@ -182,6 +169,146 @@ def traffic_from_profiles(launch_sweeps, kern_hash):
     if d.get("kernel_source_sha256") != kern_hash or d.get("sweeps_per_launch") != launch_sweeps:
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def serving_pool(log):
+    """Problems of the mixed serving workload, each a registered context with
+    proposal banks and a residual-energy target.
+
+    Spin glasses: 3D EA +-J, L in {6, 8, 10, 12, 16}, 8 instances per size,
+    ladders of 24/30/36/42/48 slots (beta 0.2..3.0 geometric), proposals every
+    50 sweeps on all but the two coldest slots. Factorization: m x m-bit
+    multipliers, m = 8..12, 4 semiprimes per size, 32 slots, proposals on the
+    23 hottest. Banks: 64 configurations per slot from a plain-PT run of the
+    instance (10^4 burn-in sweeps, then one sample every 100 sweeps). The EA
+    target is the lowest energy of that run plus 1% of N rounded up to the
+    energy grid (multiples of 4); the factorization target is the ground
+    energy -3m^2 - 4m(m-1), reached exactly by the factor pairs."""
+    import torch
+    from paper_2509_23043_amd import binding, inputs
+    B, burn, every = 64, 10_000, 100
+    specs = []
+    for L, R in ((6, 24), (8, 30), (10, 36), (12, 42), (16, 48)):
+        for i in range(8):
+            specs.append(dict(kind="ea", size=L, g=inputs.ea_lattice(L, 5100 + 10 * L + i),
+                              betas=inputs.geometric_ladder(R), slots=R - 2, period=50))
+    for m in range(8, 13):
+        for i, (C, _p, _q) in enumerate(inputs.semiprimes(m, 4, seed=5200 + m)):
+            specs.append(dict(kind="fact", size=m, g=inputs.multiplier(m, C),
+                              betas=inputs.geometric_ladder(32), slots=round(13 * 32 / 18), period=50,
+                              target=-3 * m * m - 4 * m * (m - 1)))
+    # plain-PT bank runs, one batch per shape (each fits the co-resident limit)
+    t0 = time.perf_counter()
+    groups = {}
+    for k, sp in enumerate(specs):
+        groups.setdefault((sp["kind"], sp["size"]), []).append(k)
+    for key, idx in groups.items():
+        gens = [binding.Context(specs[k]["g"], specs[k]["betas"], seed=2_000_000 + k) for k in idx]
+        bt = binding.Batch(gens, chunk_sweeps=2000)
+        bt.sweep(burn)
+        banks = [torch.empty((specs[k]["slots"], B, specs[k]["g"]["n"]), dtype=torch.int8, device="cuda")
+                 for k in idx]
+        tmp = [torch.empty((len(specs[k]["betas"]), specs[k]["g"]["n"]), dtype=torch.int8, device="cuda")
+               for k in idx]
+        for j in range(B):
+            bt.sweep(every)
+            for q, g in enumerate(gens):
+                g.state_device(tmp[q].data_ptr())
+                banks[q][:, j, :] = tmp[q][:specs[idx[q]]["slots"]]
+        torch.cuda.synchronize()
+        for q, k in enumerate(idx):
+            sp = specs[k]
+            sp["bank"] = banks[q]
+            if sp["kind"] == "ea":
+                n = sp["g"]["n"]
+                slack = -(-((n + 99) // 100) // 4) * 4
+                sp["target"] = int(gens[q].summary()["best"]) + slack
+        bt.close()
+        for g in gens:
+            g.close()
+    log(f"serving pool: {len(specs)} problems, banks in {time.perf_counter() - t0:.1f} s")
+    ctxs = []
+    for sp in specs:
+        c = binding.Context(sp["g"], sp["betas"], seed=0, prop_start=sp["period"], prop_period=sp["period"])
+        for r in range(sp["slots"]):
+            c.propose_device(r, sp["bank"][r].data_ptr(), B)
+        ctxs.append(c)
+    return specs, ctxs
+
+
+def serving_leg(args, log):
+    """Poisson arrivals of mixed requests (70% spin glass with L uniform over
+    the five sizes, 30% factorization with m uniform over 8..12) into the
+    continuous-batching server; time-to-target per request = completion seen
+    by the host minus arrival."""
+    from paper_2509_23043_amd import binding
+    specs, ctxs = serving_pool(log)
+    ea = {}
+    fa = {}
+    for k, sp in enumerate(specs):
+        (ea if sp["kind"] == "ea" else fa).setdefault(sp["size"], []).append(k)
+    rates = [float(x) for x in args.serve_rates.split(",")]
+    counts = [int(x) for x in args.serve_requests.split(",")]
+    out = []
+    srv = binding.Server(chunk_sweeps=args.serve_chunk, mem_budget=8 << 30)
+    pids = [srv.register(c) for c in ctxs]
+    seed_base = 5000
+    for lam, nreq in zip(rates, counts):
+        rng = np.random.Generator(np.random.PCG64(5000 + int(lam)))
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=nreq))
+        picks = []
+        for _ in range(nreq):
+            if rng.random() < 0.7:
+                size = sorted(ea)[rng.integers(len(ea))]
+                picks.append(ea[size][rng.integers(len(ea[size]))])
+            else:
+                size = sorted(fa)[rng.integers(len(fa))]
+                picks.append(fa[size][rng.integers(len(fa[size]))])
+        st0 = srv.stats()
+        t_start = srv.clock()
+        results = []
+        i = 0
+        while len(results) < nreq:
+            now = srv.clock() - t_start
+            while i < nreq and arrivals[i] <= now:
+                k = picks[i]
+                srv.submit(pids[k], seed_base + i, args.serve_cap, target=specs[k]["target"],
+                           want_best=False, user_tag=k)
+                i += 1
+            wait = 1 if i < nreq else 50
+            if i < nreq:
+                wait = max(0, min(50, int((arrivals[i] - (srv.clock() - t_start)) * 1000)))
+            results += srv.poll(256, wait_ms=wait)
+        seed_base += nreq
+        st1 = srv.stats()
+        wall = max(r["t_done"] for r in results) - t_start
+        ok = [r for r in results if r["status"] == 0]
+        hits = [r for r in ok if r["hit"]]
+        tt = np.array([r["t_done"] - r["t_submit"] for r in hits]) if hits else np.array([np.nan])
+        by_kind = {}
+        for kind in ("ea", "fact"):
+            h = [r["t_done"] - r["t_submit"] for r in hits if specs[r["user_tag"]]["kind"] == kind]
+            by_kind[kind] = dict(n=len(h), p50_s=round(float(np.percentile(h, 50)), 4) if h else None,
+                                 p99_s=round(float(np.percentile(h, 99)), 4) if h else None)
+        d = dict(rate_req_per_s=lam, requests=nreq, completed=len(ok), rejected=nreq - len(ok),
+                 hit_frac=round(len(hits) / max(len(ok), 1), 4), cap_frac=round(1 - len(hits) / max(len(ok), 1), 4),
+                 p50_time_to_target_s=round(float(np.percentile(tt, 50)), 4),
+                 p99_time_to_target_s=round(float(np.percentile(tt, 99)), 4),
+                 completed_req_per_s=round(len(ok) / wall, 2),
+                 attempts_per_ns=round((st1["attempts"] - st0["attempts"]) / (wall * 1e9), 2),
+                 peak_active=st1["peak_active"], by_kind=by_kind)
+        log(f"serving lambda={lam:g}: p50 {d['p50_time_to_target_s']} s, p99 {d['p99_time_to_target_s']} s, "
+            f"{d['completed_req_per_s']} req/s, hit {d['hit_frac']}, {d['attempts_per_ns']} attempts/ns, "
+            f"peak active {d['peak_active']}")
+        out.append(d)
+    srv.stop()
+    for c in ctxs:
+        c.close()
+    return dict(rates=out, sweep_cap=args.serve_cap, chunk_sweeps=args.serve_chunk,
+                pool="40 EA +-J (L=6..16, 8 each, R=24..48) + 20 multipliers (m=8..12, 4 each, R=32); "
+                     "banks 64/slot from plain-PT runs; EA target = run's best + 1% N; factorization target = "
+                     "ground energy",
+                mix="70% EA (L uniform), 30% factorization (m uniform)")
 
 
 def main():
@@ -214,8 +341,9 @@ def main():
             torch.save(bank.cpu(), args.bank_cache)
 
     if args.tiling == "auto":
-        scan = scan_tilings(probs, betas, bank, L, R, log)
-        _, G, rpt = scan[0]
+        tuned = tune_tiling(probs, betas, bank, log)
+        G, rpt = tuned["replicas_per_wg"], tuned["replicas_per_thread"]
+        scan = tuned["scan"]
     else:
         G, rpt = (int(x) for x in args.tiling.split(","))
         scan = []
@@ -273,8 +401,7 @@ def main():
     avg_ms = kern_ms / max(launches, 1)
     att_launch = attempts / max(launches, 1)
     achieved = OPS_PER_ATTEMPT * att_launch / (avg_ms * 1e-3) / 1e12
-    kern_src = open(os.path.join(ROOT, "paper_2509_23043_amd", "csrc", "kernels.hip"), "rb").read()
-    kern_hash = hashlib.sha256(kern_src).hexdigest()
+    kern_hash = kernel_source_hash()
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TOP/s",
                 frac=round(achieved / VALU_PEAK_TOPS, 4), traffic=traffic_from_profiles(S, kern_hash),
                 kernel="chunk_kernel<LatSweep<8,*>>", avg_launch_ms=round(avg_ms, 4), launches=launches,
@@ -283,6 +410,13 @@ def main():
                          achieved_TBps=round(LDS_BYTES_PER_ATTEMPT * att_launch / (avg_ms * 1e-3) / 1e12, 3),
                          peak_TBps=round(LDS_PEAK_TBS, 1),
                          frac=round(LDS_BYTES_PER_ATTEMPT * att_launch / (avg_ms * 1e-3) / 1e12 / LDS_PEAK_TBS, 4)))
+
+    serving = None
+    if not args.no_serve:
+        for c in ctxs:
+            c.close()
+        bt.close()
+        serving = serving_leg(args, log)
 
     cpu = None
     if not args.no_cpu:
@@ -298,7 +432,9 @@ def main():
                            instances=NI, L=L, replicas=R, sweeps_per_step=S, bank=args.bank,
                            tiling=dict(replicas_per_wg=G, replicas_per_thread=rpt)),
                plain=plain, roofline=roof, cpu_baseline=cpu,
-               tiling_scan=[dict(G=g, rpt=r, attempts_per_ns=round(v, 1)) for v, g, r in scan])
+               tiling_scan=[dict(G=d["replicas_per_wg"], rpt=d["replicas_per_thread"],
+                                 attempts_per_ns=d["attempts_per_ns"]) for d in scan],
+               serving=serving)
     print(json.dumps(out), flush=True)
 
 

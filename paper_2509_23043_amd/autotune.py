@@ -1,0 +1,132 @@
+"""Autotuner of the batched path.
+
+Picks the tiling of a batch and, where the caller allows it, the sweeps per
+swap stage M. The tiling is the number of beta slots each workgroup holds
+(which fixes the workgroups per ladder) and the slots each thread sweeps. The
+tuner times short runs of every feasible candidate on scratch contexts and
+caches the winner as JSON, keyed by the batch's shape and the GPU
+architecture.
+
+Every tiling realises the same chain bit for bit, because random numbers are
+keyed by site, sweep, slot and seed and never by thread or workgroup. So the
+tiling is chosen on speed alone. M is different: it changes the Markov chain
+(Algorithm 1 runs M sweeps between swap stages). A tuned M is therefore
+returned to the caller, who must run every path that is compared with the
+batch (the oracle, the plain path) with the same M.
+
+Timing uses the chunk-kernel HIP events of the batch (pt_batch_kernel_time)
+and is argument marshalling plus arithmetic on the host only.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+from . import binding
+
+G_CANDIDATES = (1, 2, 4, 8, 16, 32, 64)
+RPT_CANDIDATES = (1, 2, 4)
+
+
+def arch():
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def batch_key(contexts, extra=""):
+    """Cache key: the multiset of (kind, L or n, R) of the batch plus arch."""
+    shapes = {}
+    for c in contexts:
+        k = (c.kind, c.L if c.kind == "lattice" else c.n, c.R)
+        shapes[k] = shapes.get(k, 0) + 1
+    parts = [f"{kind}:{size}:R{R}x{cnt}" for (kind, size, R), cnt in sorted(shapes.items())]
+    return f"{arch()}|" + ",".join(parts) + (f"|{extra}" if extra else "")
+
+
+def candidates(contexts):
+    """(replicas_per_wg, replicas_per_thread) pairs worth timing: every cap on
+    the slots per workgroup up to the longest ladder, with 1, 2 or 4 slots
+    per thread (the runtime lowers the cap per context until it fits)."""
+    rmax = max(c.R for c in contexts)
+    out = []
+    for G in G_CANDIDATES:
+        if G > 2 * rmax:
+            continue
+        for rpt in RPT_CANDIDATES:
+            if rpt <= G:
+                out.append((G, rpt))
+    return out
+
+
+def _attempts_per_sweep(contexts):
+    return sum(c.R * c.nfree for c in contexts)
+
+
+def time_tiling(contexts, G, rpt, warm=200, timed=600, chunk=None):
+    """attempts/ns of the chunk kernel for one tiling, or None if infeasible."""
+    try:
+        bt = binding.Batch(contexts, replicas_per_wg=G, replicas_per_thread=rpt,
+                           chunk_sweeps=chunk or timed)
+    except binding.TaptError:
+        return None
+    try:
+        bt.sweep(warm)
+        bt.kernel_time()
+        bt.sweep(timed)
+        ms, launches = bt.kernel_time()
+    finally:
+        bt.close()
+    if launches == 0 or ms <= 0:
+        return None
+    return _attempts_per_sweep(contexts) * timed / (ms * 1e6)
+
+
+def tune(make_contexts, Ms=(1,), cache=None, key_extra="", warm=200, timed=600, log=None):
+    """Choose (M, replicas_per_wg, replicas_per_thread) for a batch.
+
+    make_contexts(M) returns fresh scratch binding.Context objects of the
+    batch's shape with M sweeps per cycle (they are run and discarded).
+    cache: JSON file path or None. Returns a dict with the choice, its rate
+    and the timed scan.
+    """
+    Ms = tuple(int(m) for m in Ms)
+    probe = make_contexts(Ms[0])
+    key = batch_key(probe, f"M{'/'.join(map(str, Ms))}" + (f"|{key_extra}" if key_extra else ""))
+    table = {}
+    if cache and os.path.exists(cache):
+        try:
+            table = json.load(open(cache))
+        except ValueError:
+            table = {}
+        if key in table:
+            for c in probe:
+                c.close()
+            return dict(table[key], cached=True, key=key)
+    scan = []
+    for i, M in enumerate(Ms):
+        ctxs = probe if i == 0 else make_contexts(M)
+        for G, rpt in candidates(ctxs):
+            t0 = time.perf_counter()
+            rate = time_tiling(ctxs, G, rpt, warm, timed)
+            if log:
+                log(f"autotune M={M} G={G} rpt={rpt}: "
+                    f"{'infeasible' if rate is None else f'{rate:.1f} attempts/ns'} ({time.perf_counter() - t0:.2f} s)")
+            if rate is not None:
+                scan.append(dict(M=M, replicas_per_wg=G, replicas_per_thread=rpt, attempts_per_ns=round(rate, 2)))
+        for c in ctxs:
+            c.close()
+    if not scan:
+        raise binding.TaptError(binding.PT_EUNSUPPORTED, "no feasible tiling for this batch")
+    best = max(scan, key=lambda d: d["attempts_per_ns"])
+    res = dict(M=best["M"], replicas_per_wg=best["replicas_per_wg"],
+               replicas_per_thread=best["replicas_per_thread"], attempts_per_ns=best["attempts_per_ns"],
+               scan=scan)
+    if cache:
+        table[key] = res
+        tmp = cache + ".tmp"
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return dict(res, cached=False, key=key)

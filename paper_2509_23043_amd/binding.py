@@ -146,6 +146,8 @@ class Context:
         n = int(problem["n"])
         self.n = n
         self.R = len(betas)
+        self.nfree = int(n - np.count_nonzero(np.asarray(problem.get("clamp", np.zeros(n)))))
+        self.M = int(M)
         self.betas = np.ascontiguousarray(betas, np.float64)
         self._keep = []
 
@@ -156,8 +158,11 @@ class Context:
 
         g = _Graph()
         g.n = n
+        self.kind, self.L = "csr", 0
         if problem.get("lattice_L") and not np.any(problem.get("h", 0)) and not np.any(problem.get("clamp", 0)):
             g.lattice_L = int(problem["lattice_L"])
+            self.kind = "lattice" if g.lattice_L <= 16 else "csr"
+            self.L = g.lattice_L
             g.J = _p(keep(np.asarray(problem["J3"]).reshape(-1), np.int32), C.c_int32)
             g.nnz = 0
         else:

@@ -1,0 +1,54 @@
+"""Host logic of the autotuner: candidate set, cache key, cache round trip
+(timing replaced by a stub, no GPU)."""
+import json
+import types
+
+from paper_2509_23043_amd import autotune
+
+
+def _ctx(kind, L, n, R):
+    return types.SimpleNamespace(kind=kind, L=L, n=n, R=R, nfree=n, close=lambda: None)
+
+
+def test_candidates_cover_caps_and_threads():
+    c = autotune.candidates([_ctx("lattice", 8, 512, 32)])
+    assert (8, 1) in c and (32, 4) in c and (64, 2) in c
+    assert all(rpt <= G for G, rpt in c)
+    c2 = autotune.candidates([_ctx("lattice", 4, 64, 3)])
+    assert max(G for G, _ in c2) <= 6
+
+
+def test_batch_key_is_a_multiset(monkeypatch):
+    monkeypatch.setattr(autotune, "arch", lambda: "gfx950")
+    a = [_ctx("lattice", 8, 512, 32), _ctx("csr", 0, 200, 32), _ctx("lattice", 8, 512, 32)]
+    b = [a[1], a[0], a[2]]
+    assert autotune.batch_key(a) == autotune.batch_key(b)
+    assert "lattice:8:R32x2" in autotune.batch_key(a)
+    assert autotune.batch_key(a) != autotune.batch_key(a[:2])
+
+
+def test_tune_picks_fastest_and_caches(monkeypatch, tmp_path):
+    monkeypatch.setattr(autotune, "arch", lambda: "gfx950")
+    rates = {(1, 8, 1): 100.0, (2, 8, 1): 150.0, (1, 16, 2): 120.0}
+    calls = []
+
+    def fake_time(ctxs, G, rpt, warm, timed):
+        M = ctxs[0].M
+        calls.append((M, G, rpt))
+        return rates.get((M, G, rpt))
+
+    monkeypatch.setattr(autotune, "time_tiling", fake_time)
+
+    def make(M):
+        c = _ctx("lattice", 8, 512, 32)
+        c.M = M
+        return [c]
+
+    cache = str(tmp_path / "tune.json")
+    r = autotune.tune(make, Ms=(1, 2), cache=cache)
+    assert (r["M"], r["replicas_per_wg"], r["replicas_per_thread"]) == (2, 8, 1)
+    assert not r["cached"] and len(r["scan"]) == 3
+    n_calls = len(calls)
+    r2 = autotune.tune(make, Ms=(1, 2), cache=cache)
+    assert r2["cached"] and r2["M"] == 2 and len(calls) == n_calls
+    assert r["key"] in json.load(open(cache))
