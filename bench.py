@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--L", type=int, default=8)
     ap.add_argument("--R", type=int, default=32)
     ap.add_argument("--bank", type=int, default=256)
-    ap.add_argument("--tiling", default="auto", help="'auto' or G,rpt (slots per workgroup, per thread)")
+    ap.add_argument("--tiling", default="auto", help="'auto' or G,rpt[,kernel] (slots per workgroup, per thread; "
+                                                     "kernel auto|block|wave)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=1500)
@@ -342,16 +343,18 @@ def main():
 
     if args.tiling == "auto":
         tuned = tune_tiling(probs, betas, bank, log)
-        G, rpt = tuned["replicas_per_wg"], tuned["replicas_per_thread"]
+        G, rpt, kern = tuned["replicas_per_wg"], tuned["replicas_per_thread"], tuned["kernel"]
         scan = tuned["scan"]
     else:
-        G, rpt = (int(x) for x in args.tiling.split(","))
+        parts = args.tiling.split(",")
+        G, rpt = int(parts[0]), int(parts[1])
+        kern = parts[2] if len(parts) > 2 else "auto"
         scan = []
-    log(f"tiling: {G} slots per workgroup, {rpt} per thread")
+    log(f"tiling: {G} slots per workgroup, {rpt} per thread, kernel {kern}")
 
     seeds = [3000 + i for i in range(NI)]
     ctxs = build_contexts(probs, betas, bank, seeds)
-    bt = binding.Batch(ctxs, replicas_per_wg=G, replicas_per_thread=rpt, chunk_sweeps=S)
+    bt = binding.Batch(ctxs, replicas_per_wg=G, replicas_per_thread=rpt, chunk_sweeps=S, kernel=kern)
     for _ in range(args.warmup):
         bt.sweep(S)
     torch.cuda.synchronize()
@@ -430,9 +433,9 @@ def main():
                                     "geometric, Metropolis, M=1, proposals every 100 sweeps from 256-entry "
                                     "plain-PT banks on 30 slots; 10^4 sweeps per step",
                            instances=NI, L=L, replicas=R, sweeps_per_step=S, bank=args.bank,
-                           tiling=dict(replicas_per_wg=G, replicas_per_thread=rpt)),
+                           tiling=dict(replicas_per_wg=G, replicas_per_thread=rpt, kernel=kern)),
                plain=plain, roofline=roof, cpu_baseline=cpu,
-               tiling_scan=[dict(G=d["replicas_per_wg"], rpt=d["replicas_per_thread"],
+               tiling_scan=[dict(G=d["replicas_per_wg"], rpt=d["replicas_per_thread"], kernel=d["kernel"],
                                  attempts_per_ns=d["attempts_per_ns"]) for d in scan],
                serving=serving)
     print(json.dumps(out), flush=True)

@@ -45,17 +45,22 @@ def batch_key(contexts, extra=""):
 
 
 def candidates(contexts):
-    """(replicas_per_wg, replicas_per_thread) pairs worth timing: every cap on
-    the slots per workgroup up to the longest ladder, with 1, 2 or 4 slots
-    per thread (the runtime lowers the cap per context until it fits)."""
+    """(replicas_per_wg, replicas_per_thread, kernel) triples worth timing:
+    every cap on the slots per workgroup up to the longest ladder, with 1, 2
+    or 4 slots per thread in the workgroup-synchronous kernel (the runtime
+    lowers the cap per context until it fits), and the wave-per-replica kernel
+    where every context is a lattice it supports."""
     rmax = max(c.R for c in contexts)
+    wave_ok = all(c.kind == "lattice" and c.L == 8 for c in contexts)
     out = []
     for G in G_CANDIDATES:
         if G > 2 * rmax:
             continue
         for rpt in RPT_CANDIDATES:
             if rpt <= G:
-                out.append((G, rpt))
+                out.append((G, rpt, "block"))
+        if wave_ok and G <= 8:
+            out.append((G, 1, "wave"))
     return out
 
 
@@ -63,11 +68,11 @@ def _attempts_per_sweep(contexts):
     return sum(c.R * c.nfree for c in contexts)
 
 
-def time_tiling(contexts, G, rpt, warm=200, timed=600, chunk=None):
+def time_tiling(contexts, G, rpt, kernel="auto", warm=200, timed=600, chunk=None):
     """attempts/ns of the chunk kernel for one tiling, or None if infeasible."""
     try:
         bt = binding.Batch(contexts, replicas_per_wg=G, replicas_per_thread=rpt,
-                           chunk_sweeps=chunk or timed)
+                           chunk_sweeps=chunk or timed, kernel=kernel)
     except binding.TaptError:
         return None
     try:
@@ -106,22 +111,23 @@ def tune(make_contexts, Ms=(1,), cache=None, key_extra="", warm=200, timed=600, 
     scan = []
     for i, M in enumerate(Ms):
         ctxs = probe if i == 0 else make_contexts(M)
-        for G, rpt in candidates(ctxs):
+        for G, rpt, kern in candidates(ctxs):
             t0 = time.perf_counter()
-            rate = time_tiling(ctxs, G, rpt, warm, timed)
+            rate = time_tiling(ctxs, G, rpt, kern, warm, timed)
             if log:
-                log(f"autotune M={M} G={G} rpt={rpt}: "
+                log(f"autotune M={M} G={G} rpt={rpt} {kern}: "
                     f"{'infeasible' if rate is None else f'{rate:.1f} attempts/ns'} ({time.perf_counter() - t0:.2f} s)")
             if rate is not None:
-                scan.append(dict(M=M, replicas_per_wg=G, replicas_per_thread=rpt, attempts_per_ns=round(rate, 2)))
+                scan.append(dict(M=M, replicas_per_wg=G, replicas_per_thread=rpt, kernel=kern,
+                                 attempts_per_ns=round(rate, 2)))
         for c in ctxs:
             c.close()
     if not scan:
         raise binding.TaptError(binding.PT_EUNSUPPORTED, "no feasible tiling for this batch")
     best = max(scan, key=lambda d: d["attempts_per_ns"])
     res = dict(M=best["M"], replicas_per_wg=best["replicas_per_wg"],
-               replicas_per_thread=best["replicas_per_thread"], attempts_per_ns=best["attempts_per_ns"],
-               scan=scan)
+               replicas_per_thread=best["replicas_per_thread"], kernel=best["kernel"],
+               attempts_per_ns=best["attempts_per_ns"], scan=scan)
     if cache:
         table[key] = res
         tmp = cache + ".tmp"

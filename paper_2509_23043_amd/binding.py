@@ -42,7 +42,10 @@ class _Summary(C.Structure):
 
 class _BatchOpts(C.Structure):
     _fields_ = [("replicas_per_wg", C.c_int32), ("replicas_per_thread", C.c_int32),
-                ("chunk_sweeps", C.c_int32), ("use_graph", C.c_int32)]
+                ("chunk_sweeps", C.c_int32), ("use_graph", C.c_int32), ("kernel", C.c_int32)]
+
+
+KERNELS = {"auto": 0, "block": 1, "wave": 2}
 
 
 class _ServeOpts(C.Structure):
@@ -254,10 +257,12 @@ class Context:
 class Batch:
     """Many contexts run by persistent chunk launches (pt_batch)."""
 
-    def __init__(self, contexts, replicas_per_wg=0, replicas_per_thread=0, chunk_sweeps=0, use_graph=False):
+    def __init__(self, contexts, replicas_per_wg=0, replicas_per_thread=0, chunk_sweeps=0, use_graph=False,
+                 kernel="auto"):
         self.contexts = list(contexts)
         arr = (C.c_void_p * len(self.contexts))(*[c.h for c in self.contexts])
-        o = _BatchOpts(int(replicas_per_wg), int(replicas_per_thread), int(chunk_sweeps), 1 if use_graph else 0)
+        o = _BatchOpts(int(replicas_per_wg), int(replicas_per_thread), int(chunk_sweeps), 1 if use_graph else 0,
+                       KERNELS[kernel])
         h = C.c_void_p()
         _check(lib().pt_batch_create(arr, len(self.contexts), C.byref(o), C.byref(h)))
         self.h = h

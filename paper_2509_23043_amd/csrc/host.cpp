@@ -40,6 +40,11 @@ int mixed_max_threads();
 int mixed_variant_of(int kind, int L, int rpt);
 hipError_t launch_chunk_mixed(const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t chunk_occupancy_mixed(int block, size_t lds, int *blocks_per_cu);
+bool wave_supported(int L);
+int wave_max_storages();
+size_t wave_lds_bytes(int n, int G, int stride, int tsw_entries);
+hipError_t launch_wave(int L, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
+hipError_t wave_occupancy(int L, int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_plain(int kind, int L, const InstDev *dI, int R, int n, int stride, uint32_t t, hipStream_t s);
 hipError_t launch_init(const InstDev *dI, int R, int n, hipStream_t s);
 hipError_t launch_energy(const InstDev *dI, const int8_t *cfg, int k, int32_t *out, hipStream_t s);
@@ -760,6 +765,7 @@ extern "C" int pt_energy_device(pt_ctx *c, const int8_t *configs_dev, int32_t k,
 struct LaunchGroup {
     int kind, L, rpt, block, grid = 0, tsw_entries = 0;
     bool mixed = false;               // one launch of chunk_kernel_mixed for several sweepers
+    bool wave = false;                // wave-per-replica kernel
     size_t lds;
     std::vector<pt_ctx *> ctxs;
     std::vector<int> Gs;              // per context: slots per workgroup (max)
@@ -856,7 +862,7 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
             it.variant = mixed_variant_of(c->kind, c->L, g->rpts[k]);
             P.items.push_back(it);
             s0 += G;
-            P.nbs += (size_t)((c->n + 15) & ~15);
+            P.nbs += g->wave ? (size_t)G * c->n : (size_t)((c->n + 15) & ~15);   // wave: one snapshot per storage
         }
         P.nbest += W;
         P.nx += (size_t)W * 4 * xwords * 8;
@@ -869,7 +875,8 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
             P.tsw_max = std::max(P.tsw_max, tot);
         }
         // a block covers the largest item's threads
-        int need = c->kind == KIND_LATTICE ? lattice_threads(c->L, P.ctx[k].gmax, g->rpts[k]) : 256;
+        int need = g->wave ? 64 * P.ctx[k].gmax
+                           : c->kind == KIND_LATTICE ? lattice_threads(c->L, P.ctx[k].gmax, g->rpts[k]) : 256;
         P.block = std::max(P.block, (need + 63) & ~63);
     }
     // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
@@ -885,10 +892,13 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
     // region with the common swap-table capacity)
     for (size_t k = 0; k < g->ctxs.size(); ++k) {
         pt_ctx *c = g->ctxs[k];
-        P.lds = std::max(P.lds, chunk_lds_bytes(c->kind, c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max));
+        P.lds = std::max(P.lds, g->wave ? wave_lds_bytes(c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max)
+                                        : chunk_lds_bytes(c->kind, c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max));
     }
     if (P.lds > 160 * 1024) return fail(PT_EUNSUPPORTED, "tiling needs %zu B of LDS per workgroup", P.lds);
-    if (g->mixed)
+    if (g->wave)
+        HIPCHK(wave_occupancy(g->L, P.block, P.lds, &P.per_cu));
+    else if (g->mixed)
         HIPCHK(chunk_occupancy_mixed(P.block, P.lds, &P.per_cu));
     else
         HIPCHK(chunk_occupancy(g->kind, g->L, g->rpt, P.block, P.lds, &P.per_cu));
@@ -920,7 +930,7 @@ static int build_group(pt_batch *b, LaunchGroup *g)
             WorkItem &it = P.items[p.first + w];
             it.best = g->best.as<BestRec>() + bi++;
             it.best_spins = g->best_spins.as<int8_t>() + bs_off;
-            bs_off += (size_t)((p.n + 15) & ~15);
+            bs_off += g->wave ? (size_t)it.G * p.n : (size_t)((p.n + 15) & ~15);
             it.xbuf = (unsigned long long *)(g->xbuf.as<int8_t>() + p.x_off);
         }
         g->x_off.push_back(p.x_off);
@@ -965,9 +975,19 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
     g->mixed = keys.size() > 1;
     g->kind = ctxs[0]->kind;
     g->L = g->kind == KIND_LATTICE ? ctxs[0]->L : 0;
+    // the wave-per-replica kernel: one lattice size whose storage is exactly
+    // one wavefront, unless the caller asks for the workgroup-synchronous one
+    g->wave = !g->mixed && g->kind == KIND_LATTICE && wave_supported(g->L) && o.kernel != 1 &&
+              (o.kernel == 2 || o.replicas_per_thread <= 1);
     for (pt_ctx *c : ctxs) {
         int G, rpt;
-        choose_tiling(c, o, g->mixed, G, rpt);
+        if (g->wave) {
+            rpt = 1;
+            G = o.replicas_per_wg > 0 ? o.replicas_per_wg : wave_max_storages();
+            G = std::min(std::min(G, c->R), wave_max_storages());
+        } else {
+            choose_tiling(c, o, g->mixed, G, rpt);
+        }
         g->rpt = rpt;
         g->ctxs.push_back(c);
         g->Gs.push_back(G);
@@ -1060,8 +1080,9 @@ static hipError_t enqueue_round(pt_batch *b, uint32_t K, bool timed)
         a.err = b->err.as<int32_t>();
         a.spin_limit = 1u << 22;
         a.tsw_entries = g->tsw_entries;
-        hipError_t e = g->mixed ? launch_chunk_mixed(a, g->block, g->lds, b->stream)
-                                : launch_chunk(g->kind, g->L, g->rpt, a, g->block, g->lds, b->stream);
+        hipError_t e = g->wave    ? launch_wave(g->L, a, g->block, g->lds, b->stream)
+                       : g->mixed ? launch_chunk_mixed(a, g->block, g->lds, b->stream)
+                                  : launch_chunk(g->kind, g->L, g->rpt, a, g->block, g->lds, b->stream);
         if (e != hipSuccess) return e;
         if (timed) {
             e = hipEventRecord(e1, b->stream);
@@ -1142,9 +1163,9 @@ extern "C" int pt_batch_sweep(pt_batch *b, uint64_t n_sweeps)
     if (err[0]) {
         for (pt_ctx *c : b->ctxs) c->broken = true;
         return fail(PT_ETIMEOUT,
-                    "cross-workgroup exchange timed out: item %d (workgroup %d of its instance) waiting on side %d "
+                    "exchange wait timed out (kind %d): item %d (workgroup %d of its instance) waiting on side %d "
                     "at cycle %d saw word %08x:%08x, epoch %d",
-                    err[1], err[2], err[3], err[4], (unsigned)err[6], (unsigned)err[5], err[7]);
+                    err[0], err[1], err[2], err[3], err[4], (unsigned)err[6], (unsigned)err[5], err[7]);
     }
     return PT_OK;
 }

@@ -70,6 +70,18 @@ __device__ __forceinline__ int wave_min(int x)
     return __builtin_amdgcn_readlane(x, 63);
 }
 
+// Sum of x over the 64 lanes of a wavefront (same DPP pattern as wave_min).
+__device__ __forceinline__ int wave_sum(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
 // ---------------------------------------------------------------------------
 // Sweepers. Each provides: storage size and LDS index of a site, per-thread
 // setup, and one sweep of every storage of the workgroup (all threads call it;
@@ -380,6 +392,23 @@ struct RunParams {
         k0 = I.seed_lo; k1 = I.seed_hi;
         prop_start = I.prop_start; prop_period = I.prop_period; prop_stop = I.prop_stop;
     }
+    // First proposal sweep at or after t, or ~0 if none is left. The loops
+    // step from it by prop_period, so no 64-bit division runs per sweep.
+    __device__ __forceinline__ uint64_t first_prop_from(uint64_t t) const
+    {
+        if (prop_period <= 0) return ~0ull;
+        uint64_t k = 0;
+        if ((int64_t)t > prop_start) k = ((uint64_t)((int64_t)t - prop_start) + (uint64_t)prop_period - 1) / (uint64_t)prop_period;
+        uint64_t at = (uint64_t)prop_start + k * (uint64_t)prop_period;
+        if (prop_stop >= 0 && (int64_t)at > prop_stop) return ~0ull;
+        return at;
+    }
+    __device__ __forceinline__ uint64_t next_prop(uint64_t at) const
+    {
+        uint64_t nx = at + (uint64_t)prop_period;
+        if (prop_stop >= 0 && (int64_t)nx > prop_stop) return ~0ull;
+        return nx;
+    }
     __device__ __forceinline__ bool prop_sweep(uint64_t t) const
     {
         if (prop_period <= 0) return false;
@@ -523,12 +552,20 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
     __syncthreads();
 
     bool failed = false;
+    // cycle bookkeeping by counting (t0 / M once per launch)
+    uint32_t cyc = (uint32_t)(t0 / (uint64_t)P.M), phase = (uint32_t)(t0 % (uint64_t)P.M);
+    uint64_t prop_at = P.first_prop_from(t0 + 1);
     for (uint64_t t = t0 + 1; t <= tend && !failed; ++t) {
-        const bool cyc_end = (t % (uint64_t)P.M) == 0;
-        const uint32_t cyc = (uint32_t)(t / (uint64_t)P.M);
+        const bool cyc_end = ++phase == (uint32_t)P.M;
+        if (cyc_end) {
+            phase = 0;
+            ++cyc;
+        }
         SweepCall<Sw>::run(sw, I, G, s0, (uint32_t)t, c, stride);   // ends with a barrier
         // ---- proposals (Eq. 2), slots in increasing order ----
-        if (cyc_end && P.prop_sweep(t)) {
+        const bool prop_now = t == prop_at;
+        if (prop_now) prop_at = P.next_prop(prop_at);
+        if (prop_now) {
             if (tid < 64) {
                 for (int l = lane; l < G; l += 64) {
                     int r = s0 + l;

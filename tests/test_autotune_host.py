@@ -12,10 +12,10 @@ def _ctx(kind, L, n, R):
 
 def test_candidates_cover_caps_and_threads():
     c = autotune.candidates([_ctx("lattice", 8, 512, 32)])
-    assert (8, 1) in c and (32, 4) in c and (64, 2) in c
-    assert all(rpt <= G for G, rpt in c)
+    assert (8, 1, "block") in c and (32, 4, "block") in c and (64, 2, "block") in c and (8, 1, "wave") in c
+    assert all(rpt <= G for G, rpt, _ in c)
     c2 = autotune.candidates([_ctx("lattice", 4, 64, 3)])
-    assert max(G for G, _ in c2) <= 6
+    assert max(G for G, _, _ in c2) <= 6 and all(k == "block" for _, _, k in c2)
 
 
 def test_batch_key_is_a_multiset(monkeypatch):
@@ -29,13 +29,13 @@ def test_batch_key_is_a_multiset(monkeypatch):
 
 def test_tune_picks_fastest_and_caches(monkeypatch, tmp_path):
     monkeypatch.setattr(autotune, "arch", lambda: "gfx950")
-    rates = {(1, 8, 1): 100.0, (2, 8, 1): 150.0, (1, 16, 2): 120.0}
+    rates = {(1, 8, 1, "block"): 100.0, (2, 8, 1, "block"): 150.0, (1, 16, 2, "block"): 120.0}
     calls = []
 
-    def fake_time(ctxs, G, rpt, warm, timed):
+    def fake_time(ctxs, G, rpt, kern, warm, timed):
         M = ctxs[0].M
-        calls.append((M, G, rpt))
-        return rates.get((M, G, rpt))
+        calls.append((M, G, rpt, kern))
+        return rates.get((M, G, rpt, kern))
 
     monkeypatch.setattr(autotune, "time_tiling", fake_time)
 
