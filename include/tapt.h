@@ -152,7 +152,9 @@ typedef struct {
     int32_t chunk_sweeps;        /* sweeps per persistent launch (0 = 1000) */
     int32_t use_graph;           /* 1: replay the chunk launches as a hipGraph */
     int32_t kernel;              /* 0 = choose; 1 = workgroup-synchronous kernel;
-                                    2 = wave-per-replica kernel (lattices with n = 512) */
+                                    2 = wave-per-replica kernel (lattices with n = 512);
+                                    3 = +-J 8^3 kernel, two slots per wavefront (every
+                                        coupling +-1, even R) */
 } pt_batch_opts;
 
 /* Group contexts for batched execution. The contexts stay owned by the

@@ -45,6 +45,10 @@ int wave_max_storages();
 size_t wave_lds_bytes(int n, int G, int stride, int tsw_entries);
 hipError_t launch_wave(int L, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t wave_occupancy(int L, int block, size_t lds, int *blocks_per_cu);
+int pm_max_storages();
+size_t pm_lds_bytes(int G, int tsw_entries);
+hipError_t launch_pm(const ChunkArgs &a, int block, size_t lds, hipStream_t s);
+hipError_t pm_occupancy(int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_plain(int kind, int L, const InstDev *dI, int R, int n, int stride, uint32_t t, hipStream_t s);
 hipError_t launch_init(const InstDev *dI, int R, int n, hipStream_t s);
 hipError_t launch_energy(const InstDev *dI, const int8_t *cfg, int k, int32_t *out, hipStream_t s);
@@ -181,6 +185,7 @@ struct pt_ctx {
     bool broken = false;
     uint64_t t_host = 0;
     int device = 0;
+    bool pmJ = false;                 // 8^3 lattice with every coupling +-1 (the +-J kernel applies)
     DevBuf arena;                     // a served request's state, carved into the views above
 };
 
@@ -436,6 +441,9 @@ extern "C" int pt_create(const pt_graph *g, const double *betas, int32_t R, cons
     c->opts = *o;
     c->clamp = P.clamp;
     c->nfree = P.nfree;
+    c->pmJ = P.kind == KIND_LATTICE && P.L == 8 && P.D == 6 && R % 2 == 0;
+    for (int8_t j : P.J3)
+        if (j != 1 && j != -1) c->pmJ = false;
     auto bail = [&](int code) {
         delete c;
         return code;
@@ -766,6 +774,7 @@ struct LaunchGroup {
     int kind, L, rpt, block, grid = 0, tsw_entries = 0;
     bool mixed = false;               // one launch of chunk_kernel_mixed for several sweepers
     bool wave = false;                // wave-per-replica kernel
+    bool pm = false;                  // +-J 8^3 kernel, two slots per wavefront
     size_t lds;
     std::vector<pt_ctx *> ctxs;
     std::vector<int> Gs;              // per context: slots per workgroup (max)
@@ -845,13 +854,15 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
 {
     for (size_t k = 0; k < g->ctxs.size(); ++k) {
         pt_ctx *c = g->ctxs[k];
-        int R = c->R, W = (R + g->Gs[k] - 1) / g->Gs[k];
+        // the +-J kernel splits the ladder into whole slot pairs (even G, even s0)
+        const int unit = g->pm ? 2 : 1;
+        int R = c->R / unit, W = (R + g->Gs[k] / unit - 1) / (g->Gs[k] / unit);
         int xwords = (((c->n + 31) >> 5) + 1 + 7) & ~7;
-        P.ctx.push_back({(int)P.items.size(), W, c->n, xwords, (R + W - 1) / W, P.nbs, P.nx});
+        P.ctx.push_back({(int)P.items.size(), W, c->n, xwords, unit * ((R + W - 1) / W), P.nbs, P.nx});
         P.first.push_back((int)P.items.size());
         int base = R / W, extra = R % W, s0 = 0;
         for (int w = 0; w < W; ++w) {
-            int G = base + (w < extra ? 1 : 0);
+            int G = unit * (base + (w < extra ? 1 : 0));
             WorkItem it{};
             it.inst = c->inst.as<InstDev>();
             it.s0 = s0;
@@ -862,7 +873,7 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
             it.variant = mixed_variant_of(c->kind, c->L, g->rpts[k]);
             P.items.push_back(it);
             s0 += G;
-            P.nbs += g->wave ? (size_t)G * c->n : (size_t)((c->n + 15) & ~15);   // wave: one snapshot per storage
+            P.nbs += (g->wave || g->pm) ? (size_t)G * c->n : (size_t)((c->n + 15) & ~15);   // one snapshot per slot
         }
         P.nbest += W;
         P.nx += (size_t)W * 4 * xwords * 8;
@@ -875,8 +886,9 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
             P.tsw_max = std::max(P.tsw_max, tot);
         }
         // a block covers the largest item's threads
-        int need = g->wave ? 64 * P.ctx[k].gmax
-                           : c->kind == KIND_LATTICE ? lattice_threads(c->L, P.ctx[k].gmax, g->rpts[k]) : 256;
+        int need = g->pm     ? 64 * (P.ctx[k].gmax / 2)
+                   : g->wave ? 64 * P.ctx[k].gmax
+                             : c->kind == KIND_LATTICE ? lattice_threads(c->L, P.ctx[k].gmax, g->rpts[k]) : 256;
         P.block = std::max(P.block, (need + 63) & ~63);
     }
     // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
@@ -892,11 +904,14 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
     // region with the common swap-table capacity)
     for (size_t k = 0; k < g->ctxs.size(); ++k) {
         pt_ctx *c = g->ctxs[k];
-        P.lds = std::max(P.lds, g->wave ? wave_lds_bytes(c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max)
-                                        : chunk_lds_bytes(c->kind, c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max));
+        P.lds = std::max(P.lds, g->pm     ? pm_lds_bytes(P.ctx[k].gmax, P.tsw_max)
+                                : g->wave ? wave_lds_bytes(c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max)
+                                          : chunk_lds_bytes(c->kind, c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max));
     }
     if (P.lds > 160 * 1024) return fail(PT_EUNSUPPORTED, "tiling needs %zu B of LDS per workgroup", P.lds);
-    if (g->wave)
+    if (g->pm)
+        HIPCHK(pm_occupancy(P.block, P.lds, &P.per_cu));
+    else if (g->wave)
         HIPCHK(wave_occupancy(g->L, P.block, P.lds, &P.per_cu));
     else if (g->mixed)
         HIPCHK(chunk_occupancy_mixed(P.block, P.lds, &P.per_cu));
@@ -930,7 +945,7 @@ static int build_group(pt_batch *b, LaunchGroup *g)
             WorkItem &it = P.items[p.first + w];
             it.best = g->best.as<BestRec>() + bi++;
             it.best_spins = g->best_spins.as<int8_t>() + bs_off;
-            bs_off += g->wave ? (size_t)it.G * p.n : (size_t)((p.n + 15) & ~15);
+            bs_off += (g->wave || g->pm) ? (size_t)it.G * p.n : (size_t)((p.n + 15) & ~15);
             it.xbuf = (unsigned long long *)(g->xbuf.as<int8_t>() + p.x_off);
         }
         g->x_off.push_back(p.x_off);
@@ -977,11 +992,19 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
     g->L = g->kind == KIND_LATTICE ? ctxs[0]->L : 0;
     // the wave-per-replica kernel: one lattice size whose storage is exactly
     // one wavefront, unless the caller asks for the workgroup-synchronous one
-    g->wave = !g->mixed && g->kind == KIND_LATTICE && wave_supported(g->L) && o.kernel != 1 &&
+    bool all_pm = !g->mixed;
+    for (pt_ctx *c : ctxs) all_pm = all_pm && c->pmJ;
+    g->pm = all_pm && (o.kernel == 3 || (o.kernel == 0 && o.replicas_per_thread <= 1));
+    g->wave = !g->pm && !g->mixed && g->kind == KIND_LATTICE && wave_supported(g->L) && o.kernel != 1 &&
               (o.kernel == 2 || o.replicas_per_thread <= 1);
     for (pt_ctx *c : ctxs) {
         int G, rpt;
-        if (g->wave) {
+        if (g->pm) {
+            rpt = 1;
+            G = o.replicas_per_wg > 0 ? o.replicas_per_wg : 8;
+            G = std::min(std::min(G, c->R), pm_max_storages()) & ~1;
+            if (G < 2) G = 2;
+        } else if (g->wave) {
             rpt = 1;
             G = o.replicas_per_wg > 0 ? o.replicas_per_wg : wave_max_storages();
             G = std::min(std::min(G, c->R), wave_max_storages());
@@ -1080,7 +1103,8 @@ static hipError_t enqueue_round(pt_batch *b, uint32_t K, bool timed)
         a.err = b->err.as<int32_t>();
         a.spin_limit = 1u << 22;
         a.tsw_entries = g->tsw_entries;
-        hipError_t e = g->wave    ? launch_wave(g->L, a, g->block, g->lds, b->stream)
+        hipError_t e = g->pm      ? launch_pm(a, g->block, g->lds, b->stream)
+                       : g->wave  ? launch_wave(g->L, a, g->block, g->lds, b->stream)
                        : g->mixed ? launch_chunk_mixed(a, g->block, g->lds, b->stream)
                                   : launch_chunk(g->kind, g->L, g->rpt, a, g->block, g->lds, b->stream);
         if (e != hipSuccess) return e;
@@ -1267,6 +1291,7 @@ int clone_ctx(const pt_ctx *tm, uint64_t seed, int has_target, int32_t target, u
     c->opts.target = target;
     c->clamp = tm->clamp;
     c->nfree = tm->nfree;
+    c->pmJ = tm->pmJ;
     c->device = tm->device;
     c->stream = s;
     c->own_stream = false;

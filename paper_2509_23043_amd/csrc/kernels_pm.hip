@@ -1,0 +1,598 @@
+// Persistent kernel for +-J couplings on the periodic 8^3 lattice (no
+// fields): every wavefront owns two adjacent beta slots (2w, 2w+1 of its
+// workgroup) and sweeps both with byte-parallel arithmetic.
+//
+// Storage. A replica is 64 rows of 8 sites (row q = y + 8z holds x = 0..7,
+// site index i = 8q + x), one byte per site that is 1 when the spin is -1.
+// Lane q of a wavefront owns row q, which is also the row of Philox call q,
+// so its 8 uniforms are the lane's own.
+//
+// Local field. With b the down-bit of a site, n the down-bit of a neighbour
+// and j = 1 when the bond is -1, the bond is unsatisfied (J m_i m_j = -1)
+// exactly when j ^ b ^ n = 1. A colour phase updates the four sites
+// x = p, p+2, p+4, p+6 of the row (p = (colour + y + z) mod 2). Their
+// neighbours along x come from the lane's own row and those along y and z
+// from four whole-row LDS reads; v_perm gathers the four relevant bytes of
+// each into one dword, three-input XORs form the six unsatisfied-bond flags
+// and byte-wise adds count them (U <= 6, no carries). Then m_i I_i = 6 - 2U,
+// the flip changes E by 12 - 4U, and the threshold is the slot's table entry
+// for that m_i I_i (held in LDS indexed by U).
+//
+// Slots and states. A wavefront's two slots are fixed; states move between
+// LDS buffers. The pair (2w, 2w+1) is decided inside the wavefront with no
+// communication. The pair (2w+1, 2w+2) meets wavefront w+1 in an LDS mailbox
+// that carries the energy and the buffer index, and an accepted swap trades
+// buffer indices. Pairs across a workgroup boundary go through cycle-tagged
+// global words and copy the state. Best energy, first hit and all counters
+// are per slot and live in registers.
+#include "sweep.h"
+
+namespace tapt {
+
+namespace pm {
+
+constexpr int L = 8, N = 512, ROWB = 8, SPW = 2;
+
+// v_perm selectors ({hi, lo}: bytes 0-3 from lo, 4-7 from hi)
+__device__ __forceinline__ uint32_t sel_sites(int p) { return p ? 0x07050301u : 0x06040200u; }   // x = p + 2j
+__device__ __forceinline__ uint32_t sel_xp(int p) { return p ? 0x00060402u : 0x07050301u; }      // x + 1
+__device__ __forceinline__ uint32_t sel_xm(int p) { return p ? 0x06040200u : 0x05030107u; }      // x - 1
+// high half of word j moved to the top: (w >> 16p) << 16 (0x0c selects a zero byte)
+__device__ __forceinline__ uint32_t sel_half(int p) { return p ? 0x03020c0cu : 0x01000c0cu; }
+// compact flags (byte j) to row bytes x = p + 2j, low and high dword
+__device__ __forceinline__ uint32_t sel_flo(int p) { return p ? 0x010c000cu : 0x0c010c00u; }
+__device__ __forceinline__ uint32_t sel_fhi(int p) { return p ? 0x030c020cu : 0x0c030c02u; }
+
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel)
+{
+    return __builtin_amdgcn_perm(hi, lo, sel);
+}
+
+struct Off {
+    size_t buf, tabu, toff, tsw, mail, xst, total;
+};
+
+__host__ __device__ inline Off offsets(int G, int tsw_entries)
+{
+    Off f;
+    size_t o = 0;
+    f.buf = o; o = align16(o + (size_t)G * N);
+    f.tabu = o; o = align16(o + (size_t)G * 8 * 4);
+    f.toff = o; o = align16(o + (size_t)(G + 2) * 4);
+    f.tsw = o; o = align16(o + (size_t)tsw_entries * 4);
+    f.mail = o; o = align16(o + (size_t)4 * G * 8);
+    f.xst = o; o = align16(o + (size_t)SPW * 2 * (G / SPW) * ((N >> 5) + 1) * 4);
+    f.total = o;
+    return f;
+}
+
+struct Rec {
+    int E, slot;
+    long long t, hit;
+};
+
+// Swap acceptance (Eq. 1) for dE = E_{r+1} - E_r with the pair's LDS table
+// row (off, len). Every input is wave-uniform; the table is read
+// unconditionally (clamped index) and the result is returned through an SGPR,
+// so that callers select on a scalar instead of branching per lane.
+__device__ __forceinline__ bool swap_ok(int dE, uint32_t u, int off, int len, const uint32_t *tsw)
+{
+    const int d = -dE;
+    const bool in_row = d >= 1 && d <= len;
+    const uint32_t Tr = tsw[in_row ? off + d - 1 : 0];
+    const uint32_t T = dE >= 0 ? ALWAYS : (in_row ? Tr : 0u);
+    const bool ok = T == ALWAYS || u < T;
+    return __builtin_amdgcn_readfirstlane(ok ? 1 : 0) != 0;
+}
+
+} // namespace pm
+
+__global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
+{
+    using namespace pm;
+    const int item = a.order[blockIdx.x];
+    if (item < 0) return;
+    const WorkItem it = a.items[item];
+    const InstDev &I = *it.inst;
+    RunParams P;
+    P.load(I);
+    const int G = it.G, s0 = it.s0;          // G even, s0 even
+    const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int NWV = G / SPW;
+    const uint64_t t0 = *I.t;
+    const uint64_t cap = I.sweep_cap;
+    const uint64_t tend = (t0 + a.K < cap) ? t0 + a.K : cap;
+    if (t0 >= tend) return;
+    const Off lof = offsets(G, a.tsw_entries);
+    uint8_t *bufs = (uint8_t *)(lds_raw + lof.buf);
+    uint32_t *tabu = (uint32_t *)(lds_raw + lof.tabu);          // [G][8] threshold by U
+    int *tsw_off = (int *)(lds_raw + lof.toff);
+    uint32_t *tsw = (uint32_t *)(lds_raw + lof.tsw);
+    unsigned long long *mail = (unsigned long long *)(lds_raw + lof.mail);   // [4][G]
+    uint32_t *xstage = (uint32_t *)(lds_raw + lof.xst);
+    constexpr int NWD = N >> 5;                                   // 32-bit words of a packed state
+
+    // ---- stage: states as down-bits (slot l in buffer l), tables ----
+    for (int x = tid; x < G * N / 4; x += bs) {
+        const int l = x / (N / 4), w4 = x - l * (N / 4);
+        const uint32_t v = *(const uint32_t *)(I.spins + (size_t)(s0 + l) * N + 4 * w4);
+        *(uint32_t *)(bufs + l * N + 4 * w4) = (v >> 7) & 0x01010101u;
+    }
+    for (int x = tid; x < G * 8; x += bs) {
+        const int l = x >> 3, U = x & 7;
+        // m_i I_i = 6 - 2U indexes the flip row at D + 6 - 2U (D = 6 here)
+        tabu[x] = U <= 6 ? I.tflip[(size_t)(s0 + l) * P.stride + P.D + 6 - 2 * U] : 0u;
+    }
+    if (tid == 0) {
+        int o = 0;
+        for (int p = 0; p <= G; ++p) {
+            tsw_off[p] = o;
+            const int r = s0 - 1 + p;
+            if (r >= 0 && r + 1 < P.R) o += I.tswap_len[r];
+        }
+        tsw_off[G + 1] = o;
+    }
+    for (int x = tid; x < 4 * G; x += bs) mail[x] = 0ull;
+    __syncthreads();
+    for (int p = 0; p <= G; ++p) {
+        const int r = s0 - 1 + p;
+        if (r < 0 || r + 1 >= P.R) continue;
+        const int lo = tsw_off[p], len = tsw_off[p + 1] - lo;
+        for (int x = tid; x < len; x += bs) tsw[lo + x] = I.tswap[I.tswap_off[r] + x];
+    }
+    __syncthreads();
+
+    const int row_off_v = lane <= G ? tsw_off[lane] : 0;
+    const int row_len_v = lane <= G ? tsw_off[lane + 1] - row_off_v : 0;
+    const bool active = wv < NWV;
+    const bool has_down = it.w > 0, has_up = it.w + 1 < it.W;
+    bool failed = false;
+
+    // per-slot state of this wavefront (k = 0, 1: local slots 2wv + k)
+    int buf[SPW], E[SPW], bestE[SPW], bestSlot[SPW];
+    long long bestT[SPW], hit[SPW];
+    unsigned nflip[SPW], satt[SPW], sacc[SPW], patt[SPW], pacc[SPW];
+    const int best0 = I.best->E;
+    const bool want_hit = P.has_target && I.best->first_hit < 0;
+#pragma unroll
+    for (int k = 0; k < SPW; ++k) {
+        buf[k] = SPW * wv + k;
+        E[k] = active ? I.E[s0 + SPW * wv + k] : 0;
+        bestE[k] = best0;
+        bestSlot[k] = -1;
+        bestT[k] = -1;
+        hit[k] = -1;
+        nflip[k] = satt[k] = sacc[k] = patt[k] = pacc[k] = 0;
+    }
+    uint32_t n_prop = 0;
+
+    if (active) {
+        // lane geometry: row q = lane, y = q & 7, z = q >> 3
+        const int y = lane & 7, z = lane >> 3;
+        const int rel_yp = ROWB * (((y + 1) & 7) + 8 * z), rel_ym = ROWB * (((y + 7) & 7) + 8 * z);
+        const int rel_zp = ROWB * (y + 8 * ((z + 1) & 7)), rel_zm = ROWB * (y + 8 * ((z + 7) & 7));
+        const int rel_me = ROWB * lane;
+        int par[2];
+        par[0] = (y + z) & 1;
+        par[1] = par[0] ^ 1;
+        // unsatisfied-bond bits of the couplings: JN[c][d] byte j = 1 when the
+        // bond of site x = par[c] + 2j in direction d is -1 (d: +x, -x, +y, -y, +z, -z)
+        uint32_t JN[2][6];
+        const int8_t *J3 = I.J3;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+#pragma unroll
+            for (int d = 0; d < 6; ++d) JN[c][d] = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int x = par[c] + 2 * j;
+                const int i = x + 8 * lane;
+                const int xm = (x + 7) & 7;
+                const int iym = x + 8 * (((y + 7) & 7) + 8 * z);
+                const int izm = x + 8 * (y + 8 * ((z + 7) & 7));
+                const int jb[6] = {J3[i], J3[xm + 8 * lane], J3[N + i], J3[N + iym], J3[2 * N + i], J3[2 * N + izm]};
+#pragma unroll
+                for (int d = 0; d < 6; ++d) JN[c][d] |= (uint32_t)(jb[d] < 0 ? 1 : 0) << (8 * j);
+            }
+        }
+        const uint32_t S0 = sel_sites(par[0]), S1 = sel_sites(par[1]);
+        const uint32_t XP0 = sel_xp(par[0]), XP1 = sel_xp(par[1]);
+        const uint32_t XM0 = sel_xm(par[0]), XM1 = sel_xm(par[1]);
+        const uint32_t H0 = sel_half(par[0]), H1 = sel_half(par[1]);
+        const uint32_t FL0 = sel_flo(par[0]), FL1 = sel_flo(par[1]);
+        const uint32_t FH0 = sel_fhi(par[0]), FH1 = sel_fhi(par[1]);
+
+        uint32_t cyc = (uint32_t)(t0 / (uint64_t)P.M), phase = (uint32_t)(t0 % (uint64_t)P.M);
+        uint64_t prop_at = P.first_prop_from(t0 + 1);
+        const int lab0 = s0 + SPW * wv;          // this wavefront's slots: lab0, lab0 + 1
+
+        for (uint64_t t = t0 + 1; t <= tend && !failed; ++t) {
+            const bool ends = phase + 1 == (uint32_t)P.M;
+            // swap uniforms of the pairs of this workgroup (lane p: pair s0 - 1 + p)
+            uint32_t u_vec = 0;
+            if (ends) u_vec = philox_word0((uint32_t)(s0 - 1 + lane), cyc + 1, TAG_SWAP, P.k0, P.k1);
+
+            // ---- sweep both slots (colour phases outermost, so that the two
+            // slots' independent work interleaves) ----
+            P4 r[SPW];
+            uint2 me[SPW];
+            int nf[SPW], su[SPW];
+#pragma unroll
+            for (int k = 0; k < SPW; ++k) {
+                r[k] = philox((uint32_t)lane, (uint32_t)t, (uint32_t)(lab0 + k), TAG_SWEEP, P.k0, P.k1);
+                me[k] = *(const uint2 *)(bufs + buf[k] * N + rel_me);
+                nf[k] = 0;
+                su[k] = 0;
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const uint32_t Ss = c ? S1 : S0, Xp = c ? XP1 : XP0, Xm = c ? XM1 : XM0;
+                const uint32_t Hs = c ? H1 : H0, FL = c ? FL1 : FL0, FH = c ? FH1 : FH0;
+#pragma unroll
+                for (int k = 0; k < SPW; ++k) {
+                    const uint8_t *B = bufs + buf[k] * N;
+                    const uint32_t *tu = tabu + (SPW * wv + k) * 8;
+                    const uint2 yp = *(const uint2 *)(B + rel_yp);
+                    const uint2 ym = *(const uint2 *)(B + rel_ym);
+                    const uint2 zp = *(const uint2 *)(B + rel_zp);
+                    const uint2 zm = *(const uint2 *)(B + rel_zm);
+                    const uint32_t b = perm(me[k].y, me[k].x, Ss);
+                    uint32_t U = (JN[c][0] ^ b ^ perm(me[k].y, me[k].x, Xp)) +
+                                 (JN[c][1] ^ b ^ perm(me[k].y, me[k].x, Xm)) + (JN[c][2] ^ b ^ perm(yp.y, yp.x, Ss));
+                    U += (JN[c][3] ^ b ^ perm(ym.y, ym.x, Ss)) + (JN[c][4] ^ b ^ perm(zp.y, zp.x, Ss)) +
+                         (JN[c][5] ^ b ^ perm(zm.y, zm.x, Ss));
+                    uint32_t T[4], hs[4];
+                    bool acc[4], maybe[4];
+                    bool any_maybe = false;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        T[j] = tu[(U >> (8 * j)) & 0xFFu];
+                        hs[j] = perm(r[k].v[j], r[k].v[j], Hs);
+                        acc[j] = coarse_accept(T[j], hs[j], maybe[j]);
+                        any_maybe |= maybe[j];
+                    }
+                    if (any_lane(any_maybe)) {
+                        const P4 r2 = philox((uint32_t)lane, (uint32_t)t, (uint32_t)(lab0 + k), TAG_REFINE, P.k0, P.k1);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const uint32_t lo = perm(r2.v[j], r2.v[j], Hs) >> 16;
+                            if (maybe[j]) acc[j] = (T[j] == ALWAYS) || ((hs[j] | lo) < T[j]);
+                        }
+                    }
+                    const uint32_t F = (acc[0] ? 1u : 0u) | (acc[1] ? 0x100u : 0u) | (acc[2] ? 0x10000u : 0u) |
+                                       (acc[3] ? 0x1000000u : 0u);
+                    me[k].x ^= perm(0u, F, FL);
+                    me[k].y ^= perm(0u, F, FH);
+                    *(uint2 *)(bufs + buf[k] * N + rel_me) = me[k];
+                    nf[k] += __builtin_popcount(F);
+                    su[k] = (int)__builtin_amdgcn_udot4(U, F, (uint32_t)su[k], false);
+                }
+                // the next colour reads what this one wrote (in-order LDS within a wavefront)
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+            int dEl[SPW];
+#pragma unroll
+            for (int k = 0; k < SPW; ++k) {
+                nflip[k] += (unsigned)nf[k];   // per lane; reduced at the end
+                dEl[k] = 12 * nf[k] - 4 * su[k];
+            }
+#pragma unroll
+            for (int k = 0; k < SPW; ++k) E[k] += wave_sum(dEl[k]);
+
+            if (ends) {
+                phase = 0;
+                ++cyc;
+                // ---- proposals (Eq. 2), this wavefront's slots ----
+                const bool prop_now = t == prop_at;
+                if (prop_now) {
+                    prop_at = P.next_prop(prop_at);
+#pragma unroll
+                    for (int k = 0; k < SPW; ++k) {
+                        const int slot = lab0 + k;
+                        const int Bn = I.bank_n[slot];
+                        if (Bn <= 0) continue;
+                        const int cur0 = I.cursor[slot];
+                        const int kk = (int)(((uint32_t)cur0 + n_prop % (uint32_t)Bn) % (uint32_t)Bn);
+                        patt[k] += 1;
+                        const int ET = I.bankE[slot][kk];
+                        const long long dd = (long long)ET - (long long)E[k];
+                        uint32_t T;
+                        if (dd <= 0) T = ALWAYS;
+                        else if (dd <= I.tprop_len[slot]) T = I.tprop[I.tprop_off[slot] + (int)dd - 1];
+                        else T = 0;
+                        const uint32_t u = philox_word0((uint32_t)slot, cyc, TAG_PROPOSE, P.k0, P.k1);
+                        if (T == ALWAYS || u < T) {
+                            const uint2 v = *(const uint2 *)(I.bank[slot] + (size_t)kk * N + rel_me);
+                            uint2 d;
+                            d.x = (v.x >> 7) & 0x01010101u;
+                            d.y = (v.y >> 7) & 0x01010101u;
+                            *(uint2 *)(bufs + buf[k] * N + rel_me) = d;
+                            E[k] = ET;
+                            pacc[k] += 1;
+                        }
+                    }
+                    ++n_prop;
+                }
+                // ---- swaps (Eq. 1), alternating parity ----
+                if (cyc & 1) {
+                    // pairs (2w, 2w+1): inside this wavefront
+                    const int r = lab0;
+                    if (r + 1 < P.R) {
+                        const int prow = r - (s0 - 1);
+                        const bool ok = swap_ok(E[1] - E[0], __builtin_amdgcn_readlane(u_vec, prow),
+                                                __builtin_amdgcn_readlane(row_off_v, prow),
+                                                __builtin_amdgcn_readlane(row_len_v, prow), tsw);
+                        satt[0] += 1;
+                        sacc[0] += ok ? 1u : 0u;
+                        const int b0 = buf[0], b1 = buf[1], e0 = E[0], e1 = E[1];
+                        buf[0] = ok ? b1 : b0;
+                        buf[1] = ok ? b0 : b1;
+                        E[0] = ok ? e1 : e0;
+                        E[1] = ok ? e0 : e1;
+                    }
+                } else {
+                    // pairs (2w+1, 2w+2): with the next wavefront or across the upper
+                    // boundary; (2w-1, 2w): with the previous one or across the lower
+                    const int lu = SPW * wv + 1;                 // local slot of the upper one
+                    unsigned long long *mb = mail + (cyc & 3) * G;
+                    const bool up_here = lab0 + 2 < P.R && wv + 1 < NWV;
+                    const bool dn_here = wv > 0;
+                    // publish (energy, buffer) of the slots that meet a neighbour wavefront
+                    if (lane == 0) {
+                        if (up_here)
+                            __hip_atomic_store(mb + lu, ((unsigned long long)cyc << 32) | ((uint32_t)buf[1] << 24) |
+                                                            ((uint32_t)E[1] & 0xFFFFFFu),
+                                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        if (dn_here)
+                            __hip_atomic_store(mb + lu - 1, ((unsigned long long)cyc << 32) | ((uint32_t)buf[0] << 24) |
+                                                                ((uint32_t)E[0] & 0xFFFFFFu),
+                                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    // across the workgroup boundaries: tagged words, state copy
+#pragma unroll
+                    for (int side = 0; side < 2; ++side) {
+                        const int k = side == 0 ? 0 : 1;
+                        const bool cross = side == 0 ? (wv == 0 && has_down && lab0 >= 1)
+                                                     : (wv + 1 == NWV && has_up && lab0 + 2 < P.R);
+                        if (!cross || failed) continue;
+                        const int buf_x = (cyc >> 1) & 1;
+                        const unsigned long long tag = (unsigned long long)cyc << 32;
+                        unsigned long long *out = it.xbuf + ((size_t)(it.w * 2 + side) * 2 + buf_x) * it.xwords;
+                        const uint8_t *B = bufs + buf[k] * N;
+                        // 8 ballots of 64 down-bits: word 2m + h holds sites 64m + 32h .. +31
+#pragma unroll
+                        for (int m8 = 0; m8 < 8; ++m8) {
+                            const unsigned long long bal = __ballot(B[64 * m8 + lane] == 0);   // bit = spin +1
+                            if (lane < 2)
+                                __hip_atomic_store(out + 2 * m8 + lane,
+                                                   tag | (lane ? (bal >> 32) : (bal & 0xFFFFFFFFull)),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                        if (lane == 0)
+                            __hip_atomic_store(out + NWD, tag | (uint32_t)E[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const int pw = side == 0 ? it.w - 1 : it.w + 1;
+                        const unsigned long long *in =
+                            it.xbuf + ((size_t)(pw * 2 + (side == 0 ? 1 : 0)) * 2 + buf_x) * it.xwords;
+                        uint32_t *stage = xstage + (size_t)(wv * 2 + side) * (NWD + 1);
+                        uint32_t polls = 0;
+                        bool ok_all = false;
+                        unsigned long long bad = 0;
+                        for (;;) {
+                            bool ok = true;
+                            if (lane <= NWD) {
+                                const unsigned long long v =
+                                    __hip_atomic_load(in + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                if ((uint32_t)(v >> 32) == cyc) stage[lane] = (uint32_t)v;
+                                else {
+                                    ok = false;
+                                    bad = v;
+                                }
+                            }
+                            if (__all(ok)) {
+                                ok_all = true;
+                                break;
+                            }
+                            if (++polls > a.spin_limit) break;
+                        }
+                        if (!ok_all) {
+                            if (lane == 0 && atomicCAS(a.err, 0, 1) == 0) {
+                                a.err[1] = item; a.err[2] = it.w; a.err[3] = side; a.err[4] = (int)cyc;
+                                a.err[5] = (int)(bad & 0xFFFFFFFFu); a.err[6] = (int)(bad >> 32); a.err[7] = (int)I.epoch;
+                            }
+                            failed = true;
+                            continue;
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        const int pE = __builtin_amdgcn_readfirstlane((int)stage[NWD]);
+                        const int slot = lab0 + k;
+                        const int r = side == 0 ? slot - 1 : slot;
+                        const int prow = r - (s0 - 1);
+                        const int dEs = side == 0 ? E[k] - pE : pE - E[k];
+                        const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, prow),
+                                                 __builtin_amdgcn_readlane(row_off_v, prow),
+                                                 __builtin_amdgcn_readlane(row_len_v, prow), tsw);
+                        if (side == 1) {   // the lower workgroup owns the pair's counters
+                            satt[1] += 1;
+                            if (okx) sacc[1] += 1;
+                        }
+                        E[k] = okx ? pE : E[k];
+                        if (okx) {
+                            // row of this lane: sites 8 lane .. 8 lane + 7 = bits (8 lane) & 31 .. of word lane >> 2
+                            const uint32_t wd = stage[lane >> 2] >> ((8 * lane) & 31);
+                            uint2 d;
+                            d.x = (~wd & 1u) | ((~wd & 2u) << 7) | ((~wd & 4u) << 14) | ((~wd & 8u) << 21);
+                            d.y = ((~wd >> 4) & 1u) | (((~wd >> 4) & 2u) << 7) | (((~wd >> 4) & 4u) << 14) |
+                                  (((~wd >> 4) & 8u) << 21);
+                            *(uint2 *)(bufs + buf[k] * N + rel_me) = d;
+                        }
+                    }
+                    if (!failed) {
+                        // inside the workgroup: read the neighbour wavefronts' words
+#pragma unroll
+                        for (int side = 0; side < 2; ++side) {
+                            const bool here = side == 0 ? dn_here : up_here;
+                            if (!here || failed) continue;
+                            const int k = side == 0 ? 0 : 1;
+                            const int pl = side == 0 ? SPW * wv - 1 : SPW * wv + 2;   // partner local slot
+                            uint32_t polls = 0;
+                            unsigned long long v;
+                            for (;;) {
+                                v = __hip_atomic_load(mb + pl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                if ((uint32_t)(v >> 32) == cyc) break;
+                                __builtin_amdgcn_s_sleep(1);
+                                if (++polls > a.spin_limit) break;
+                            }
+                            if ((uint32_t)(v >> 32) != cyc) {
+                                if (lane == 0 && atomicCAS(a.err, 0, 2) == 0) {
+                                    a.err[1] = item; a.err[2] = it.w; a.err[3] = 2; a.err[4] = (int)cyc;
+                                    a.err[5] = (int)(v & 0xFFFFFFFFu); a.err[6] = (int)(v >> 32); a.err[7] = (int)I.epoch;
+                                }
+                                failed = true;
+                                continue;
+                            }
+                            // every value here is wave-uniform: keep it scalar
+                            const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)v);
+                            const int pE = ((int)(lo32 << 8)) >> 8;      // 24-bit signed energy
+                            const int pb = (int)((lo32 >> 24) & 0xFFu);
+                            const int slot = lab0 + k;
+                            const int r = side == 0 ? slot - 1 : slot;
+                            const int prow = r - (s0 - 1);
+                            const int dEs = side == 0 ? E[k] - pE : pE - E[k];
+                            const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, prow),
+                                                     __builtin_amdgcn_readlane(row_off_v, prow),
+                                                     __builtin_amdgcn_readlane(row_len_v, prow), tsw);
+                            if (side == 1) {
+                                satt[1] += 1;
+                                sacc[1] += okx ? 1u : 0u;
+                            }
+                            // trade buffers on acceptance: the partner takes ours
+                            buf[k] = okx ? pb : buf[k];
+                            E[k] = okx ? pE : E[k];
+                        }
+                    }
+                }
+            } else {
+                ++phase;
+            }
+            // ---- best energy and first hit, per slot ----
+#pragma unroll
+            for (int k = 0; k < SPW; ++k) {
+                if (want_hit && hit[k] < 0 && E[k] <= P.target) hit[k] = (long long)t;
+                if (E[k] < bestE[k]) {
+                    bestE[k] = E[k];
+                    bestT[k] = (long long)t;
+                    bestSlot[k] = lab0 + k;
+                    const uint2 v = *(const uint2 *)(bufs + buf[k] * N + rel_me);
+                    uint2 o;
+                    o.x = v.x * 0xFEu + 0x01010101u;       // down-bit 1 -> -1 (0xFF), 0 -> +1
+                    o.y = v.y * 0xFEu + 0x01010101u;
+                    *(uint2 *)(it.best_spins + (size_t)(SPW * wv + k) * N + rel_me) = o;
+                }
+            }
+        }
+    }
+
+    // ---- end of launch ----
+    __shared__ int any_failed, win;
+    __shared__ int slot_buf[64], slot_E[64];
+    __shared__ Rec rec[64];
+    __shared__ unsigned cnt[64][5];
+    if (tid == 0) any_failed = 0;
+    __syncthreads();
+    if (active) {
+        unsigned nfw[SPW];
+#pragma unroll
+        for (int k = 0; k < SPW; ++k) nfw[k] = (unsigned)wave_sum((int)nflip[k]);
+        if (failed && lane == 0) any_failed = 1;
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < SPW; ++k) {
+                const int l = SPW * wv + k;
+                slot_buf[l] = buf[k];
+                slot_E[l] = E[k];
+                Rec rr;
+                rr.E = bestE[k];
+                rr.slot = bestSlot[k];
+                rr.t = bestT[k];
+                rr.hit = hit[k];
+                rec[l] = rr;
+                cnt[l][0] = nfw[k];
+                cnt[l][1] = satt[k];
+                cnt[l][2] = sacc[k];
+                cnt[l][3] = patt[k];
+                cnt[l][4] = pacc[k];
+            }
+        }
+    }
+    __syncthreads();
+    if (any_failed) return;   // the host reports the error; the launch's state is abandoned
+    for (int x = tid; x < G * N / 4; x += bs) {
+        const int l = x / (N / 4), w4 = x - l * (N / 4);
+        const uint32_t v = *(const uint32_t *)(bufs + slot_buf[l] * N + 4 * w4);
+        *(uint32_t *)(I.spins + (size_t)(s0 + l) * N + 4 * w4) = v * 0xFEu + 0x01010101u;
+    }
+    for (int l = tid; l < G; l += bs) {
+        const int slot = s0 + l;
+        I.E[slot] = slot_E[l];
+        I.flips[slot] += cnt[l][0];
+        I.prop_att[slot] += cnt[l][3];
+        I.prop_acc[slot] += cnt[l][4];
+        const int Bn = I.bank_n[slot];
+        if (Bn > 0) I.cursor[slot] = (int)(((uint32_t)I.cursor[slot] + n_prop % (uint32_t)Bn) % (uint32_t)Bn);
+    }
+    // swap counters: pair (2w, 2w+1) in slot 2w's k=0 entry; pair (2w+1, 2w+2) in k=1
+    for (int l = tid; l < G; l += bs) {
+        const int slot = s0 + l;
+        if (slot + 1 < P.R) {
+            I.swap_att[slot] += cnt[l][1];
+            I.swap_acc[slot] += cnt[l][2];
+        }
+    }
+    if (tid == 0) {
+        int wb = -1;
+        long long h = -1;
+        for (int l = 0; l < G; ++l) {
+            const Rec r = rec[l];
+            if (r.hit >= 0 && (h < 0 || r.hit < h)) h = r.hit;
+            if (r.t < 0) continue;
+            if (wb < 0 || r.E < rec[wb].E || (r.E == rec[wb].E && (r.t < rec[wb].t || (r.t == rec[wb].t && r.slot < rec[wb].slot))))
+                wb = l;
+        }
+        BestRec b;
+        b.E = wb >= 0 ? rec[wb].E : 0x7FFFFFFF;
+        b.slot = wb >= 0 ? rec[wb].slot : -1;
+        b.t = wb >= 0 ? rec[wb].t : -1;
+        b.first_hit = h;
+        b.pad = 0;
+        *it.best = b;
+        win = wb;
+    }
+    __syncthreads();
+    if (win > 0)
+        for (int i = tid; i < N; i += bs) it.best_spins[i] = it.best_spins[(size_t)win * N + i];
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (C++ linkage, used by the runtime in host.cpp).
+
+int pm_max_storages() { return 16; }
+
+size_t pm_lds_bytes(int G, int tsw_entries) { return pm::offsets(G, tsw_entries).total; }
+
+hipError_t launch_pm(const ChunkArgs &a, int block, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL(pm_kernel, dim3(a.n_items), dim3(block), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t pm_occupancy(int block, size_t lds, int *blocks_per_cu)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)pm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, pm_kernel, block, lds);
+}
+
+} // namespace tapt

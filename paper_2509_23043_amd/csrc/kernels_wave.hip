@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(512) wave_kernel(ChunkArgs a)
     unsigned *flips = (unsigned *)ints;              // [G] by local slot
     unsigned *satt = flips + G, *sacc = flips + 2 * G;   // [G] by pair (s0 + l, s0 + l + 1)
     unsigned *patt = flips + 3 * G, *pacc = flips + 4 * G;
-    int *cursor = ints + 5 * G;                      // [G] bank cursor by local slot
+    int *cursor = ints + 5 * G;                      // [G] bank cursor by local slot at launch start
     int *stor_of = ints + 6 * G;                     // [G] final slot -> storage
     int *Efin = ints + 7 * G;                        // [G] final energy by storage
     WaveRec *rec = (WaveRec *)(ints + 8 * G);        // [G] (4 ints each)
@@ -221,8 +221,13 @@ __global__ void __launch_bounds__(512) wave_kernel(ChunkArgs a)
     }
     __syncthreads();
 
+    // lane p of every wavefront: LDS swap-table row (offset, length) of pair s0 - 1 + p
+    const int row_off_v = lane <= G ? tsw_off[lane] : 0;
+    const int row_len_v = lane <= G ? tsw_off[lane + 1] - row_off_v : 0;
     const bool active = wv < G;
     int label = s0 + wv;                // global slot held by this storage
+    uint32_t n_prop = 0;                // proposal stages run in this launch (every banked slot's
+                                        // cursor advances by one per stage)
     int E = active ? I.E[s0 + wv] : 0;
     int bestE = I.best->E;
     long long bestT = -1, hit = -1;
@@ -242,6 +247,12 @@ __global__ void __launch_bounds__(512) wave_kernel(ChunkArgs a)
         uint64_t prop_at = P.first_prop_from(t0 + 1);
         for (uint64_t t = t0 + 1; t <= tend && !failed; ++t) {
             const int l = label - s0;
+            // swap uniforms of every pair this workgroup touches (lane p: pair s0 - 1 + p)
+            // for the cycle this sweep ends, drawn before the sweep so that their
+            // latency hides behind it
+            uint32_t u_vec = 0;
+            if (phase + 1 == (uint32_t)P.M)
+                u_vec = philox_word0((uint32_t)(s0 - 1 + lane), cyc + 1, TAG_SWAP, P.k0, P.k1);
             int dE, nf;
             sw.sweep((uint32_t)lane, (uint32_t)t, (uint32_t)label, P.k0, P.k1, sp, tab + l * stride + P.D, dE, nf);
             dE = wave_sum(dE);
@@ -257,11 +268,8 @@ __global__ void __launch_bounds__(512) wave_kernel(ChunkArgs a)
                 if (prop_now) {
                     const int B = I.bank_n[label];
                     if (B > 0) {
-                        const int k = cursor[l];
-                        if (lane == 0) {
-                            cursor[l] = (k + 1 == B) ? 0 : k + 1;
-                            atomicAdd(&patt[l], 1u);
-                        }
+                        const int k = (int)(((uint32_t)cursor[l] + n_prop % (uint32_t)B) % (uint32_t)B);
+                        if (lane == 0) atomicAdd(&patt[l], 1u);
                         const int ET = I.bankE[label][k];
                         const long long dd = (long long)ET - (long long)E;
                         uint32_t T;
@@ -277,6 +285,7 @@ __global__ void __launch_bounds__(512) wave_kernel(ChunkArgs a)
                         }
                     }
                 }
+                if (prop_now) ++n_prop;
                 // ---- swap of this slot's pair (Eq. 1), alternating parity ----
                 const int first = (cyc & 1) ? 0 : 1;
                 const bool lower = ((label - first) & 1) == 0;
@@ -289,13 +298,14 @@ __global__ void __launch_bounds__(512) wave_kernel(ChunkArgs a)
                     if (pl >= 0 && pl < G) {
                         // same workgroup: LDS mailboxes by (cycle mod 4, local slot)
                         unsigned long long *mb = mail + (cyc & 3) * G;
+                        // (the word itself is the message: relaxed accesses suffice)
                         if (lane == 0)
-                            __hip_atomic_store(mb + l, ((unsigned long long)cyc << 32) | (uint32_t)E, __ATOMIC_RELEASE,
+                            __hip_atomic_store(mb + l, ((unsigned long long)cyc << 32) | (uint32_t)E, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_WORKGROUP);
                         uint32_t polls = 0;
                         unsigned long long v;
                         for (;;) {
-                            v = __hip_atomic_load(mb + pl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            v = __hip_atomic_load(mb + pl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                             if ((uint32_t)(v >> 32) == cyc) break;
                             __builtin_amdgcn_s_sleep(1);
                             if (++polls > a.spin_limit) break;
@@ -310,10 +320,10 @@ __global__ void __launch_bounds__(512) wave_kernel(ChunkArgs a)
                         }
                         pE = (int)(uint32_t)v;
                         const int dEs = lower ? pE - E : E - pE;    // E_{r+1} - E_r
-                        const uint32_t T = dEs >= 0 ? ALWAYS
-                                                    : (-dEs <= tsw_off[prow + 1] - tsw_off[prow]
-                                                           ? tsw[tsw_off[prow] - dEs - 1] : 0u);
-                        const uint32_t u = philox_word0((uint32_t)r, cyc, TAG_SWAP, P.k0, P.k1);
+                        const int off = __builtin_amdgcn_readlane(row_off_v, prow);
+                        const int len = __builtin_amdgcn_readlane(row_len_v, prow);
+                        const uint32_t T = dEs >= 0 ? ALWAYS : (-dEs <= len ? tsw[off - dEs - 1] : 0u);
+                        const uint32_t u = __builtin_amdgcn_readlane(u_vec, prow);
                         const bool acc = T == ALWAYS || u < T;
                         if (lower && lane == 0) {
                             atomicAdd(&satt[l], 1u);
@@ -382,10 +392,10 @@ __global__ void __launch_bounds__(512) wave_kernel(ChunkArgs a)
                         __builtin_amdgcn_wave_barrier();
                         pE = (int)stage[nw];
                         const int dEs = lower ? pE - E : E - pE;
-                        const uint32_t T = dEs >= 0 ? ALWAYS
-                                                    : (-dEs <= tsw_off[prow + 1] - tsw_off[prow]
-                                                           ? tsw[tsw_off[prow] - dEs - 1] : 0u);
-                        const uint32_t u = philox_word0((uint32_t)r, cyc, TAG_SWAP, P.k0, P.k1);
+                        const int off = __builtin_amdgcn_readlane(row_off_v, prow);
+                        const int len = __builtin_amdgcn_readlane(row_len_v, prow);
+                        const uint32_t T = dEs >= 0 ? ALWAYS : (-dEs <= len ? tsw[off - dEs - 1] : 0u);
+                        const uint32_t u = __builtin_amdgcn_readlane(u_vec, prow);
                         const bool acc = T == ALWAYS || u < T;
                         if (side == 1 && lane == 0) {   // the lower workgroup owns the pair's counters
                             atomicAdd(&satt[l], 1u);
@@ -441,7 +451,10 @@ __global__ void __launch_bounds__(512) wave_kernel(ChunkArgs a)
     for (int l = tid; l < G; l += bs) {
         I.E[s0 + l] = Efin[stor_of[l]];
         I.flips[s0 + l] += flips[l];
-        I.cursor[s0 + l] = cursor[l];
+        {   // every wavefront ran the same proposal stages; these threads are in wavefront 0
+            const int B = I.bank_n[s0 + l];
+            if (B > 0) I.cursor[s0 + l] = (int)(((uint32_t)cursor[l] + n_prop % (uint32_t)B) % (uint32_t)B);
+        }
         I.prop_att[s0 + l] += patt[l];
         I.prop_acc[s0 + l] += pacc[l];
         if (s0 + l + 1 < P.R) {

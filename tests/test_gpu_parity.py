@@ -238,3 +238,32 @@ def test_mixed_sizes_one_launch():
         ref = oracle.Run(g, b, seed=seed, banks=banks, **kw)
         ref.run(60)
         compare(ctx, ref)
+
+
+@pytest.mark.parametrize("kernel,G,rule,M", [("pm", 8, "metropolis", 1), ("pm", 2, "gibbs", 1), ("pm", 4, "metropolis", 3),
+                                             ("pm", 16, "gibbs", 2), ("wave", 8, "metropolis", 1), ("wave", 3, "gibbs", 2),
+                                             ("block", 8, "metropolis", 1)])
+def test_l8_kernels(kernel, G, rule, M):
+    """The three persistent kernels that run 8^3 lattices, on the benchmark's
+    shape (R = 32, proposals from banks) for several instances."""
+    announce(f"L=8 R=32 x 6 instances, kernel={kernel} G={G} rule={rule} M={M}, 2 launches of 90 sweeps")
+    betas = inputs.geometric_ladder(32)
+    cases = []
+    for i in range(6):
+        g = inputs.ea_lattice(8, 4100 + i)
+        banks = {r: inputs.random_bank(512, 5, seed=9100 + 40 * i + r) for r in range(0, 30, 3)}
+        cases.append((g, banks, 6100 + i))
+    kw = dict(rule=rule, M=M, prop_start=6 * M, prop_period=6 * M, target=-700)
+    ctxs = []
+    for g, banks, seed in cases:
+        c = binding.Context(g, betas, seed=seed, **kw)
+        for r, b in banks.items():
+            c.propose(r, b)
+        ctxs.append(c)
+    bt = binding.Batch(ctxs, replicas_per_wg=G, chunk_sweeps=90, kernel=kernel)
+    bt.sweep(180)
+    import oracle
+    for c, (g, banks, seed) in zip(ctxs, cases):
+        ref = oracle.Run(g, betas, seed=seed, banks=banks, **kw)
+        ref.run(180)
+        compare(c, ref)
