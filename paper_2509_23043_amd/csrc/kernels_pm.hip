@@ -206,12 +206,18 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
         uint32_t cyc = (uint32_t)(t0 / (uint64_t)P.M), phase = (uint32_t)(t0 % (uint64_t)P.M);
         uint64_t prop_at = P.first_prop_from(t0 + 1);
         const int lab0 = s0 + SPW * wv;          // this wavefront's slots: lab0, lab0 + 1
+        uint32_t u_vec = 0, u_base = 0xFFFFFFFFu;
 
         for (uint64_t t = t0 + 1; t <= tend && !failed; ++t) {
             const bool ends = phase + 1 == (uint32_t)P.M;
-            // swap uniforms of the pairs of this workgroup (lane p: pair s0 - 1 + p)
-            uint32_t u_vec = 0;
-            if (ends) u_vec = philox_word0((uint32_t)(s0 - 1 + lane), cyc + 1, TAG_SWAP, P.k0, P.k1);
+            // swap uniforms of the pairs of this workgroup: lane p < 32 holds pair
+            // s0 - 1 + p at cycle u_base, lane 32 + p the same pair at u_base + 1
+            // (one Philox call per two cycles, drawn before the sweep so that its
+            // latency hides behind it)
+            if (ends && cyc + 1 != u_base && cyc + 1 != u_base + 1) {
+                u_base = cyc + 1;
+                u_vec = philox_word0((uint32_t)(s0 - 1 + (lane & 31)), u_base + (uint32_t)(lane >> 5), TAG_SWAP, P.k0, P.k1);
+            }
 
             // ---- sweep both slots (colour phases outermost, so that the two
             // slots' independent work interleaves) ----
@@ -321,7 +327,7 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                     const int r = lab0;
                     if (r + 1 < P.R) {
                         const int prow = r - (s0 - 1);
-                        const bool ok = swap_ok(E[1] - E[0], __builtin_amdgcn_readlane(u_vec, prow),
+                        const bool ok = swap_ok(E[1] - E[0], __builtin_amdgcn_readlane(u_vec, (cyc == u_base ? 0 : 32) + prow),
                                                 __builtin_amdgcn_readlane(row_off_v, prow),
                                                 __builtin_amdgcn_readlane(row_len_v, prow), tsw);
                         satt[0] += 1;
@@ -360,14 +366,16 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                         const int buf_x = (cyc >> 1) & 1;
                         const unsigned long long tag = (unsigned long long)cyc << 32;
                         unsigned long long *out = it.xbuf + ((size_t)(it.w * 2 + side) * 2 + buf_x) * it.xwords;
-                        const uint8_t *B = bufs + buf[k] * N;
-                        // 8 ballots of 64 down-bits: word 2m + h holds sites 64m + 32h .. +31
+                        // one ballot per x over the lanes' rows (no LDS round trip per
+                        // ballot): word 2x + h holds the sites 8q + x of rows
+                        // q = 32h .. 32h + 31 (bit set = spin +1)
+                        const uint2 row = *(const uint2 *)(bufs + buf[k] * N + rel_me);
 #pragma unroll
-                        for (int m8 = 0; m8 < 8; ++m8) {
-                            const unsigned long long bal = __ballot(B[64 * m8 + lane] == 0);   // bit = spin +1
+                        for (int x = 0; x < 8; ++x) {
+                            const uint32_t byte = ((x < 4 ? row.x : row.y) >> (8 * (x & 3))) & 0xFFu;
+                            const unsigned long long bal = __ballot(byte == 0);
                             if (lane < 2)
-                                __hip_atomic_store(out + 2 * m8 + lane,
-                                                   tag | (lane ? (bal >> 32) : (bal & 0xFFFFFFFFull)),
+                                __hip_atomic_store(out + 2 * x + lane, tag | (lane ? (bal >> 32) : (bal & 0xFFFFFFFFull)),
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         }
                         if (lane == 0)
@@ -411,7 +419,7 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                         const int r = side == 0 ? slot - 1 : slot;
                         const int prow = r - (s0 - 1);
                         const int dEs = side == 0 ? E[k] - pE : pE - E[k];
-                        const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, prow),
+                        const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, (cyc == u_base ? 0 : 32) + prow),
                                                  __builtin_amdgcn_readlane(row_off_v, prow),
                                                  __builtin_amdgcn_readlane(row_len_v, prow), tsw);
                         if (side == 1) {   // the lower workgroup owns the pair's counters
@@ -420,12 +428,19 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                         }
                         E[k] = okx ? pE : E[k];
                         if (okx) {
-                            // row of this lane: sites 8 lane .. 8 lane + 7 = bits (8 lane) & 31 .. of word lane >> 2
-                            const uint32_t wd = stage[lane >> 2] >> ((8 * lane) & 31);
+                            // this lane's row: bit (lane & 31) of words 2x + (lane >> 5)
+                            const int h = lane >> 5, bit = lane & 31;
+                            uint32_t wx[8];
+#pragma unroll
+                            for (int x = 0; x < 8; ++x) wx[x] = stage[2 * x + h];
                             uint2 d;
-                            d.x = (~wd & 1u) | ((~wd & 2u) << 7) | ((~wd & 4u) << 14) | ((~wd & 8u) << 21);
-                            d.y = ((~wd >> 4) & 1u) | (((~wd >> 4) & 2u) << 7) | (((~wd >> 4) & 4u) << 14) |
-                                  (((~wd >> 4) & 8u) << 21);
+                            d.x = d.y = 0;
+#pragma unroll
+                            for (int x = 0; x < 8; ++x) {
+                                const uint32_t down = ((wx[x] >> bit) & 1u) ^ 1u;
+                                if (x < 4) d.x |= down << (8 * x);
+                                else d.y |= down << (8 * (x - 4));
+                            }
                             *(uint2 *)(bufs + buf[k] * N + rel_me) = d;
                         }
                     }
@@ -461,7 +476,7 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                             const int r = side == 0 ? slot - 1 : slot;
                             const int prow = r - (s0 - 1);
                             const int dEs = side == 0 ? E[k] - pE : pE - E[k];
-                            const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, prow),
+                            const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, (cyc == u_base ? 0 : 32) + prow),
                                                      __builtin_amdgcn_readlane(row_off_v, prow),
                                                      __builtin_amdgcn_readlane(row_len_v, prow), tsw);
                             if (side == 1) {
