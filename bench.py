@@ -154,15 +154,24 @@ def cpu_baseline(bank_host, L, R, sweeps, log):
 
 
 def kernel_source_hash():
-    """Hash of the sources of the chunk kernel (body and specialisations)."""
+    """Hash of every device source of the library (a counter file taken on
+    another version of the kernels does not apply)."""
     h = hashlib.sha256()
-    for f in ("sweep.h", "kernels.hip", "tapt_dev.h"):
-        h.update(open(os.path.join(ROOT, "paper_2509_23043_amd", "csrc", f), "rb").read())
+    csrc = os.path.join(ROOT, "paper_2509_23043_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()
 
 
-def traffic_from_profiles(launch_sweeps, kern_hash):
-    path = os.path.join(ROOT, "profiles", "traffic_chunk_kernel_ea_l8_r32_x64.json")
+KERNEL_NAMES = {"pm": "pm_kernel", "wave": "wave_kernel<8>", "block": "chunk_kernel<LatSweep<8,*>>"}
+
+
+def traffic_from_profiles(launch_sweeps, kern_hash, kern):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, if it was taken on these sources with this launch length."""
+    tag = {"pm": "pm_kernel", "wave": "wave_kernel", "block": "chunk_kernel"}[kern]
+    path = os.path.join(ROOT, "profiles", f"traffic_{tag}_ea_l8_r32_x64.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
@@ -405,9 +414,10 @@ def main():
     att_launch = attempts / max(launches, 1)
     achieved = OPS_PER_ATTEMPT * att_launch / (avg_ms * 1e-3) / 1e12
     kern_hash = kernel_source_hash()
+    ran = kern if kern != "auto" else ("pm" if ctxs[0].pm else "wave")
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TOP/s",
-                frac=round(achieved / VALU_PEAK_TOPS, 4), traffic=traffic_from_profiles(S, kern_hash),
-                kernel="chunk_kernel<LatSweep<8,*>>", avg_launch_ms=round(avg_ms, 4), launches=launches,
+                frac=round(achieved / VALU_PEAK_TOPS, 4), traffic=traffic_from_profiles(S, kern_hash, ran),
+                kernel=KERNEL_NAMES[ran], avg_launch_ms=round(avg_ms, 4), launches=launches,
                 ops_per_attempt=OPS_PER_ATTEMPT,
                 lds=dict(bytes_per_attempt=LDS_BYTES_PER_ATTEMPT,
                          achieved_TBps=round(LDS_BYTES_PER_ATTEMPT * att_launch / (avg_ms * 1e-3) / 1e12, 3),

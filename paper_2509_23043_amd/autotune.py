@@ -48,10 +48,12 @@ def candidates(contexts):
     """(replicas_per_wg, replicas_per_thread, kernel) triples worth timing:
     every cap on the slots per workgroup up to the longest ladder, with 1, 2
     or 4 slots per thread in the workgroup-synchronous kernel (the runtime
-    lowers the cap per context until it fits), and the wave-per-replica kernel
-    where every context is a lattice it supports."""
+    lowers the cap per context until it fits), the wave-per-replica kernel
+    where every context is an 8^3 lattice, and the +-J 8^3 kernel where every
+    coupling is +-1 and every ladder has even length."""
     rmax = max(c.R for c in contexts)
     wave_ok = all(c.kind == "lattice" and c.L == 8 for c in contexts)
+    pm_ok = all(getattr(c, "pm", False) for c in contexts)
     out = []
     for G in G_CANDIDATES:
         if G > 2 * rmax:
@@ -61,6 +63,8 @@ def candidates(contexts):
                 out.append((G, rpt, "block"))
         if wave_ok and G <= 8:
             out.append((G, 1, "wave"))
+        if pm_ok and 2 <= G <= 16:
+            out.append((G, 1, "pm"))
     return out
 
 

@@ -162,10 +162,12 @@ class Context:
         g = _Graph()
         g.n = n
         self.kind, self.L = "csr", 0
+        self.pm = False     # the +-J 8^3 kernel applies (every coupling +-1, even ladder)
         if problem.get("lattice_L") and not np.any(problem.get("h", 0)) and not np.any(problem.get("clamp", 0)):
             g.lattice_L = int(problem["lattice_L"])
             self.kind = "lattice" if g.lattice_L <= 16 else "csr"
             self.L = g.lattice_L
+            self.pm = self.L == 8 and self.R % 2 == 0 and bool(np.all(np.abs(np.asarray(problem["J3"])) == 1))
             g.J = _p(keep(np.asarray(problem["J3"]).reshape(-1), np.int32), C.c_int32)
             g.nnz = 0
         else:

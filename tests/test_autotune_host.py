@@ -6,14 +6,17 @@ import types
 from paper_2509_23043_amd import autotune
 
 
-def _ctx(kind, L, n, R):
-    return types.SimpleNamespace(kind=kind, L=L, n=n, R=R, nfree=n, close=lambda: None)
+def _ctx(kind, L, n, R, pm=False):
+    return types.SimpleNamespace(kind=kind, L=L, n=n, R=R, nfree=n, pm=pm, close=lambda: None)
 
 
 def test_candidates_cover_caps_and_threads():
     c = autotune.candidates([_ctx("lattice", 8, 512, 32)])
     assert (8, 1, "block") in c and (32, 4, "block") in c and (64, 2, "block") in c and (8, 1, "wave") in c
     assert all(rpt <= G for G, rpt, _ in c)
+    assert not any(k == "pm" for _, _, k in c)
+    c3 = autotune.candidates([_ctx("lattice", 8, 512, 32, pm=True)])
+    assert (8, 1, "pm") in c3 and (16, 1, "pm") in c3
     c2 = autotune.candidates([_ctx("lattice", 4, 64, 3)])
     assert max(G for G, _, _ in c2) <= 6 and all(k == "block" for _, _, k in c2)
 
