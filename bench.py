@@ -153,14 +153,16 @@ def cpu_baseline(bank_host, L, R, sweeps, log):
                        f"with proposals every 100 sweeps, banks as on the GPU")
 
 
-def kernel_source_hash():
-    """Hash of every device source of the library (a counter file taken on
-    another version of the kernels does not apply)."""
+KERNEL_SOURCES = {"pm": "kernels_pm.hip", "wave": "kernels_wave.hip", "block": "kernels.hip"}
+
+
+def kernel_source_hash(kern="pm"):
+    """Hash of the device sources that make up one kernel (a counter file
+    taken on another version of that kernel does not apply)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2509_23043_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in ("tapt_dev.h", "sweep.h", KERNEL_SOURCES[kern]):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()
 
 
@@ -413,8 +415,8 @@ def main():
     avg_ms = kern_ms / max(launches, 1)
     att_launch = attempts / max(launches, 1)
     achieved = OPS_PER_ATTEMPT * att_launch / (avg_ms * 1e-3) / 1e12
-    kern_hash = kernel_source_hash()
     ran = kern if kern != "auto" else ("pm" if ctxs[0].pm else "wave")
+    kern_hash = kernel_source_hash(ran)
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TOP/s",
                 frac=round(achieved / VALU_PEAK_TOPS, 4), traffic=traffic_from_profiles(S, kern_hash, ran),
                 kernel=KERNEL_NAMES[ran], avg_launch_ms=round(avg_ms, 4), launches=launches,

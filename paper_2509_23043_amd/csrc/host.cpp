@@ -811,19 +811,22 @@ struct pt_batch {
     }
 };
 
-// Choose (slots per workgroup, slots per thread) for a context. A mixed
-// launch takes at most two slots per thread (its block limit is the same).
+// Choose (slots per workgroup, slots per thread) for a context. In a mixed
+// launch every size has 1, 2 or 4 slots per thread (its block limit is the
+// same); large lattices take 4 so that a batch of many sizes stays co-resident.
 static void choose_tiling(const pt_ctx *c, const pt_batch_opts &o, bool mixed, int &G, int &rpt)
 {
     const int R = c->R;
     rpt = o.replicas_per_thread > 0 ? o.replicas_per_thread : 0;
+    if (rpt == 3) rpt = 2;      // the kernels come with 1, 2 or 4 slots per thread
+    if (rpt > 4) rpt = 4;
     G = o.replicas_per_wg > 0 ? std::min(std::min(o.replicas_per_wg, R), 64) : 0;
     if (c->kind == KIND_CSR) {
         rpt = 1;
         if (!G) G = std::min(R, 32);
         return;
     }
-    if (mixed && rpt > 2) rpt = 2;
+    if (mixed && !rpt && c->n >= 1000) rpt = 4;
     // the cycle-end stages keep one slot per lane of a wavefront: G <= 64
     const int NC = c->n / 8;
     const int maxt = mixed ? mixed_max_threads() : lattice_max_threads();

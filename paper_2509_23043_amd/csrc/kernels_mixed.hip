@@ -13,7 +13,7 @@ constexpr int MIXED_MAXT = 512;
 
 __host__ __device__ constexpr int mixed_variant(int kind, int L, int rpt)
 {
-    return kind == KIND_CSR ? 0 : 1 + ((L - 4) / 2) * 2 + (rpt - 1);
+    return kind == KIND_CSR ? 0 : 1 + ((L - 4) / 2) * 3 + (rpt == 4 ? 2 : rpt - 1);
 }
 
 // Each variant is a separate (not inlined) function, so that it gets its own
@@ -32,7 +32,8 @@ __global__ void __launch_bounds__(MIXED_MAXT) chunk_kernel_mixed(ChunkArgs a)
     case 0: chunk_body_call<CsrSweep>(a, item); break;
 #define X(LL)                                                                      \
     case mixed_variant(KIND_LATTICE, LL, 1): chunk_body_call<LatSweep<LL, 1>>(a, item); break; \
-    case mixed_variant(KIND_LATTICE, LL, 2): chunk_body_call<LatSweep<LL, 2>>(a, item); break;
+    case mixed_variant(KIND_LATTICE, LL, 2): chunk_body_call<LatSweep<LL, 2>>(a, item); break; \
+    case mixed_variant(KIND_LATTICE, LL, 4): chunk_body_call<LatSweep<LL, 4>>(a, item); break;
         TAPT_MIXED_LATTICE_LIST(X)
 #undef X
     default: break;

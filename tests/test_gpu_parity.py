@@ -267,3 +267,63 @@ def test_l8_kernels(kernel, G, rule, M):
         ref = oracle.Run(g, betas, seed=seed, banks=banks, **kw)
         ref.run(180)
         compare(c, ref)
+
+
+def test_mixed_sizes_full_batch():
+    """The mixed-size workload at its full count: 8 instances of each of
+    L = 6, 8, 10, 12, 16 with ladders of 24..48 slots, proposals every 50
+    sweeps, one persistent launch; one instance per size checked against
+    the oracle, every instance against its own recomputed energies."""
+    announce("mixed sizes x 8 instances each (40 contexts, 1440 replicas), one launch, 2 x 50 sweeps")
+    import oracle
+    sizes = [(6, 24), (8, 30), (10, 36), (12, 42), (16, 48)]
+    ctxs, cases = [], []
+    for k, (L, R) in enumerate(sizes):
+        betas = inputs.geometric_ladder(R)
+        for i in range(8):
+            g = inputs.ea_lattice(L, 3000 + 10 * k + i)
+            banks = {r: inputs.random_bank(g["n"], 3, seed=8000 + 100 * k + 10 * i + r) for r in range(0, R - 2, 8)}
+            kw = dict(prop_start=50, prop_period=50)
+            c = binding.Context(g, betas, seed=300 + 10 * k + i, **kw)
+            for r, b in banks.items():
+                c.propose(r, b)
+            ctxs.append(c)
+            cases.append((g, betas, banks, kw, 300 + 10 * k + i, i == 0))
+    bt = binding.Batch(ctxs, chunk_sweeps=50)
+    bt.sweep(100)
+    for c, (g, betas, banks, kw, seed, check) in zip(ctxs, cases):
+        spins, t = c.state()
+        assert t == 100
+        erun = oracle.Run(g, [1.0], seed=0)
+        want = np.array([erun.energy(spins[r]) for r in range(len(betas))])
+        assert np.array_equal(c.energies(), want)
+        if check:
+            ref = oracle.Run(g, betas, seed=seed, banks=banks, **kw)
+            ref.run(100)
+            compare(c, ref)
+
+
+def test_factorization_batch_8bit():
+    """8 x 8-bit multipliers (200 spins, 176 free) with R = 32 in one launch,
+    the factorization batch's shape; two instances checked against the oracle."""
+    announce("8-bit multipliers x 8 products, R=32, one launch, 120 sweeps")
+    import oracle
+    betas = inputs.geometric_ladder(32)
+    egnd = -3 * 64 - 4 * 8 * 7
+    ctxs, cases = [], []
+    for i, (C, p, q) in enumerate(inputs.semiprimes(8, 8, seed=4000)):
+        g = inputs.multiplier(8, C)
+        banks = {r: inputs.random_bank(g["n"], 4, seed=4100 + 32 * i + r, clamp=g["clamp"]) for r in range(0, 23, 4)}
+        kw = dict(prop_start=20, prop_period=20, target=egnd)
+        c = binding.Context(g, betas, seed=4200 + i, **kw)
+        for r, b in banks.items():
+            c.propose(r, b)
+        ctxs.append(c)
+        cases.append((g, banks, kw, 4200 + i))
+    bt = binding.Batch(ctxs, chunk_sweeps=60)
+    bt.sweep(120)
+    for i in (0, 5):
+        g, banks, kw, seed = cases[i]
+        ref = oracle.Run(g, betas, seed=seed, banks=banks, **kw)
+        ref.run(120)
+        compare(ctxs[i], ref)
