@@ -31,7 +31,7 @@ namespace tapt {
 bool lattice_supported(int L);
 int lattice_max_threads();
 int lattice_threads(int L, int G, int rpt);
-size_t chunk_lds_bytes(int kind, int n, int G, int stride, int tsw_entries);
+size_t chunk_lds_bytes(int kind, int n, int G, int stride, int tsw_entries, int nnz, int nfree, int ncolors);
 hipError_t launch_chunk(int kind, int L, int rpt, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t chunk_occupancy(int kind, int L, int rpt, int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_finish(const WorkItem *items, const int *first_item, int n_inst, uint32_t K, InstStatus *status,
@@ -49,7 +49,8 @@ int pm_max_storages();
 size_t pm_lds_bytes(int G, int tsw_entries);
 hipError_t launch_pm(const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t pm_occupancy(int block, size_t lds, int *blocks_per_cu);
-hipError_t launch_plain(int kind, int L, const InstDev *dI, int R, int n, int stride, uint32_t t, hipStream_t s);
+hipError_t launch_plain(int kind, int L, const InstDev *dI, int R, int n, int stride, int nnz, int nfree, int ncolors,
+                        uint32_t t, hipStream_t s);
 hipError_t launch_init(const InstDev *dI, int R, int n, hipStream_t s);
 hipError_t launch_energy(const InstDev *dI, const int8_t *cfg, int k, int32_t *out, hipStream_t s);
 hipError_t launch_init_best(const InstDev *dI, hipStream_t s);
@@ -658,7 +659,8 @@ extern "C" int pt_sweep(pt_ctx *c, uint64_t n_sweeps)
     const int stride = 2 * c->D + 1;
     for (uint64_t k = 0; k < n_sweeps; ++k) {
         uint32_t t = (uint32_t)(c->t_host + k + 1);
-        hipError_t e = launch_plain(c->kind, c->L, c->inst.as<InstDev>(), c->R, c->n, stride, t, s);
+        hipError_t e = launch_plain(c->kind, c->L, c->inst.as<InstDev>(), c->R, c->n, stride, c->hI.nnz, c->hI.nfree,
+                                    c->ncolors, t, s);
         if (e != hipSuccess) {
             c->broken = true;
             return fail(PT_EDEVICE, "plain sweep launch: %s", hipGetErrorString(e));
@@ -909,7 +911,8 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         pt_ctx *c = g->ctxs[k];
         P.lds = std::max(P.lds, g->pm     ? pm_lds_bytes(P.ctx[k].gmax, P.tsw_max)
                                 : g->wave ? wave_lds_bytes(c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max)
-                                          : chunk_lds_bytes(c->kind, c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max));
+                                          : chunk_lds_bytes(c->kind, c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max,
+                                                            c->hI.nnz, c->hI.nfree, c->ncolors));
     }
     if (P.lds > 160 * 1024) return fail(PT_EUNSUPPORTED, "tiling needs %zu B of LDS per workgroup", P.lds);
     if (g->pm)

@@ -92,8 +92,10 @@ __global__ void __launch_bounds__(Sw::MAXT) plain_sweep_kernel(const InstDev *Ip
     sw.setup(I, 1);
     const int SB = SweepCall<Sw>::SB(sw);
     const int stride = I.tflip_stride;
-    const ChunkOff lof = chunk_lds_offsets(1, SB, stride, Sw::RND ? ((n + 7) & ~7) : 0, 0, n);
+    const ChunkOff lof = chunk_lds_offsets(1, SB, stride, Sw::RND ? ((n + 7) & ~7) : 0, 0, n,
+                                           SweepCall<Sw>::graph_bytes(I));
     CHUNK_LDS_POINTERS(c, lof, 1, lds_raw);
+    SweepCall<Sw>::bind(sw, I, lds_raw + lof.graph, tid, bs);
     for (int x = tid; x < stride; x += bs) c.tab[x] = I.tflip[(size_t)r * stride + x];
     for (int i = tid; i < n; i += bs) c.sp[SweepCall<Sw>::lidx(sw, i)] = I.spins[(size_t)r * n + i];
     if (tid == 0) {
@@ -310,11 +312,12 @@ int lattice_max_threads() { return 512; }
 
 int lattice_threads(int L, int G, int rpt) { return ((G + rpt - 1) / rpt) * (L * L * L / 8); }
 
-size_t chunk_lds_bytes(int kind, int n, int G, int stride, int tsw_entries)
+size_t chunk_lds_bytes(int kind, int n, int G, int stride, int tsw_entries, int nnz, int nfree, int ncolors)
 {
     int SB = kind == KIND_LATTICE ? n : CsrSweep::storage_bytes(n);
     int nr = kind == KIND_LATTICE ? 0 : ((n + 7) & ~7);
-    return chunk_lds_offsets(G, SB, stride, nr, tsw_entries, n).total;
+    size_t gb = kind == KIND_LATTICE ? 0 : csr_graph_bytes(n, nnz, nfree, ncolors);
+    return chunk_lds_offsets(G, SB, stride, nr, tsw_entries, n, gb).total;
 }
 
 template <class K>
@@ -385,9 +388,10 @@ static hipError_t launch_plain_sweep_t(const InstDev *dI, int R, int block, size
     return hipGetLastError();
 }
 
-hipError_t launch_plain(int kind, int L, const InstDev *dI, int R, int n, int stride, uint32_t t, hipStream_t s)
+hipError_t launch_plain(int kind, int L, const InstDev *dI, int R, int n, int stride, int nnz, int nfree, int ncolors,
+                        uint32_t t, hipStream_t s)
 {
-    size_t lds = chunk_lds_bytes(kind, n, 1, stride, 0);
+    size_t lds = chunk_lds_bytes(kind, n, 1, stride, 0, nnz, nfree, ncolors);
     hipError_t e;
     if (kind == KIND_CSR) {
         e = launch_plain_sweep_t<CsrSweep>(dI, R, 256, lds, t, s);

@@ -249,18 +249,64 @@ struct LatSweep {
     }
 };
 
+// LDS copy of a general graph, staged once per launch: row offsets, packed
+// (column << 8 | coupling) words, fields, free sites sorted by colour and the
+// colour offsets. Sizes come from the instance, so host and device agree.
+struct CsrGraph {
+    int *rp;
+    uint32_t *cw;
+    int16_t *h;
+    int16_t *cs;
+    int *coff;
+};
+
+__host__ __device__ inline size_t csr_graph_bytes(int n, int nnz, int nfree, int ncolors)
+{
+    size_t o = 0;
+    o = (o + (size_t)(n + 1) * 4 + 15) & ~(size_t)15;
+    o = (o + (size_t)(nnz > 0 ? nnz : 1) * 4 + 15) & ~(size_t)15;
+    o = (o + (size_t)n * 2 + 15) & ~(size_t)15;
+    o = (o + (size_t)(nfree > 0 ? nfree : 1) * 2 + 15) & ~(size_t)15;
+    o = (o + (size_t)(ncolors + 1) * 4 + 15) & ~(size_t)15;
+    return o;
+}
+
+__device__ __forceinline__ CsrGraph csr_graph_carve(unsigned char *base, int n, int nnz, int nfree, int ncolors)
+{
+    CsrGraph g;
+    size_t o = 0;
+    g.rp = (int *)(base + o); o = (o + (size_t)(n + 1) * 4 + 15) & ~(size_t)15;
+    g.cw = (uint32_t *)(base + o); o = (o + (size_t)(nnz > 0 ? nnz : 1) * 4 + 15) & ~(size_t)15;
+    g.h = (int16_t *)(base + o); o = (o + (size_t)n * 2 + 15) & ~(size_t)15;
+    g.cs = (int16_t *)(base + o); o = (o + (size_t)(nfree > 0 ? nfree : 1) * 2 + 15) & ~(size_t)15;
+    g.coff = (int *)(base + o);
+    (void)ncolors;
+    return g;
+}
+
+__device__ __forceinline__ void csr_graph_stage(const InstDev &I, const CsrGraph &g, int tid, int bs)
+{
+    for (int i = tid; i <= I.n; i += bs) g.rp[i] = I.row_ptr[i];
+    for (int e = tid; e < I.nnz; e += bs) g.cw[e] = ((uint32_t)I.col[e] << 8) | ((uint32_t)I.Jc[e] & 0xFFu);
+    for (int i = tid; i < I.n; i += bs) g.h[i] = I.h[i];
+    for (int k = tid; k < I.nfree; k += bs) g.cs[k] = I.color_sites[k];
+    for (int c = tid; c <= I.ncolors; c += bs) g.coff[c] = I.color_off[c];
+}
+
 // General sparse graph (CSR, any proper coloring, clamps, fields). Random
 // halves for every site of every storage are staged in LDS at the start of
 // the sweep (one Philox call per 8 sites), then each color class is spread
 // over all threads of the workgroup.
 struct CsrSweep {
     static constexpr int RPTV = 1;
-    static constexpr int MAXT = 1024;
+    static constexpr int MAXT = 512;    // leaves 256 VGPRs, no spills
     static constexpr bool RND = true;   // random halves staged in LDS
     int n, SB, nr;
+    CsrGraph gr;
 
     __host__ __device__ static int storage_bytes(int n) { return (n + 15) & ~15; }
     __device__ int lidx(int i) const { return i; }
+    __device__ static size_t graph_bytes(const InstDev &I) { return csr_graph_bytes(I.n, I.nnz, I.nfree, I.ncolors); }
 
     __device__ void setup(const InstDev &I, int G)
     {
@@ -268,6 +314,13 @@ struct CsrSweep {
         n = I.n;
         SB = storage_bytes(n);
         nr = (n + 7) & ~7;
+    }
+
+    // carve and fill the LDS copy of the graph (before the staging barrier)
+    __device__ __forceinline__ void bind(const InstDev &I, unsigned char *base, int tid, int bs)
+    {
+        gr = csr_graph_carve(base, I.n, I.nnz, I.nfree, I.ncolors);
+        csr_graph_stage(I, gr, tid, bs);
     }
 
     __device__ __forceinline__ void sweep(const InstDev &I, int G, int s0, uint32_t t, const int *slot_of,
@@ -284,26 +337,44 @@ struct CsrSweep {
         }
         __syncthreads();
         const int D = I.D;
-        for (int c = 0; c < I.ncolors; ++c) {
-            int off = I.color_off[c], cnt = I.color_off[c + 1] - off;
+        const int ncol = I.ncolors;
+        for (int c = 0; c < ncol; ++c) {
+            const int off = gr.coff[c], cnt = gr.coff[c + 1] - off;
+            if (cnt <= 0) continue;
+            // (storage k, site index s) of idx = k * cnt + s, stepped without division
+            const int dq = bs / cnt, dr = bs - dq * cnt;
+            int k = tid / cnt, s = tid - k * cnt;
             for (int idx = tid; idx < G * cnt; idx += bs) {
-                int k = idx / cnt;
-                int i = I.color_sites[off + idx - k * cnt];
+                const int i = gr.cs[off + s];
                 int8_t *m_k = sp + k * SB;
-                int f = I.h[i];
-                for (int e = I.row_ptr[i]; e < I.row_ptr[i + 1]; ++e) f += (int)I.Jc[e] * (int)m_k[I.col[e]];
-                int m = m_k[i];
-                int d = m * f;
-                int sl = slot_of[k];
-                uint32_t T = tab[sl * stride + D + d];
-                uint32_t hs = (uint32_t)rnd[(size_t)k * nr + i] << 16;
+                int f = gr.h[i];
+                const int e1 = gr.rp[i + 1];
+                int e = gr.rp[i];
+                // four neighbours per step: their words, then their spins, are
+                // independent loads (two LDS round trips per four bonds)
+                for (; e + 4 <= e1; e += 4) {
+                    const uint32_t w0 = gr.cw[e], w1 = gr.cw[e + 1], w2 = gr.cw[e + 2], w3 = gr.cw[e + 3];
+                    const int n0 = m_k[w0 >> 8], n1 = m_k[w1 >> 8], n2 = m_k[w2 >> 8], n3 = m_k[w3 >> 8];
+                    f += (int)(int8_t)(w0 & 0xFFu) * n0 + (int)(int8_t)(w1 & 0xFFu) * n1 +
+                         (int)(int8_t)(w2 & 0xFFu) * n2 + (int)(int8_t)(w3 & 0xFFu) * n3;
+                }
+                for (; e < e1; ++e) {
+                    const uint32_t w = gr.cw[e];
+                    f += (int)(int8_t)(w & 0xFFu) * (int)m_k[w >> 8];
+                }
+                const int m = m_k[i];
+                const int d = m * f;
+                const int sl = slot_of[k];
+                const uint32_t T = tab[sl * stride + D + d];
+                const uint32_t hs = (uint32_t)rnd[(size_t)k * nr + i] << 16;
                 bool maybe;
                 bool acc = coarse_accept(T, hs, maybe);
                 if (any_lane(maybe)) {
                     if (maybe) {
                         P4 r2 = philox((uint32_t)(i >> 3), t, (uint32_t)(s0 + sl), TAG_REFINE, I.seed_lo, I.seed_hi);
-                        uint32_t wd = r2.v[(i & 7) >> 1];
-                        uint32_t lo = ((i & 1) ? (wd >> 16) : wd) & 0xFFFFu;
+                        const int wq = (i & 7) >> 1;   // word of the half (no dynamic indexing)
+                        const uint32_t wd = wq == 0 ? r2.v[0] : wq == 1 ? r2.v[1] : wq == 2 ? r2.v[2] : r2.v[3];
+                        const uint32_t lo = ((i & 1) ? (wd >> 16) : wd) & 0xFFFFu;
                         acc = (T == ALWAYS) || ((hs | lo) < T);
                     }
                 }
@@ -311,6 +382,12 @@ struct CsrSweep {
                     m_k[i] = (int8_t)(-m);
                     atomicAdd(&Elds[k], 2 * d);
                     atomicAdd(&flips_lds[sl], 1u);
+                }
+                s += dr;
+                k += dq;
+                if (s >= cnt) {
+                    s -= cnt;
+                    ++k;
                 }
             }
             __syncthreads();
@@ -337,13 +414,13 @@ struct ChunkLds {
 };
 
 struct ChunkOff {
-    size_t sp, tab, ints, src, rnd, toff, tsw, xst, usw, total;
+    size_t sp, tab, ints, src, rnd, toff, tsw, xst, usw, graph, total;
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 __host__ __device__ __forceinline__ ChunkOff chunk_lds_offsets(int G, int SB, int stride, int nr_csr, int tsw_entries,
-                                                                int n)
+                                                                int n, size_t graph_bytes = 0)
 {
     ChunkOff f;
     size_t o = 0;
@@ -356,6 +433,7 @@ __host__ __device__ __forceinline__ ChunkOff chunk_lds_offsets(int G, int SB, in
     f.tsw = o; o = align16(o + (size_t)tsw_entries * 4);
     f.xst = o; o = align16(o + (size_t)2 * (((n + 31) >> 5) + 1) * 4);
     f.usw = o; o = align16(o + (size_t)2 * 65 * 4);
+    f.graph = o; o = align16(o + graph_bytes);
     f.total = o;
     return f;
 }
@@ -449,6 +527,8 @@ struct SweepCall<LatSweep<L, RPT>> {
     }
     static __device__ int SB(const LatSweep<L, RPT> &) { return LatSweep<L, RPT>::SB; }
     static __device__ int lidx(const LatSweep<L, RPT> &, int i) { return LatSweep<L, RPT>::lidx(i); }
+    static __device__ size_t graph_bytes(const InstDev &) { return 0; }
+    static __device__ void bind(LatSweep<L, RPT> &, const InstDev &, unsigned char *, int, int) {}
 };
 
 template <>
@@ -459,6 +539,11 @@ struct SweepCall<CsrSweep> {
     }
     static __device__ int SB(const CsrSweep &s) { return s.SB; }
     static __device__ int lidx(const CsrSweep &, int i) { return i; }
+    static __device__ size_t graph_bytes(const InstDev &I) { return CsrSweep::graph_bytes(I); }
+    static __device__ void bind(CsrSweep &sw, const InstDev &I, unsigned char *base, int tid, int bs)
+    {
+        sw.bind(I, base, tid, bs);
+    }
 };
 
 
@@ -486,8 +571,10 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
     sw.setup(I, G);
     const int SB = SweepCall<Sw>::SB(sw);
     const int stride = P.stride;
-    const ChunkOff lof = chunk_lds_offsets(G, SB, stride, Sw::RND ? ((n + 7) & ~7) : 0, a.tsw_entries, n);
+    const ChunkOff lof = chunk_lds_offsets(G, SB, stride, Sw::RND ? ((n + 7) & ~7) : 0, a.tsw_entries, n,
+                                           SweepCall<Sw>::graph_bytes(I));
     CHUNK_LDS_POINTERS(c, lof, G, lds_raw);
+    SweepCall<Sw>::bind(sw, I, lds_raw + lof.graph, tid, bs);
 
     // stage tables and state
     for (int x = tid; x < G * stride; x += bs) c.tab[x] = I.tflip[(size_t)s0 * stride + x];
