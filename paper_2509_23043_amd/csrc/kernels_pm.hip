@@ -39,6 +39,8 @@ __device__ __forceinline__ uint32_t sel_xp(int p) { return p ? 0x00060402u : 0x0
 __device__ __forceinline__ uint32_t sel_xm(int p) { return p ? 0x06040200u : 0x05030107u; }      // x - 1
 // high half of word j moved to the top: (w >> 16p) << 16 (0x0c selects a zero byte)
 __device__ __forceinline__ uint32_t sel_half(int p) { return p ? 0x03020c0cu : 0x01000c0cu; }
+// halves p of words j and j+1 side by side: {hi: word j+1, lo: word j}
+__device__ __forceinline__ uint32_t sel_pair(int p) { return p ? 0x07060302u : 0x05040100u; }
 // compact flags (byte j) to row bytes x = p + 2j, low and high dword
 __device__ __forceinline__ uint32_t sel_flo(int p) { return p ? 0x010c000cu : 0x0c010c00u; }
 __device__ __forceinline__ uint32_t sel_fhi(int p) { return p ? 0x030c020cu : 0x0c030c02u; }
@@ -202,6 +204,24 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
         const uint32_t H0 = sel_half(par[0]), H1 = sel_half(par[1]);
         const uint32_t FL0 = sel_flo(par[0]), FL1 = sel_flo(par[1]);
         const uint32_t FH0 = sel_fhi(par[0]), FH1 = sel_fhi(par[1]);
+        const uint32_t HP0 = sel_pair(par[0]), HP1 = sel_pair(par[1]);
+        // coarse thresholds (upper 16 bits of each slot's threshold by U) as
+        // byte tables for v_perm: tb* hold the high bytes, tl* the low bytes,
+        // *lo for U = 0..3 and *hi for U = 4..7
+        uint32_t tbl[SPW], tbh[SPW], tll[SPW], tlh[SPW];
+#pragma unroll
+        for (int k = 0; k < SPW; ++k) {
+            const uint32_t *tu = tabu + (SPW * wv + k) * 8;
+            tbl[k] = tbh[k] = tll[k] = tlh[k] = 0;
+#pragma unroll
+            for (int U = 0; U < 4; ++U) {
+                tbl[k] |= (tu[U] >> 24) << (8 * U);
+                tbh[k] |= (tu[U + 4] >> 24) << (8 * U);
+                tll[k] |= ((tu[U] >> 16) & 0xFFu) << (8 * U);
+                tlh[k] |= ((tu[U + 4] >> 16) & 0xFFu) << (8 * U);
+            }
+        }
+        const uint32_t ONE2 = 0x00010001u;
 
         uint32_t cyc = (uint32_t)(t0 / (uint64_t)P.M), phase = (uint32_t)(t0 % (uint64_t)P.M);
         uint64_t prop_at = P.first_prop_from(t0 + 1);
@@ -226,7 +246,7 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
             int nf[SPW], su[SPW];
 #pragma unroll
             for (int k = 0; k < SPW; ++k) {
-                r[k] = philox((uint32_t)lane, (uint32_t)t, (uint32_t)(lab0 + k), TAG_SWEEP, P.k0, P.k1);
+                r[k] = philox_v((uint32_t)lane, (uint32_t)t, (uint32_t)(lab0 + k), TAG_SWEEP, P.k0, P.k1);
                 me[k] = *(const uint2 *)(bufs + buf[k] * N + rel_me);
                 nf[k] = 0;
                 su[k] = 0;
@@ -235,6 +255,7 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
             for (int c = 0; c < 2; ++c) {
                 const uint32_t Ss = c ? S1 : S0, Xp = c ? XP1 : XP0, Xm = c ? XM1 : XM0;
                 const uint32_t Hs = c ? H1 : H0, FL = c ? FL1 : FL0, FH = c ? FH1 : FH0;
+                const uint32_t Hp = c ? HP1 : HP0;
 #pragma unroll
                 for (int k = 0; k < SPW; ++k) {
                     const uint8_t *B = bufs + buf[k] * N;
@@ -244,30 +265,39 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                     const uint2 zp = *(const uint2 *)(B + rel_zp);
                     const uint2 zm = *(const uint2 *)(B + rel_zm);
                     const uint32_t b = perm(me[k].y, me[k].x, Ss);
-                    uint32_t U = (JN[c][0] ^ b ^ perm(me[k].y, me[k].x, Xp)) +
-                                 (JN[c][1] ^ b ^ perm(me[k].y, me[k].x, Xm)) + (JN[c][2] ^ b ^ perm(yp.y, yp.x, Ss));
-                    U += (JN[c][3] ^ b ^ perm(ym.y, ym.x, Ss)) + (JN[c][4] ^ b ^ perm(zp.y, zp.x, Ss)) +
-                         (JN[c][5] ^ b ^ perm(zm.y, zm.x, Ss));
-                    uint32_t T[4], hs[4];
-                    bool acc[4], maybe[4];
-                    bool any_maybe = false;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        T[j] = tu[(U >> (8 * j)) & 0xFFu];
-                        hs[j] = perm(r[k].v[j], r[k].v[j], Hs);
-                        acc[j] = coarse_accept(T[j], hs[j], maybe[j]);
-                        any_maybe |= maybe[j];
-                    }
-                    if (any_lane(any_maybe)) {
-                        const P4 r2 = philox((uint32_t)lane, (uint32_t)t, (uint32_t)(lab0 + k), TAG_REFINE, P.k0, P.k1);
+                    const uint32_t x0 = xor3(JN[c][0], b, perm(me[k].y, me[k].x, Xp));
+                    const uint32_t x1 = xor3(JN[c][1], b, perm(me[k].y, me[k].x, Xm));
+                    const uint32_t x2 = xor3(JN[c][2], b, perm(yp.y, yp.x, Ss));
+                    const uint32_t x3 = xor3(JN[c][3], b, perm(ym.y, ym.x, Ss));
+                    const uint32_t x4 = xor3(JN[c][4], b, perm(zp.y, zp.x, Ss));
+                    const uint32_t x5 = xor3(JN[c][5], b, perm(zm.y, zm.x, Ss));
+                    const uint32_t U = x0 + x1 + x2 + x3 + x4 + x5;
+                    // Coarse test of all four sites at once, on 16-bit halves:
+                    // site j flips when its uniform's upper half is below the
+                    // upper half of its threshold, and stays when above; equal
+                    // halves (or an always-accept entry, whose upper half is
+                    // 0xFFFF) leave the decision to the exact test below.
+                    const uint32_t TB = perm(tbh[k], tbl[k], U);        // U <= 6 selects a table byte
+                    const uint32_t TL = perm(tlh[k], tll[k], U);
+                    const uint32_t T01 = perm(TB, TL, 0x05010400u), T23 = perm(TB, TL, 0x07030602u);
+                    const uint32_t U01 = perm(r[k].v[1], r[k].v[0], Hp), U23 = perm(r[k].v[3], r[k].v[2], Hp);
+                    uint32_t F = perm(pk_min_u16(pk_sub_sat_u16(T23, U23), ONE2),
+                                      pk_min_u16(pk_sub_sat_u16(T01, U01), ONE2), 0x06040200u);
+                    const uint32_t Z = pk_min_u16(pk_min_u16(T01 ^ U01, T23 ^ U23), ONE2);
+                    if (any_lane(Z != ONE2)) {
+                        // exact test: u = (upper << 16) | lower, the lower half
+                        // from the refinement call
+                        const uint32_t *tu = tabu + (SPW * wv + k) * 8;
+                        const P4 r2 = philox_v((uint32_t)lane, (uint32_t)t, (uint32_t)(lab0 + k), TAG_REFINE, P.k0, P.k1);
+                        uint32_t Fx = 0;
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
-                            const uint32_t lo = perm(r2.v[j], r2.v[j], Hs) >> 16;
-                            if (maybe[j]) acc[j] = (T[j] == ALWAYS) || ((hs[j] | lo) < T[j]);
+                            const uint32_t T = tu[(U >> (8 * j)) & 0xFFu];
+                            const uint32_t u = perm(r[k].v[j], r[k].v[j], Hs) | (perm(r2.v[j], r2.v[j], Hs) >> 16);
+                            Fx |= (T == ALWAYS || u < T) ? (1u << (8 * j)) : 0u;
                         }
+                        F = Fx;
                     }
-                    const uint32_t F = (acc[0] ? 1u : 0u) | (acc[1] ? 0x100u : 0u) | (acc[2] ? 0x10000u : 0u) |
-                                       (acc[3] ? 0x1000000u : 0u);
                     me[k].x ^= perm(0u, F, FL);
                     me[k].y ^= perm(0u, F, FH);
                     *(uint2 *)(bufs + buf[k] * N + rel_me) = me[k];

@@ -45,6 +45,57 @@ __host__ __device__ __forceinline__ uint32_t philox_word0(uint32_t c0, uint32_t 
     return philox(c0, c1, 0, c3, k0, k1).v[0];
 }
 
+// Three-input XOR in one instruction (gfx950 v_bitop3_b32, truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// The same generator as philox(), for device code whose counter word 0 varies
+// by lane and whose other counter words are wave-uniform: the first two
+// rounds keep their uniform XORs on the scalar unit, the remaining eight
+// fold each pair of XORs into one v_bitop3.
+__device__ __forceinline__ P4 philox_v(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                       uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t a = (uint64_t)c0 * 0xD2511F53u;
+        uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
+        uint32_t n0, n2;
+        if (r < 2) {
+            n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+            n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        } else {
+            n0 = xor3((uint32_t)(b >> 32), c1, k0);
+            n2 = xor3((uint32_t)(a >> 32), c3, k1);
+        }
+        c1 = (uint32_t)b;
+        c3 = (uint32_t)a;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    P4 o;
+    o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+    return o;
+}
+
+// Packed unsigned 16-bit operations on two lanes of a dword.
+__device__ __forceinline__ uint32_t pk_sub_sat_u16(uint32_t a, uint32_t b)   // max(a - b, 0) per half
+{
+    uint32_t r;
+    asm("v_pk_sub_u16 %0, %1, %2 clamp" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ uint32_t pk_min_u16(uint32_t a, uint32_t b)
+{
+    uint32_t r;
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // accept iff T == ALWAYS or u < T, with u = (hi << 16) | lo and the low half
 // drawn only when the high half leaves the decision open.
 __device__ __forceinline__ bool coarse_accept(uint32_t T, uint32_t hs, bool &maybe)
