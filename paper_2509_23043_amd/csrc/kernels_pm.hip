@@ -244,10 +244,17 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
             P4 r[SPW];
             uint2 me[SPW];
             int nf[SPW], su[SPW];
+            uint32_t a_me[SPW], a_yp[SPW], a_ym[SPW], a_zp[SPW], a_zm[SPW];   // row addresses in bufs
 #pragma unroll
             for (int k = 0; k < SPW; ++k) {
                 r[k] = philox_v((uint32_t)lane, (uint32_t)t, (uint32_t)(lab0 + k), TAG_SWEEP, P.k0, P.k1);
-                me[k] = *(const uint2 *)(bufs + buf[k] * N + rel_me);
+                const uint32_t B = (uint32_t)(buf[k] * N);
+                a_me[k] = B + rel_me;
+                a_yp[k] = B + rel_yp;
+                a_ym[k] = B + rel_ym;
+                a_zp[k] = B + rel_zp;
+                a_zm[k] = B + rel_zm;
+                me[k] = *(const uint2 *)(bufs + a_me[k]);
                 nf[k] = 0;
                 su[k] = 0;
             }
@@ -256,21 +263,25 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                 const uint32_t Ss = c ? S1 : S0, Xp = c ? XP1 : XP0, Xm = c ? XM1 : XM0;
                 const uint32_t Hs = c ? H1 : H0, FL = c ? FL1 : FL0, FH = c ? FH1 : FH0;
                 const uint32_t Hp = c ? HP1 : HP0;
+                // both slots' neighbour rows first (the slots use different
+                // buffers), so that all eight reads are in flight together
+                uint2 yp[SPW], ym[SPW], zp[SPW], zm[SPW];
 #pragma unroll
                 for (int k = 0; k < SPW; ++k) {
-                    const uint8_t *B = bufs + buf[k] * N;
-                    const uint32_t *tu = tabu + (SPW * wv + k) * 8;
-                    const uint2 yp = *(const uint2 *)(B + rel_yp);
-                    const uint2 ym = *(const uint2 *)(B + rel_ym);
-                    const uint2 zp = *(const uint2 *)(B + rel_zp);
-                    const uint2 zm = *(const uint2 *)(B + rel_zm);
+                    yp[k] = *(const uint2 *)(bufs + a_yp[k]);
+                    ym[k] = *(const uint2 *)(bufs + a_ym[k]);
+                    zp[k] = *(const uint2 *)(bufs + a_zp[k]);
+                    zm[k] = *(const uint2 *)(bufs + a_zm[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < SPW; ++k) {
                     const uint32_t b = perm(me[k].y, me[k].x, Ss);
                     const uint32_t x0 = xor3(JN[c][0], b, perm(me[k].y, me[k].x, Xp));
                     const uint32_t x1 = xor3(JN[c][1], b, perm(me[k].y, me[k].x, Xm));
-                    const uint32_t x2 = xor3(JN[c][2], b, perm(yp.y, yp.x, Ss));
-                    const uint32_t x3 = xor3(JN[c][3], b, perm(ym.y, ym.x, Ss));
-                    const uint32_t x4 = xor3(JN[c][4], b, perm(zp.y, zp.x, Ss));
-                    const uint32_t x5 = xor3(JN[c][5], b, perm(zm.y, zm.x, Ss));
+                    const uint32_t x2 = xor3(JN[c][2], b, perm(yp[k].y, yp[k].x, Ss));
+                    const uint32_t x3 = xor3(JN[c][3], b, perm(ym[k].y, ym[k].x, Ss));
+                    const uint32_t x4 = xor3(JN[c][4], b, perm(zp[k].y, zp[k].x, Ss));
+                    const uint32_t x5 = xor3(JN[c][5], b, perm(zm[k].y, zm[k].x, Ss));
                     const uint32_t U = x0 + x1 + x2 + x3 + x4 + x5;
                     // Coarse test of all four sites at once, on 16-bit halves:
                     // site j flips when its uniform's upper half is below the
@@ -300,7 +311,7 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                     }
                     me[k].x ^= perm(0u, F, FL);
                     me[k].y ^= perm(0u, F, FH);
-                    *(uint2 *)(bufs + buf[k] * N + rel_me) = me[k];
+                    *(uint2 *)(bufs + a_me[k]) = me[k];
                     nf[k] += __builtin_popcount(F);
                     su[k] = (int)__builtin_amdgcn_udot4(U, F, (uint32_t)su[k], false);
                 }
