@@ -397,30 +397,83 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                                                                 ((uint32_t)E[0] & 0xFFFFFFu),
                                                __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
-                    // across the workgroup boundaries: tagged words, state copy
+                    // across the workgroup boundaries: publish first (one store of
+                    // 17 tagged words: lane 2x + h holds the sites 8q + x of rows
+                    // q = 32h .. 32h + 31, one ballot per x, bit set = spin +1;
+                    // lane 16 the energy), then settle the pairs inside the
+                    // workgroup while the words travel, then poll
+                    const int buf_x = (cyc >> 1) & 1;
+                    const unsigned long long tag = (unsigned long long)cyc << 32;
 #pragma unroll
                     for (int side = 0; side < 2; ++side) {
                         const int k = side == 0 ? 0 : 1;
                         const bool cross = side == 0 ? (wv == 0 && has_down && lab0 >= 1)
                                                      : (wv + 1 == NWV && has_up && lab0 + 2 < P.R);
                         if (!cross || failed) continue;
-                        const int buf_x = (cyc >> 1) & 1;
-                        const unsigned long long tag = (unsigned long long)cyc << 32;
                         unsigned long long *out = it.xbuf + ((size_t)(it.w * 2 + side) * 2 + buf_x) * it.xwords;
-                        // one ballot per x over the lanes' rows (no LDS round trip per
-                        // ballot): word 2x + h holds the sites 8q + x of rows
-                        // q = 32h .. 32h + 31 (bit set = spin +1)
                         const uint2 row = *(const uint2 *)(bufs + buf[k] * N + rel_me);
+                        uint32_t pay = (uint32_t)E[k];
 #pragma unroll
                         for (int x = 0; x < 8; ++x) {
                             const uint32_t byte = ((x < 4 ? row.x : row.y) >> (8 * (x & 3))) & 0xFFu;
                             const unsigned long long bal = __ballot(byte == 0);
-                            if (lane < 2)
-                                __hip_atomic_store(out + 2 * x + lane, tag | (lane ? (bal >> 32) : (bal & 0xFFFFFFFFull)),
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            const uint32_t half = (lane & 1) ? (uint32_t)(bal >> 32) : (uint32_t)bal;
+                            pay = (lane >> 1) == x ? half : pay;
                         }
-                        if (lane == 0)
-                            __hip_atomic_store(out + NWD, tag | (uint32_t)E[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (lane <= NWD)
+                            __hip_atomic_store(out + lane, tag | pay, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    if (!failed) {
+                        // inside the workgroup: read the neighbour wavefronts' words
+#pragma unroll
+                        for (int side = 0; side < 2; ++side) {
+                            const bool here = side == 0 ? dn_here : up_here;
+                            if (!here || failed) continue;
+                            const int k = side == 0 ? 0 : 1;
+                            const int pl = side == 0 ? SPW * wv - 1 : SPW * wv + 2;   // partner local slot
+                            uint32_t polls = 0;
+                            unsigned long long v;
+                            for (;;) {
+                                v = __hip_atomic_load(mb + pl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                if ((uint32_t)(v >> 32) == cyc) break;
+                                __builtin_amdgcn_s_sleep(1);
+                                if (++polls > a.spin_limit) break;
+                            }
+                            if ((uint32_t)(v >> 32) != cyc) {
+                                if (lane == 0 && atomicCAS(a.err, 0, 2) == 0) {
+                                    a.err[1] = item; a.err[2] = it.w; a.err[3] = 2; a.err[4] = (int)cyc;
+                                    a.err[5] = (int)(v & 0xFFFFFFFFu); a.err[6] = (int)(v >> 32); a.err[7] = (int)I.epoch;
+                                }
+                                failed = true;
+                                continue;
+                            }
+                            // every value here is wave-uniform: keep it scalar
+                            const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)v);
+                            const int pE = ((int)(lo32 << 8)) >> 8;      // 24-bit signed energy
+                            const int pb = (int)((lo32 >> 24) & 0xFFu);
+                            const int slot = lab0 + k;
+                            const int r = side == 0 ? slot - 1 : slot;
+                            const int prow = r - (s0 - 1);
+                            const int dEs = side == 0 ? E[k] - pE : pE - E[k];
+                            const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, (cyc == u_base ? 0 : 32) + prow),
+                                                     __builtin_amdgcn_readlane(row_off_v, prow),
+                                                     __builtin_amdgcn_readlane(row_len_v, prow), tsw);
+                            if (side == 1) {
+                                satt[1] += 1;
+                                sacc[1] += okx ? 1u : 0u;
+                            }
+                            // trade buffers on acceptance: the partner takes ours
+                            buf[k] = okx ? pb : buf[k];
+                            E[k] = okx ? pE : E[k];
+                        }
+                    }
+                    // across the workgroup boundaries: poll, decide, copy
+#pragma unroll
+                    for (int side = 0; side < 2; ++side) {
+                        const int k = side == 0 ? 0 : 1;
+                        const bool cross = side == 0 ? (wv == 0 && has_down && lab0 >= 1)
+                                                     : (wv + 1 == NWV && has_up && lab0 + 2 < P.R);
+                        if (!cross || failed) continue;
                         const int pw = side == 0 ? it.w - 1 : it.w + 1;
                         const unsigned long long *in =
                             it.xbuf + ((size_t)(pw * 2 + (side == 0 ? 1 : 0)) * 2 + buf_x) * it.xwords;
@@ -483,50 +536,6 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                                 else d.y |= down << (8 * (x - 4));
                             }
                             *(uint2 *)(bufs + buf[k] * N + rel_me) = d;
-                        }
-                    }
-                    if (!failed) {
-                        // inside the workgroup: read the neighbour wavefronts' words
-#pragma unroll
-                        for (int side = 0; side < 2; ++side) {
-                            const bool here = side == 0 ? dn_here : up_here;
-                            if (!here || failed) continue;
-                            const int k = side == 0 ? 0 : 1;
-                            const int pl = side == 0 ? SPW * wv - 1 : SPW * wv + 2;   // partner local slot
-                            uint32_t polls = 0;
-                            unsigned long long v;
-                            for (;;) {
-                                v = __hip_atomic_load(mb + pl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                                if ((uint32_t)(v >> 32) == cyc) break;
-                                __builtin_amdgcn_s_sleep(1);
-                                if (++polls > a.spin_limit) break;
-                            }
-                            if ((uint32_t)(v >> 32) != cyc) {
-                                if (lane == 0 && atomicCAS(a.err, 0, 2) == 0) {
-                                    a.err[1] = item; a.err[2] = it.w; a.err[3] = 2; a.err[4] = (int)cyc;
-                                    a.err[5] = (int)(v & 0xFFFFFFFFu); a.err[6] = (int)(v >> 32); a.err[7] = (int)I.epoch;
-                                }
-                                failed = true;
-                                continue;
-                            }
-                            // every value here is wave-uniform: keep it scalar
-                            const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)v);
-                            const int pE = ((int)(lo32 << 8)) >> 8;      // 24-bit signed energy
-                            const int pb = (int)((lo32 >> 24) & 0xFFu);
-                            const int slot = lab0 + k;
-                            const int r = side == 0 ? slot - 1 : slot;
-                            const int prow = r - (s0 - 1);
-                            const int dEs = side == 0 ? E[k] - pE : pE - E[k];
-                            const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, (cyc == u_base ? 0 : 32) + prow),
-                                                     __builtin_amdgcn_readlane(row_off_v, prow),
-                                                     __builtin_amdgcn_readlane(row_len_v, prow), tsw);
-                            if (side == 1) {
-                                satt[1] += 1;
-                                sacc[1] += okx ? 1u : 0u;
-                            }
-                            // trade buffers on acceptance: the partner takes ours
-                            buf[k] = okx ? pb : buf[k];
-                            E[k] = okx ? pE : E[k];
                         }
                     }
                 }
