@@ -145,8 +145,11 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
     }
     __syncthreads();
 
-    const int row_off_v = lane <= G ? tsw_off[lane] : 0;
-    const int row_len_v = lane <= G ? tsw_off[lane + 1] - row_off_v : 0;
+    // swap-table rows of this wavefront's three pairs, lane i: pair s0 - 1 + 2wv + i
+    // (i = 0: below its first slot, 1: between its slots, 2: above its second)
+    const int prow_w = wv < G / SPW ? 2 * wv + (lane < 3 ? lane : 0) : 0;
+    const int row_off_v = tsw_off[prow_w];
+    const int row_len_v = tsw_off[prow_w + 1] - row_off_v;
     const bool active = wv < NWV;
     const bool has_down = it.w > 0, has_up = it.w + 1 < it.W;
     bool failed = false;
@@ -226,17 +229,19 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
         uint32_t cyc = (uint32_t)(t0 / (uint64_t)P.M), phase = (uint32_t)(t0 % (uint64_t)P.M);
         uint64_t prop_at = P.first_prop_from(t0 + 1);
         const int lab0 = s0 + SPW * wv;          // this wavefront's slots: lab0, lab0 + 1
-        uint32_t u_vec = 0, u_base = 0xFFFFFFFFu;
+        // swap uniforms of this wavefront's three pairs for 21 cycles: lane
+        // 3c + i holds pair lab0 - 1 + i at cycle u_base + c
+        constexpr uint32_t UCYC = 21;
+        uint32_t u_vec = 0, u_base = (uint32_t)-100;
+        const uint32_t u_i = (uint32_t)lane % 3u, u_c = (uint32_t)lane / 3u;
 
         for (uint64_t t = t0 + 1; t <= tend && !failed; ++t) {
             const bool ends = phase + 1 == (uint32_t)P.M;
-            // swap uniforms of the pairs of this workgroup: lane p < 32 holds pair
-            // s0 - 1 + p at cycle u_base, lane 32 + p the same pair at u_base + 1
-            // (one Philox call per two cycles, drawn before the sweep so that its
-            // latency hides behind it)
-            if (ends && cyc + 1 != u_base && cyc + 1 != u_base + 1) {
+            // one Philox call per 21 cycles, drawn before the sweep so that its
+            // latency hides behind it
+            if (ends && cyc + 1 - u_base >= UCYC) {
                 u_base = cyc + 1;
-                u_vec = philox_word0((uint32_t)(s0 - 1 + (lane & 31)), u_base + (uint32_t)(lane >> 5), TAG_SWAP, P.k0, P.k1);
+                u_vec = philox_v((uint32_t)(lab0 - 1) + u_i, u_base + u_c, 0, TAG_SWAP, P.k0, P.k1).v[0];
             }
 
             // ---- sweep both slots (colour phases outermost, so that the two
@@ -367,10 +372,9 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                     // pairs (2w, 2w+1): inside this wavefront
                     const int r = lab0;
                     if (r + 1 < P.R) {
-                        const int prow = r - (s0 - 1);
-                        const bool ok = swap_ok(E[1] - E[0], __builtin_amdgcn_readlane(u_vec, (cyc == u_base ? 0 : 32) + prow),
-                                                __builtin_amdgcn_readlane(row_off_v, prow),
-                                                __builtin_amdgcn_readlane(row_len_v, prow), tsw);
+                        const bool ok = swap_ok(E[1] - E[0], __builtin_amdgcn_readlane(u_vec, 3 * (cyc - u_base) + 1),
+                                                __builtin_amdgcn_readlane(row_off_v, 1),
+                                                __builtin_amdgcn_readlane(row_len_v, 1), tsw);
                         satt[0] += 1;
                         sacc[0] += ok ? 1u : 0u;
                         const int b0 = buf[0], b1 = buf[1], e0 = E[0], e1 = E[1];
@@ -387,15 +391,19 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                     const bool up_here = lab0 + 2 < P.R && wv + 1 < NWV;
                     const bool dn_here = wv > 0;
                     // publish (energy, buffer) of the slots that meet a neighbour wavefront
+                    // LDS operations of a wavefront complete in order, so the row
+                    // writes of the sweep land before these words; only the
+                    // compiler must not move them past (signal fence)
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
                     if (lane == 0) {
                         if (up_here)
                             __hip_atomic_store(mb + lu, ((unsigned long long)cyc << 32) | ((uint32_t)buf[1] << 24) |
                                                             ((uint32_t)E[1] & 0xFFFFFFu),
-                                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                         if (dn_here)
                             __hip_atomic_store(mb + lu - 1, ((unsigned long long)cyc << 32) | ((uint32_t)buf[0] << 24) |
                                                                 ((uint32_t)E[0] & 0xFFFFFFu),
-                                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
                     // across the workgroup boundaries: publish first (one store of
                     // 17 tagged words: lane 2x + h holds the sites 8q + x of rows
@@ -453,11 +461,11 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                             const int pb = (int)((lo32 >> 24) & 0xFFu);
                             const int slot = lab0 + k;
                             const int r = side == 0 ? slot - 1 : slot;
-                            const int prow = r - (s0 - 1);
+                            const int pi = r - (lab0 - 1);                // 0 or 2
                             const int dEs = side == 0 ? E[k] - pE : pE - E[k];
-                            const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, (cyc == u_base ? 0 : 32) + prow),
-                                                     __builtin_amdgcn_readlane(row_off_v, prow),
-                                                     __builtin_amdgcn_readlane(row_len_v, prow), tsw);
+                            const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, 3 * (cyc - u_base) + pi),
+                                                     __builtin_amdgcn_readlane(row_off_v, pi),
+                                                     __builtin_amdgcn_readlane(row_len_v, pi), tsw);
                             if (side == 1) {
                                 satt[1] += 1;
                                 sacc[1] += okx ? 1u : 0u;
@@ -511,11 +519,11 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                         const int pE = __builtin_amdgcn_readfirstlane((int)stage[NWD]);
                         const int slot = lab0 + k;
                         const int r = side == 0 ? slot - 1 : slot;
-                        const int prow = r - (s0 - 1);
+                        const int pi = r - (lab0 - 1);                    // 0 or 2
                         const int dEs = side == 0 ? E[k] - pE : pE - E[k];
-                        const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, (cyc == u_base ? 0 : 32) + prow),
-                                                 __builtin_amdgcn_readlane(row_off_v, prow),
-                                                 __builtin_amdgcn_readlane(row_len_v, prow), tsw);
+                        const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, 3 * (cyc - u_base) + pi),
+                                                 __builtin_amdgcn_readlane(row_off_v, pi),
+                                                 __builtin_amdgcn_readlane(row_len_v, pi), tsw);
                         if (side == 1) {   // the lower workgroup owns the pair's counters
                             satt[1] += 1;
                             if (okx) sacc[1] += 1;
