@@ -153,7 +153,7 @@ def cpu_baseline(bank_host, L, R, sweeps, log):
                        f"with proposals every 100 sweeps, banks as on the GPU")
 
 
-KERNEL_SOURCES = {"pm": "kernels_pm.hip", "wave": "kernels_wave.hip", "block": "kernels.hip"}
+KERNEL_SOURCES = {"pm": "kernels_pm.hip", "pm1": "kernels_pm.hip", "wave": "kernels_wave.hip", "block": "kernels.hip"}
 
 
 def kernel_source_hash(kern="pm"):
@@ -166,13 +166,13 @@ def kernel_source_hash(kern="pm"):
     return h.hexdigest()
 
 
-KERNEL_NAMES = {"pm": "pm_kernel", "wave": "wave_kernel<8>", "block": "chunk_kernel<LatSweep<8,*>>"}
+KERNEL_NAMES = {"pm": "pm_kernel<2>", "pm1": "pm_kernel<1>", "wave": "wave_kernel<8>", "block": "chunk_kernel<LatSweep<8,*>>"}
 
 
 def traffic_from_profiles(launch_sweeps, kern_hash, kern):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, if it was taken on these sources with this launch length."""
-    tag = {"pm": "pm_kernel", "wave": "wave_kernel", "block": "chunk_kernel"}[kern]
+    tag = {"pm": "pm_kernel", "pm1": "pm_kernel_spw1", "wave": "wave_kernel", "block": "chunk_kernel"}[kern]
     path = os.path.join(ROOT, "profiles", f"traffic_{tag}_ea_l8_r32_x64.json")
     try:
         d = json.load(open(path))

@@ -154,7 +154,9 @@ typedef struct {
     int32_t kernel;              /* 0 = choose; 1 = workgroup-synchronous kernel;
                                     2 = wave-per-replica kernel (lattices with n = 512);
                                     3 = +-J 8^3 kernel, two slots per wavefront (every
-                                        coupling +-1, even R) */
+                                        coupling +-1, even R);
+                                    4 = the same kernel with one slot per wavefront
+                                        (at most 8 slots per workgroup) */
 } pt_batch_opts;
 
 /* Group contexts for batched execution. The contexts stay owned by the

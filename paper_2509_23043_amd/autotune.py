@@ -49,8 +49,9 @@ def candidates(contexts):
     every cap on the slots per workgroup up to the longest ladder, with 1, 2
     or 4 slots per thread in the workgroup-synchronous kernel (the runtime
     lowers the cap per context until it fits), the wave-per-replica kernel
-    where every context is an 8^3 lattice, and the +-J 8^3 kernel where every
-    coupling is +-1 and every ladder has even length."""
+    where every context is an 8^3 lattice, and the +-J 8^3 kernel (two slots
+    or one slot per wavefront) where every coupling is +-1 and every ladder
+    has even length."""
     rmax = max(c.R for c in contexts)
     wave_ok = all(c.kind == "lattice" and c.L == 8 for c in contexts)
     pm_ok = all(getattr(c, "pm", False) for c in contexts)
@@ -65,6 +66,8 @@ def candidates(contexts):
             out.append((G, 1, "wave"))
         if pm_ok and 2 <= G <= 16:
             out.append((G, 1, "pm"))
+        if pm_ok and G <= 8:
+            out.append((G, 1, "pm1"))
     return out
 
 

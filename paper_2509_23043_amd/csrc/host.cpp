@@ -45,10 +45,10 @@ int wave_max_storages();
 size_t wave_lds_bytes(int n, int G, int stride, int tsw_entries);
 hipError_t launch_wave(int L, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t wave_occupancy(int L, int block, size_t lds, int *blocks_per_cu);
-int pm_max_storages();
+int pm_max_storages(int spw);
 size_t pm_lds_bytes(int G, int tsw_entries);
-hipError_t launch_pm(const ChunkArgs &a, int block, size_t lds, hipStream_t s);
-hipError_t pm_occupancy(int block, size_t lds, int *blocks_per_cu);
+hipError_t launch_pm(int spw, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
+hipError_t pm_occupancy(int spw, int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_plain(int kind, int L, const InstDev *dI, int R, int n, int stride, int nnz, int nfree, int ncolors,
                         uint32_t t, hipStream_t s);
 hipError_t launch_init(const InstDev *dI, int R, int n, hipStream_t s);
@@ -776,7 +776,8 @@ struct LaunchGroup {
     int kind, L, rpt, block, grid = 0, tsw_entries = 0;
     bool mixed = false;               // one launch of chunk_kernel_mixed for several sweepers
     bool wave = false;                // wave-per-replica kernel
-    bool pm = false;                  // +-J 8^3 kernel, two slots per wavefront
+    bool pm = false;                  // +-J 8^3 kernel
+    int spw = 2;                      // its slots per wavefront (1 or 2)
     size_t lds;
     std::vector<pt_ctx *> ctxs;
     std::vector<int> Gs;              // per context: slots per workgroup (max)
@@ -859,8 +860,8 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
 {
     for (size_t k = 0; k < g->ctxs.size(); ++k) {
         pt_ctx *c = g->ctxs[k];
-        // the +-J kernel splits the ladder into whole slot pairs (even G, even s0)
-        const int unit = g->pm ? 2 : 1;
+        // the two-slot +-J kernel splits the ladder into whole slot pairs (even G, even s0)
+        const int unit = g->pm ? g->spw : 1;
         int R = c->R / unit, W = (R + g->Gs[k] / unit - 1) / (g->Gs[k] / unit);
         int xwords = (((c->n + 31) >> 5) + 1 + 7) & ~7;
         P.ctx.push_back({(int)P.items.size(), W, c->n, xwords, unit * ((R + W - 1) / W), P.nbs, P.nx});
@@ -891,7 +892,7 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
             P.tsw_max = std::max(P.tsw_max, tot);
         }
         // a block covers the largest item's threads
-        int need = g->pm     ? 64 * (P.ctx[k].gmax / 2)
+        int need = g->pm     ? 64 * (P.ctx[k].gmax / g->spw)
                    : g->wave ? 64 * P.ctx[k].gmax
                              : c->kind == KIND_LATTICE ? lattice_threads(c->L, P.ctx[k].gmax, g->rpts[k]) : 256;
         P.block = std::max(P.block, (need + 63) & ~63);
@@ -916,7 +917,7 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
     }
     if (P.lds > 160 * 1024) return fail(PT_EUNSUPPORTED, "tiling needs %zu B of LDS per workgroup", P.lds);
     if (g->pm)
-        HIPCHK(pm_occupancy(P.block, P.lds, &P.per_cu));
+        HIPCHK(pm_occupancy(g->spw, P.block, P.lds, &P.per_cu));
     else if (g->wave)
         HIPCHK(wave_occupancy(g->L, P.block, P.lds, &P.per_cu));
     else if (g->mixed)
@@ -1000,7 +1001,8 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
     // one wavefront, unless the caller asks for the workgroup-synchronous one
     bool all_pm = !g->mixed;
     for (pt_ctx *c : ctxs) all_pm = all_pm && c->pmJ;
-    g->pm = all_pm && (o.kernel == 3 || (o.kernel == 0 && o.replicas_per_thread <= 1));
+    g->pm = all_pm && (o.kernel == 3 || o.kernel == 4 || (o.kernel == 0 && o.replicas_per_thread <= 1));
+    g->spw = o.kernel == 4 ? 1 : 2;
     g->wave = !g->pm && !g->mixed && g->kind == KIND_LATTICE && wave_supported(g->L) && o.kernel != 1 &&
               (o.kernel == 2 || o.replicas_per_thread <= 1);
     for (pt_ctx *c : ctxs) {
@@ -1008,8 +1010,8 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
         if (g->pm) {
             rpt = 1;
             G = o.replicas_per_wg > 0 ? o.replicas_per_wg : 8;
-            G = std::min(std::min(G, c->R), pm_max_storages()) & ~1;
-            if (G < 2) G = 2;
+            G = std::min(std::min(G, c->R), pm_max_storages(g->spw));
+            if (g->spw == 2) G = std::max(G & ~1, 2);
         } else if (g->wave) {
             rpt = 1;
             G = o.replicas_per_wg > 0 ? o.replicas_per_wg : wave_max_storages();
@@ -1109,7 +1111,7 @@ static hipError_t enqueue_round(pt_batch *b, uint32_t K, bool timed)
         a.err = b->err.as<int32_t>();
         a.spin_limit = 1u << 22;
         a.tsw_entries = g->tsw_entries;
-        hipError_t e = g->pm      ? launch_pm(a, g->block, g->lds, b->stream)
+        hipError_t e = g->pm      ? launch_pm(g->spw, a, g->block, g->lds, b->stream)
                        : g->wave  ? launch_wave(g->L, a, g->block, g->lds, b->stream)
                        : g->mixed ? launch_chunk_mixed(a, g->block, g->lds, b->stream)
                                   : launch_chunk(g->kind, g->L, g->rpt, a, g->block, g->lds, b->stream);

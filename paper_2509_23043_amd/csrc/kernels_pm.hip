@@ -1,6 +1,9 @@
 // Persistent kernel for +-J couplings on the periodic 8^3 lattice (no
-// fields): every wavefront owns two adjacent beta slots (2w, 2w+1 of its
-// workgroup) and sweeps both with byte-parallel arithmetic.
+// fields): every wavefront owns SPW adjacent beta slots (SPW = 2: slots 2w,
+// 2w+1 of its workgroup; SPW = 1: slot w) and sweeps them with byte-parallel
+// arithmetic. Two slots per wavefront give each wavefront two independent
+// chains to interleave; one slot per wavefront gives the SIMDs twice as many
+// wavefronts to switch between.
 //
 // Storage. A replica is 64 rows of 8 sites (row q = y + 8z holds x = 0..7,
 // site index i = 8q + x), one byte per site that is 1 when the spin is -1.
@@ -18,20 +21,20 @@
 // the flip changes E by 12 - 4U, and the threshold is the slot's table entry
 // for that m_i I_i (held in LDS indexed by U).
 //
-// Slots and states. A wavefront's two slots are fixed; states move between
-// LDS buffers. The pair (2w, 2w+1) is decided inside the wavefront with no
-// communication. The pair (2w+1, 2w+2) meets wavefront w+1 in an LDS mailbox
-// that carries the energy and the buffer index, and an accepted swap trades
-// buffer indices. Pairs across a workgroup boundary go through cycle-tagged
-// global words and copy the state. Best energy, first hit and all counters
-// are per slot and live in registers.
+// Slots and states. A wavefront's slots are fixed; states move between LDS
+// buffers. With two slots, the pair (2w, 2w+1) is decided inside the
+// wavefront with no communication. A pair that spans two wavefronts meets in
+// an LDS mailbox that carries the energy and the buffer index, and an
+// accepted swap trades buffer indices. Pairs across a workgroup boundary go
+// through cycle-tagged global words and copy the state. Best energy, first
+// hit and all counters are per slot and live in registers.
 #include "sweep.h"
 
 namespace tapt {
 
 namespace pm {
 
-constexpr int L = 8, N = 512, ROWB = 8, SPW = 2;
+constexpr int L = 8, N = 512, ROWB = 8;
 
 // v_perm selectors ({hi, lo}: bytes 0-3 from lo, 4-7 from hi)
 __device__ __forceinline__ uint32_t sel_sites(int p) { return p ? 0x07050301u : 0x06040200u; }   // x = p + 2j
@@ -63,7 +66,7 @@ __host__ __device__ inline Off offsets(int G, int tsw_entries)
     f.toff = o; o = align16(o + (size_t)(G + 2) * 4);
     f.tsw = o; o = align16(o + (size_t)tsw_entries * 4);
     f.mail = o; o = align16(o + (size_t)4 * G * 8);
-    f.xst = o; o = align16(o + (size_t)SPW * 2 * (G / SPW) * ((N >> 5) + 1) * 4);
+    f.xst = o; o = align16(o + (size_t)2 * G * ((N >> 5) + 1) * 4);   // [2 G][17] staged words
     f.total = o;
     return f;
 }
@@ -89,9 +92,11 @@ __device__ __forceinline__ bool swap_ok(int dE, uint32_t u, int off, int len, co
 
 } // namespace pm
 
+template <int SPW>
 __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
 {
     using namespace pm;
+    constexpr int NP = SPW + 1;               // pairs a wavefront takes part in
     const int item = a.order[blockIdx.x];
     if (item < 0) return;
     const WorkItem it = a.items[item];
@@ -145,9 +150,9 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
     }
     __syncthreads();
 
-    // swap-table rows of this wavefront's three pairs, lane i: pair s0 - 1 + 2wv + i
-    // (i = 0: below its first slot, 1: between its slots, 2: above its second)
-    const int prow_w = wv < G / SPW ? 2 * wv + (lane < 3 ? lane : 0) : 0;
+    // swap-table rows of this wavefront's NP pairs, lane i: pair s0 - 1 + SPW wv + i
+    // (i = 0: below its first slot, NP - 1: above its last, 1 between two slots)
+    const int prow_w = wv < G / SPW ? SPW * wv + (lane < NP ? lane : 0) : 0;
     const int row_off_v = tsw_off[prow_w];
     const int row_len_v = tsw_off[prow_w + 1] - row_off_v;
     const bool active = wv < NWV;
@@ -228,17 +233,17 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
 
         uint32_t cyc = (uint32_t)(t0 / (uint64_t)P.M), phase = (uint32_t)(t0 % (uint64_t)P.M);
         uint64_t prop_at = P.first_prop_from(t0 + 1);
-        const int lab0 = s0 + SPW * wv;          // this wavefront's slots: lab0, lab0 + 1
-        // swap uniforms of this wavefront's three pairs for 21 cycles: lane
-        // 3c + i holds pair lab0 - 1 + i at cycle u_base + c
-        constexpr uint32_t UCYC = 21;
+        const int lab0 = s0 + SPW * wv;          // this wavefront's slots: lab0 .. lab0 + SPW - 1
+        // swap uniforms of this wavefront's NP pairs for UCYC cycles: lane
+        // NP c + i holds pair lab0 - 1 + i at cycle u_base + c
+        constexpr uint32_t UCYC = 64 / NP;
         uint32_t u_vec = 0, u_base = (uint32_t)-100;
-        const uint32_t u_i = (uint32_t)lane % 3u, u_c = (uint32_t)lane / 3u;
+        const uint32_t u_i = (uint32_t)lane % (uint32_t)NP, u_c = (uint32_t)lane / (uint32_t)NP;
 
         for (uint64_t t = t0 + 1; t <= tend && !failed; ++t) {
             const bool ends = phase + 1 == (uint32_t)P.M;
-            // one Philox call per 21 cycles, drawn before the sweep so that its
-            // latency hides behind it
+            // one Philox call per UCYC cycles, drawn before the sweep so that
+            // its latency hides behind it
             if (ends && cyc + 1 - u_base >= UCYC) {
                 u_base = cyc + 1;
                 u_vec = philox_v((uint32_t)(lab0 - 1) + u_i, u_base + u_c, 0, TAG_SWAP, P.k0, P.k1).v[0];
@@ -368,59 +373,27 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                     ++n_prop;
                 }
                 // ---- swaps (Eq. 1), alternating parity ----
-                if (cyc & 1) {
-                    // pairs (2w, 2w+1): inside this wavefront
-                    const int r = lab0;
-                    if (r + 1 < P.R) {
-                        const bool ok = swap_ok(E[1] - E[0], __builtin_amdgcn_readlane(u_vec, 3 * (cyc - u_base) + 1),
-                                                __builtin_amdgcn_readlane(row_off_v, 1),
-                                                __builtin_amdgcn_readlane(row_len_v, 1), tsw);
-                        satt[0] += 1;
-                        sacc[0] += ok ? 1u : 0u;
-                        const int b0 = buf[0], b1 = buf[1], e0 = E[0], e1 = E[1];
-                        buf[0] = ok ? b1 : b0;
-                        buf[1] = ok ? b0 : b1;
-                        E[0] = ok ? e1 : e0;
-                        E[1] = ok ? e0 : e1;
-                    }
-                } else {
-                    // pairs (2w+1, 2w+2): with the next wavefront or across the upper
-                    // boundary; (2w-1, 2w): with the previous one or across the lower
-                    const int lu = SPW * wv + 1;                 // local slot of the upper one
+                if constexpr (SPW == 1) {
+                    // the slot is the lower member of its pair when its parity
+                    // differs from the cycle's
+                    const int slot = lab0;
+                    const bool lower = ((slot ^ (int)cyc) & 1) != 0;
+                    const int side = lower ? 1 : 0;                   // 1: partner slot + 1
+                    const bool paired = lower ? slot + 1 < P.R : slot >= 1;
+                    const bool intra = paired && (lower ? wv + 1 < NWV : wv > 0);
+                    const bool cross = paired && !intra && (lower ? has_up : has_down);
+                    const int pi = lower ? 1 : 0;                     // pair lab0 - 1 + pi
                     unsigned long long *mb = mail + (cyc & 3) * G;
-                    const bool up_here = lab0 + 2 < P.R && wv + 1 < NWV;
-                    const bool dn_here = wv > 0;
-                    // publish (energy, buffer) of the slots that meet a neighbour wavefront
-                    // LDS operations of a wavefront complete in order, so the row
-                    // writes of the sweep land before these words; only the
-                    // compiler must not move them past (signal fence)
                     __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                    if (lane == 0) {
-                        if (up_here)
-                            __hip_atomic_store(mb + lu, ((unsigned long long)cyc << 32) | ((uint32_t)buf[1] << 24) |
-                                                            ((uint32_t)E[1] & 0xFFFFFFu),
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        if (dn_here)
-                            __hip_atomic_store(mb + lu - 1, ((unsigned long long)cyc << 32) | ((uint32_t)buf[0] << 24) |
-                                                                ((uint32_t)E[0] & 0xFFFFFFu),
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    }
-                    // across the workgroup boundaries: publish first (one store of
-                    // 17 tagged words: lane 2x + h holds the sites 8q + x of rows
-                    // q = 32h .. 32h + 31, one ballot per x, bit set = spin +1;
-                    // lane 16 the energy), then settle the pairs inside the
-                    // workgroup while the words travel, then poll
+                    if (intra && lane == 0)
+                        __hip_atomic_store(mb + wv, ((unsigned long long)cyc << 32) | ((uint32_t)buf[0] << 24) |
+                                                        ((uint32_t)E[0] & 0xFFFFFFu),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     const int buf_x = (cyc >> 1) & 1;
-                    const unsigned long long tag = (unsigned long long)cyc << 32;
-#pragma unroll
-                    for (int side = 0; side < 2; ++side) {
-                        const int k = side == 0 ? 0 : 1;
-                        const bool cross = side == 0 ? (wv == 0 && has_down && lab0 >= 1)
-                                                     : (wv + 1 == NWV && has_up && lab0 + 2 < P.R);
-                        if (!cross || failed) continue;
+                    if (cross) {
                         unsigned long long *out = it.xbuf + ((size_t)(it.w * 2 + side) * 2 + buf_x) * it.xwords;
-                        const uint2 row = *(const uint2 *)(bufs + buf[k] * N + rel_me);
-                        uint32_t pay = (uint32_t)E[k];
+                        const uint2 row = *(const uint2 *)(bufs + buf[0] * N + rel_me);
+                        uint32_t pay = (uint32_t)E[0];
 #pragma unroll
                         for (int x = 0; x < 8; ++x) {
                             const uint32_t byte = ((x < 4 ? row.x : row.y) >> (8 * (x & 3))) & 0xFFu;
@@ -429,62 +402,44 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                             pay = (lane >> 1) == x ? half : pay;
                         }
                         if (lane <= NWD)
-                            __hip_atomic_store(out + lane, tag | pay, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            __hip_atomic_store(out + lane, ((unsigned long long)cyc << 32) | pay, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
                     }
-                    if (!failed) {
-                        // inside the workgroup: read the neighbour wavefronts' words
-#pragma unroll
-                        for (int side = 0; side < 2; ++side) {
-                            const bool here = side == 0 ? dn_here : up_here;
-                            if (!here || failed) continue;
-                            const int k = side == 0 ? 0 : 1;
-                            const int pl = side == 0 ? SPW * wv - 1 : SPW * wv + 2;   // partner local slot
-                            uint32_t polls = 0;
-                            unsigned long long v;
-                            for (;;) {
-                                v = __hip_atomic_load(mb + pl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                                if ((uint32_t)(v >> 32) == cyc) break;
-                                __builtin_amdgcn_s_sleep(1);
-                                if (++polls > a.spin_limit) break;
+                    if (intra) {
+                        uint32_t polls = 0;
+                        unsigned long long v;
+                        for (;;) {
+                            v = __hip_atomic_load(mb + wv + (lower ? 1 : -1), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            if ((uint32_t)(v >> 32) == cyc) break;
+                            __builtin_amdgcn_s_sleep(1);
+                            if (++polls > a.spin_limit) break;
+                        }
+                        if ((uint32_t)(v >> 32) != cyc) {
+                            if (lane == 0 && atomicCAS(a.err, 0, 2) == 0) {
+                                a.err[1] = item; a.err[2] = it.w; a.err[3] = 2; a.err[4] = (int)cyc;
+                                a.err[5] = (int)(v & 0xFFFFFFFFu); a.err[6] = (int)(v >> 32); a.err[7] = (int)I.epoch;
                             }
-                            if ((uint32_t)(v >> 32) != cyc) {
-                                if (lane == 0 && atomicCAS(a.err, 0, 2) == 0) {
-                                    a.err[1] = item; a.err[2] = it.w; a.err[3] = 2; a.err[4] = (int)cyc;
-                                    a.err[5] = (int)(v & 0xFFFFFFFFu); a.err[6] = (int)(v >> 32); a.err[7] = (int)I.epoch;
-                                }
-                                failed = true;
-                                continue;
-                            }
-                            // every value here is wave-uniform: keep it scalar
+                            failed = true;
+                        } else {
                             const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)v);
                             const int pE = ((int)(lo32 << 8)) >> 8;      // 24-bit signed energy
                             const int pb = (int)((lo32 >> 24) & 0xFFu);
-                            const int slot = lab0 + k;
-                            const int r = side == 0 ? slot - 1 : slot;
-                            const int pi = r - (lab0 - 1);                // 0 or 2
-                            const int dEs = side == 0 ? E[k] - pE : pE - E[k];
-                            const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, 3 * (cyc - u_base) + pi),
+                            const int dEs = lower ? pE - E[0] : E[0] - pE;
+                            const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, NP * (cyc - u_base) + pi),
                                                      __builtin_amdgcn_readlane(row_off_v, pi),
                                                      __builtin_amdgcn_readlane(row_len_v, pi), tsw);
-                            if (side == 1) {
-                                satt[1] += 1;
-                                sacc[1] += okx ? 1u : 0u;
+                            if (lower) {   // the lower member owns the pair's counters
+                                satt[0] += 1;
+                                sacc[0] += okx ? 1u : 0u;
                             }
-                            // trade buffers on acceptance: the partner takes ours
-                            buf[k] = okx ? pb : buf[k];
-                            E[k] = okx ? pE : E[k];
+                            buf[0] = okx ? pb : buf[0];
+                            E[0] = okx ? pE : E[0];
                         }
                     }
-                    // across the workgroup boundaries: poll, decide, copy
-#pragma unroll
-                    for (int side = 0; side < 2; ++side) {
-                        const int k = side == 0 ? 0 : 1;
-                        const bool cross = side == 0 ? (wv == 0 && has_down && lab0 >= 1)
-                                                     : (wv + 1 == NWV && has_up && lab0 + 2 < P.R);
-                        if (!cross || failed) continue;
-                        const int pw = side == 0 ? it.w - 1 : it.w + 1;
+                    if (cross && !failed) {
+                        const int pw = lower ? it.w + 1 : it.w - 1;
                         const unsigned long long *in =
-                            it.xbuf + ((size_t)(pw * 2 + (side == 0 ? 1 : 0)) * 2 + buf_x) * it.xwords;
+                            it.xbuf + ((size_t)(pw * 2 + (1 - side)) * 2 + buf_x) * it.xwords;
                         uint32_t *stage = xstage + (size_t)(wv * 2 + side) * (NWD + 1);
                         uint32_t polls = 0;
                         bool ok_all = false;
@@ -512,38 +467,215 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                                 a.err[5] = (int)(bad & 0xFFFFFFFFu); a.err[6] = (int)(bad >> 32); a.err[7] = (int)I.epoch;
                             }
                             failed = true;
-                            continue;
-                        }
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        const int pE = __builtin_amdgcn_readfirstlane((int)stage[NWD]);
-                        const int slot = lab0 + k;
-                        const int r = side == 0 ? slot - 1 : slot;
-                        const int pi = r - (lab0 - 1);                    // 0 or 2
-                        const int dEs = side == 0 ? E[k] - pE : pE - E[k];
-                        const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, 3 * (cyc - u_base) + pi),
-                                                 __builtin_amdgcn_readlane(row_off_v, pi),
-                                                 __builtin_amdgcn_readlane(row_len_v, pi), tsw);
-                        if (side == 1) {   // the lower workgroup owns the pair's counters
-                            satt[1] += 1;
-                            if (okx) sacc[1] += 1;
-                        }
-                        E[k] = okx ? pE : E[k];
-                        if (okx) {
-                            // this lane's row: bit (lane & 31) of words 2x + (lane >> 5)
-                            const int h = lane >> 5, bit = lane & 31;
-                            uint32_t wx[8];
-#pragma unroll
-                            for (int x = 0; x < 8; ++x) wx[x] = stage[2 * x + h];
-                            uint2 d;
-                            d.x = d.y = 0;
-#pragma unroll
-                            for (int x = 0; x < 8; ++x) {
-                                const uint32_t down = ((wx[x] >> bit) & 1u) ^ 1u;
-                                if (x < 4) d.x |= down << (8 * x);
-                                else d.y |= down << (8 * (x - 4));
+                        } else {
+                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                            __builtin_amdgcn_wave_barrier();
+                            const int pE = __builtin_amdgcn_readfirstlane((int)stage[NWD]);
+                            const int dEs = lower ? pE - E[0] : E[0] - pE;
+                            const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, NP * (cyc - u_base) + pi),
+                                                     __builtin_amdgcn_readlane(row_off_v, pi),
+                                                     __builtin_amdgcn_readlane(row_len_v, pi), tsw);
+                            if (lower) {
+                                satt[0] += 1;
+                                if (okx) sacc[0] += 1;
                             }
-                            *(uint2 *)(bufs + buf[k] * N + rel_me) = d;
+                            E[0] = okx ? pE : E[0];
+                            if (okx) {
+                                // this lane's row: bit (lane & 31) of words 2x + (lane >> 5)
+                                const int h = lane >> 5, bit = lane & 31;
+                                uint32_t wx[8];
+#pragma unroll
+                                for (int x = 0; x < 8; ++x) wx[x] = stage[2 * x + h];
+                                uint2 d;
+                                d.x = d.y = 0;
+#pragma unroll
+                                for (int x = 0; x < 8; ++x) {
+                                    const uint32_t down = ((wx[x] >> bit) & 1u) ^ 1u;
+                                    if (x < 4) d.x |= down << (8 * x);
+                                    else d.y |= down << (8 * (x - 4));
+                                }
+                                *(uint2 *)(bufs + buf[0] * N + rel_me) = d;
+                            }
+                        }
+                    }
+                } else {
+                    if (cyc & 1) {
+                        // pairs (2w, 2w+1): inside this wavefront
+                        const int r = lab0;
+                        if (r + 1 < P.R) {
+                            const bool ok = swap_ok(E[1] - E[0], __builtin_amdgcn_readlane(u_vec, NP * (cyc - u_base) + 1),
+                                                    __builtin_amdgcn_readlane(row_off_v, 1),
+                                                    __builtin_amdgcn_readlane(row_len_v, 1), tsw);
+                            satt[0] += 1;
+                            sacc[0] += ok ? 1u : 0u;
+                            const int b0 = buf[0], b1 = buf[1], e0 = E[0], e1 = E[1];
+                            buf[0] = ok ? b1 : b0;
+                            buf[1] = ok ? b0 : b1;
+                            E[0] = ok ? e1 : e0;
+                            E[1] = ok ? e0 : e1;
+                        }
+                    } else {
+                        // pairs (2w+1, 2w+2): with the next wavefront or across the upper
+                        // boundary; (2w-1, 2w): with the previous one or across the lower
+                        const int lu = SPW * wv + 1;                 // local slot of the upper one
+                        unsigned long long *mb = mail + (cyc & 3) * G;
+                        const bool up_here = lab0 + 2 < P.R && wv + 1 < NWV;
+                        const bool dn_here = wv > 0;
+                        // publish (energy, buffer) of the slots that meet a neighbour wavefront
+                        // LDS operations of a wavefront complete in order, so the row
+                        // writes of the sweep land before these words; only the
+                        // compiler must not move them past (signal fence)
+                        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                        if (lane == 0) {
+                            if (up_here)
+                                __hip_atomic_store(mb + lu, ((unsigned long long)cyc << 32) | ((uint32_t)buf[1] << 24) |
+                                                                ((uint32_t)E[1] & 0xFFFFFFu),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            if (dn_here)
+                                __hip_atomic_store(mb + lu - 1, ((unsigned long long)cyc << 32) | ((uint32_t)buf[0] << 24) |
+                                                                    ((uint32_t)E[0] & 0xFFFFFFu),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                        // across the workgroup boundaries: publish first (one store of
+                        // 17 tagged words: lane 2x + h holds the sites 8q + x of rows
+                        // q = 32h .. 32h + 31, one ballot per x, bit set = spin +1;
+                        // lane 16 the energy), then settle the pairs inside the
+                        // workgroup while the words travel, then poll
+                        const int buf_x = (cyc >> 1) & 1;
+                        const unsigned long long tag = (unsigned long long)cyc << 32;
+    #pragma unroll
+                        for (int side = 0; side < 2; ++side) {
+                            const int k = side == 0 ? 0 : 1;
+                            const bool cross = side == 0 ? (wv == 0 && has_down && lab0 >= 1)
+                                                         : (wv + 1 == NWV && has_up && lab0 + 2 < P.R);
+                            if (!cross || failed) continue;
+                            unsigned long long *out = it.xbuf + ((size_t)(it.w * 2 + side) * 2 + buf_x) * it.xwords;
+                            const uint2 row = *(const uint2 *)(bufs + buf[k] * N + rel_me);
+                            uint32_t pay = (uint32_t)E[k];
+    #pragma unroll
+                            for (int x = 0; x < 8; ++x) {
+                                const uint32_t byte = ((x < 4 ? row.x : row.y) >> (8 * (x & 3))) & 0xFFu;
+                                const unsigned long long bal = __ballot(byte == 0);
+                                const uint32_t half = (lane & 1) ? (uint32_t)(bal >> 32) : (uint32_t)bal;
+                                pay = (lane >> 1) == x ? half : pay;
+                            }
+                            if (lane <= NWD)
+                                __hip_atomic_store(out + lane, tag | pay, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                        if (!failed) {
+                            // inside the workgroup: read the neighbour wavefronts' words
+    #pragma unroll
+                            for (int side = 0; side < 2; ++side) {
+                                const bool here = side == 0 ? dn_here : up_here;
+                                if (!here || failed) continue;
+                                const int k = side == 0 ? 0 : 1;
+                                const int pl = side == 0 ? SPW * wv - 1 : SPW * wv + 2;   // partner local slot
+                                uint32_t polls = 0;
+                                unsigned long long v;
+                                for (;;) {
+                                    v = __hip_atomic_load(mb + pl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                    if ((uint32_t)(v >> 32) == cyc) break;
+                                    __builtin_amdgcn_s_sleep(1);
+                                    if (++polls > a.spin_limit) break;
+                                }
+                                if ((uint32_t)(v >> 32) != cyc) {
+                                    if (lane == 0 && atomicCAS(a.err, 0, 2) == 0) {
+                                        a.err[1] = item; a.err[2] = it.w; a.err[3] = 2; a.err[4] = (int)cyc;
+                                        a.err[5] = (int)(v & 0xFFFFFFFFu); a.err[6] = (int)(v >> 32); a.err[7] = (int)I.epoch;
+                                    }
+                                    failed = true;
+                                    continue;
+                                }
+                                // every value here is wave-uniform: keep it scalar
+                                const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)v);
+                                const int pE = ((int)(lo32 << 8)) >> 8;      // 24-bit signed energy
+                                const int pb = (int)((lo32 >> 24) & 0xFFu);
+                                const int slot = lab0 + k;
+                                const int r = side == 0 ? slot - 1 : slot;
+                                const int pi = r - (lab0 - 1);                // 0 or 2
+                                const int dEs = side == 0 ? E[k] - pE : pE - E[k];
+                                const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, NP * (cyc - u_base) + pi),
+                                                         __builtin_amdgcn_readlane(row_off_v, pi),
+                                                         __builtin_amdgcn_readlane(row_len_v, pi), tsw);
+                                if (side == 1) {
+                                    satt[1] += 1;
+                                    sacc[1] += okx ? 1u : 0u;
+                                }
+                                // trade buffers on acceptance: the partner takes ours
+                                buf[k] = okx ? pb : buf[k];
+                                E[k] = okx ? pE : E[k];
+                            }
+                        }
+                        // across the workgroup boundaries: poll, decide, copy
+    #pragma unroll
+                        for (int side = 0; side < 2; ++side) {
+                            const int k = side == 0 ? 0 : 1;
+                            const bool cross = side == 0 ? (wv == 0 && has_down && lab0 >= 1)
+                                                         : (wv + 1 == NWV && has_up && lab0 + 2 < P.R);
+                            if (!cross || failed) continue;
+                            const int pw = side == 0 ? it.w - 1 : it.w + 1;
+                            const unsigned long long *in =
+                                it.xbuf + ((size_t)(pw * 2 + (side == 0 ? 1 : 0)) * 2 + buf_x) * it.xwords;
+                            uint32_t *stage = xstage + (size_t)(wv * 2 + side) * (NWD + 1);
+                            uint32_t polls = 0;
+                            bool ok_all = false;
+                            unsigned long long bad = 0;
+                            for (;;) {
+                                bool ok = true;
+                                if (lane <= NWD) {
+                                    const unsigned long long v =
+                                        __hip_atomic_load(in + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                    if ((uint32_t)(v >> 32) == cyc) stage[lane] = (uint32_t)v;
+                                    else {
+                                        ok = false;
+                                        bad = v;
+                                    }
+                                }
+                                if (__all(ok)) {
+                                    ok_all = true;
+                                    break;
+                                }
+                                if (++polls > a.spin_limit) break;
+                            }
+                            if (!ok_all) {
+                                if (lane == 0 && atomicCAS(a.err, 0, 1) == 0) {
+                                    a.err[1] = item; a.err[2] = it.w; a.err[3] = side; a.err[4] = (int)cyc;
+                                    a.err[5] = (int)(bad & 0xFFFFFFFFu); a.err[6] = (int)(bad >> 32); a.err[7] = (int)I.epoch;
+                                }
+                                failed = true;
+                                continue;
+                            }
+                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                            __builtin_amdgcn_wave_barrier();
+                            const int pE = __builtin_amdgcn_readfirstlane((int)stage[NWD]);
+                            const int slot = lab0 + k;
+                            const int r = side == 0 ? slot - 1 : slot;
+                            const int pi = r - (lab0 - 1);                    // 0 or 2
+                            const int dEs = side == 0 ? E[k] - pE : pE - E[k];
+                            const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, NP * (cyc - u_base) + pi),
+                                                     __builtin_amdgcn_readlane(row_off_v, pi),
+                                                     __builtin_amdgcn_readlane(row_len_v, pi), tsw);
+                            if (side == 1) {   // the lower workgroup owns the pair's counters
+                                satt[1] += 1;
+                                if (okx) sacc[1] += 1;
+                            }
+                            E[k] = okx ? pE : E[k];
+                            if (okx) {
+                                // this lane's row: bit (lane & 31) of words 2x + (lane >> 5)
+                                const int h = lane >> 5, bit = lane & 31;
+                                uint32_t wx[8];
+    #pragma unroll
+                                for (int x = 0; x < 8; ++x) wx[x] = stage[2 * x + h];
+                                uint2 d;
+                                d.x = d.y = 0;
+    #pragma unroll
+                                for (int x = 0; x < 8; ++x) {
+                                    const uint32_t down = ((wx[x] >> bit) & 1u) ^ 1u;
+                                    if (x < 4) d.x |= down << (8 * x);
+                                    else d.y |= down << (8 * (x - 4));
+                                }
+                                *(uint2 *)(bufs + buf[k] * N + rel_me) = d;
+                            }
                         }
                     }
                 }
@@ -651,21 +783,25 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
 // ---------------------------------------------------------------------------
 // Host-side launchers (C++ linkage, used by the runtime in host.cpp).
 
-int pm_max_storages() { return 16; }
+// spw: slots per wavefront (1 or 2); a workgroup holds at most 8 wavefronts
+int pm_max_storages(int spw) { return spw == 1 ? 8 : 16; }
 
 size_t pm_lds_bytes(int G, int tsw_entries) { return pm::offsets(G, tsw_entries).total; }
 
-hipError_t launch_pm(const ChunkArgs &a, int block, size_t lds, hipStream_t s)
+hipError_t launch_pm(int spw, const ChunkArgs &a, int block, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL(pm_kernel, dim3(a.n_items), dim3(block), lds, s, a);
+    if (spw == 1) hipLaunchKernelGGL(pm_kernel<1>, dim3(a.n_items), dim3(block), lds, s, a);
+    else hipLaunchKernelGGL(pm_kernel<2>, dim3(a.n_items), dim3(block), lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t pm_occupancy(int block, size_t lds, int *blocks_per_cu)
+hipError_t pm_occupancy(int spw, int block, size_t lds, int *blocks_per_cu)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)pm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const void *f = spw == 1 ? (const void *)pm_kernel<1> : (const void *)pm_kernel<2>;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, pm_kernel, block, lds);
+    return spw == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, pm_kernel<1>, block, lds)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, pm_kernel<2>, block, lds);
 }
 
 } // namespace tapt

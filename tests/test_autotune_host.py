@@ -16,7 +16,7 @@ def test_candidates_cover_caps_and_threads():
     assert all(rpt <= G for G, rpt, _ in c)
     assert not any(k == "pm" for _, _, k in c)
     c3 = autotune.candidates([_ctx("lattice", 8, 512, 32, pm=True)])
-    assert (8, 1, "pm") in c3 and (16, 1, "pm") in c3
+    assert (8, 1, "pm") in c3 and (16, 1, "pm") in c3 and (8, 1, "pm1") in c3 and (16, 1, "pm1") not in c3
     c2 = autotune.candidates([_ctx("lattice", 4, 64, 3)])
     assert max(G for G, _, _ in c2) <= 6 and all(k == "block" for _, _, k in c2)
 

@@ -242,10 +242,13 @@ def test_mixed_sizes_one_launch():
 
 @pytest.mark.parametrize("kernel,G,rule,M", [("pm", 8, "metropolis", 1), ("pm", 2, "gibbs", 1), ("pm", 4, "metropolis", 3),
                                              ("pm", 16, "gibbs", 2), ("wave", 8, "metropolis", 1), ("wave", 3, "gibbs", 2),
-                                             ("block", 8, "metropolis", 1)])
+                                             ("block", 8, "metropolis", 1), ("pm1", 8, "metropolis", 1),
+                                             ("pm1", 1, "gibbs", 1), ("pm1", 5, "metropolis", 3), ("pm1", 3, "gibbs", 2)])
 def test_l8_kernels(kernel, G, rule, M):
-    """The three persistent kernels that run 8^3 lattices, on the benchmark's
-    shape (R = 32, proposals from banks) for several instances."""
+    """The persistent kernels that run 8^3 lattices (the +-J kernel with two
+    slots or one slot per wavefront, wave-per-replica, workgroup-synchronous),
+    on the benchmark's shape (R = 32, proposals from banks) for several
+    instances."""
     announce(f"L=8 R=32 x 6 instances, kernel={kernel} G={G} rule={rule} M={M}, 2 launches of 90 sweeps")
     betas = inputs.geometric_ladder(32)
     cases = []
