@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                         // exact test: u = (upper << 16) | lower, the lower half
                         // from the refinement call
                         const uint32_t *tu = tabu + (SPW * wv + k) * 8;
-                        const P4 r2 = philox_v((uint32_t)lane, (uint32_t)t, (uint32_t)(lab0 + k), TAG_REFINE, P.k0, P.k1);
+                        const P4 r2 = philox_v(opaque((uint32_t)lane), (uint32_t)t, (uint32_t)(lab0 + k), TAG_REFINE, P.k0, P.k1);
                         uint32_t Fx = 0;
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {

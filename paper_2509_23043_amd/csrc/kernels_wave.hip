@@ -104,7 +104,7 @@ struct WaveLat {
                 any_maybe |= maybe[s];
             }
             if (any_lane(any_maybe)) {
-                P4 r2 = philox(q, t, slot, TAG_REFINE, k0, k1);
+                P4 r2 = philox(opaque(q), t, slot, TAG_REFINE, k0, k1);
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     uint32_t lo = (r2.v[s] >> sh[c][s]) & 0xFFFFu;

@@ -45,6 +45,15 @@ __host__ __device__ __forceinline__ uint32_t philox_word0(uint32_t c0, uint32_t 
     return philox(c0, c1, 0, c3, k0, k1).v[0];
 }
 
+// An opaque copy of x. A rarely taken branch passes its Philox counter
+// through it, so that the compiler cannot hoist the (pure) draw out of the
+// branch and pay for it on every pass.
+__device__ __forceinline__ uint32_t opaque(uint32_t x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // Three-input XOR in one instruction (gfx950 v_bitop3_b32, truth table 0x96).
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 {
@@ -254,7 +263,7 @@ struct LatSweep {
                         any_maybe |= maybe[s];
                     }
                     if (any_lane(any_maybe)) {
-                        P4 r2 = philox((uint32_t)q, t, (uint32_t)(s0 + sl[k]), TAG_REFINE, I.seed_lo, I.seed_hi);
+                        P4 r2 = philox(opaque((uint32_t)q), t, (uint32_t)(s0 + sl[k]), TAG_REFINE, I.seed_lo, I.seed_hi);
 #pragma unroll
                         for (int s = 0; s < 4; ++s) {
                             uint32_t lo = (r2.v[s] >> sh[c][s]) & 0xFFFFu;
@@ -422,7 +431,7 @@ struct CsrSweep {
                 bool acc = coarse_accept(T, hs, maybe);
                 if (any_lane(maybe)) {
                     if (maybe) {
-                        P4 r2 = philox((uint32_t)(i >> 3), t, (uint32_t)(s0 + sl), TAG_REFINE, I.seed_lo, I.seed_hi);
+                        P4 r2 = philox(opaque((uint32_t)(i >> 3)), t, (uint32_t)(s0 + sl), TAG_REFINE, I.seed_lo, I.seed_hi);
                         const int wq = (i & 7) >> 1;   // word of the half (no dynamic indexing)
                         const uint32_t wd = wq == 0 ? r2.v[0] : wq == 1 ? r2.v[1] : wq == 2 ? r2.v[2] : r2.v[3];
                         const uint32_t lo = ((i & 1) ? (wd >> 16) : wd) & 0xFFFFu;
