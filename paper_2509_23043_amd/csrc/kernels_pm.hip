@@ -19,7 +19,10 @@
 // each into one dword, three-input XORs form the six unsatisfied-bond flags
 // and byte-wise adds count them (U <= 6, no carries). Then m_i I_i = 6 - 2U,
 // the flip changes E by 12 - 4U, and the threshold is the slot's table entry
-// for that m_i I_i (held in LDS indexed by U).
+// for that m_i I_i. The upper halves of the slot's eight thresholds (by U)
+// sit in registers as byte tables, so one v_perm looks up all four sites and
+// saturating 16-bit subtractions test them against their uniforms at once;
+// the rare tie of the upper halves takes the exact 32-bit test.
 //
 // Slots and states. A wavefront's slots are fixed; states move between LDS
 // buffers. With two slots, the pair (2w, 2w+1) is decided inside the
