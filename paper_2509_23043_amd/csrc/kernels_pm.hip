@@ -237,6 +237,22 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
         uint32_t cyc = (uint32_t)(t0 / (uint64_t)P.M), phase = (uint32_t)(t0 % (uint64_t)P.M);
         uint64_t prop_at = P.first_prop_from(t0 + 1);
         const int lab0 = s0 + SPW * wv;          // this wavefront's slots: lab0 .. lab0 + SPW - 1
+        // one slot per wavefront: its exchange by cycle parity, three bits per
+        // parity (1: lower member of its pair, 2: partner in this workgroup,
+        // 4: partner across a workgroup boundary), so that the cycle end tests
+        // bits of one scalar
+        int xflags = 0;
+        if constexpr (SPW == 1) {
+#pragma unroll
+            for (int par = 0; par < 2; ++par) {
+                const bool lower = ((lab0 ^ par) & 1) != 0;
+                const bool paired = lower ? lab0 + 1 < P.R : lab0 >= 1;
+                const bool intra = paired && (lower ? wv + 1 < NWV : wv > 0);
+                const bool cross = paired && !intra && (lower ? has_up : has_down);
+                xflags |= ((lower ? 1 : 0) | (intra ? 2 : 0) | (cross ? 4 : 0)) << (3 * par);
+            }
+            xflags = __builtin_amdgcn_readfirstlane(xflags);
+        }
         // swap uniforms of this wavefront's NP pairs for UCYC cycles: lane
         // NP c + i holds pair lab0 - 1 + i at cycle u_base + c
         constexpr uint32_t UCYC = 64 / NP;
@@ -379,13 +395,12 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                 if constexpr (SPW == 1) {
                     // the slot is the lower member of its pair when its parity
                     // differs from the cycle's
-                    const int slot = lab0;
-                    const bool lower = ((slot ^ (int)cyc) & 1) != 0;
-                    const int side = lower ? 1 : 0;                   // 1: partner slot + 1
-                    const bool paired = lower ? slot + 1 < P.R : slot >= 1;
-                    const bool intra = paired && (lower ? wv + 1 < NWV : wv > 0);
-                    const bool cross = paired && !intra && (lower ? has_up : has_down);
-                    const int pi = lower ? 1 : 0;                     // pair lab0 - 1 + pi
+                    const int xf = (xflags >> (3 * (int)(cyc & 1))) & 7;
+                    const bool lower = (xf & 1) != 0;
+                    const int side = xf & 1;                          // 1: partner lab0 + 1
+                    const bool intra = (xf & 2) != 0;
+                    const bool cross = (xf & 4) != 0;
+                    const int pi = xf & 1;                            // pair lab0 - 1 + pi
                     unsigned long long *mb = mail + (cyc & 3) * G;
                     __atomic_signal_fence(__ATOMIC_SEQ_CST);
                     if (intra && lane == 0)
