@@ -412,12 +412,15 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                         unsigned long long *out = it.xbuf + ((size_t)(it.w * 2 + side) * 2 + buf_x) * it.xwords;
                         const uint2 row = *(const uint2 *)(bufs + buf[0] * N + rel_me);
                         uint32_t pay = (uint32_t)E[0];
+                        // lane >> 1 made opaque here: otherwise the compiler keeps the eight
+                        // lane masks (lane >> 1) == x in SGPRs for the whole launch
+                        const uint32_t lh = opaque((uint32_t)lane >> 1);
 #pragma unroll
                         for (int x = 0; x < 8; ++x) {
                             const uint32_t byte = ((x < 4 ? row.x : row.y) >> (8 * (x & 3))) & 0xFFu;
                             const unsigned long long bal = __ballot(byte == 0);
                             const uint32_t half = (lane & 1) ? (uint32_t)(bal >> 32) : (uint32_t)bal;
-                            pay = (lane >> 1) == x ? half : pay;
+                            pay = lh == (uint32_t)x ? half : pay;
                         }
                         if (lane <= NWD)
                             __hip_atomic_store(out + lane, ((unsigned long long)cyc << 32) | pay, __ATOMIC_RELAXED,
@@ -561,7 +564,7 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                         // workgroup while the words travel, then poll
                         const int buf_x = (cyc >> 1) & 1;
                         const unsigned long long tag = (unsigned long long)cyc << 32;
-    #pragma unroll
+#pragma unroll
                         for (int side = 0; side < 2; ++side) {
                             const int k = side == 0 ? 0 : 1;
                             const bool cross = side == 0 ? (wv == 0 && has_down && lab0 >= 1)
@@ -570,19 +573,22 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                             unsigned long long *out = it.xbuf + ((size_t)(it.w * 2 + side) * 2 + buf_x) * it.xwords;
                             const uint2 row = *(const uint2 *)(bufs + buf[k] * N + rel_me);
                             uint32_t pay = (uint32_t)E[k];
-    #pragma unroll
+                            // lane >> 1 made opaque here: otherwise the compiler keeps the eight
+                            // lane masks (lane >> 1) == x in SGPRs for the whole launch
+                            const uint32_t lh = opaque((uint32_t)lane >> 1);
+#pragma unroll
                             for (int x = 0; x < 8; ++x) {
                                 const uint32_t byte = ((x < 4 ? row.x : row.y) >> (8 * (x & 3))) & 0xFFu;
                                 const unsigned long long bal = __ballot(byte == 0);
                                 const uint32_t half = (lane & 1) ? (uint32_t)(bal >> 32) : (uint32_t)bal;
-                                pay = (lane >> 1) == x ? half : pay;
+                                pay = lh == (uint32_t)x ? half : pay;
                             }
                             if (lane <= NWD)
                                 __hip_atomic_store(out + lane, tag | pay, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         }
                         if (!failed) {
                             // inside the workgroup: read the neighbour wavefronts' words
-    #pragma unroll
+#pragma unroll
                             for (int side = 0; side < 2; ++side) {
                                 const bool here = side == 0 ? dn_here : up_here;
                                 if (!here || failed) continue;
@@ -625,7 +631,7 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                             }
                         }
                         // across the workgroup boundaries: poll, decide, copy
-    #pragma unroll
+#pragma unroll
                         for (int side = 0; side < 2; ++side) {
                             const int k = side == 0 ? 0 : 1;
                             const bool cross = side == 0 ? (wv == 0 && has_down && lab0 >= 1)
@@ -682,11 +688,11 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                                 // this lane's row: bit (lane & 31) of words 2x + (lane >> 5)
                                 const int h = lane >> 5, bit = lane & 31;
                                 uint32_t wx[8];
-    #pragma unroll
+#pragma unroll
                                 for (int x = 0; x < 8; ++x) wx[x] = stage[2 * x + h];
                                 uint2 d;
                                 d.x = d.y = 0;
-    #pragma unroll
+#pragma unroll
                                 for (int x = 0; x < 8; ++x) {
                                     const uint32_t down = ((wx[x] >> bit) & 1u) ^ 1u;
                                     if (x < 4) d.x |= down << (8 * x);
