@@ -159,6 +159,15 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
     const int row_off_v = tsw_off[prow_w];
     const int row_len_v = tsw_off[prow_w + 1] - row_off_v;
     const bool active = wv < NWV;
+    // the wavefronts at the workgroup's ends carry the cross-workgroup
+    // exchanges that pace the whole ladder: the closer a wavefront is to an
+    // end, the earlier it issues on its SIMD
+    if (it.W > 1) {
+        const int dist = wv < NWV - 1 - wv ? wv : NWV - 1 - wv;
+        if (dist == 0) __builtin_amdgcn_s_setprio(3);
+        else if (dist == 1) __builtin_amdgcn_s_setprio(2);
+        else if (dist == 2) __builtin_amdgcn_s_setprio(1);
+    }
     const bool has_down = it.w > 0, has_up = it.w + 1 < it.W;
     bool failed = false;
 
