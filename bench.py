@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--L", type=int, default=8)
     ap.add_argument("--R", type=int, default=32)
     ap.add_argument("--bank", type=int, default=256)
+    ap.add_argument("--sweeps-per-swap", type=int, default=1,
+                    help="M, sweeps per swap stage (the workload's value is 1; must divide 100)")
     ap.add_argument("--tiling", default="auto", help="'auto' or G,rpt[,kernel] (slots per workgroup, per thread; "
                                                      "kernel auto|block|wave)")
     ap.add_argument("--no-plain", action="store_true")
@@ -98,26 +100,26 @@ def make_banks(probs, betas, B, n_prop_slots, log):
     return bank
 
 
-def build_contexts(probs, betas, bank, seeds):
+def build_contexts(probs, betas, bank, seeds, M=1):
     from paper_2509_23043_amd import binding
     ctxs = []
     for i, p in enumerate(probs):
-        c = binding.Context(p, betas, seed=seeds[i], prop_start=100, prop_period=100)
+        c = binding.Context(p, betas, seed=seeds[i], M=M, prop_start=100, prop_period=100)
         for r in range(bank.shape[1]):
             c.propose_device(r, bank[i, r].data_ptr(), bank.shape[2])
         ctxs.append(c)
     return ctxs
 
 
-def tune_tiling(probs, betas, bank, log):
+def tune_tiling(probs, betas, bank, log, M=1):
     """The autotuner's choice of tiling on scratch contexts of the same batch
-    (M stays 1: the workload fixes one sweep per swap stage)."""
+    (M is fixed by the workload: one sweep per swap stage unless asked)."""
     from paper_2509_23043_amd import autotune
 
-    def make(M):
-        return build_contexts(probs, betas, bank, [7 + i for i in range(len(probs))])
+    def make(m):
+        return build_contexts(probs, betas, bank, [7 + i for i in range(len(probs))], M=m)
 
-    res = autotune.tune(make, Ms=(1,), warm=300, timed=1500, log=log)
+    res = autotune.tune(make, Ms=(M,), warm=300, timed=1500, log=log)
     return res
 
 
@@ -338,6 +340,9 @@ def main():
     torch.cuda.set_device(0)
     binding.lib()
     L, R, NI, S = args.L, args.R, args.instances, args.sweeps_per_step
+    M = args.sweeps_per_swap
+    if M < 1 or 100 % M:
+        sys.exit("--sweeps-per-swap must divide the proposal period (100)")
     n = L ** 3
     n_prop = R - 2
     probs, betas = problems(NI, L, R)
@@ -353,7 +358,7 @@ def main():
             torch.save(bank.cpu(), args.bank_cache)
 
     if args.tiling == "auto":
-        tuned = tune_tiling(probs, betas, bank, log)
+        tuned = tune_tiling(probs, betas, bank, log, M=M)
         G, rpt, kern = tuned["replicas_per_wg"], tuned["replicas_per_thread"], tuned["kernel"]
         scan = tuned["scan"]
     else:
@@ -364,7 +369,7 @@ def main():
     log(f"tiling: {G} slots per workgroup, {rpt} per thread, kernel {kern}")
 
     seeds = [3000 + i for i in range(NI)]
-    ctxs = build_contexts(probs, betas, bank, seeds)
+    ctxs = build_contexts(probs, betas, bank, seeds, M=M)
     bt = binding.Batch(ctxs, replicas_per_wg=G, replicas_per_thread=rpt, chunk_sweeps=S, kernel=kern)
     for _ in range(args.warmup):
         bt.sweep(S)
@@ -384,7 +389,7 @@ def main():
     # the plain path on instance 0, same seed and bank: same chain, compared bit for bit
     plain = None
     if not args.no_plain:
-        p_ctx = build_contexts(probs[:1], betas, bank[:1], seeds[:1])[0]
+        p_ctx = build_contexts(probs[:1], betas, bank[:1], seeds[:1], M=M)[0]
         total = (args.warmup + args.steps) * S
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -441,10 +446,10 @@ def main():
     out = dict(metric=METRIC, value=round(value, 2), unit="attempts/ns", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms_step, 3), higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="int8", data="synthetic",
-               config=dict(workload="3D EA +-J L=8 (512 spins) x 64 instances, 32 replicas beta 0.2..3.0 "
-                                    "geometric, Metropolis, M=1, proposals every 100 sweeps from 256-entry "
-                                    "plain-PT banks on 30 slots; 10^4 sweeps per step",
-                           instances=NI, L=L, replicas=R, sweeps_per_step=S, bank=args.bank,
+               config=dict(workload=f"3D EA +-J L={L} ({n} spins) x {NI} instances, {R} replicas beta 0.2..3.0 "
+                                    f"geometric, Metropolis, M={M}, proposals every 100 sweeps from {args.bank}-entry "
+                                    f"plain-PT banks on {n_prop} slots; {S} sweeps per step",
+                           instances=NI, L=L, replicas=R, sweeps_per_step=S, sweeps_per_swap=M, bank=args.bank,
                            tiling=dict(replicas_per_wg=G, replicas_per_thread=rpt, kernel=kern)),
                plain=plain, roofline=roof, cpu_baseline=cpu,
                tiling_scan=[dict(G=d["replicas_per_wg"], rpt=d["replicas_per_thread"], kernel=d["kernel"],

@@ -186,11 +186,12 @@ def test_invalid_inputs_rejected():
             ctxm.propose(0, wrong)
 
 
-@pytest.mark.parametrize("G,rpt", [(4, 4), (4, 1), (2, 1)])
-def test_many_instances_split_ladders(G, rpt):
+@pytest.mark.parametrize("G,rpt,kernel", [(4, 4, "auto"), (4, 1, "auto"), (2, 1, "auto"), (8, 1, "pm1"), (8, 1, "pm")])
+def test_many_instances_split_ladders(G, rpt, kernel):
     """64 EA L=8 instances with R=32 split into 32/G workgroups each, several
-    launches; sampled instances checked against the oracle."""
-    announce(f"64 instances, L=8 R=32, G={G} rpt={rpt}, 3 launches of 40 sweeps")
+    launches; sampled instances checked against the oracle. (8, 1, pm1) is
+    the benchmark's own launch configuration."""
+    announce(f"64 instances, L=8 R=32, G={G} rpt={rpt} kernel={kernel}, 3 launches of 40 sweeps")
     from tests.gpu_util import make_pair
     betas = inputs.geometric_ladder(32)
     pairs = []
@@ -203,7 +204,8 @@ def test_many_instances_split_ladders(G, rpt):
             for r, b in banks.items():
                 ctx.propose(r, b)
         pairs.append((ctx, g, banks, kw))
-    bt = binding.Batch([p[0] for p in pairs], replicas_per_wg=G, replicas_per_thread=rpt, chunk_sweeps=40)
+    bt = binding.Batch([p[0] for p in pairs], replicas_per_wg=G, replicas_per_thread=rpt, chunk_sweeps=40,
+                       kernel=kernel)
     bt.sweep(120)
     import oracle
     for i in (0, 8, 37, 63):
