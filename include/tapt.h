@@ -75,14 +75,19 @@ typedef struct {
     const int32_t *color;
 } pt_graph;
 
-/* Run options (Algorithm 1 inputs). prop_period = 0 disables proposals;
+/* Run options (Algorithm 1 inputs). sweeps_per_cycle = 0 makes the slots
+ * independent chains: no swap stage and no proposal stage ever runs, the
+ * betas need only be positive (equal values allowed), and a context may run
+ * at most 2^31 - 2 sweeps. This is the long-run MCMC that generates proposal
+ * banks (Supp. Table S3 and the bank protocol after it: each sample from its
+ * own randomly initialised chain after a burn-in). prop_period = 0 disables proposals;
  * otherwise a proposal stage runs at the end of sweep t when t >= prop_start,
  * (t - prop_start) % prop_period == 0 and (prop_stop < 0 or t <= prop_stop);
  * prop_start and prop_period must be multiples of sweeps_per_cycle.
  * target: first_hit records the first sweep with min_r E_r <= target. */
 typedef struct {
     int32_t rule;              /* PT_METROPOLIS or PT_GIBBS */
-    int32_t sweeps_per_cycle;  /* M >= 1: sweeps between swap stages */
+    int32_t sweeps_per_cycle;  /* M >= 1: sweeps between swap stages; 0: independent chains */
     int64_t prop_start;
     int64_t prop_period;
     int64_t prop_stop;
@@ -103,7 +108,8 @@ typedef struct {
 /* Create a context: validate and copy the problem, build the uint32
  * acceptance tables on the host in FP64 (Eqs. 1, 2, 5), allocate device
  * state and initialise the replicas randomly (Algorithm 1, first line).
- * betas: host [R], strictly increasing, > 0 (slot 0 hottest). R in 2..1024. */
+ * betas: host [R], strictly increasing, > 0 (slot 0 hottest); any positive
+ * values for independent chains. R in 1..1024. */
 int pt_create(const pt_graph *g, const double *betas, int32_t R, const pt_opts *o, pt_ctx **out);
 int pt_destroy(pt_ctx *c);
 

@@ -131,9 +131,12 @@ typedef struct {
     const int32_t *color;   /* [n] proper coloring, colors 0..ncolors-1 */
     int32_t ncolors;
     int32_t R;
-    const double *beta;     /* [R] strictly increasing: slot 0 hottest */
+    const double *beta;     /* [R] strictly increasing: slot 0 hottest (any
+                               positive values when M == 0) */
     int32_t rule;           /* RULE_METROPOLIS | RULE_GIBBS */
-    int32_t M;              /* sweeps per cycle (between swap stages) */
+    int32_t M;              /* sweeps per cycle (between swap stages); 0: the
+                               slots are independent chains with no cycle end
+                               (the bank-generation runs of Supp. Table S3) */
     int64_t prop_start, prop_period, prop_stop; /* proposal schedule, sweeps */
     uint64_t seed;
     const int8_t *const *bank; /* [R]: NULL or [bank_n[r]][n] configurations */
@@ -276,7 +279,7 @@ int orc_run(const orc_problem *P, orc_state *S, uint64_t n_sweeps)
         /* local MCMC sweeps: every replica, one sweep each */
         for (int32_t r = 0; r < R; ++r) sweep_slot(P, S, r, (uint32_t)t);
         S->t = t;
-        if (t % (uint64_t)P->M == 0) {
+        if (P->M > 0 && t % (uint64_t)P->M == 0) {
             uint64_t cyc = t / (uint64_t)P->M; /* cycle n of Algorithm 1, 1-based */
             /* "Compute E(S_r) for all replicas" */
             for (int32_t r = 0; r < R; ++r) {

@@ -196,6 +196,16 @@ static int push_inst(pt_ctx *c)
     return PT_OK;
 }
 
+// Independent chains (sweeps_per_cycle 0) run with a cycle this long, so
+// that no cycle ends within the sweeps such a context may run.
+constexpr int32_t INDEPENDENT_M = 0x7FFFFFFF;
+
+// Largest sweep counter a context may reach.
+static uint64_t sweep_limit(const pt_ctx *c)
+{
+    return c->opts.sweeps_per_cycle == 0 ? (uint64_t)INDEPENDENT_M - 1 : 0xFFFFFFFFull;
+}
+
 static int check_ctx(pt_ctx *c)
 {
     if (!c) return fail(PT_EINVAL, "null context");
@@ -415,12 +425,16 @@ extern "C" int pt_create(const pt_graph *g, const double *betas, int32_t R, cons
     *out = nullptr;
     if (!betas || !o) return fail(PT_EINVAL, "null betas or options");
     if (R < 1 || R > 1024) return fail(PT_EINVAL, "R must be in 1..1024 (got %d)", R);
+    // sweeps_per_cycle == 0: independent chains (no swap stage, no proposals),
+    // where any positive betas are allowed, equal ones included
+    const bool independent = o->sweeps_per_cycle == 0;
     for (int r = 0; r < R; ++r) {
         if (!(betas[r] > 0.0) || !std::isfinite(betas[r])) return fail(PT_EINVAL, "beta[%d] must be finite and > 0", r);
-        if (r && !(betas[r] > betas[r - 1])) return fail(PT_EINVAL, "betas must be strictly increasing");
+        if (!independent && r && !(betas[r] > betas[r - 1])) return fail(PT_EINVAL, "betas must be strictly increasing");
     }
     if (o->rule != PT_METROPOLIS && o->rule != PT_GIBBS) return fail(PT_EINVAL, "unknown rule %d", o->rule);
-    if (o->sweeps_per_cycle < 1) return fail(PT_EINVAL, "sweeps_per_cycle must be >= 1");
+    if (o->sweeps_per_cycle < 0) return fail(PT_EINVAL, "sweeps_per_cycle must be >= 0");
+    if (independent && o->prop_period != 0) return fail(PT_EINVAL, "independent chains (sweeps_per_cycle 0) take no proposals");
     if (o->prop_period < 0) return fail(PT_EINVAL, "prop_period must be >= 0");
     if (o->prop_period > 0) {
         if (o->prop_start < 0) return fail(PT_EINVAL, "prop_start must be >= 0");
@@ -470,7 +484,7 @@ extern "C" int pt_create(const pt_graph *g, const double *betas, int32_t R, cons
     }
     for (int r = 0; r + 1 < R; ++r) {
         tswap_off[r] = (int32_t)tswap.size();
-        tail_table(betas[r + 1] - betas[r], tswap);
+        if (!independent) tail_table(betas[r + 1] - betas[r], tswap);
         tswap_len[r] = (int32_t)tswap.size() - tswap_off[r];
     }
     if (tprop.empty()) tprop.push_back(0);
@@ -529,7 +543,8 @@ extern "C" int pt_create(const pt_graph *g, const double *betas, int32_t R, cons
     I.R = R;
     I.kind = P.kind;
     I.rule = o->rule;
-    I.M = o->sweeps_per_cycle;
+    // independent chains: a cycle longer than any run the sweep counter allows
+    I.M = independent ? INDEPENDENT_M : o->sweeps_per_cycle;
     I.D = P.D;
     I.tflip_stride = stride;
     I.has_target = o->has_target ? 1 : 0;
@@ -654,7 +669,8 @@ extern "C" int pt_sweep(pt_ctx *c, uint64_t n_sweeps)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    if (c->t_host + n_sweeps > 0xFFFFFFFFull) return fail(PT_EINVAL, "sweep counter would exceed 2^32-1");
+    if (c->t_host + n_sweeps > sweep_limit(c)) return fail(PT_EINVAL, "sweep counter would exceed %llu",
+                                                            (unsigned long long)sweep_limit(c));
     hipStream_t s = c->stream;
     const int stride = 2 * c->D + 1;
     for (uint64_t k = 0; k < n_sweeps; ++k) {
@@ -1135,7 +1151,8 @@ extern "C" int pt_batch_sweep(pt_batch *b, uint64_t n_sweeps)
     // every context stops exactly at its own t + n_sweeps
     for (pt_ctx *c : b->ctxs) {
         if (c->broken) return fail(PT_ESTATE, "a context of the batch is unusable");
-        if (c->t_host + n_sweeps > 0xFFFFFFFFull) return fail(PT_EINVAL, "sweep counter would exceed 2^32-1");
+        if (c->t_host + n_sweeps > sweep_limit(c))
+            return fail(PT_EINVAL, "sweep counter would exceed %llu", (unsigned long long)sweep_limit(c));
         HIPCHK(hipStreamSynchronize(c->stream));
         c->hI.sweep_cap = c->t_host + n_sweeps;
         HIPCHK(hipMemcpyAsync(c->inst.p, &c->hI, sizeof(InstDev), hipMemcpyHostToDevice, b->stream));

@@ -332,3 +332,56 @@ def test_factorization_batch_8bit():
         ref = oracle.Run(g, betas, seed=seed, banks=banks, **kw)
         ref.run(120)
         compare(ctxs[i], ref)
+
+
+@pytest.mark.parametrize("case", ["plain", "block", "pm", "pm1", "csr"])
+def test_independent_chains(case):
+    """Independent chains (no cycle end, equal betas allowed): the
+    bank-generation runs of Supp. Table S3, on every kernel family."""
+    announce(f"independent chains, {case}")
+    import oracle
+    if case == "csr":
+        ps = inputs.primes_in(8, 16)
+        g = inputs.multiplier(4, ps[0] * ps[-1])
+        betas = np.full(8, 1.5)
+    elif case in ("pm", "pm1"):
+        g = inputs.ea_lattice(8, 41)
+        betas = np.full(16, 1.0)
+    else:
+        g = inputs.ea_lattice(6 if case == "plain" else 10, 42)
+        betas = np.array([0.8, 0.8, 1.6, 1.6, 2.4, 0.5])
+    seeds = (900, 901)
+    ctxs = [binding.Context(g, betas, seed=s, M=0) for s in seeds]
+    if case == "plain":
+        ctxs[0].sweep(30)
+        ctxs[0].sweep(30)
+        ctxs = ctxs[:1]
+    else:
+        kern = {"block": "block", "pm": "pm", "pm1": "pm1", "csr": "auto"}[case]
+        G = {"block": 4, "pm": 8, "pm1": 4, "csr": 4}[case]
+        bt = binding.Batch(ctxs, replicas_per_wg=G, chunk_sweeps=30, kernel=kern)
+        bt.sweep(60)
+    for c, s in zip(ctxs, seeds):
+        ref = oracle.Run(g, betas, seed=s, M=0)
+        ref.run(60)
+        compare(c, ref)
+        assert ref.swap_att.sum() == 0
+
+
+def test_generate_bank_matches_independent_oracle_chains():
+    """banks.generate_bank: sample j is slot j mod 1024 of context j // 1024,
+    an independent chain at beta after the burn-in, bit for bit."""
+    announce("generate_bank: 2100 chains of L=4 at beta 1.3, 40 sweeps, 3 contexts")
+    import oracle
+    from paper_2509_23043_amd import banks
+    g = inputs.ea_lattice(4, 61)
+    timing = {}
+    cfg, E = banks.generate_bank(g, 1.3, 2100, 40, seed=300, timing=timing)
+    assert cfg.shape == (2100, 64) and E.shape == (2100,)
+    assert timing["attempts"] == 2100 * 40 * 64
+    for c, R in ((0, 1024), (2, 52)):
+        ref = oracle.Run(g, np.full(R, 1.3), seed=300 + c, M=0)
+        ref.run(40)
+        for slot in (0, R // 2, R - 1):
+            j = 1024 * c + slot
+            assert np.array_equal(cfg[j], ref.spins[slot]) and E[j] == ref.E[slot], (c, slot)

@@ -504,3 +504,45 @@ def test_counter_wiring_brute_force():
     got = {run.spins[0].tobytes(), run.spins[1].tobytes()}
     want = {m[0].astype(np.int8).tobytes(), m[1].astype(np.int8).tobytes()}
     assert got == want
+
+
+# ---------------------------------------------------------------------------
+# independent chains (M = 0): the bank-generation runs of Supp. Table S3
+
+
+def test_independent_chains_equal_a_run_without_cycle_ends():
+    """With M = 0 no cycle ever ends: every slot is a plain Metropolis chain.
+    That is the same chain as a ladder whose first cycle end lies beyond the
+    run (M larger than the sweeps run), slot for slot."""
+    g = inputs.ea_lattice(4, 7)
+    betas = inputs.geometric_ladder(8)
+    a = oracle.Run(g, betas, seed=77, M=0)
+    b = oracle.Run(g, betas, seed=77, M=1000)
+    a.run(300)
+    b.run(300)
+    assert np.array_equal(a.spins, b.spins) and np.array_equal(a.E, b.E)
+    assert a.swap_att.sum() == 0 and b.swap_att.sum() == 0
+    for r in range(8):
+        assert a.E[r] == a.energy(a.spins[r])
+
+
+def test_independent_chains_do_not_see_other_slots():
+    """A slot's chain depends only on its own beta (equal betas allowed):
+    changing every other slot's beta leaves it bit-identical."""
+    g = inputs.ea_lattice(4, 8)
+    a = oracle.Run(g, [1.0, 1.0, 1.0], seed=5, M=0)
+    b = oracle.Run(g, [0.3, 1.0, 2.5], seed=5, M=0)
+    a.run(200)
+    b.run(200)
+    assert np.array_equal(a.spins[1], b.spins[1]) and a.E[1] == b.E[1]
+    assert not np.array_equal(a.spins[0], b.spins[0])
+
+
+def test_independent_chain_samples_boltzmann():
+    """One independent chain at beta = 0.7 on a single spin in a field samples
+    P(+1) = e^{beta h} / (2 cosh beta h), as with swaps switched off."""
+    g = inputs.graph(1, np.array([0, 0]), np.zeros(0), np.zeros(0), h=np.array([1]))
+    run, H = _state_series(g, [0.7, 0.7], "metropolis", 200_000, seed=9, M=0)
+    for r in range(2):
+        frac = H[:, r, 1] / H[:, r, :].sum(axis=1)
+        assert abs(_batch_z(frac, np.exp(0.7) / (2 * np.cosh(0.7)))) < 5
