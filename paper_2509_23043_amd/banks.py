@@ -18,9 +18,9 @@ from . import binding
 
 
 def _batches(ctxs, make_batch):
-    """Yield batches over consecutive groups of ctxs that fit one launch: the
-    runtime refuses a batch whose workgroups cannot all be resident, and the
-    group is then halved."""
+    """Yield batches over consecutive groups of ctxs. Independent chains never
+    wait for each other, so the runtime queues their workgroups and one batch
+    normally takes them all; a refused batch (device memory) is halved."""
     i, k = 0, len(ctxs)
     while i < len(ctxs):
         k = min(k, len(ctxs) - i)
@@ -36,7 +36,7 @@ def _batches(ctxs, make_batch):
 
 
 def generate_bank(problem, beta, n_samples, burn_in, seed, chains_per_context=1024, replicas_per_wg=0,
-                  kernel="auto", chunk_sweeps=2000, timing=None):
+                  replicas_per_thread=0, kernel="auto", chunk_sweeps=2000, timing=None):
     """n_samples configurations, each the state of its own independent chain
     at ``beta`` after ``burn_in`` sweeps from a random start.
 
@@ -55,7 +55,8 @@ def generate_bank(problem, beta, n_samples, burn_in, seed, chains_per_context=10
     kern_ms = 0.0
     t0 = time.perf_counter()
     try:
-        make = lambda group: binding.Batch(group, replicas_per_wg=replicas_per_wg, chunk_sweeps=chunk_sweeps,
+        make = lambda group: binding.Batch(group, replicas_per_wg=replicas_per_wg,
+                                           replicas_per_thread=replicas_per_thread, chunk_sweeps=chunk_sweeps,
                                            kernel=kernel)
         for group, bt in _batches(ctxs, make):
             bt.kernel_time()

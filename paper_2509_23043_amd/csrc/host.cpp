@@ -942,8 +942,11 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         HIPCHK(chunk_occupancy(g->kind, g->L, g->rpt, P.block, P.lds, &P.per_cu));
     if (P.per_cu < 1) return fail(PT_EUNSUPPORTED, "kernel cannot run with block %d, LDS %zu", P.block, P.lds);
     // the cross-workgroup waits need every workgroup of the launch resident
-    // (counted with the padding blocks, so that every XCD's share fits its CUs)
-    if ((long long)P.per_cu * b->cus < (long long)P.grid)
+    // (counted with the padding blocks, so that every XCD's share fits its CUs);
+    // independent chains never wait, so their workgroups may queue
+    bool waits = false;
+    for (pt_ctx *c : g->ctxs) waits = waits || c->opts.sweeps_per_cycle != 0;
+    if (waits && (long long)P.per_cu * b->cus < (long long)P.grid)
         return fail(PT_EUNSUPPORTED, "%d workgroups exceed the %d that can be co-resident; use fewer contexts per batch",
                     P.grid, P.per_cu * b->cus);
     return PT_OK;
