@@ -17,6 +17,7 @@ baseline on this host.
 import argparse
 import hashlib
 import json
+import math
 import multiprocessing as mp
 import os
 import sys
@@ -48,10 +49,16 @@ def parse():
     ap.add_argument("--L", type=int, default=8)
     ap.add_argument("--R", type=int, default=32)
     ap.add_argument("--bank", type=int, default=256)
-    ap.add_argument("--workload", default="pt", choices=("pt", "bankgen-sg", "bankgen-fact"),
+    ap.add_argument("--workload", default="pt", choices=("pt", "bankgen-sg", "bankgen-fact", "tts"),
                     help="pt: the batched PT benchmark (default); bankgen-*: the long-run MCMC bank "
                          "generation of Supp. Table S3 (3D spin glass L=10, or 16-bit factorization)")
     ap.add_argument("--bank-samples", type=int, default=100_000, help="bankgen: chains (samples) per bank")
+    ap.add_argument("--tts-bits", default="16,18,20", help="tts: product bit lengths (even)")
+    ap.add_argument("--tts-instances", type=int, default=8, help="tts: semiprimes per size")
+    ap.add_argument("--tts-runs", type=int, default=100, help="tts: independent runs per instance and method")
+    ap.add_argument("--tts-tmax", type=int, default=20_000, help="tts: longest run length, sweeps")
+    ap.add_argument("--tts-bank", type=int, default=1024, help="tts: MCMC bank samples per proposal slot")
+    ap.add_argument("--tts-bank-burn-in", type=int, default=10_000, help="tts: burn-in of each bank sample")
     ap.add_argument("--bank-burn-in", type=int, default=0, help="bankgen: burn-in sweeps (0: the paper's)")
     ap.add_argument("--sweeps-per-swap", type=int, default=1,
                     help="M, sweeps per swap stage (the workload's value is 1; must divide 100)")
@@ -382,12 +389,79 @@ def bankgen(args, log):
     print(json.dumps(out), flush=True)
 
 
+def tts_study(args, log):
+    """Reduced TTS scaling study on factorization (Supp. TTS methodology):
+    PT vs TAPT with long-run MCMC proposal banks on the 13 hottest of 18
+    slots, proposals every sweep; median TTS per size with bootstrap CIs and
+    the fitted exponent k of TTS(n) = A exp(k n)."""
+    import torch
+    from paper_2509_23043_amd import banks, binding, inputs, tts
+    torch.cuda.set_device(0)
+    binding.lib()
+    R, NPROP = 18, 13
+    betas = inputs.geometric_ladder(R)
+    grid = [t for t in (250, 500, 1000, 2000, 5000, 10_000, 20_000, 50_000, 100_000) if t <= args.tts_tmax]
+    sizes = [int(b) for b in args.tts_bits.split(",")]
+    res = {"pt": {}, "tapt": {}}
+    t0 = time.perf_counter()
+    for n_bits in sizes:
+        m = n_bits // 2
+        egnd = -3 * m * m - 4 * m * (m - 1)
+        per = {"pt": [], "tapt": []}
+        succ = {"pt": [], "tapt": []}
+        for i, (C, p, q) in enumerate(inputs.semiprimes(m, args.tts_instances, seed=9100 + m)):
+            g = inputs.multiplier(m, C)
+            bank = {r: banks.generate_bank(g, betas[r], args.tts_bank, args.tts_bank_burn_in,
+                                           seed=500_000 + 1000 * i + 37 * r)[0] for r in range(NPROP)}
+            for method, bk in (("pt", None), ("tapt", bank)):
+                hits, dt = tts.run_instance(g, betas, args.tts_runs, args.tts_tmax, seed=10_000 * i + 7,
+                                            target=egnd, banks=bk)
+                star, t_a = tts.tts_star(hits, grid)
+                per[method].append(star * dt)
+                succ[method].append(tts.success_probability(hits, args.tts_tmax))
+        for method in ("pt", "tapt"):
+            v = np.array(per[method])
+            lo, hi = tts.bootstrap_median_ci(v, seed=n_bits)
+            med = float(np.median(v))
+            res[method][n_bits] = dict(median_tts_s=med, ci95=[lo, hi],
+                                       mean_success_at_tmax=round(float(np.mean(succ[method])), 3),
+                                       solved_instances=int(np.sum(np.isfinite(v))))
+            log(f"tts {n_bits}-bit {method}: median {med:.3g} s [{lo:.3g}, {hi:.3g}], "
+                f"success at t_max {np.mean(succ[method]):.2f}")
+    fits = {}
+    for method in ("pt", "tapt"):
+        ns = [n for n in sizes if math.isfinite(res[method][n]["median_tts_s"])]
+        fits[method] = None
+        if len(ns) >= 3:                  # two points fit any exponent exactly
+            A, k = tts.fit_exponential(ns, [res[method][n]["median_tts_s"] for n in ns])
+            fits[method] = dict(A=A, k=round(k, 4), sizes=ns)
+    k_tapt = fits["tapt"]["k"] if fits["tapt"] else None
+    fin = lambda x: None if isinstance(x, float) and not math.isfinite(x) else x
+    clean = lambda d: {str(k): {kk: ([fin(x) for x in vv] if isinstance(vv, list) else fin(vv))
+                                for kk, vv in v.items()} for k, v in d.items()}
+    out = dict(metric="fitted TTS scaling exponent k, TTS(n) = A exp(k n), factorization, TAPT with MCMC banks",
+               value=k_tapt, unit="1/bit", n_gpus=1, steps=1, warmup=0,
+               ms_per_step=round((time.perf_counter() - t0) * 1e3, 1), higher_is_better=False, scaling="weak",
+               vs_baseline=None, dtype="int8", data="synthetic",
+               config=dict(workload=f"semiprimes of two m-bit primes, product bits {sizes}, {args.tts_instances} "
+                                    f"instances per size, {args.tts_runs} runs each, t_a in {grid}, R={R} geometric "
+                                    f"0.2..3.0, proposals every sweep on the {NPROP} hottest slots from "
+                                    f"{args.tts_bank}-sample MCMC banks ({args.tts_bank_burn_in} burn-in sweeps)"),
+               fits=fits, pt=clean(res["pt"]), tapt=clean(res["tapt"]),
+               paper=dict(k_pt=0.846, k_tapt=0.564, sizes=[16, 18, 20, 22, 24], instances=440, runs=400,
+                          note="Supp. TTS scaling; adaptive ladders and 10^5-sample banks; context only"))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); instances would shard "
               f"across GPUs with no communication between them", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "tts":
+        tts_study(args, lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True))
+        return
     if args.workload != "pt":
         bankgen(args, lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True))
         return

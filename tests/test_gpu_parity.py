@@ -385,3 +385,27 @@ def test_generate_bank_matches_independent_oracle_chains():
         for slot in (0, R // 2, R - 1):
             j = 1024 * c + slot
             assert np.array_equal(cfg[j], ref.spins[slot]) and E[j] == ref.E[slot], (c, slot)
+
+
+def test_tts_runs_match_oracle_first_hits():
+    """tts.run_instance: every run's first hit (the sweep its ladder first
+    reaches the multiplier's ground energy) equals the oracle's, for PT and
+    for TAPT with proposal banks every sweep."""
+    announce("tts.run_instance: m=3 multiplier, 6 runs x 400 sweeps, PT and TAPT")
+    import oracle
+    from paper_2509_23043_amd import tts
+    m = 3
+    g = inputs.multiplier(m, 5 * 7)
+    egnd = -3 * m * m - 4 * m * (m - 1)
+    betas = inputs.geometric_ladder(6)
+    bank = {r: inputs.random_bank(g["n"], 16, seed=50 + r, clamp=g["clamp"]) for r in range(4)}
+    for banks in (None, bank):
+        hits, dt = tts.run_instance(g, betas, 6, 400, seed=700, target=egnd, banks=banks)
+        assert dt > 0
+        for k in range(6):
+            kw = dict(M=1, target=egnd)
+            if banks:
+                kw.update(prop_start=1, prop_period=1)
+            ref = oracle.Run(g, betas, seed=700 + k, banks=banks, **kw)
+            ref.run(400)
+            assert hits[k] == ref.first_hit, (k, hits[k], ref.first_hit)
