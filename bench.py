@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--tts-tmax", type=int, default=20_000, help="tts: longest run length, sweeps")
     ap.add_argument("--tts-bank", type=int, default=1024, help="tts: MCMC bank samples per proposal slot")
     ap.add_argument("--tts-bank-burn-in", type=int, default=10_000, help="tts: burn-in of each bank sample")
+    ap.add_argument("--tts-ladder", default="adaptive", choices=("adaptive", "geometric"),
+                    help="tts: adaptive (uniform swap acceptance, fitted per size on the first instance) "
+                         "or geometric 0.2..3.0")
     ap.add_argument("--bank-burn-in", type=int, default=0, help="bankgen: burn-in sweeps (0: the paper's)")
     ap.add_argument("--sweeps-per-swap", type=int, default=1,
                     help="M, sweeps per swap stage (the workload's value is 1; must divide 100)")
@@ -395,21 +398,31 @@ def tts_study(args, log):
     slots, proposals every sweep; median TTS per size with bootstrap CIs and
     the fitted exponent k of TTS(n) = A exp(k n)."""
     import torch
-    from paper_2509_23043_amd import banks, binding, inputs, tts
+    from paper_2509_23043_amd import banks, binding, inputs, ladder, tts
     torch.cuda.set_device(0)
     binding.lib()
     R, NPROP = 18, 13
-    betas = inputs.geometric_ladder(R)
+    betas0 = inputs.geometric_ladder(R)
     grid = [t for t in (250, 500, 1000, 2000, 5000, 10_000, 20_000, 50_000, 100_000) if t <= args.tts_tmax]
     sizes = [int(b) for b in args.tts_bits.split(",")]
     res = {"pt": {}, "tapt": {}}
+    ladders = {}
     t0 = time.perf_counter()
     for n_bits in sizes:
         m = n_bits // 2
         egnd = -3 * m * m - 4 * m * (m - 1)
+        insts = inputs.semiprimes(m, args.tts_instances, seed=9100 + m)
+        betas = betas0
+        if args.tts_ladder == "adaptive":
+            # one ladder per size, fitted on the first instance and fixed for every run
+            betas, hist = ladder.adapt(inputs.multiplier(m, insts[0][0]), betas0, rounds=8, sweeps=4000,
+                                       runs=4, seed=m)
+            log(f"tts {n_bits}-bit ladder: swap acceptance spread {hist[0][1].std():.3f} -> "
+                f"{hist[-1][1].std():.3f} (mean {hist[-1][1].mean():.3f})")
+            ladders[n_bits] = [round(float(x), 5) for x in betas]
         per = {"pt": [], "tapt": []}
         succ = {"pt": [], "tapt": []}
-        for i, (C, p, q) in enumerate(inputs.semiprimes(m, args.tts_instances, seed=9100 + m)):
+        for i, (C, p, q) in enumerate(insts):
             g = inputs.multiplier(m, C)
             bank = {r: banks.generate_bank(g, betas[r], args.tts_bank, args.tts_bank_burn_in,
                                            seed=500_000 + 1000 * i + 37 * r)[0] for r in range(NPROP)}
@@ -444,10 +457,11 @@ def tts_study(args, log):
                ms_per_step=round((time.perf_counter() - t0) * 1e3, 1), higher_is_better=False, scaling="weak",
                vs_baseline=None, dtype="int8", data="synthetic",
                config=dict(workload=f"semiprimes of two m-bit primes, product bits {sizes}, {args.tts_instances} "
-                                    f"instances per size, {args.tts_runs} runs each, t_a in {grid}, R={R} geometric "
-                                    f"0.2..3.0, proposals every sweep on the {NPROP} hottest slots from "
+                                    f"instances per size, {args.tts_runs} runs each, t_a in {grid}, R={R} "
+                                    f"{args.tts_ladder} ladder on 0.2..3.0, proposals every sweep on the {NPROP} "
+                                    f"hottest slots from "
                                     f"{args.tts_bank}-sample MCMC banks ({args.tts_bank_burn_in} burn-in sweeps)"),
-               fits=fits, pt=clean(res["pt"]), tapt=clean(res["tapt"]),
+               fits=fits, pt=clean(res["pt"]), tapt=clean(res["tapt"]), ladders=ladders,
                paper=dict(k_pt=0.846, k_tapt=0.564, sizes=[16, 18, 20, 22, 24], instances=440, runs=400,
                           note="Supp. TTS scaling; adaptive ladders and 10^5-sample banks; context only"))
     print(json.dumps(out), flush=True)

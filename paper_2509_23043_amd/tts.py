@@ -73,7 +73,9 @@ def bootstrap_median_ci(values, n_boot=2000, alpha=0.05, seed=0):
     v = np.asarray(values, np.float64)
     rng = np.random.Generator(np.random.PCG64(seed))
     meds = np.median(v[rng.integers(0, len(v), size=(n_boot, len(v)))], axis=1)
-    return float(np.quantile(meds, alpha / 2)), float(np.quantile(meds, 1 - alpha / 2))
+    # order statistics without interpolation, so that infinite medians stay infinite
+    return (float(np.quantile(meds, alpha / 2, method="lower")),
+            float(np.quantile(meds, 1 - alpha / 2, method="higher")))
 
 
 def run_instance(problem, betas, runs, t_max, seed, target, banks=None, prop_period=1, chunk_sweeps=2000,

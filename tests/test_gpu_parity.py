@@ -409,3 +409,27 @@ def test_tts_runs_match_oracle_first_hits():
             ref = oracle.Run(g, betas, seed=700 + k, banks=banks, **kw)
             ref.run(400)
             assert hits[k] == ref.first_hit, (k, hits[k], ref.first_hit)
+
+
+def test_ladder_acceptance_matches_oracle_and_adapts():
+    """ladder.measure_acceptance sums the library's swap counters over its
+    runs, equal to the oracle's; ladder.adapt on the library evens out the
+    acceptance of a linear ladder."""
+    announce("adaptive ladder: L=4 counters vs oracle, then 4 rounds on L=6")
+    import oracle
+    from paper_2509_23043_amd import ladder
+    g = inputs.ea_lattice(4, 9)
+    b = np.linspace(0.3, 2.5, 8)
+    A = ladder.measure_acceptance(g, b, 300, runs=3, seed=40)
+    att = np.zeros(7)
+    acc = np.zeros(7)
+    for k in range(3):
+        ref = oracle.Run(g, b, seed=40 + k, M=1)
+        ref.run(300)
+        att += ref.swap_att[:7]
+        acc += ref.swap_acc[:7]
+    assert np.array_equal(A, acc / np.maximum(att, 1))
+    g6 = inputs.ea_lattice(6, 10)
+    b0 = np.linspace(0.2, 3.0, 12)
+    b1, hist = ladder.adapt(g6, b0, rounds=4, sweeps=2000, runs=4, seed=7)
+    assert hist[-1][1].std() < 0.7 * hist[0][1].std(), (hist[0][1], hist[-1][1])

@@ -49,3 +49,11 @@ def test_bootstrap_interval_covers_the_median():
         lo, hi = tts.bootstrap_median_ci(x, n_boot=400, seed=rep)
         cover += lo <= math.log(2) <= hi
     assert cover >= 51                               # nominal 95%: 57 of 60
+
+
+def test_bootstrap_interval_with_unsolved_instances():
+    """Instances that never succeed have infinite TTS; the interval's ends are
+    order statistics (infinite, not NaN) when enough of them are."""
+    x = np.array([1.0, 2.0, 3.0, np.inf, np.inf, np.inf, np.inf])
+    lo, hi = tts.bootstrap_median_ci(x, n_boot=500, seed=1)
+    assert not np.isnan(lo) and hi == np.inf
