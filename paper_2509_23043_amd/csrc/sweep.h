@@ -398,13 +398,18 @@ struct CsrSweep {
         __syncthreads();
         const int D = I.D;
         const int ncol = I.ncolors;
+        // Work item idx = s * G + k (site s of the colour, storage k): the G
+        // lanes of a site read the same graph words (LDS broadcasts). When G
+        // divides the block, a thread keeps one storage for the whole sweep
+        // and sums its energy change and flips in registers.
+        const bool fixed_k = bs % G == 0;
+        const int dq = bs / G, dr = bs - dq * G;
+        int dE_acc = 0;
+        unsigned nf_acc = 0;
         for (int c = 0; c < ncol; ++c) {
             const int off = gr.coff[c], cnt = gr.coff[c + 1] - off;
-            if (cnt <= 0) continue;
-            // (storage k, site index s) of idx = k * cnt + s, stepped without division
-            const int dq = bs / cnt, dr = bs - dq * cnt;
-            int k = tid / cnt, s = tid - k * cnt;
-            for (int idx = tid; idx < G * cnt; idx += bs) {
+            int s = tid / G, k = tid - (tid / G) * G;
+            while (s < cnt) {
                 const int i = gr.cs[off + s];
                 int8_t *m_k = sp + k * SB;
                 int f = gr.h[i];
@@ -440,16 +445,27 @@ struct CsrSweep {
                 }
                 if (acc) {
                     m_k[i] = (int8_t)(-m);
-                    atomicAdd(&Elds[k], 2 * d);
-                    atomicAdd(&flips_lds[sl], 1u);
+                    if (fixed_k) {
+                        dE_acc += 2 * d;
+                        nf_acc += 1;
+                    } else {
+                        atomicAdd(&Elds[k], 2 * d);
+                        atomicAdd(&flips_lds[sl], 1u);
+                    }
                 }
-                s += dr;
-                k += dq;
-                if (s >= cnt) {
-                    s -= cnt;
-                    ++k;
+                s += dq;
+                k += dr;
+                if (k >= G) {
+                    k -= G;
+                    ++s;
                 }
             }
+            __syncthreads();
+        }
+        if (fixed_k) {
+            const int k = tid - (tid / G) * G;
+            if (dE_acc) atomicAdd(&Elds[k], dE_acc);
+            if (nf_acc) atomicAdd(&flips_lds[slot_of[k]], nf_acc);
             __syncthreads();
         }
     }
