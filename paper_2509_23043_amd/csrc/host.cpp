@@ -830,10 +830,15 @@ struct pt_batch {
     }
 };
 
-// Choose (slots per workgroup, slots per thread) for a context. In a mixed
-// launch every size has 1, 2 or 4 slots per thread (its block limit is the
-// same); large lattices take 4 so that a batch of many sizes stays co-resident.
-static void choose_tiling(const pt_ctx *c, const pt_batch_opts &o, bool mixed, int &G, int &rpt)
+// Choose (slots per workgroup, slots per thread) for a context. What the
+// caller leaves free comes from one of TILING_LEVELS automatic tilings,
+// finest (most workgroups, fewest sites per thread: the shortest sweep) at
+// level 0, coarsest at the last level; a launch takes the finest level whose
+// workgroups can all be co-resident. At the last level a mixed launch gives
+// large lattices 4 slots per thread, so that a batch of many sizes fits.
+static constexpr int TILING_LEVELS = 3;
+
+static void choose_tiling(const pt_ctx *c, const pt_batch_opts &o, bool mixed, int level, int &G, int &rpt)
 {
     const int R = c->R;
     rpt = o.replicas_per_thread > 0 ? o.replicas_per_thread : 0;
@@ -841,15 +846,15 @@ static void choose_tiling(const pt_ctx *c, const pt_batch_opts &o, bool mixed, i
     if (rpt > 4) rpt = 4;
     G = o.replicas_per_wg > 0 ? std::min(std::min(o.replicas_per_wg, R), 64) : 0;
     if (c->kind == KIND_CSR) {
+        static const int csr_g[TILING_LEVELS] = {2, 4, 32};
         rpt = 1;
-        if (!G) G = std::min(R, 32);
+        if (!G) G = std::min(R, csr_g[level]);
         return;
     }
-    if (mixed && !rpt && c->n >= 1000) rpt = 4;
+    if (!rpt) rpt = level == 0 ? 1 : (level == TILING_LEVELS - 1 && mixed && c->n >= 1000) ? 4 : 2;
     // the cycle-end stages keep one slot per lane of a wavefront: G <= 64
     const int NC = c->n / 8;
     const int maxt = mixed ? mixed_max_threads() : lattice_max_threads();
-    if (!rpt) rpt = 2;
     if (!G) {
         // whole ladder in one workgroup when it fits the block limit, else split
         int maxg = (maxt / NC) * rpt;
@@ -1004,12 +1009,12 @@ static void clear_groups(pt_batch *b)
 // The launch group for a set of contexts (host fields only). Contexts that
 // share one sweeper instantiation run in the specialised kernel; a set that
 // needs several sweepers runs as a single launch of the mixed kernel.
-static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx *> &ctxs)
+static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx *> &ctxs, int level)
 {
     std::map<std::tuple<int, int, int>, int> keys;
     for (pt_ctx *c : ctxs) {
         int G, rpt;
-        choose_tiling(c, o, false, G, rpt);
+        choose_tiling(c, o, false, level, G, rpt);
         keys[std::make_tuple(c->kind, c->kind == KIND_LATTICE ? c->L : 0, rpt)] += 1;
     }
     LaunchGroup *g = new LaunchGroup();
@@ -1036,7 +1041,7 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
             G = o.replicas_per_wg > 0 ? o.replicas_per_wg : wave_max_storages();
             G = std::min(std::min(G, c->R), wave_max_storages());
         } else {
-            choose_tiling(c, o, g->mixed, G, rpt);
+            choose_tiling(c, o, g->mixed, level, G, rpt);
         }
         g->rpt = rpt;
         g->ctxs.push_back(c);
@@ -1044,6 +1049,26 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
         g->rpts.push_back(rpt);
     }
     return g;
+}
+
+// The launch group of a set of contexts at the finest automatic tiling
+// level whose workgroups fit (the caller's fixed tiling choices hold at
+// every level). On failure *out is null and the last level's error stands.
+static int pick_group(const pt_batch *b, const std::vector<pt_ctx *> &ctxs, LaunchGroup **out)
+{
+    *out = nullptr;
+    int rc = PT_OK;
+    for (int level = 0; level < TILING_LEVELS; ++level) {
+        LaunchGroup *g = make_group(b->opts, ctxs, level);
+        GroupPlan P;
+        rc = plan_group(b, g, P);
+        if (rc == PT_OK) {
+            *out = g;
+            return PT_OK;
+        }
+        delete g;
+    }
+    return rc;
 }
 
 // (Re)build the launch group of a batch for the contexts ctxs[0..k).
@@ -1057,7 +1082,9 @@ static int batch_set_contexts(pt_batch *b, pt_ctx *const *ctxs, int32_t k)
             if (ctxs[j] == ctxs[i]) return fail(PT_EINVAL, "context %d appears twice", i);
         b->ctxs.push_back(ctxs[i]);
     }
-    LaunchGroup *g = make_group(b->opts, b->ctxs);
+    LaunchGroup *g = nullptr;
+    int rc = pick_group(b, b->ctxs, &g);
+    if (rc) return rc;
     b->groups.push_back(g);
     return build_group(b, g);
 }
@@ -1065,9 +1092,8 @@ static int batch_set_contexts(pt_batch *b, pt_ctx *const *ctxs, int32_t k)
 // PT_OK if the contexts could run in one launch of this batch (no allocation).
 static int batch_fits(const pt_batch *b, const std::vector<pt_ctx *> &ctxs)
 {
-    LaunchGroup *g = make_group(b->opts, ctxs);
-    GroupPlan P;
-    int rc = plan_group(b, g, P);
+    LaunchGroup *g = nullptr;
+    int rc = pick_group(b, ctxs, &g);
     delete g;
     return rc;
 }

@@ -764,6 +764,42 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
             }
             __syncthreads();
         }
+        // the boundary slots in a cross pair this cycle (alternating parity)
+        const int first = (cyc & 1) ? 0 : 1;
+        const bool down = cyc_end && has_down && (((s0 - 1 - first) & 1) == 0);
+        const bool up = cyc_end && has_up && (((s0 + G - 1 - first) & 1) == 0);
+        const int buf = (cyc >> 1) & 1;
+        const unsigned long long tag = (unsigned long long)cyc << 32;
+        if (down || up) {
+            // publish the boundary states, every wavefront a share of the 64-byte
+            // chunks. A boundary slot in a cross pair is in no local pair this
+            // cycle. Bit j of the words is the sign of storage byte j (both sides
+            // of a pair run the same sweeper, so they share the storage layout).
+            // Every 64-bit word carries 32 spin bits (or the energy) and the cycle
+            // number, written with relaxed device-scope atomics; the reader takes a
+            // word only when its tag is this cycle, so no fence or flag is needed.
+            // Buffers alternate with the cycle parity: a partner is at most one
+            // exchange ahead.
+            const int nch = (n + 63) >> 6, wv = tid >> 6, nwv = bs >> 6;
+            for (int side = 0; side < 2; ++side) {
+                if (!(side == 0 ? down : up)) continue;
+                const int st = c.stor_of[side == 0 ? 0 : G - 1];
+                const int8_t *stor = c.sp + st * SB;
+                unsigned long long *out = it.xbuf + ((size_t)(it.w * 2 + side) * 2 + buf) * it.xwords;
+                for (int ch = wv; ch < nch; ch += nwv) {
+                    const int j = 64 * ch + lane;
+                    const int8_t v = stor[j < n ? j : n - 1];
+                    const unsigned long long m = __ballot(j < n && v > 0);
+                    const int wd = 2 * ch + lane;
+                    if (lane < 2 && wd < nw)
+                        __hip_atomic_store(out + wd, tag | (lane ? (m >> 32) : (m & 0xFFFFFFFFull)),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                if (tid == 0)
+                    __hip_atomic_store(out + nw, tag | (uint32_t)c.Elds[st], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         if (tid >= 64 && tid < 128 && cyc_end) {
             // wave 1 draws the next cycle's swap uniforms while wave 0 works
             const uint32_t nx = cyc + 1;
@@ -775,45 +811,8 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
             if (cyc_end) {
                 const uint32_t u_pair = c.usw[(cyc & 1) * 65 + lane];
                 const uint32_t u_dn = c.usw[(cyc & 1) * 65 + 64];
-                // ---- replica exchange (Eq. 1), alternating parity ----
-                const int first = (cyc & 1) ? 0 : 1;
-                const bool down = has_down && (((s0 - 1 - first) & 1) == 0);
-                const bool up = has_up && (((s0 + G - 1 - first) & 1) == 0);
-                const int buf = (cyc >> 1) & 1;
-                const unsigned long long tag = (unsigned long long)cyc << 32;
-                // (1) publish the boundary states first. A boundary slot in a cross
-                // pair is in no local pair this cycle. Every 64-bit word carries 32
-                // spin bits (or the energy) and the cycle number, written with relaxed
-                // device-scope atomics; the reader accepts a word only when its tag is
-                // this cycle, so no fence or flag is needed. Buffers alternate with the
-                // cycle parity: a partner is at most one exchange ahead.
-                for (int side = 0; side < 2; ++side) {
-                    if (!(side == 0 ? down : up)) continue;
-                    const int st = __shfl(my_st, side == 0 ? 0 : G - 1);
-                    const int eb = __shfl(e, side == 0 ? 0 : G - 1);
-                    const int8_t *stor = c.sp + st * SB;
-                    unsigned long long *out = it.xbuf + ((size_t)(it.w * 2 + side) * 2 + buf) * it.xwords;
-                    const int nch = (n + 63) >> 6;
-                    for (int k0 = 0; k0 < nch; k0 += 8) {
-                        int8_t v[8];
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) {   // unconditional reads: one LDS round trip
-                            const int i = 64 * (k0 + j) + lane;
-                            v[j] = stor[SweepCall<Sw>::lidx(sw, i < n ? i : n - 1)];
-                        }
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) {
-                            const unsigned long long m = __ballot(64 * (k0 + j) + lane < n && v[j] > 0);
-                            const int wd = 2 * (k0 + j) + lane;
-                            if (lane < 2 && wd < nw)
-                                __hip_atomic_store(out + wd, tag | (lane ? (m >> 32) : (m & 0xFFFFFFFFull)),
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        }
-                    }
-                    if (lane == 0)
-                        __hip_atomic_store(out + nw, tag | (uint32_t)eb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-                // (2) pairs inside the workgroup: exchange labels (lane l decides (l, l+1))
+                // ---- replica exchange (Eq. 1): the boundary states are published ----
+                // pairs inside the workgroup: exchange labels (lane l decides (l, l+1))
                 const int e_nx = __shfl_down(e, 1), st_nx = __shfl_down(my_st, 1);
                 const bool act = lane + 1 < G && (((s0 + lane - first) & 1) == 0);
                 bool acc = false;
@@ -837,8 +836,9 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                     c.stor_of[lane] = my_st;
                     c.slot_of[my_st] = lane;
                 }
-                // (3) pairs across a workgroup boundary: the partner's words, the
-                // decision (both sides draw the same uniform), and a state copy
+                // pairs across a workgroup boundary: the partner's words and the
+                // decision (both sides draw the same uniform); the block copies the
+                // accepted states after the barrier
                 if (down || up) {
                     int timeout = 0;
                     for (int side = 0; side < 2 && !timeout; ++side) {
@@ -899,24 +899,11 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                                 my_acc += sacc ? 1u : 0u;
                             }
                             if (sacc) {
-                                int8_t *stor = c.sp + st * SB;
-                                for (int i0 = 0; i0 < n; i0 += 512) {
-                                    uint32_t wd[8];
-#pragma unroll
-                                    for (int j = 0; j < 8; ++j) {   // all stage reads first
-                                        const int i = i0 + 64 * j + lane;
-                                        wd[j] = stage[(i < n ? i : n - 1) >> 5];
-                                    }
-#pragma unroll
-                                    for (int j = 0; j < 8; ++j) {
-                                        const int i = i0 + 64 * j + lane;
-                                        if (i < n) stor[SweepCall<Sw>::lidx(sw, i)] = ((wd[j] >> (i & 31)) & 1u) ? 1 : -1;
-                                    }
-                                }
                                 if (lane == bl) {
                                     e = pE;
                                     c.Elds[st] = pE;
                                 }
+                                if (lane == 0) c.misc[4 + side] = st + 1;
                             }
                         }
                     }
@@ -937,11 +924,35 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                 bestT = (int64_t)t;
                 bestSlot = s0 + lm;
                 const int st = __shfl(my_st, lm);
-                for (int i = lane; i < n; i += 64) it.best_spins[i] = c.sp[st * SB + SweepCall<Sw>::lidx(sw, i)];
+                if (lane == 0) c.misc[2] = st + 1;   // the whole block copies it below
             }
         }
         __syncthreads();
         if (cyc_end && (has_down || has_up)) failed = c.misc[0] != 0;
+        if (down || up) {   // accepted cross swaps: the partner's state into the storage
+            const int x0 = c.misc[4], x1 = c.misc[5];
+            if (x0 | x1) {
+                for (int side = 0; side < 2; ++side) {
+                    const int xs = side == 0 ? x0 : x1;
+                    if (!xs) continue;
+                    const uint32_t *stage = c.xstage + side * (nw + 1);
+                    int8_t *stor = c.sp + (xs - 1) * SB;
+                    for (int j = tid; j < n; j += bs) stor[j] = ((stage[j >> 5] >> (j & 31)) & 1u) ? 1 : -1;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    c.misc[4] = 0;
+                    c.misc[5] = 0;
+                }
+            }
+        }
+        const int bst = c.misc[2];
+        if (bst) {   // snapshot of the new best state, before the next sweep changes it
+            const int8_t *src = c.sp + (bst - 1) * SB;
+            for (int i = tid; i < n; i += bs) it.best_spins[i] = src[SweepCall<Sw>::lidx(sw, i)];
+            __syncthreads();
+            if (tid == 0) c.misc[2] = 0;
+        }
     }
     if (tid < 64 && lane < G) {
         c.satt[lane] = my_att;
