@@ -834,9 +834,9 @@ struct pt_batch {
 // caller leaves free comes from one of TILING_LEVELS automatic tilings,
 // finest (most workgroups, fewest sites per thread: the shortest sweep) at
 // level 0, coarsest at the last level; a launch takes the finest level whose
-// workgroups can all be co-resident. At the last level a mixed launch gives
-// large lattices 4 slots per thread, so that a batch of many sizes fits.
-static constexpr int TILING_LEVELS = 3;
+// workgroups can all be co-resident. At the last two levels a mixed launch
+// gives large lattices 4 slots per thread, so that a batch of many sizes fits.
+static constexpr int TILING_LEVELS = 5;
 
 static void choose_tiling(const pt_ctx *c, const pt_batch_opts &o, bool mixed, int level, int &G, int &rpt)
 {
@@ -846,12 +846,12 @@ static void choose_tiling(const pt_ctx *c, const pt_batch_opts &o, bool mixed, i
     if (rpt > 4) rpt = 4;
     G = o.replicas_per_wg > 0 ? std::min(std::min(o.replicas_per_wg, R), 64) : 0;
     if (c->kind == KIND_CSR) {
-        static const int csr_g[TILING_LEVELS] = {2, 4, 32};
+        static const int csr_g[TILING_LEVELS] = {2, 4, 8, 16, 32};
         rpt = 1;
         if (!G) G = std::min(R, csr_g[level]);
         return;
     }
-    if (!rpt) rpt = level == 0 ? 1 : (level == TILING_LEVELS - 1 && mixed && c->n >= 1000) ? 4 : 2;
+    if (!rpt) rpt = level < 2 ? 1 : (level >= TILING_LEVELS - 2 && mixed && c->n >= 1000) ? 4 : 2;
     // the cycle-end stages keep one slot per lane of a wavefront: G <= 64
     const int NC = c->n / 8;
     const int maxt = mixed ? mixed_max_threads() : lattice_max_threads();
@@ -1053,12 +1053,17 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
 
 // The launch group of a set of contexts at the finest automatic tiling
 // level whose workgroups fit (the caller's fixed tiling choices hold at
-// every level). On failure *out is null and the last level's error stands.
+// every level). Independent chains never wait for one another, so nothing
+// bounds their workgroup count and they take the coarsest level, which
+// fills the workgroups best. On failure *out is null and the last level's
+// error stands.
 static int pick_group(const pt_batch *b, const std::vector<pt_ctx *> &ctxs, LaunchGroup **out)
 {
     *out = nullptr;
     int rc = PT_OK;
-    for (int level = 0; level < TILING_LEVELS; ++level) {
+    bool waits = false;
+    for (pt_ctx *c : ctxs) waits = waits || c->opts.sweeps_per_cycle != 0;
+    for (int level = waits ? 0 : TILING_LEVELS - 1; level < TILING_LEVELS; ++level) {
         LaunchGroup *g = make_group(b->opts, ctxs, level);
         GroupPlan P;
         rc = plan_group(b, g, P);
