@@ -45,6 +45,8 @@ class _Problem(C.Structure):
         ("has_target", C.c_int32),
         ("target", C.c_int64),
         ("check_energy", C.c_int32),
+        ("ctx_T", C.c_uint32),
+        ("ctx_sweeps", C.c_int32),
     ]
 
 
@@ -94,6 +96,9 @@ def lib():
         L.orc_flip_table.restype = None
         L.orc_run_sampled.argtypes = [C.POINTER(_Problem), C.POINTER(_State), C.c_uint64, C.c_uint64,
                                       C.POINTER(C.c_uint64)]
+        L.orc_context_candidate.argtypes = [C.POINTER(_Problem), C.c_int32, C.c_uint32, C.POINTER(C.c_int8),
+                                            C.POINTER(C.c_int8), C.POINTER(C.c_int8), C.POINTER(C.c_uint8)]
+        L.orc_context_candidate.restype = None
         _lib = L
     return _lib
 
@@ -129,12 +134,15 @@ class Run:
 
     problem: dict from ``paper_2509_23043_amd.inputs`` (n, row_ptr, col, J, h,
     clamp, color). banks: optional {slot: int8 [B, n]} proposal banks; a slot
-    is proposal-enabled iff it has a bank.
+    is proposal-enabled iff it has a bank. ctx_fraction / ctx_sweeps: the
+    contextual proposals of the context ablation (each free site joins the
+    context with probability ctx_fraction; the rest is completed by
+    ctx_sweeps sweeps from the bank entry).
     """
 
     def __init__(self, problem, betas, seed, M=1, rule="metropolis", banks=None,
                  prop_start=0, prop_period=0, prop_stop=-1, target=None,
-                 check_energy=True):
+                 check_energy=True, ctx_fraction=0.0, ctx_sweeps=0):
         n = int(problem["n"])
         self.n = n
         self.R = R = len(betas)
@@ -181,6 +189,8 @@ class Run:
         P.has_target = 0 if target is None else 1
         P.target = 0 if target is None else int(target)
         P.check_energy = 1 if check_energy else 0
+        P.ctx_T = threshold(ctx_fraction) if ctx_fraction > 0 else 0
+        P.ctx_sweeps = int(ctx_sweeps)
         self.P = P
 
         self.spins = np.zeros((R, n), np.int8)
@@ -217,6 +227,18 @@ class Run:
         if rc != 0:
             raise RuntimeError("oracle sampled run failed")
         return hist
+
+    def context_candidate(self, r, cyc, start, current):
+        """The contextual proposal of slot r at cycle cyc built from the bank
+        entry ``start`` and the slot's ``current`` spins: (candidate, mask of
+        the context sites)."""
+        a = np.ascontiguousarray(start, np.int8)
+        b = np.ascontiguousarray(current, np.int8)
+        out = np.zeros(self.n, np.int8)
+        mask = np.zeros(self.n, np.uint8)
+        lib().orc_context_candidate(C.byref(self.P), int(r), C.c_uint32(int(cyc)), _p(a, C.c_int8),
+                                    _p(b, C.c_int8), _p(out, C.c_int8), _p(mask, C.c_uint8))
+        return out, mask
 
     def energy(self, spins):
         s = np.ascontiguousarray(spins, np.int8)

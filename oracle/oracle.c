@@ -27,6 +27,11 @@
  *     SWAP   (5): swap at cycle n of pair (r, r+1): word 0 of ctr (r, n, 0, 5).
  *     BANK   (6): start cursor of a B-entry bank on slot r:
  *                 word 0 of ctr (r, 0, 0, 6) mod B.
+ *     CONTEXT(7): contextual proposal at cycle n on slot r: site i is a context
+ *                 site iff word (i&3) of ctr (i>>2, n, r, 7) passes the
+ *                 fraction's threshold.
+ *     CTXSWEEP(8): attempt on site i in completion sweep j (1-based) of that
+ *                 proposal: u = word (i&3) of ctr (i>>2, n, r + 65536 j, 8).
  *   An event with probability p is accepted iff T(p) == 0xFFFFFFFF or u < T(p),
  *   T(p) = 0xFFFFFFFF for p >= 1, else min(floor(p * 2^32), 0xFFFFFFFF).
  */
@@ -41,6 +46,8 @@
 #define TAG_PROPOSE 4u
 #define TAG_SWAP 5u
 #define TAG_BANK 6u
+#define TAG_CONTEXT 7u
+#define TAG_CTXSWEEP 8u
 
 #define RULE_METROPOLIS 0
 #define RULE_GIBBS 1
@@ -144,6 +151,13 @@ typedef struct {
     int32_t has_target;
     int64_t target;
     int32_t check_energy;   /* 1: compare incremental and recomputed energies */
+    /* contextual proposals (Supp. context ablation): when ctx_T or ctx_sweeps
+     * is nonzero, a proposal starts from its bank entry, takes the slot's
+     * current spins on the context sites (probability T/2^32 each, every site
+     * when T = 0xFFFFFFFF) and completes the other free sites by ctx_sweeps
+     * MCMC sweeps at the slot's beta (1..65535, or 0 for none) */
+    uint32_t ctx_T;
+    int32_t ctx_sweeps;
 } orc_problem;
 
 typedef struct {
@@ -259,6 +273,36 @@ static void sweep_slot(const orc_problem *P, orc_state *S, int32_t r, uint32_t t
     }
 }
 
+/* Contextual proposal of slot r at cycle cyc (Supp. context ablation): a
+ * random subset of the spins is clamped to the slot's current values and the
+ * remaining spins are generated by MCMC under those clamps. The generation
+ * starts from the bank entry (a sample of the unconstrained long-run MCMC at
+ * beta_r) and runs ctx_sweeps sweeps at beta_r with the run's rule, color
+ * classes in increasing color and sites in increasing index, as in
+ * sweep_slot. ctx_mask[i] = 1 marks the context sites. */
+void orc_context_candidate(const orc_problem *P, int32_t r, uint32_t cyc, const int8_t *start,
+                           const int8_t *current, int8_t *out, uint8_t *ctx_mask)
+{
+    const int32_t n = P->n;
+    for (int32_t i = 0; i < n; ++i) {
+        uint32_t u = philox_word((uint32_t)i >> 2, cyc, (uint32_t)r, TAG_CONTEXT, P->seed, i & 3);
+        ctx_mask[i] = (!P->clamp[i] && accept(P->ctx_T, u)) ? 1 : 0;
+        out[i] = ctx_mask[i] ? current[i] : start[i];
+    }
+    for (int32_t j = 1; j <= P->ctx_sweeps; ++j) {
+        for (int32_t c = 0; c < P->ncolors; ++c) {
+            for (int32_t i = 0; i < n; ++i) {
+                if (P->color[i] != c || P->clamp[i] || ctx_mask[i]) continue;
+                int64_t dE = 2 * (int64_t)out[i] * local_field(P, out, i);
+                uint32_t T = orc_threshold(orc_flip_prob(P->rule, P->beta[r], dE));
+                uint32_t u = philox_word((uint32_t)i >> 2, cyc, (uint32_t)r + 65536u * (uint32_t)j, TAG_CTXSWEEP,
+                                         P->seed, i & 3);
+                if (accept(T, u)) out[i] = (int8_t)-out[i];
+            }
+        }
+    }
+}
+
 static int is_proposal_sweep(const orc_problem *P, uint64_t t)
 {
     if (P->prop_period <= 0 || !P->bank) return 0;
@@ -273,7 +317,15 @@ int orc_run(const orc_problem *P, orc_state *S, uint64_t n_sweeps)
 {
     int32_t n = P->n, R = P->R;
     int8_t *tmp = (int8_t *)malloc((size_t)n);
-    if (!tmp) return -1;
+    int8_t *cand = (int8_t *)malloc((size_t)n);
+    uint8_t *mask = (uint8_t *)malloc((size_t)n);
+    const int contextual = P->ctx_T != 0 || P->ctx_sweeps != 0;
+    if (!tmp || !cand || !mask) {
+        free(tmp);
+        free(cand);
+        free(mask);
+        return -1;
+    }
     for (uint64_t step = 0; step < n_sweeps; ++step) {
         uint64_t t = S->t + 1;
         /* local MCMC sweeps: every replica, one sweep each */
@@ -295,6 +347,10 @@ int orc_run(const orc_problem *P, orc_state *S, uint64_t n_sweeps)
                     int32_t k = S->cursor[r];
                     S->cursor[r] = (k + 1) % P->bank_n[r];
                     const int8_t *prop = P->bank[r] + (size_t)k * n;
+                    if (contextual) {
+                        orc_context_candidate(P, r, (uint32_t)cyc, prop, S->spins + (size_t)r * n, cand, mask);
+                        prop = cand;
+                    }
                     int64_t ET = orc_energy(P, prop);
                     int64_t d = ET - S->E[r];
                     double p = (d <= 0) ? 1.0 : exp(-(P->beta[r] * (double)d));
@@ -332,6 +388,8 @@ int orc_run(const orc_problem *P, orc_state *S, uint64_t n_sweeps)
         track_best(P, S);
     }
     free(tmp);
+    free(cand);
+    free(mask);
     return 0;
 }
 
