@@ -122,6 +122,23 @@ int pt_propose(pt_ctx *c, double beta, const int8_t *configs, int32_t n_configs)
 /* Same with configs in device memory (not validated entry by entry). */
 int pt_propose_device(pt_ctx *c, double beta, const int8_t *configs_dev, int32_t n_configs);
 
+/* Contextual proposals (Supp., ablation of proposal context, Fig. S4b):
+ * with fraction > 0 or sweeps > 0, the proposal of a slot at cycle n is
+ * built on the device rather than taken from the bank as is. It starts from
+ * the slot's bank entry; each free site joins the context with probability
+ * `fraction` (Philox tag 7, ctr (i>>2, n, r, 7), word i&3, against the
+ * threshold T(fraction)) and takes the slot's current value; `sweeps` colored
+ * sweeps at the slot's beta, with the context's rule, update the other free
+ * sites (Philox tag 8, ctr (i>>2, n, r + 65536 j, 8) for sweep j = 1..sweeps,
+ * word i&3 as the 32-bit uniform); its energy is recomputed and the Delta-E
+ * rule of Eq. 2 decides as for a bank entry, and the cursor advances as
+ * usual. fraction = 0 and sweeps = 0 restore plain bank proposals.
+ * fraction in [0, 1], sweeps in 0..65535, else PT_EINVAL. Contextual
+ * contexts run in batches and the server only: pt_sweep returns
+ * PT_EUNSUPPORTED for them, and a batch built before the mode changed
+ * returns PT_ESTATE (build it again). */
+int pt_set_context(pt_ctx *c, double fraction, int32_t sweeps);
+
 /* Plain path: run n_sweeps sweeps of Algorithm 1 on this context alone with
  * one launch sequence per cycle (sweep kernel, cycle-end kernel). */
 int pt_sweep(pt_ctx *c, uint64_t n_sweeps);

@@ -74,7 +74,7 @@ class _ServeStats(C.Structure):
                 ("mem_peak", C.c_uint64)]
 
 
-EXPORTS = ["pt_create", "pt_destroy", "pt_propose", "pt_propose_device", "pt_sweep", "pt_energies",
+EXPORTS = ["pt_create", "pt_destroy", "pt_propose", "pt_propose_device", "pt_set_context", "pt_sweep", "pt_energies",
            "pt_state", "pt_state_device", "pt_set_state", "pt_summary_get", "pt_counters",
            "pt_energy_device", "pt_set_stream", "pt_batch_create", "pt_batch_sweep", "pt_batch_destroy",
            "pt_batch_set_stream", "pt_batch_kernel_time", "pt_serve_start", "pt_serve_register",
@@ -101,6 +101,7 @@ def lib():
     L.pt_destroy.argtypes = [vp]
     L.pt_propose.argtypes = [vp, C.c_double, C.POINTER(C.c_int8), C.c_int32]
     L.pt_propose_device.argtypes = [vp, C.c_double, vp, C.c_int32]
+    L.pt_set_context.argtypes = [vp, C.c_double, C.c_int32]
     L.pt_sweep.argtypes = [vp, C.c_uint64]
     L.pt_energies.argtypes = [vp, C.POINTER(C.c_int32)]
     L.pt_state.argtypes = [vp, C.POINTER(C.c_int8), C.POINTER(C.c_uint64)]
@@ -212,6 +213,12 @@ class Context:
 
     def propose_device(self, slot, dev_ptr, count):
         _check(lib().pt_propose_device(self.h, float(self.betas[slot]), C.c_void_p(dev_ptr), int(count)))
+
+    def set_context(self, fraction, sweeps):
+        """Contextual proposals: a random ``fraction`` of each proposal's free
+        sites takes the slot's current values, the rest is completed by
+        ``sweeps`` sweeps from the bank entry (0, 0: plain bank proposals)."""
+        _check(lib().pt_set_context(self.h, float(fraction), int(sweeps)))
 
     def sweep(self, n):
         """Plain path: n sweeps of Algorithm 1, per-sweep launches."""

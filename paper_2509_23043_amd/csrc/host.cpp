@@ -31,9 +31,12 @@ namespace tapt {
 bool lattice_supported(int L);
 int lattice_max_threads();
 int lattice_threads(int L, int G, int rpt);
-size_t chunk_lds_bytes(int kind, int n, int G, int stride, int tsw_entries, int nnz, int nfree, int ncolors);
+size_t chunk_lds_bytes(int kind, int n, int G, int stride, int tsw_entries, int nnz, int nfree, int ncolors,
+                       bool contextual);
 hipError_t launch_chunk(int kind, int L, int rpt, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t chunk_occupancy(int kind, int L, int rpt, int block, size_t lds, int *blocks_per_cu);
+hipError_t launch_chunk_ctx(int kind, int L, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
+hipError_t chunk_occupancy_ctx(int kind, int L, int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_finish(const WorkItem *items, const int *first_item, int n_inst, uint32_t K, InstStatus *status,
                          hipStream_t s);
 int mixed_max_threads();
@@ -205,6 +208,10 @@ static uint64_t sweep_limit(const pt_ctx *c)
 {
     return c->opts.sweeps_per_cycle == 0 ? (uint64_t)INDEPENDENT_M - 1 : 0xFFFFFFFFull;
 }
+
+// Proposals of this context are contextual (built on the device from the
+// bank entry and the slot's current state) rather than plain bank entries.
+static bool contextual(const pt_ctx *c) { return (c->hI.ctx_T | (uint32_t)c->hI.ctx_sweeps) != 0; }
 
 static int check_ctx(pt_ctx *c)
 {
@@ -665,10 +672,22 @@ extern "C" int pt_propose_device(pt_ctx *c, double beta, const int8_t *configs_d
     return rc;
 }
 
+extern "C" int pt_set_context(pt_ctx *c, double fraction, int32_t sweeps)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!(fraction >= 0.0 && fraction <= 1.0)) return fail(PT_EINVAL, "context fraction must lie in [0, 1]");
+    if (sweeps < 0 || sweeps > 65535) return fail(PT_EINVAL, "completion sweeps must lie in 0..65535");
+    c->hI.ctx_T = fraction > 0.0 ? threshold(fraction) : 0u;
+    c->hI.ctx_sweeps = sweeps;
+    return push_inst(c);
+}
+
 extern "C" int pt_sweep(pt_ctx *c, uint64_t n_sweeps)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
+    if (contextual(c)) return fail(PT_EUNSUPPORTED, "contextual proposals run in batches (pt_batch_*), not on the plain path");
     if (c->t_host + n_sweeps > sweep_limit(c)) return fail(PT_EINVAL, "sweep counter would exceed %llu",
                                                             (unsigned long long)sweep_limit(c));
     hipStream_t s = c->stream;
@@ -794,6 +813,7 @@ struct LaunchGroup {
     bool wave = false;                // wave-per-replica kernel
     bool pm = false;                  // +-J 8^3 kernel
     int spw = 2;                      // its slots per wavefront (1 or 2)
+    bool ctx = false;                 // some context has contextual proposals (chunk_kernel_ctx)
     size_t lds;
     std::vector<pt_ctx *> ctxs;
     std::vector<int> Gs;              // per context: slots per workgroup (max)
@@ -801,6 +821,7 @@ struct LaunchGroup {
     DevBuf items, order, first_item, best, best_spins, xbuf, status;
     std::vector<size_t> x_off, x_bytes;   // per context: its exchange words
     std::vector<uint32_t> x_epoch;        // epoch the exchange words were cleared for
+    std::vector<char> ctx_mode;           // contextual proposals at build time (sizes the LDS)
     int n_items = 0;
 };
 
@@ -838,7 +859,8 @@ struct pt_batch {
 // gives large lattices 4 slots per thread, so that a batch of many sizes fits.
 static constexpr int TILING_LEVELS = 5;
 
-static void choose_tiling(const pt_ctx *c, const pt_batch_opts &o, bool mixed, int level, int &G, int &rpt)
+static void choose_tiling(const pt_ctx *c, const pt_batch_opts &o, bool mixed, bool ctx_group, int level, int &G,
+                          int &rpt)
 {
     const int R = c->R;
     rpt = o.replicas_per_thread > 0 ? o.replicas_per_thread : 0;
@@ -852,6 +874,7 @@ static void choose_tiling(const pt_ctx *c, const pt_batch_opts &o, bool mixed, i
         return;
     }
     if (!rpt) rpt = level < 2 ? 1 : (level >= TILING_LEVELS - 2 && mixed && c->n >= 1000) ? 4 : 2;
+    if (ctx_group) rpt = 1;   // the contextual kernels hold one slot per thread
     // the cycle-end stages keep one slot per lane of a wavefront: G <= 64
     const int NC = c->n / 8;
     const int maxt = mixed ? mixed_max_threads() : lattice_max_threads();
@@ -934,15 +957,21 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         P.lds = std::max(P.lds, g->pm     ? pm_lds_bytes(P.ctx[k].gmax, P.tsw_max)
                                 : g->wave ? wave_lds_bytes(c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max)
                                           : chunk_lds_bytes(c->kind, c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max,
-                                                            c->hI.nnz, c->hI.nfree, c->ncolors));
+                                                            c->hI.nnz, c->hI.nfree, c->ncolors, contextual(c)));
     }
     if (P.lds > 160 * 1024) return fail(PT_EUNSUPPORTED, "tiling needs %zu B of LDS per workgroup", P.lds);
+    if (g->ctx && g->mixed)
+        return fail(PT_EUNSUPPORTED, "contextual proposals need a batch of one lattice size or of general graphs");
+    for (int r : g->rpts)
+        if (g->ctx && r != 1) return fail(PT_EUNSUPPORTED, "contextual proposals take one slot per thread");
     if (g->pm)
         HIPCHK(pm_occupancy(g->spw, P.block, P.lds, &P.per_cu));
     else if (g->wave)
         HIPCHK(wave_occupancy(g->L, P.block, P.lds, &P.per_cu));
     else if (g->mixed)
         HIPCHK(chunk_occupancy_mixed(P.block, P.lds, &P.per_cu));
+    else if (g->ctx)
+        HIPCHK(chunk_occupancy_ctx(g->kind, g->L, P.block, P.lds, &P.per_cu));
     else
         HIPCHK(chunk_occupancy(g->kind, g->L, g->rpt, P.block, P.lds, &P.per_cu));
     if (P.per_cu < 1) return fail(PT_EUNSUPPORTED, "kernel cannot run with block %d, LDS %zu", P.block, P.lds);
@@ -982,6 +1011,7 @@ static int build_group(pt_batch *b, LaunchGroup *g)
         g->x_off.push_back(p.x_off);
         g->x_bytes.push_back((size_t)p.W * 4 * p.xwords * 8);
         g->x_epoch.push_back(g->ctxs[k]->hI.epoch);
+        g->ctx_mode.push_back(contextual(g->ctxs[k]) ? 1 : 0);
     }
     g->n_items = (int)P.items.size();
     g->grid = P.grid;
@@ -1011,10 +1041,12 @@ static void clear_groups(pt_batch *b)
 // needs several sweepers runs as a single launch of the mixed kernel.
 static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx *> &ctxs, int level)
 {
+    bool any_ctx = false;
+    for (pt_ctx *c : ctxs) any_ctx = any_ctx || contextual(c);
     std::map<std::tuple<int, int, int>, int> keys;
     for (pt_ctx *c : ctxs) {
         int G, rpt;
-        choose_tiling(c, o, false, level, G, rpt);
+        choose_tiling(c, o, false, any_ctx, level, G, rpt);
         keys[std::make_tuple(c->kind, c->kind == KIND_LATTICE ? c->L : 0, rpt)] += 1;
     }
     LaunchGroup *g = new LaunchGroup();
@@ -1025,9 +1057,12 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
     // one wavefront, unless the caller asks for the workgroup-synchronous one
     bool all_pm = !g->mixed;
     for (pt_ctx *c : ctxs) all_pm = all_pm && c->pmJ;
+    // contextual proposals run in the workgroup-synchronous kernels only
+    all_pm = all_pm && !any_ctx;
+    g->ctx = any_ctx;
     g->pm = all_pm && (o.kernel == 3 || o.kernel == 4 || (o.kernel == 0 && o.replicas_per_thread <= 1));
     g->spw = o.kernel == 4 ? 1 : 2;
-    g->wave = !g->pm && !g->mixed && g->kind == KIND_LATTICE && wave_supported(g->L) && o.kernel != 1 &&
+    g->wave = !g->pm && !g->mixed && !any_ctx && g->kind == KIND_LATTICE && wave_supported(g->L) && o.kernel != 1 &&
               (o.kernel == 2 || o.replicas_per_thread <= 1);
     for (pt_ctx *c : ctxs) {
         int G, rpt;
@@ -1041,7 +1076,7 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
             G = o.replicas_per_wg > 0 ? o.replicas_per_wg : wave_max_storages();
             G = std::min(std::min(G, c->R), wave_max_storages());
         } else {
-            choose_tiling(c, o, g->mixed, level, G, rpt);
+            choose_tiling(c, o, g->mixed, any_ctx, level, G, rpt);
         }
         g->rpt = rpt;
         g->ctxs.push_back(c);
@@ -1164,6 +1199,7 @@ static hipError_t enqueue_round(pt_batch *b, uint32_t K, bool timed)
         hipError_t e = g->pm      ? launch_pm(g->spw, a, g->block, g->lds, b->stream)
                        : g->wave  ? launch_wave(g->L, a, g->block, g->lds, b->stream)
                        : g->mixed ? launch_chunk_mixed(a, g->block, g->lds, b->stream)
+                       : g->ctx   ? launch_chunk_ctx(g->kind, g->L, a, g->block, g->lds, b->stream)
                                   : launch_chunk(g->kind, g->L, g->rpt, a, g->block, g->lds, b->stream);
         if (e != hipSuccess) return e;
         if (timed) {
@@ -1191,6 +1227,10 @@ extern "C" int pt_batch_sweep(pt_batch *b, uint64_t n_sweeps)
         c->hI.sweep_cap = c->t_host + n_sweeps;
         HIPCHK(hipMemcpyAsync(c->inst.p, &c->hI, sizeof(InstDev), hipMemcpyHostToDevice, b->stream));
     }
+    for (auto *g : b->groups)
+        for (size_t k = 0; k < g->ctxs.size(); ++k)
+            if (g->ctx_mode[k] != (contextual(g->ctxs[k]) ? 1 : 0))
+                return fail(PT_ESTATE, "a context's proposal mode changed after the batch was built");
     // a replaced state restarts the cycle count: clear that instance's exchange words
     for (auto *g : b->groups)
         for (size_t k = 0; k < g->ctxs.size(); ++k)

@@ -312,12 +312,13 @@ int lattice_max_threads() { return 512; }
 
 int lattice_threads(int L, int G, int rpt) { return ((G + rpt - 1) / rpt) * (L * L * L / 8); }
 
-size_t chunk_lds_bytes(int kind, int n, int G, int stride, int tsw_entries, int nnz, int nfree, int ncolors)
+size_t chunk_lds_bytes(int kind, int n, int G, int stride, int tsw_entries, int nnz, int nfree, int ncolors,
+                       bool contextual)
 {
     int SB = kind == KIND_LATTICE ? n : CsrSweep::storage_bytes(n);
     int nr = kind == KIND_LATTICE ? 0 : ((n + 7) & ~7);
     size_t gb = kind == KIND_LATTICE ? 0 : csr_graph_bytes(n, nnz, nfree, ncolors);
-    return chunk_lds_offsets(G, SB, stride, nr, tsw_entries, n, gb).total;
+    return chunk_lds_offsets(G, SB, stride, nr, tsw_entries, n, gb, contextual).total;
 }
 
 template <class K>
@@ -391,7 +392,7 @@ static hipError_t launch_plain_sweep_t(const InstDev *dI, int R, int block, size
 hipError_t launch_plain(int kind, int L, const InstDev *dI, int R, int n, int stride, int nnz, int nfree, int ncolors,
                         uint32_t t, hipStream_t s)
 {
-    size_t lds = chunk_lds_bytes(kind, n, 1, stride, 0, nnz, nfree, ncolors);
+    size_t lds = chunk_lds_bytes(kind, n, 1, stride, 0, nnz, nfree, ncolors, false);
     hipError_t e;
     if (kind == KIND_CSR) {
         e = launch_plain_sweep_t<CsrSweep>(dI, R, 256, lds, t, s);

@@ -487,16 +487,18 @@ struct ChunkLds {
     uint32_t *tsw;
     uint32_t *xstage;          // [2][ceil(n/32) + 1] validated exchange words
     uint32_t *usw;             // [2][65] swap uniforms by cycle parity (lane l: pair s0+l; 64: pair s0-1)
+    int8_t *cx;                // contextual proposal: candidate storage [SB]
+    uint8_t *cm;               // and its context mask [SB], both in the storage layout
 };
 
 struct ChunkOff {
-    size_t sp, tab, ints, src, rnd, toff, tsw, xst, usw, graph, total;
+    size_t sp, tab, ints, src, rnd, toff, tsw, xst, usw, graph, ctx, cmask, total;
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 __host__ __device__ __forceinline__ ChunkOff chunk_lds_offsets(int G, int SB, int stride, int nr_csr, int tsw_entries,
-                                                                int n, size_t graph_bytes = 0)
+                                                                int n, size_t graph_bytes = 0, bool contextual = false)
 {
     ChunkOff f;
     size_t o = 0;
@@ -510,6 +512,8 @@ __host__ __device__ __forceinline__ ChunkOff chunk_lds_offsets(int G, int SB, in
     f.xst = o; o = align16(o + (size_t)2 * (((n + 31) >> 5) + 1) * 4);
     f.usw = o; o = align16(o + (size_t)2 * 65 * 4);
     f.graph = o; o = align16(o + graph_bytes);
+    f.ctx = o; o = align16(o + (contextual ? (size_t)SB : 0));     // contextual candidate
+    f.cmask = o; o = align16(o + (contextual ? (size_t)SB : 0));   // and its context mask
     f.total = o;
     return f;
 }
@@ -532,7 +536,9 @@ __host__ __device__ __forceinline__ ChunkOff chunk_lds_offsets(int G, int SB, in
     c.tsw_off = (int *)((base) + (f).toff);                       \
     c.tsw = (uint32_t *)((base) + (f).tsw);                       \
     c.xstage = (uint32_t *)((base) + (f).xst);                    \
-    c.usw = (uint32_t *)((base) + (f).usw)
+    c.usw = (uint32_t *)((base) + (f).usw);                       \
+    c.cx = (int8_t *)((base) + (f).ctx);                          \
+    c.cm = (uint8_t *)((base) + (f).cmask)
 
 // Run parameters of one instance, read once per launch (kept in SGPRs).
 struct RunParams {
@@ -605,6 +611,46 @@ struct SweepCall<LatSweep<L, RPT>> {
     static __device__ int lidx(const LatSweep<L, RPT> &, int i) { return LatSweep<L, RPT>::lidx(i); }
     static __device__ size_t graph_bytes(const InstDev &) { return 0; }
     static __device__ void bind(LatSweep<L, RPT> &, const InstDev &, unsigned char *, int, int) {}
+
+    // Contextual proposals work on one candidate storage X (same layout),
+    // through a view of the graph that is passed by value (a lattice needs
+    // none). ctx_sites calls f(i) for the sites of colour col this thread updates.
+    struct CtxView {};
+    static __device__ CtxView ctx_view(const LatSweep<L, RPT> &) { return CtxView{}; }
+    static __device__ __forceinline__ int ctx_lidx(int i) { return LatSweep<L, RPT>::lidx(i); }
+    template <class F>
+    static __device__ __forceinline__ void ctx_sites(const CtxView &, const InstDev &, int col, int tid, int bs, F f)
+    {
+        constexpr int N = L * L * L;
+        for (int i = tid; i < N; i += bs) {
+            const int x = i % L, y = (i / L) % L, z = i / (L * L);
+            if (((x + y + z) & 1) == col) f(i);
+        }
+    }
+    // local field of site i (Eq. 4; a lattice has no fields)
+    static __device__ __forceinline__ int ctx_field(const CtxView &, const InstDev &I, const int8_t *X, int i)
+    {
+        constexpr int N = L * L * L;
+        using S = LatSweep<L, RPT>;
+        const int x = i % L, y = (i / L) % L, z = i / (L * L);
+        const int xm = (x + L - 1) % L + L * (y + L * z), xp = (x + 1) % L + L * (y + L * z);
+        const int ym = x + L * ((y + L - 1) % L + L * z), yp = x + L * ((y + 1) % L + L * z);
+        const int zm = x + L * (y + L * ((z + L - 1) % L)), zp = x + L * (y + L * ((z + 1) % L));
+        const int8_t *J = I.J3;
+        return J[i] * X[S::lidx(xp)] + J[xm] * X[S::lidx(xm)] + J[N + i] * X[S::lidx(yp)] + J[N + ym] * X[S::lidx(ym)] +
+               J[2 * N + i] * X[S::lidx(zp)] + J[2 * N + zm] * X[S::lidx(zm)];
+    }
+    // twice site i's share of E(X): its +x, +y, +z bonds
+    static __device__ __forceinline__ int ctx_energy2(const CtxView &, const InstDev &I, const int8_t *X, int i)
+    {
+        constexpr int N = L * L * L;
+        using S = LatSweep<L, RPT>;
+        const int x = i % L, y = (i / L) % L, z = i / (L * L);
+        const int xp = (x + 1) % L + L * (y + L * z), yp = x + L * ((y + 1) % L + L * z);
+        const int zp = x + L * (y + L * ((z + 1) % L));
+        const int8_t *J = I.J3;
+        return -2 * X[S::lidx(i)] * (J[i] * X[S::lidx(xp)] + J[N + i] * X[S::lidx(yp)] + J[2 * N + i] * X[S::lidx(zp)]);
+    }
 };
 
 template <>
@@ -620,7 +666,129 @@ struct SweepCall<CsrSweep> {
     {
         sw.bind(I, base, tid, bs);
     }
+
+    // Contextual proposals: the free sites of colour col from the LDS graph
+    using CtxView = CsrGraph;
+    static __device__ CtxView ctx_view(const CsrSweep &sw) { return sw.gr; }
+    static __device__ __forceinline__ int ctx_lidx(int i) { return i; }
+    template <class F>
+    static __device__ __forceinline__ void ctx_sites(const CtxView &g, const InstDev &, int col, int tid, int bs, F f)
+    {
+        const int end = g.coff[col + 1];
+        for (int q = g.coff[col] + tid; q < end; q += bs) f((int)g.cs[q]);
+    }
+    static __device__ __forceinline__ int ctx_field(const CtxView &g, const InstDev &, const int8_t *X, int i)
+    {
+        int f = g.h[i];
+        for (int e = g.rp[i]; e < g.rp[i + 1]; ++e) {
+            const uint32_t w = g.cw[e];
+            f += (int)(int8_t)(w & 0xFFu) * (int)X[w >> 8];
+        }
+        return f;
+    }
+    // twice site i's share of E(X): half of each of its bonds, all of its field
+    static __device__ __forceinline__ int ctx_energy2(const CtxView &g, const InstDev &, const int8_t *X, int i)
+    {
+        int s = 0;
+        for (int e = g.rp[i]; e < g.rp[i + 1]; ++e) {
+            const uint32_t w = g.cw[e];
+            s += (int)(int8_t)(w & 0xFFu) * (int)X[w >> 8];
+        }
+        const int m = X[i];
+        return -m * s - 2 * (int)g.h[i] * m;
+    }
 };
+
+__device__ __forceinline__ uint32_t pick4(const P4 &r, int k)
+{
+    return k == 0 ? r.v[0] : k == 1 ? r.v[1] : k == 2 ? r.v[2] : r.v[3];
+}
+
+// Contextual proposals of the slots this workgroup holds (Supp. context
+// ablation), at the proposal stage of cycle cyc. For each proposal-enabled
+// slot, in increasing order: the candidate starts from the slot's bank entry;
+// each free site joins the context with the probability behind ctx_T (Philox
+// CONTEXT) and then holds the slot's current value; ctx_sweeps colored sweeps
+// at the slot's beta (Philox CTXSWEEP, one 32-bit word per attempt) update
+// the other free sites; the Delta-E rule of Eq. 2 judges the candidate's
+// recomputed energy. Every thread of the block takes part. Only the
+// kernels instantiated for contextual batches compile it in, so the others
+// keep their register allocation.
+template <class Sw>
+__device__ __forceinline__ void ctx_proposals(const typename SweepCall<Sw>::CtxView &gv, const InstDev &I, int G, int s0,
+                                              uint32_t cyc, ChunkLds &c, int SB, int stride)
+{
+    const int tid = threadIdx.x, bs = blockDim.x, n = I.n, D = I.D;
+    const uint32_t k0 = I.seed_lo, k1 = I.seed_hi, cT = I.ctx_T;
+    const int K = I.ctx_sweeps;
+    for (int l = 0; l < G; ++l) {
+        const int r = s0 + l;
+        const int B = I.bank_n[r];
+        if (B <= 0) continue;
+        if (tid == 0) {
+            c.misc[8] = I.cursor[r];
+            c.misc[6] = 0;
+        }
+        __syncthreads();
+        const int k = c.misc[8];
+        const int st = c.stor_of[l];
+        const int8_t *cur = c.sp + st * SB;
+        const int8_t *src = I.bank[r] + (size_t)k * n;
+        for (int i = tid; i < n; i += bs) {
+            const int li = SweepCall<Sw>::ctx_lidx(i);
+            const uint32_t u = pick4(philox((uint32_t)i >> 2, cyc, (uint32_t)r, TAG_CONTEXT, k0, k1), i & 3);
+            const bool ctx = I.clamp[i] == 0 && (cT == ALWAYS || u < cT);
+            c.cm[li] = ctx ? 1 : 0;
+            c.cx[li] = ctx ? cur[li] : src[i];
+        }
+        __syncthreads();
+        const uint32_t *trow = c.tab + l * stride + D;
+        for (int j = 1; j <= K; ++j) {
+            const uint32_t c2 = (uint32_t)r + 65536u * (uint32_t)j;
+            for (int col = 0; col < I.ncolors; ++col) {
+                SweepCall<Sw>::ctx_sites(gv, I, col, tid, bs, [&](int i) {
+                    const int li = SweepCall<Sw>::ctx_lidx(i);
+                    if (c.cm[li]) return;
+                    const int m = c.cx[li];
+                    const int d = m * SweepCall<Sw>::ctx_field(gv, I, c.cx, i);
+                    const uint32_t T = trow[d];
+                    const uint32_t u = pick4(philox((uint32_t)i >> 2, cyc, c2, TAG_CTXSWEEP, k0, k1), i & 3);
+                    if (T == ALWAYS || u < T) c.cx[li] = (int8_t)(-m);
+                });
+                __syncthreads();
+            }
+        }
+        // E of the candidate: twice each site's share, summed over the block
+        int e2 = 0;
+        for (int i = tid; i < n; i += bs) e2 += SweepCall<Sw>::ctx_energy2(gv, I, c.cx, i);
+        e2 = wave_sum(e2);
+        if ((tid & 63) == 0) atomicAdd(&c.misc[6], e2);
+        __syncthreads();
+        if (tid == 0) {
+            const int ET = c.misc[6] / 2;
+            const long long dd = (long long)ET - (long long)c.Elds[st];
+            uint32_t T;
+            if (dd <= 0) T = ALWAYS;
+            else if (dd <= I.tprop_len[r]) T = I.tprop[I.tprop_off[r] + (int)dd - 1];
+            else T = 0;
+            const uint32_t u = philox_word0((uint32_t)r, cyc, TAG_PROPOSE, k0, k1);
+            I.cursor[r] = (k + 1 == B) ? 0 : k + 1;
+            I.prop_att[r] += 1;
+            const bool acc = T == ALWAYS || u < T;
+            if (acc) {
+                I.prop_acc[r] += 1;
+                c.Elds[st] = ET;
+            }
+            c.misc[7] = acc ? 1 : 0;
+        }
+        __syncthreads();
+        if (c.misc[7]) {
+            int8_t *dst = c.sp + st * SB;
+            for (int x = tid; x < n; x += bs) dst[x] = c.cx[x];
+        }
+        __syncthreads();
+    }
+}
 
 
 #define TAPT_LATTICE_LIST(X) X(4) X(6) X(8) X(10) X(12) X(14) X(16)
@@ -629,7 +797,7 @@ struct SweepCall<CsrSweep> {
 // Dynamic LDS of the persistent and plain kernels.
 extern __shared__ __align__(16) unsigned char lds_raw[];
 
-template <class Sw>
+template <class Sw, bool CTX = false>
 __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
 {
     const WorkItem it = a.items[item];
@@ -647,8 +815,9 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
     sw.setup(I, G);
     const int SB = SweepCall<Sw>::SB(sw);
     const int stride = P.stride;
+    const bool contextual = CTX && (I.ctx_T | (uint32_t)I.ctx_sweeps) != 0;
     const ChunkOff lof = chunk_lds_offsets(G, SB, stride, Sw::RND ? ((n + 7) & ~7) : 0, a.tsw_entries, n,
-                                           SweepCall<Sw>::graph_bytes(I));
+                                           SweepCall<Sw>::graph_bytes(I), contextual);
     CHUNK_LDS_POINTERS(c, lof, G, lds_raw);
     SweepCall<Sw>::bind(sw, I, lds_raw + lof.graph, tid, bs);
 
@@ -728,7 +897,15 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
         // ---- proposals (Eq. 2), slots in increasing order ----
         const bool prop_now = t == prop_at;
         if (prop_now) prop_at = P.next_prop(prop_at);
-        if (prop_now) {
+        bool bank_prop = prop_now;
+        if constexpr (CTX) {
+            if (prop_now && contextual) {
+                const typename SweepCall<Sw>::CtxView gv = SweepCall<Sw>::ctx_view(sw);
+                ctx_proposals<Sw>(gv, I, G, s0, cyc, c, SB, stride);
+                bank_prop = false;
+            }
+        }
+        if (bank_prop) {
             if (tid < 64) {
                 for (int l = lane; l < G; l += 64) {
                     int r = s0 + l;

@@ -8,7 +8,10 @@
 namespace tapt {
 
 enum : int32_t { KIND_LATTICE = 0, KIND_CSR = 1 };
-enum : uint32_t { TAG_INIT = 1, TAG_SWEEP = 2, TAG_REFINE = 3, TAG_PROPOSE = 4, TAG_SWAP = 5, TAG_BANK = 6 };
+enum : uint32_t {
+    TAG_INIT = 1, TAG_SWEEP = 2, TAG_REFINE = 3, TAG_PROPOSE = 4, TAG_SWAP = 5, TAG_BANK = 6,
+    TAG_CONTEXT = 7, TAG_CTXSWEEP = 8
+};
 constexpr uint32_t ALWAYS = 0xFFFFFFFFu;   // threshold meaning "accept unconditionally"
 constexpr int MAX_COLORS = 64;
 
@@ -24,9 +27,9 @@ struct InstDev {
     int32_t n, L, R, kind;
     int32_t rule, M, D, tflip_stride;       // flip table: index d + D, d = m_i I_i in [-D, D]
     int32_t has_target, target, ncolors, nfree;
-    int32_t nnz, pad0;
+    int32_t nnz, ctx_sweeps;                // ctx_sweeps: completion sweeps of a contextual proposal
     uint32_t seed_lo, seed_hi;
-    uint32_t epoch, pad1;                   // bumps when the state is replaced
+    uint32_t epoch, ctx_T;                  // epoch bumps when the state is replaced; ctx_T: context threshold
     int64_t prop_start, prop_period, prop_stop;
     uint64_t sweep_cap;                     // batched runs stop at this sweep count
 
