@@ -49,9 +49,14 @@ def parse():
     ap.add_argument("--L", type=int, default=8)
     ap.add_argument("--R", type=int, default=32)
     ap.add_argument("--bank", type=int, default=256)
-    ap.add_argument("--workload", default="pt", choices=("pt", "bankgen-sg", "bankgen-fact", "tts"),
+    ap.add_argument("--workload", default="pt", choices=("pt", "bankgen-sg", "bankgen-fact", "tts", "context"),
                     help="pt: the batched PT benchmark (default); bankgen-*: the long-run MCMC bank "
-                         "generation of Supp. Table S3 (3D spin glass L=10, or 16-bit factorization)")
+                         "generation of Supp. Table S3 (3D spin glass L=10, or 16-bit factorization); "
+                         "tts: the factorization TTS study; context: the proposal-context ablation")
+    ap.add_argument("--ctx-instances", type=int, default=16, help="context: spin-glass instances")
+    ap.add_argument("--ctx-runs", type=int, default=16, help="context: independent runs per instance and variant")
+    ap.add_argument("--ctx-sweeps", type=int, default=5000, help="context: sweeps per run")
+    ap.add_argument("--ctx-completion", type=int, default=20, help="context: completion sweeps per proposal")
     ap.add_argument("--bank-samples", type=int, default=100_000, help="bankgen: chains (samples) per bank")
     ap.add_argument("--tts-bits", default="16,18,20", help="tts: product bit lengths (even)")
     ap.add_argument("--tts-instances", type=int, default=8, help="tts: semiprimes per size")
@@ -467,6 +472,83 @@ def tts_study(args, log):
     print(json.dumps(out), flush=True)
 
 
+def context_study(args, log):
+    """Proposal-context ablation (Supp., Fig. S4b) on 3D spin glasses: PT,
+    TAPT with long-run MCMC bank proposals (no context), and contextual
+    proposals that clamp 12.5%, 25% or 50% of the slot's current spins and
+    complete the rest by MCMC from the bank entry. Residual energy per spin
+    of each run's best energy at checkpoints, against the lowest energy any
+    run found on the instance, and the chain's sweep throughput."""
+    import torch
+    from paper_2509_23043_amd import banks, binding, inputs
+    torch.cuda.set_device(0)
+    binding.lib()
+    L, R, NPROP, B, PERIOD = 10, 22, 20, 128, 10
+    n = L ** 3
+    betas = inputs.geometric_ladder(R)
+    T = args.ctx_sweeps
+    checkpoints = [t for t in (100, 250, 500, 1000, 2000, 5000, 10_000) if t < T] + [T]
+    variants = [("pt", None), ("bank", 0.0), ("ctx12.5", 0.125), ("ctx25", 0.25), ("ctx50", 0.5)]
+    t0 = time.perf_counter()
+    insts = [inputs.ea_lattice(L, 7000 + i) for i in range(args.ctx_instances)]
+    bank_sets = []
+    for i, g in enumerate(insts):
+        bank_sets.append({r: banks.generate_bank(g, betas[r], B, 10_000, seed=800_000 + 1000 * i + 37 * r)[0]
+                          for r in range(NPROP)})
+    log(f"context: {len(insts)} instances, {NPROP} banks of {B} samples each in {time.perf_counter() - t0:.1f} s")
+    best = {}
+    rate = {}
+    for name, frac in variants:
+        ctxs = []
+        for i, g in enumerate(insts):
+            for k in range(args.ctx_runs):
+                kw = {} if frac is None else dict(prop_start=PERIOD, prop_period=PERIOD)
+                c = binding.Context(g, betas, seed=90_000 + 100 * i + k, **kw)
+                if frac is not None:
+                    for r, b in bank_sets[i].items():
+                        c.propose(r, b)
+                    if frac > 0:
+                        c.set_context(frac, args.ctx_completion)
+                ctxs.append(c)
+        traj = np.zeros((len(ctxs), len(checkpoints)), np.int64)
+        make = lambda group: binding.Batch(group, chunk_sweeps=min(250, checkpoints[0]))
+        ms = 0.0
+        at = 0
+        # batches of as many runs as stay co-resident, one after the other
+        for group, bt in banks._batches(ctxs, make):
+            bt.kernel_time()
+            done = 0
+            for j, t in enumerate(checkpoints):
+                bt.sweep(t - done)
+                done = t
+                traj[at:at + len(group), j] = [c.summary()["best"] for c in group]
+            ms += bt.kernel_time()[0]
+            at += len(group)
+            bt.close()
+        rate[name] = len(ctxs) * R * n * T / (ms * 1e6)
+        best[name] = traj.reshape(len(insts), args.ctx_runs, len(checkpoints))
+        for c in ctxs:
+            c.close()
+        log(f"context {name}: {rate[name]:.1f} attempts/ns of chain sweeps")
+    eref = np.min([best[v][:, :, -1].min(axis=1) for v, _ in variants], axis=0)     # per instance
+    rho = {v: [(best[v][:, :, j] - eref[:, None]).mean() / n for j in range(len(checkpoints))] for v, _ in variants}
+    for v, _ in variants:
+        log(f"context {v}: rho_E " + ", ".join(f"t={t}: {r:.5f}" for t, r in zip(checkpoints, rho[v])))
+    out = dict(metric="residual energy per spin at t_max, TAPT with MCMC bank proposals (no context)",
+               value=round(float(rho["bank"][-1]), 6), unit="energy/spin", n_gpus=1, steps=1, warmup=0,
+               ms_per_step=round((time.perf_counter() - t0) * 1e3, 1), higher_is_better=False, scaling="weak",
+               vs_baseline=None, dtype="int8", data="synthetic",
+               config=dict(workload=f"3D EA +-J L={L}, {len(insts)} instances x {args.ctx_runs} runs per variant, "
+                                    f"R={R} geometric 0.2..3.0, proposals every {PERIOD} sweeps on the {NPROP} "
+                                    f"hottest slots from {B}-sample MCMC banks (10^4 burn-in), contextual "
+                                    f"completion {args.ctx_completion} sweeps, {T} sweeps; rho_E against the "
+                                    f"lowest energy any run found per instance"),
+               checkpoints=checkpoints,
+               rho_E={v: [round(float(x), 6) for x in rho[v]] for v, _ in variants},
+               attempts_per_ns={v: round(float(x), 2) for v, x in rate.items()})
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -475,6 +557,9 @@ def main():
         sys.exit(2)
     if args.workload == "tts":
         tts_study(args, lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True))
+        return
+    if args.workload == "context":
+        context_study(args, lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True))
         return
     if args.workload != "pt":
         bankgen(args, lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True))
