@@ -33,8 +33,8 @@ int lattice_max_threads();
 int lattice_threads(int L, int G, int rpt);
 size_t chunk_lds_bytes(int kind, int n, int G, int stride, int tsw_entries, int nnz, int nfree, int ncolors,
                        bool contextual);
-hipError_t launch_chunk(int kind, int L, int rpt, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
-hipError_t chunk_occupancy(int kind, int L, int rpt, int block, size_t lds, int *blocks_per_cu);
+hipError_t launch_chunk(int kind, int L, int rpt, bool wide, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
+hipError_t chunk_occupancy(int kind, int L, int rpt, bool wide, int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_chunk_ctx(int kind, int L, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t chunk_occupancy_ctx(int kind, int L, int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_finish(const WorkItem *items, const int *first_item, int n_inst, uint32_t K, InstStatus *status,
@@ -814,6 +814,7 @@ struct LaunchGroup {
     bool pm = false;                  // +-J 8^3 kernel
     int spw = 2;                      // its slots per wavefront (1 or 2)
     bool ctx = false;                 // some context has contextual proposals (chunk_kernel_ctx)
+    bool wide = false;                // sparse graphs at 512 threads: the lane-sharing sweeper
     size_t lds;
     std::vector<pt_ctx *> ctxs;
     std::vector<int> Gs;              // per context: slots per workgroup (max)
@@ -898,6 +899,7 @@ struct GroupPlan {
     std::vector<Ctx> ctx;
     size_t nbest = 0, nbs = 0, nx = 0, lds = 0;
     int block = 64, grid = 0, tsw_max = 0, per_cu = 0;
+    bool wide = false;
 };
 
 static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
@@ -938,7 +940,10 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         // a block covers the largest item's threads
         int need = g->pm     ? 64 * (P.ctx[k].gmax / g->spw)
                    : g->wave ? 64 * P.ctx[k].gmax
-                             : c->kind == KIND_LATTICE ? lattice_threads(c->L, P.ctx[k].gmax, g->rpts[k]) : 256;
+                             : c->kind == KIND_LATTICE ? lattice_threads(c->L, P.ctx[k].gmax, g->rpts[k])
+                             // sparse graphs: a few slots per workgroup (the latency tilings) get 512
+                             // threads, so that 2 or 4 lanes can share a site's bonds
+                             : P.ctx[k].gmax <= 2 ? 512 : 256;
         P.block = std::max(P.block, (need + 63) & ~63);
     }
     // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
@@ -972,8 +977,11 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         HIPCHK(chunk_occupancy_mixed(P.block, P.lds, &P.per_cu));
     else if (g->ctx)
         HIPCHK(chunk_occupancy_ctx(g->kind, g->L, P.block, P.lds, &P.per_cu));
-    else
-        HIPCHK(chunk_occupancy(g->kind, g->L, g->rpt, P.block, P.lds, &P.per_cu));
+    else {
+        // a specialised sparse-graph launch at 512 threads takes the lane-sharing sweeper
+        P.wide = g->kind == KIND_CSR && P.block == 512;
+        HIPCHK(chunk_occupancy(g->kind, g->L, g->rpt, P.wide, P.block, P.lds, &P.per_cu));
+    }
     if (P.per_cu < 1) return fail(PT_EUNSUPPORTED, "kernel cannot run with block %d, LDS %zu", P.block, P.lds);
     // the cross-workgroup waits need every workgroup of the launch resident
     // (counted with the padding blocks, so that every XCD's share fits its CUs);
@@ -1014,6 +1022,7 @@ static int build_group(pt_batch *b, LaunchGroup *g)
         g->ctx_mode.push_back(contextual(g->ctxs[k]) ? 1 : 0);
     }
     g->n_items = (int)P.items.size();
+    g->wide = P.wide;
     g->grid = P.grid;
     g->block = P.block;
     g->lds = P.lds;
@@ -1200,7 +1209,7 @@ static hipError_t enqueue_round(pt_batch *b, uint32_t K, bool timed)
                        : g->wave  ? launch_wave(g->L, a, g->block, g->lds, b->stream)
                        : g->mixed ? launch_chunk_mixed(a, g->block, g->lds, b->stream)
                        : g->ctx   ? launch_chunk_ctx(g->kind, g->L, a, g->block, g->lds, b->stream)
-                                  : launch_chunk(g->kind, g->L, g->rpt, a, g->block, g->lds, b->stream);
+                                  : launch_chunk(g->kind, g->L, g->rpt, g->wide, a, g->block, g->lds, b->stream);
         if (e != hipSuccess) return e;
         if (timed) {
             e = hipEventRecord(e1, b->stream);

@@ -25,7 +25,7 @@
 namespace tapt {
 
 template <class Sw>
-__global__ void __launch_bounds__(Sw::MAXT) chunk_kernel(ChunkArgs a)
+__global__ void __launch_bounds__(Sw::MAXT, Sw::MINW) chunk_kernel(ChunkArgs a)
 {
     const int item = a.order[blockIdx.x];
     if (item < 0) return;   // padding block that keeps the XCD placement aligned
@@ -336,9 +336,9 @@ static hipError_t launch_chunk_t(const ChunkArgs &a, int block, size_t lds, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_chunk(int kind, int L, int rpt, const ChunkArgs &a, int block, size_t lds, hipStream_t s)
+hipError_t launch_chunk(int kind, int L, int rpt, bool wide, const ChunkArgs &a, int block, size_t lds, hipStream_t s)
 {
-    if (kind == KIND_CSR) return launch_chunk_t<CsrSweep>(a, block, lds, s);
+    if (kind == KIND_CSR) return wide ? launch_chunk_t<CsrSweepWide>(a, block, lds, s) : launch_chunk_t<CsrSweep>(a, block, lds, s);
 #define X(LL)                                                                         \
     if (L == LL) {                                                                    \
         if (rpt == 1) return launch_chunk_t<LatSweep<LL, 1>>(a, block, lds, s);       \
@@ -358,9 +358,10 @@ static hipError_t occupancy_t(int block, size_t lds, int *blocks_per_cu)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, chunk_kernel<Sw>, block, lds);
 }
 
-hipError_t chunk_occupancy(int kind, int L, int rpt, int block, size_t lds, int *blocks_per_cu)
+hipError_t chunk_occupancy(int kind, int L, int rpt, bool wide, int block, size_t lds, int *blocks_per_cu)
 {
-    if (kind == KIND_CSR) return occupancy_t<CsrSweep>(block, lds, blocks_per_cu);
+    if (kind == KIND_CSR)
+        return wide ? occupancy_t<CsrSweepWide>(block, lds, blocks_per_cu) : occupancy_t<CsrSweep>(block, lds, blocks_per_cu);
 #define X(LL)                                                                      \
     if (L == LL) {                                                                 \
         if (rpt == 1) return occupancy_t<LatSweep<LL, 1>>(block, lds, blocks_per_cu); \

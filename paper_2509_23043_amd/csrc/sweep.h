@@ -162,6 +162,7 @@ struct LatSweep {
     static_assert(L % 2 == 0 && L >= 4, "even L >= 4");
     static constexpr int SB = N;   // bytes per storage
     static constexpr int MAXT = 512;  // block limit: leaves up to 256 VGPRs per lane
+    static constexpr int MINW = 1;    // waves per SIMD the register budget must allow
     static constexpr bool RND = false;  // no staged random halves
 
     __host__ __device__ static constexpr int lidx(int i) { return (i & 7) * NC + (i >> 3); }
@@ -356,10 +357,15 @@ __device__ __forceinline__ void csr_graph_stage(const InstDev &I, const CsrGraph
 // General sparse graph (CSR, any proper coloring, clamps, fields). Random
 // halves for every site of every storage are staged in LDS at the start of
 // the sweep (one Philox call per 8 sites), then each color class is spread
-// over all threads of the workgroup.
-struct CsrSweep {
+// over all threads of the workgroup. WIDE lets a colour class with few
+// (site, storage) items share each site's bonds among 2 or 4 lanes; it is
+// instantiated for the latency tilings (512 threads, at most 2 slots per
+// workgroup), and left out elsewhere, where it would only cost registers.
+template <bool WIDE>
+struct CsrSweepT {
     static constexpr int RPTV = 1;
-    static constexpr int MAXT = 512;    // leaves 256 VGPRs, no spills
+    static constexpr int MAXT = 512;    // block limit
+    static constexpr int MINW = WIDE ? 3 : 1;   // wide: at most 168 VGPRs, as the plain one needs anyway
     static constexpr bool RND = true;   // random halves staged in LDS
     int n, SB, nr;
     CsrGraph gr;
@@ -408,56 +414,109 @@ struct CsrSweep {
         unsigned nf_acc = 0;
         for (int c = 0; c < ncol; ++c) {
             const int off = gr.coff[c], cnt = gr.coff[c + 1] - off;
-            int s = tid / G, k = tid - (tid / G) * G;
-            while (s < cnt) {
-                const int i = gr.cs[off + s];
-                int8_t *m_k = sp + k * SB;
-                int f = gr.h[i];
-                const int e1 = gr.rp[i + 1];
-                int e = gr.rp[i];
-                // four neighbours per step: their words, then their spins, are
-                // independent loads (two LDS round trips per four bonds)
-                for (; e + 4 <= e1; e += 4) {
-                    const uint32_t w0 = gr.cw[e], w1 = gr.cw[e + 1], w2 = gr.cw[e + 2], w3 = gr.cw[e + 3];
-                    const int n0 = m_k[w0 >> 8], n1 = m_k[w1 >> 8], n2 = m_k[w2 >> 8], n3 = m_k[w3 >> 8];
-                    f += (int)(int8_t)(w0 & 0xFFu) * n0 + (int)(int8_t)(w1 & 0xFFu) * n1 +
-                         (int)(int8_t)(w2 & 0xFFu) * n2 + (int)(int8_t)(w3 & 0xFFu) * n3;
-                }
-                for (; e < e1; ++e) {
-                    const uint32_t w = gr.cw[e];
-                    f += (int)(int8_t)(w & 0xFFu) * (int)m_k[w >> 8];
-                }
-                const int m = m_k[i];
-                const int d = m * f;
-                const int sl = slot_of[k];
-                const uint32_t T = tab[sl * stride + D + d];
-                const uint32_t hs = (uint32_t)rnd[(size_t)k * nr + i] << 16;
-                bool maybe;
-                bool acc = coarse_accept(T, hs, maybe);
-                if (any_lane(maybe)) {
-                    if (maybe) {
-                        P4 r2 = philox(opaque((uint32_t)(i >> 3)), t, (uint32_t)(s0 + sl), TAG_REFINE, I.seed_lo, I.seed_hi);
-                        const int wq = (i & 7) >> 1;   // word of the half (no dynamic indexing)
-                        const uint32_t wd = wq == 0 ? r2.v[0] : wq == 1 ? r2.v[1] : wq == 2 ? r2.v[2] : r2.v[3];
-                        const uint32_t lo = ((i & 1) ? (wd >> 16) : wd) & 0xFFFFu;
-                        acc = (T == ALWAYS) || ((hs | lo) < T);
+            // A colour class with few (site, storage) items spreads each site's
+            // bonds over 2 or 4 adjacent lanes (a contiguous share each, summed
+            // by DPP), which shortens the chain of dependent LDS reads per item.
+            const int items = cnt * G;
+            const int lp = !WIDE ? 0 : (items * 4 <= bs) ? 2 : (items * 2 <= bs) ? 1 : 0;
+            if (lp == 0) {
+                int s = tid / G, k = tid - (tid / G) * G;
+                while (s < cnt) {
+                    const int i = gr.cs[off + s];
+                    int8_t *m_k = sp + k * SB;
+                    int f = gr.h[i];
+                    const int e1 = gr.rp[i + 1];
+                    int e = gr.rp[i];
+                    // four neighbours per step: their words, then their spins, are
+                    // independent loads (two LDS round trips per four bonds)
+                    for (; e + 4 <= e1; e += 4) {
+                        const uint32_t w0 = gr.cw[e], w1 = gr.cw[e + 1], w2 = gr.cw[e + 2], w3 = gr.cw[e + 3];
+                        const int n0 = m_k[w0 >> 8], n1 = m_k[w1 >> 8], n2 = m_k[w2 >> 8], n3 = m_k[w3 >> 8];
+                        f += (int)(int8_t)(w0 & 0xFFu) * n0 + (int)(int8_t)(w1 & 0xFFu) * n1 +
+                             (int)(int8_t)(w2 & 0xFFu) * n2 + (int)(int8_t)(w3 & 0xFFu) * n3;
+                    }
+                    for (; e < e1; ++e) {
+                        const uint32_t w = gr.cw[e];
+                        f += (int)(int8_t)(w & 0xFFu) * (int)m_k[w >> 8];
+                    }
+                    const int m = m_k[i];
+                    const int d = m * f;
+                    const int sl = slot_of[k];
+                    const uint32_t T = tab[sl * stride + D + d];
+                    const uint32_t hs = (uint32_t)rnd[(size_t)k * nr + i] << 16;
+                    bool maybe;
+                    bool acc = coarse_accept(T, hs, maybe);
+                    if (any_lane(maybe)) {
+                        if (maybe) {
+                            P4 r2 = philox(opaque((uint32_t)(i >> 3)), t, (uint32_t)(s0 + sl), TAG_REFINE, I.seed_lo, I.seed_hi);
+                            const int wq = (i & 7) >> 1;   // word of the half (no dynamic indexing)
+                            const uint32_t wd = wq == 0 ? r2.v[0] : wq == 1 ? r2.v[1] : wq == 2 ? r2.v[2] : r2.v[3];
+                            const uint32_t lo = ((i & 1) ? (wd >> 16) : wd) & 0xFFFFu;
+                            acc = (T == ALWAYS) || ((hs | lo) < T);
+                        }
+                    }
+                    if (acc) {
+                        m_k[i] = (int8_t)(-m);
+                        if (fixed_k) {
+                            dE_acc += 2 * d;
+                            nf_acc += 1;
+                        } else {
+                            atomicAdd(&Elds[k], 2 * d);
+                            atomicAdd(&flips_lds[sl], 1u);
+                        }
+                    }
+                    s += dq;
+                    k += dr;
+                    if (k >= G) {
+                        k -= G;
+                        ++s;
                     }
                 }
-                if (acc) {
-                    m_k[i] = (int8_t)(-m);
-                    if (fixed_k) {
-                        dE_acc += 2 * d;
-                        nf_acc += 1;
-                    } else {
+            } else {
+                const int sub = tid & ((1 << lp) - 1), it = tid >> lp;
+                if (it < items) {
+                    const int s = it / G, k = it - s * G;
+                    const int i = gr.cs[off + s];
+                    int8_t *m_k = sp + k * SB;
+                    const int e0 = gr.rp[i], e1 = gr.rp[i + 1];
+                    const int ch = (e1 - e0 + (1 << lp) - 1) >> lp;
+                    int e = e0 + sub * ch;
+                    const int ee = e + ch < e1 ? e + ch : e1;
+                    int f = sub == 0 ? (int)gr.h[i] : 0;
+                    for (; e + 4 <= ee; e += 4) {
+                        const uint32_t w0 = gr.cw[e], w1 = gr.cw[e + 1], w2 = gr.cw[e + 2], w3 = gr.cw[e + 3];
+                        const int n0 = m_k[w0 >> 8], n1 = m_k[w1 >> 8], n2 = m_k[w2 >> 8], n3 = m_k[w3 >> 8];
+                        f += (int)(int8_t)(w0 & 0xFFu) * n0 + (int)(int8_t)(w1 & 0xFFu) * n1 +
+                             (int)(int8_t)(w2 & 0xFFu) * n2 + (int)(int8_t)(w3 & 0xFFu) * n3;
+                    }
+                    for (; e < ee; ++e) {
+                        const uint32_t w = gr.cw[e];
+                        f += (int)(int8_t)(w & 0xFFu) * (int)m_k[w >> 8];
+                    }
+                    f += __builtin_amdgcn_update_dpp(0, f, 0xB1, 0xf, 0xf, false);       // quad_perm 1,0,3,2
+                    if (lp == 2) f += __builtin_amdgcn_update_dpp(0, f, 0x4E, 0xf, 0xf, false);   // 2,3,0,1
+                    const int m = m_k[i];
+                    const int d = m * f;
+                    const int sl = slot_of[k];
+                    const uint32_t T = tab[sl * stride + D + d];
+                    const uint32_t hs = (uint32_t)rnd[(size_t)k * nr + i] << 16;
+                    bool maybe;
+                    bool acc = coarse_accept(T, hs, maybe);
+                    if (any_lane(maybe)) {
+                        if (maybe) {
+                            P4 r2 = philox(opaque((uint32_t)(i >> 3)), t, (uint32_t)(s0 + sl), TAG_REFINE, I.seed_lo,
+                                           I.seed_hi);
+                            const int wq = (i & 7) >> 1;
+                            const uint32_t wd = wq == 0 ? r2.v[0] : wq == 1 ? r2.v[1] : wq == 2 ? r2.v[2] : r2.v[3];
+                            const uint32_t lo = ((i & 1) ? (wd >> 16) : wd) & 0xFFFFu;
+                            acc = (T == ALWAYS) || ((hs | lo) < T);
+                        }
+                    }
+                    if (acc && sub == 0) {   // the lanes of an item agree; one of them writes
+                        m_k[i] = (int8_t)(-m);
                         atomicAdd(&Elds[k], 2 * d);
                         atomicAdd(&flips_lds[sl], 1u);
                     }
-                }
-                s += dq;
-                k += dr;
-                if (k >= G) {
-                    k -= G;
-                    ++s;
                 }
             }
             __syncthreads();
@@ -470,6 +529,8 @@ struct CsrSweep {
         }
     }
 };
+using CsrSweep = CsrSweepT<false>;
+using CsrSweepWide = CsrSweepT<true>;
 
 // ---------------------------------------------------------------------------
 // LDS carve-up shared by the persistent kernel and the host's size query.
@@ -653,23 +714,23 @@ struct SweepCall<LatSweep<L, RPT>> {
     }
 };
 
-template <>
-struct SweepCall<CsrSweep> {
-    static __device__ __forceinline__ void run(CsrSweep &sw, const InstDev &I, int G, int s0, uint32_t t, ChunkLds &c, int stride)
+template <bool W>
+struct SweepCall<CsrSweepT<W>> {
+    static __device__ __forceinline__ void run(CsrSweepT<W> &sw, const InstDev &I, int G, int s0, uint32_t t, ChunkLds &c, int stride)
     {
         sw.sweep(I, G, s0, t, c.slot_of, c.sp, c.tab, stride, c.Elds, c.flips, c.rnd);
     }
-    static __device__ int SB(const CsrSweep &s) { return s.SB; }
-    static __device__ int lidx(const CsrSweep &, int i) { return i; }
-    static __device__ size_t graph_bytes(const InstDev &I) { return CsrSweep::graph_bytes(I); }
-    static __device__ void bind(CsrSweep &sw, const InstDev &I, unsigned char *base, int tid, int bs)
+    static __device__ int SB(const CsrSweepT<W> &s) { return s.SB; }
+    static __device__ int lidx(const CsrSweepT<W> &, int i) { return i; }
+    static __device__ size_t graph_bytes(const InstDev &I) { return CsrSweepT<W>::graph_bytes(I); }
+    static __device__ void bind(CsrSweepT<W> &sw, const InstDev &I, unsigned char *base, int tid, int bs)
     {
         sw.bind(I, base, tid, bs);
     }
 
     // Contextual proposals: the free sites of colour col from the LDS graph
     using CtxView = CsrGraph;
-    static __device__ CtxView ctx_view(const CsrSweep &sw) { return sw.gr; }
+    static __device__ CtxView ctx_view(const CsrSweepT<W> &sw) { return sw.gr; }
     static __device__ __forceinline__ int ctx_lidx(int i) { return i; }
     template <class F>
     static __device__ __forceinline__ void ctx_sites(const CtxView &g, const InstDev &, int col, int tid, int bs, F f)
