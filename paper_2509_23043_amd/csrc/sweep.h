@@ -289,12 +289,9 @@ struct LatSweep {
         for (int k = 0; k < RPT; ++k) {
             int e = dE[k], f = nf[k];
             if constexpr (NC % 64 == 0) {
-                // a wave belongs to one storage group
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-                    e += __shfl_xor(e, off);
-                    f += __shfl_xor(f, off);
-                }
+                // a wave belongs to one storage group: DPP sums, no LDS round trips
+                e = wave_sum(e);
+                f = wave_sum(f);
                 if (ok[k] && (threadIdx.x & 63) == 0) {
                     atomicAdd(&Elds[grp * RPT + k], e);
                     atomicAdd(&flips_lds[sl[k]], (unsigned)f);
