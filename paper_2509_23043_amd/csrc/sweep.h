@@ -296,6 +296,20 @@ struct LatSweep {
                     atomicAdd(&Elds[grp * RPT + k], e);
                     atomicAdd(&flips_lds[sl[k]], (unsigned)f);
                 }
+            } else if constexpr (NC >= 64) {
+                // a wave spans at most two storage groups: one DPP sum for each
+                const int lane = threadIdx.x & 63;
+                const bool first = grp == (int)(threadIdx.x - lane) / NC;
+                const int e0 = wave_sum(first ? e : 0), f0 = wave_sum(first ? f : 0);
+                const int e1 = wave_sum(first ? 0 : e), f1 = wave_sum(first ? 0 : f);
+                if (ok[k] && lane == 0) {
+                    atomicAdd(&Elds[grp * RPT + k], e0);
+                    atomicAdd(&flips_lds[sl[k]], (unsigned)f0);
+                }
+                if (ok[k] && lane == 63 && !first) {
+                    atomicAdd(&Elds[grp * RPT + k], e1);
+                    atomicAdd(&flips_lds[sl[k]], (unsigned)f1);
+                }
             } else {
                 if (ok[k] && (e != 0 || f != 0)) {
                     atomicAdd(&Elds[grp * RPT + k], e);
