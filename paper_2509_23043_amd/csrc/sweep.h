@@ -130,6 +130,11 @@ __device__ __forceinline__ int wave_min(int x)
     return __builtin_amdgcn_readlane(x, 63);
 }
 
+// x of the next (lane + 1) and the previous (lane - 1) lane by DPP wave
+// shifts; the last and the first lane keep their own value.
+__device__ __forceinline__ int from_next_lane(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ int from_prev_lane(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x138, 0xf, 0xf, false); }
+
 // Sum of x over the 64 lanes of a wavefront (same DPP pattern as wave_min).
 __device__ __forceinline__ int wave_sum(int x)
 {
@@ -1035,14 +1040,23 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                 const int st = c.stor_of[side == 0 ? 0 : G - 1];
                 const int8_t *stor = c.sp + st * SB;
                 unsigned long long *out = it.xbuf + ((size_t)(it.w * 2 + side) * 2 + buf) * it.xwords;
-                for (int ch = wv; ch < nch; ch += nwv) {
-                    const int j = 64 * ch + lane;
-                    const int8_t v = stor[j < n ? j : n - 1];
-                    const unsigned long long m = __ballot(j < n && v > 0);
-                    const int wd = 2 * ch + lane;
-                    if (lane < 2 && wd < nw)
-                        __hip_atomic_store(out + wd, tag | (lane ? (m >> 32) : (m & 0xFFFFFFFFull)),
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int ch0 = wv; ch0 < nch; ch0 += 4 * nwv) {
+                    int8_t v[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {   // four chunks' reads in flight
+                        const int j = 64 * (ch0 + q * nwv) + lane;
+                        v[q] = stor[j < n ? j : n - 1];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int ch = ch0 + q * nwv;
+                        if (ch >= nch) break;
+                        const unsigned long long m = __ballot(64 * ch + lane < n && v[q] > 0);
+                        const int wd = 2 * ch + lane;
+                        if (lane < 2 && wd < nw)
+                            __hip_atomic_store(out + wd, tag | (lane ? (m >> 32) : (m & 0xFFFFFFFFull)),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
                 }
                 if (tid == 0)
                     __hip_atomic_store(out + nw, tag | (uint32_t)c.Elds[st], __ATOMIC_RELAXED,
@@ -1062,7 +1076,7 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                 const uint32_t u_dn = c.usw[(cyc & 1) * 65 + 64];
                 // ---- replica exchange (Eq. 1): the boundary states are published ----
                 // pairs inside the workgroup: exchange labels (lane l decides (l, l+1))
-                const int e_nx = __shfl_down(e, 1), st_nx = __shfl_down(my_st, 1);
+                const int e_nx = from_next_lane(e), st_nx = from_next_lane(my_st);
                 const bool act = lane + 1 < G && (((s0 + lane - first) & 1) == 0);
                 bool acc = false;
                 if (act) {
@@ -1072,8 +1086,8 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                     my_att += 1;
                     my_acc += acc ? 1u : 0u;
                 }
-                const bool acc_pv = (__shfl_up((int)acc, 1) != 0) && lane > 0;
-                const int st_pv = __shfl_up(my_st, 1), e_pv = __shfl_up(e, 1);
+                const bool acc_pv = (from_prev_lane((int)acc) != 0) && lane > 0;
+                const int st_pv = from_prev_lane(my_st), e_pv = from_prev_lane(e);
                 if (acc) {
                     my_st = st_nx;
                     e = e_nx;
@@ -1126,7 +1140,7 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                             }
                         }
                     }
-                    timeout = __shfl(timeout, 0);
+                    timeout = __builtin_amdgcn_readlane(timeout, 0);
                     if (timeout) {
                         if (lane == 0) c.misc[0] = 1;
                     } else {
@@ -1135,13 +1149,13 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                             const uint32_t *stage = c.xstage + side * (nw + 1);
                             const int pE = (int)stage[nw];
                             const int bl = side == 0 ? 0 : G - 1;            // my boundary slot
-                            const int st = __shfl(my_st, bl);
-                            const int myE = __shfl(e, bl);
+                            const int st = __builtin_amdgcn_readlane(my_st, bl);
+                            const int myE = __builtin_amdgcn_readlane(e, bl);
                             const int dE = side == 0 ? myE - pE : pE - myE; // E_{r+1} - E_r
-                            const int off = side == 0 ? dn_off : __shfl(row_off, G - 1);
-                            const int len = side == 0 ? dn_len : __shfl(row_len, G - 1);
+                            const int off = side == 0 ? dn_off : __builtin_amdgcn_readlane(row_off, G - 1);
+                            const int len = side == 0 ? dn_len : __builtin_amdgcn_readlane(row_len, G - 1);
                             const uint32_t T = dE >= 0 ? ALWAYS : (-dE <= len ? c.tsw[off - dE - 1] : 0u);
-                            const uint32_t u = side == 0 ? u_dn : __shfl(u_pair, G - 1);
+                            const uint32_t u = side == 0 ? u_dn : (uint32_t)__builtin_amdgcn_readlane((int)u_pair, G - 1);
                             const bool sacc = (T == ALWAYS || u < T);
                             if (side == 1 && lane == G - 1) {   // the lower workgroup owns the pair's counters
                                 my_att += 1;
@@ -1172,7 +1186,7 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                 bestE = em;
                 bestT = (int64_t)t;
                 bestSlot = s0 + lm;
-                const int st = __shfl(my_st, lm);
+                const int st = __builtin_amdgcn_readlane(my_st, lm);
                 if (lane == 0) c.misc[2] = st + 1;   // the whole block copies it below
             }
         }
