@@ -437,6 +437,8 @@ def tts_study(args, log):
                 star, t_a = tts.tts_star(hits, grid)
                 per[method].append(star * dt)
                 succ[method].append(tts.success_probability(hits, args.tts_tmax))
+                log(f"tts {n_bits}-bit instance {i} {method}: success at t_max {succ[method][-1]:.2f}, "
+                    f"TTS {star * dt:.3g} s")
         for method in ("pt", "tapt"):
             v = np.array(per[method])
             lo, hi = tts.bootstrap_median_ci(v, seed=n_bits)
