@@ -43,6 +43,37 @@ def test_cfg1_full_1000_sweeps_graph():
     compare(ctx, ref)
 
 
+def test_graph_replays_match_eager_after_every_replay():
+    """hipGraph path: each replay (one chunk) is checked against an eager batch
+    of the same contexts, with eager work and synchronisations between replays."""
+    announce("hipGraph replays vs eager batch, EA L=4 R=16 x 3 instances, split ladders, 6 replays")
+    g, b = _cfg1()
+    banks = {r: inputs.random_bank(64, 5, seed=900 + r) for r in range(10)}
+    kw = dict(prop_start=4, prop_period=8)
+    pairs = []
+    for k in range(3):
+        a = binding.Context(g, b, seed=40 + k, **kw)
+        e = binding.Context(g, b, seed=40 + k, **kw)
+        for r, bk in banks.items():
+            a.propose(r, bk)
+            e.propose(r, bk)
+        pairs.append((a, e))
+    bg = binding.Batch([p[0] for p in pairs], replicas_per_wg=5, chunk_sweeps=24, use_graph=True)
+    be = binding.Batch([p[1] for p in pairs], replicas_per_wg=5, chunk_sweeps=24)
+    for rep in range(6):
+        bg.sweep(24)
+        be.sweep(24)
+        for a, e in pairs:
+            sa, ta = a.state()
+            se, te = e.state()
+            assert ta == te == 24 * (rep + 1)
+            assert np.array_equal(sa, se), rep
+            assert np.array_equal(a.energies(), e.energies()), rep
+            assert a.summary()["best"] == e.summary()["best"]
+    bg.close()
+    be.close()
+
+
 @pytest.mark.parametrize("path", ["plain", "batched", "split"])
 def test_proposals(path):
     announce(f"proposals, {path}")
