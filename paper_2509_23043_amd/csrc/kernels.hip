@@ -425,6 +425,37 @@ hipError_t launch_energy(const InstDev *dI, const int8_t *cfg, int k, int32_t *o
     return hipGetLastError();
 }
 
+// Sweep caps of up to CAPS_PER_LAUNCH contexts of a batch, set on the device
+// in one launch (the caps travel as kernel arguments).
+constexpr int CAPS_PER_LAUNCH = 64;
+struct CapSet {
+    InstDev *inst[CAPS_PER_LAUNCH];
+    unsigned long long cap[CAPS_PER_LAUNCH];
+    int n;
+};
+
+__global__ void set_caps_kernel(CapSet cs)
+{
+    const int k = threadIdx.x;
+    if (k < cs.n) cs.inst[k]->sweep_cap = cs.cap[k];
+}
+
+hipError_t launch_set_caps(InstDev *const *insts, const unsigned long long *caps, int n, hipStream_t s)
+{
+    for (int a = 0; a < n; a += CAPS_PER_LAUNCH) {
+        CapSet cs{};
+        cs.n = n - a < CAPS_PER_LAUNCH ? n - a : CAPS_PER_LAUNCH;
+        for (int k = 0; k < cs.n; ++k) {
+            cs.inst[k] = insts[a + k];
+            cs.cap[k] = caps[a + k];
+        }
+        hipLaunchKernelGGL(set_caps_kernel, dim3(1), dim3(CAPS_PER_LAUNCH), 0, s, cs);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_init_best(const InstDev *dI, hipStream_t s)
 {
     hipLaunchKernelGGL(init_best_kernel, dim3(1), dim3(256), 0, s, dI);
