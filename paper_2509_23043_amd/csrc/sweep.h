@@ -230,7 +230,7 @@ struct LatSweep {
             int stor = grp * RPT + k;
             ok[k] = active && stor < G;
             sl[k] = ok[k] ? slot_of[stor] : 0;
-            P4 r = philox((uint32_t)q, t, (uint32_t)(s0 + sl[k]), TAG_SWEEP, I.seed_lo, I.seed_hi);
+            P4 r = philox_v((uint32_t)q, t, (uint32_t)(s0 + sl[k]), TAG_SWEEP, I.seed_lo, I.seed_hi);
 #pragma unroll
             for (int j = 0; j < 4; ++j) w[k][j] = r.v[j];
             dE[k] = 0;
@@ -413,7 +413,7 @@ struct CsrSweepT {
         const int ncall = nr >> 3;
         for (int idx = tid; idx < G * ncall; idx += bs) {
             int k = idx / ncall, q = idx - k * ncall;
-            P4 r = philox((uint32_t)q, t, (uint32_t)(s0 + slot_of[k]), TAG_SWEEP, I.seed_lo, I.seed_hi);
+            P4 r = philox_v((uint32_t)q, t, (uint32_t)(s0 + slot_of[k]), TAG_SWEEP, I.seed_lo, I.seed_hi);
             uint4 v = make_uint4(r.v[0], r.v[1], r.v[2], r.v[3]);
             *(uint4 *)(rnd + (size_t)k * nr + 8 * q) = v;
         }
