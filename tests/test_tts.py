@@ -57,4 +57,3 @@ def test_bootstrap_interval_with_unsolved_instances():
     x = np.array([1.0, 2.0, 3.0, np.inf, np.inf, np.inf, np.inf])
     lo, hi = tts.bootstrap_median_ci(x, n_boot=500, seed=1)
     assert not np.isnan(lo) and hi == np.inf
-
