@@ -139,19 +139,49 @@ int pt_propose_device(pt_ctx *c, double beta, const int8_t *configs_dev, int32_t
  * returns PT_ESTATE (build it again). */
 int pt_set_context(pt_ctx *c, double fraction, int32_t sweeps);
 
-/* Plain path: run n_sweeps sweeps of Algorithm 1 on this context alone with
- * one launch sequence per cycle (sweep kernel, cycle-end kernel). */
+/* Plain path: run n_sweeps more sweeps of Algorithm 1's main loop on this
+ * context alone -- per sweep, one colored local sweep of every replica
+ * (Methods, Eq. 4 and Graph coloring), then at the end of every cycle of
+ * sweeps_per_cycle sweeps the proposal stage (Eq. 2) when the schedule says
+ * so and the alternating-parity exchange stage (Eq. 1) -- with one launch
+ * sequence per sweep (sweep kernel, cycle-end kernel). Blocks until done.
+ * PT_EINVAL if the sweep counter would pass 2^32 - 1 (2^31 - 2 for
+ * independent chains); PT_EUNSUPPORTED with contextual proposals. */
 int pt_sweep(pt_ctx *c, uint64_t n_sweeps);
 
-/* Current replica energies by slot: host [R]. */
+/* Current replica energies E(S_r) by slot (the energies Algorithm 1 holds
+ * at the end of a cycle; Supp. S4 convention): host [R] int32, written
+ * before the call returns. */
 int pt_energies(pt_ctx *c, int32_t *out);
-/* Current spins by slot: host [R][n]; sweep counter to *t if non-NULL. */
+/* Current replica states S_r by slot (Algorithm 1's output): host [R][n]
+ * int8 +-1, row r = slot r; the completed sweep count to *t if non-NULL.
+ * spins may be NULL to read t alone. */
 int pt_state(pt_ctx *c, int8_t *spins, uint64_t *t);
 /* Same into device memory [R][n]. */
 int pt_state_device(pt_ctx *c, int8_t *spins_dev);
-/* Replace the state (resume): host [R][n] spins and sweep counter t. The
- * counters restart at zero; energies are recomputed. */
+/* Replace the spins (a fresh chain from a given state): host [R][n] spins
+ * and sweep counter t. The counters and the best record restart; energies
+ * are recomputed; bank cursors keep their values. For an exact resume use
+ * pt_save / pt_restore. */
 int pt_set_state(pt_ctx *c, const int8_t *spins, uint64_t t);
+
+/* Checkpoint and resume. pt_save writes the whole chain state of a context
+ * into a host buffer of pt_save_size bytes: spins and energies by slot, the
+ * sweep counter, every bank cursor, the swap, proposal and flip counters and
+ * the best record (energy, sweep, slot, first hit, configuration). Since
+ * every random number is keyed by (seed, site, sweep, slot), pt_restore into
+ * a context created with the same problem, ladder, options and seed, with
+ * banks of the same sizes installed (the same banks, for the same chain) and
+ * the same proposal mode, continues Algorithm 1 bit for bit as if the run had
+ * never stopped, on any path (plain, batched, served). pt_restore checks the
+ * blob's format, shape and fingerprint (problem, ladder, options, seed, bank
+ * sizes, proposal mode), the spins (+-1, clamps), the cursors and that the
+ * energies are those of the spins; on any mismatch it returns PT_EINVAL and
+ * leaves the context unchanged. The blob is plain host memory in the
+ * machine's byte order, owned by the caller. */
+int pt_save_size(pt_ctx *c, uint64_t *bytes);
+int pt_save(pt_ctx *c, void *buf, uint64_t bytes);
+int pt_restore(pt_ctx *c, const void *buf, uint64_t bytes);
 
 /* Summary and counters. swap_att/swap_acc: host [R-1] per pair (r, r+1);
  * prop_att/prop_acc/flips: host [R]; any may be NULL. best_spins: host [n]

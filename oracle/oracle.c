@@ -220,7 +220,7 @@ static void track_best(const orc_problem *P, orc_state *S)
     if (P->has_target && S->first_hit < 0 && lo <= P->target) S->first_hit = (int64_t)S->t;
 }
 
-/* "Initialize replica states {S_r} randomly" (Algorithm 1). Clamped spins
+/* Random initial replica states (Algorithm 1, initialisation step). Clamped spins
  * take their clamp value. Counters and bank cursors start here too. */
 int orc_init(const orc_problem *P, orc_state *S)
 {
@@ -333,7 +333,7 @@ int orc_run(const orc_problem *P, orc_state *S, uint64_t n_sweeps)
         S->t = t;
         if (P->M > 0 && t % (uint64_t)P->M == 0) {
             uint64_t cyc = t / (uint64_t)P->M; /* cycle n of Algorithm 1, 1-based */
-            /* "Compute E(S_r) for all replicas" */
+            /* energies of all replicas (Algorithm 1, cycle-end energy step) */
             for (int32_t r = 0; r < R; ++r) {
                 int64_t e = orc_energy(P, S->spins + (size_t)r * n);
                 if (P->check_energy && e != S->E[r]) S->energy_mismatch++;

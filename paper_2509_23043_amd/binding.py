@@ -75,7 +75,8 @@ class _ServeStats(C.Structure):
 
 
 EXPORTS = ["pt_create", "pt_destroy", "pt_propose", "pt_propose_device", "pt_set_context", "pt_sweep", "pt_energies",
-           "pt_state", "pt_state_device", "pt_set_state", "pt_summary_get", "pt_counters",
+           "pt_state", "pt_state_device", "pt_set_state", "pt_save_size", "pt_save", "pt_restore",
+           "pt_summary_get", "pt_counters",
            "pt_energy_device", "pt_set_stream", "pt_batch_create", "pt_batch_sweep", "pt_batch_destroy",
            "pt_batch_set_stream", "pt_batch_kernel_time", "pt_serve_start", "pt_serve_register",
            "pt_serve_submit", "pt_serve_poll", "pt_serve_stats_get", "pt_serve_clock", "pt_serve_stop",
@@ -107,6 +108,9 @@ def lib():
     L.pt_state.argtypes = [vp, C.POINTER(C.c_int8), C.POINTER(C.c_uint64)]
     L.pt_state_device.argtypes = [vp, vp]
     L.pt_set_state.argtypes = [vp, C.POINTER(C.c_int8), C.c_uint64]
+    L.pt_save_size.argtypes = [vp, C.POINTER(C.c_uint64)]
+    L.pt_save.argtypes = [vp, vp, C.c_uint64]
+    L.pt_restore.argtypes = [vp, vp, C.c_uint64]
     L.pt_summary_get.argtypes = [vp, C.POINTER(_Summary), C.POINTER(C.c_int8)]
     L.pt_counters.argtypes = [vp] + [C.POINTER(C.c_uint64)] * 5
     L.pt_energy_device.argtypes = [vp, vp, C.c_int32, vp]
@@ -241,6 +245,19 @@ class Context:
     def set_state(self, spins, t):
         s = np.ascontiguousarray(spins, np.int8)
         _check(lib().pt_set_state(self.h, _p(s, C.c_int8), int(t)))
+
+    def save(self):
+        """Checkpoint of the whole chain state (pt_save) as bytes."""
+        nb = C.c_uint64()
+        _check(lib().pt_save_size(self.h, C.byref(nb)))
+        buf = C.create_string_buffer(nb.value)
+        _check(lib().pt_save(self.h, buf, nb.value))
+        return buf.raw
+
+    def restore(self, blob):
+        """Resume from a checkpoint taken by save() (pt_restore)."""
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        _check(lib().pt_restore(self.h, buf, len(blob)))
 
     def summary(self):
         s = _Summary()

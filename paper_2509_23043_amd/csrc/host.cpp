@@ -108,14 +108,26 @@ static double flip_probability(int rule, double beta, long long dE)
     return std::exp(-(beta * (double)dE));
 }
 
-// entries T(exp(-a d)) for d = 1, 2, ... up to the last nonzero one
-static void tail_table(double a, std::vector<uint32_t> &out)
+// Longest single proposal or swap table, and the most entries all of a
+// context's tables may hold together. A table is never truncated: a cut
+// table would reject moves whose probability is not zero.
+static const size_t TAIL_TABLE_MAX = (size_t)1 << 22;
+static const size_t TAIL_TABLES_TOTAL_MAX = (size_t)1 << 26;
+
+// Appends the entries T(exp(-a d)) for d = 1, 2, ... up to the last nonzero
+// one. Returns false, leaving `out` as it was, if that table would be longer
+// than TAIL_TABLE_MAX or push `out` past TAIL_TABLES_TOTAL_MAX.
+static bool tail_table(double a, std::vector<uint32_t> &out)
 {
+    const size_t start = out.size();
     for (long long d = 1;; ++d) {
         uint32_t T = threshold(std::exp(-(a * (double)d)));
-        if (T == 0) break;
+        if (T == 0) return true;
+        if (out.size() - start >= TAIL_TABLE_MAX || out.size() >= TAIL_TABLES_TOTAL_MAX) {
+            out.resize(start);
+            return false;
+        }
         out.push_back(T);
-        if (out.size() > (1u << 22)) break;
     }
 }
 
@@ -172,6 +184,7 @@ struct pt_ctx {
     pt_opts opts{};
     std::vector<int8_t> clamp;
     int64_t nfree = 0;
+    uint64_t problem_fp = 0;          // FNV-1a of the problem, ladder, options and seed
 
     // device allocations
     DevBuf J3, row_ptr, col, Jc, h, clampd, color_sites, color_off;
@@ -232,6 +245,23 @@ static hipError_t upload(DevBuf &b, const std::vector<T> &v, hipStream_t s)
 
 // ---------------------------------------------------------------------------
 // problem validation and preparation
+
+// 64-bit FNV-1a, used to fingerprint a context for its checkpoints
+struct Fnv {
+    uint64_t h = 1469598103934665603ull;
+    void add(const void *p, size_t bytes)
+    {
+        const unsigned char *b = (const unsigned char *)p;
+        for (size_t k = 0; k < bytes; ++k) h = (h ^ b[k]) * 1099511628211ull;
+    }
+    template <class T> void add(const std::vector<T> &v)
+    {
+        uint64_t k = v.size();
+        add(&k, sizeof k);
+        if (!v.empty()) add(v.data(), v.size() * sizeof(T));
+    }
+    template <class T> void val(T x) { add(&x, sizeof x); }
+};
 
 struct Prepared {
     int kind, L, n, D, ncolors;
@@ -464,20 +494,24 @@ extern "C" int pt_create(const pt_graph *g, const double *betas, int32_t R, cons
     c->opts = *o;
     c->clamp = P.clamp;
     c->nfree = P.nfree;
+    {
+        Fnv f;
+        f.val(P.kind); f.val(P.L); f.val(P.n); f.val(P.D); f.val(P.ncolors);
+        f.add(P.J3); f.add(P.row_ptr); f.add(P.col); f.add(P.Jc); f.add(P.h); f.add(P.clamp);
+        f.add(P.color_sites); f.add(P.color_off); f.add(c->betas);
+        f.val(o->rule); f.val(o->sweeps_per_cycle); f.val(o->prop_start); f.val(o->prop_period);
+        f.val(o->prop_stop); f.val(o->seed); f.val(o->has_target); f.val(o->target);
+        c->problem_fp = f.h;
+    }
     c->pmJ = P.kind == KIND_LATTICE && P.L == 8 && P.D == 6 && R % 2 == 0;
     for (int8_t j : P.J3)
         if (j != 1 && j != -1) c->pmJ = false;
     auto bail = [&](int code) {
+        if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return code;
     };
-    if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(PT_EDEVICE, "no HIP device"));
-    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
-        return bail(fail(PT_EDEVICE, "stream creation failed"));
-    c->own_stream = true;
-    hipStream_t s = c->stream;
-
-    // tables
+    // tables (on the host, before any device call)
     const int stride = 2 * P.D + 1;
     std::vector<uint32_t> tflip((size_t)R * stride);
     for (int r = 0; r < R; ++r)
@@ -487,14 +521,25 @@ extern "C" int pt_create(const pt_graph *g, const double *betas, int32_t R, cons
     std::vector<int32_t> tprop_off(R), tprop_len(R), tswap_off(std::max(R - 1, 1)), tswap_len(std::max(R - 1, 1));
     for (int r = 0; r < R; ++r) {
         tprop_off[r] = (int32_t)tprop.size();
-        tail_table(betas[r], tprop);
+        if (!tail_table(betas[r], tprop))
+            return bail(fail(PT_EUNSUPPORTED, "proposal table of slot %d (beta %g) has more than %zu entries "
+                             "(or all tables more than %zu)", r, betas[r], TAIL_TABLE_MAX, TAIL_TABLES_TOTAL_MAX));
         tprop_len[r] = (int32_t)tprop.size() - tprop_off[r];
     }
     for (int r = 0; r + 1 < R; ++r) {
         tswap_off[r] = (int32_t)tswap.size();
-        if (!independent) tail_table(betas[r + 1] - betas[r], tswap);
+        if (!independent && !tail_table(betas[r + 1] - betas[r], tswap))
+            return bail(fail(PT_EUNSUPPORTED, "swap table of pair (%d, %d) (beta gap %g) has more than %zu entries "
+                             "(or all tables more than %zu)", r, r + 1, betas[r + 1] - betas[r], TAIL_TABLE_MAX,
+                             TAIL_TABLES_TOTAL_MAX));
         tswap_len[r] = (int32_t)tswap.size() - tswap_off[r];
     }
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(PT_EDEVICE, "no HIP device"));
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(PT_EDEVICE, "stream creation failed"));
+    c->own_stream = true;
+    hipStream_t s = c->stream;
+
     if (tprop.empty()) tprop.push_back(0);
     if (tswap.empty()) tswap.push_back(0);
 
@@ -792,6 +837,169 @@ extern "C" int pt_counters(pt_ctx *c, uint64_t *swap_att, uint64_t *swap_acc, ui
     if (prop_acc) HIPCHK(hipMemcpyAsync(prop_acc, c->prop_acc.p, R * 8, hipMemcpyDeviceToHost, s));
     if (flips) HIPCHK(hipMemcpyAsync(flips, c->flips.p, R * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    return PT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// checkpoints: the whole chain state of a context as one host blob
+
+namespace {
+struct CkptHeader {
+    char magic[8];            // "TAPTCKP" + format version byte
+    uint64_t bytes;           // whole blob
+    uint64_t fingerprint;     // problem, ladder, options, seed, bank sizes, proposal mode
+    int32_t n, R;
+    uint64_t t;
+    BestRec best;
+};
+const char CKPT_MAGIC[8] = {'T', 'A', 'P', 'T', 'C', 'K', 'P', 1};
+
+// Layout after the header, each array in slot order: int32 E[R],
+// int32 cursor[R], uint64 swap_att[P], swap_acc[P] (P = max(R - 1, 1)),
+// uint64 prop_att[R], prop_acc[R], flips[R], int8 spins[R][n], int8 best_spins[n].
+uint64_t ckpt_bytes(int R, int n)
+{
+    uint64_t P = (uint64_t)std::max(R - 1, 1);
+    return sizeof(CkptHeader) + 8ull * R + 16ull * P + 24ull * R + (uint64_t)R * n + (uint64_t)n;
+}
+} // namespace
+
+// what a checkpoint must match: the problem and options fixed at creation,
+// the bank sizes and the contextual-proposal mode
+static uint64_t ckpt_fingerprint(const pt_ctx *c)
+{
+    Fnv f;
+    f.val(c->problem_fp);
+    f.add(c->h_bank_n);
+    f.val(c->hI.ctx_T);
+    f.val(c->hI.ctx_sweeps);
+    return f.h;
+}
+
+extern "C" int pt_save_size(pt_ctx *c, uint64_t *bytes)
+{
+    if (!c) return fail(PT_EINVAL, "null context");
+    if (!bytes) return fail(PT_EINVAL, "null output");
+    *bytes = ckpt_bytes(c->R, c->n);
+    return PT_OK;
+}
+
+extern "C" int pt_save(pt_ctx *c, void *buf, uint64_t bytes)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    const int R = c->R, n = c->n;
+    const size_t P = (size_t)std::max(R - 1, 1);
+    if (!buf) return fail(PT_EINVAL, "null buffer");
+    if (bytes < ckpt_bytes(R, n)) return fail(PT_EINVAL, "checkpoint needs %llu bytes (got %llu)",
+                                               (unsigned long long)ckpt_bytes(R, n), (unsigned long long)bytes);
+    hipStream_t s = c->stream;
+    CkptHeader hd;
+    memset(&hd, 0, sizeof hd);
+    memcpy(hd.magic, CKPT_MAGIC, 8);
+    hd.bytes = ckpt_bytes(R, n);
+    hd.fingerprint = ckpt_fingerprint(c);
+    hd.n = n;
+    hd.R = R;
+    char *q = (char *)buf + sizeof hd;
+    unsigned long long tt = 0;
+    HIPCHK(hipMemcpyAsync(&tt, c->t.p, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hd.best, c->best.p, sizeof(BestRec), hipMemcpyDeviceToHost, s));
+    auto take = [&](const DevBuf &b, size_t nbytes) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(q, b.p, nbytes, hipMemcpyDeviceToHost, s);
+        q += nbytes;
+        return e;
+    };
+    HIPCHK(take(c->E, 4 * (size_t)R));
+    HIPCHK(take(c->cursor, 4 * (size_t)R));
+    HIPCHK(take(c->swap_att, 8 * P));
+    HIPCHK(take(c->swap_acc, 8 * P));
+    HIPCHK(take(c->prop_att, 8 * (size_t)R));
+    HIPCHK(take(c->prop_acc, 8 * (size_t)R));
+    HIPCHK(take(c->flips, 8 * (size_t)R));
+    HIPCHK(take(c->spins, (size_t)R * n));
+    HIPCHK(take(c->best_spins, (size_t)n));
+    HIPCHK(hipStreamSynchronize(s));
+    hd.t = tt;
+    memcpy(buf, &hd, sizeof hd);
+    return PT_OK;
+}
+
+extern "C" int pt_restore(pt_ctx *c, const void *buf, uint64_t bytes)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    const int R = c->R, n = c->n;
+    const size_t P = (size_t)std::max(R - 1, 1);
+    if (!buf) return fail(PT_EINVAL, "null buffer");
+    if (bytes < sizeof(CkptHeader)) return fail(PT_EINVAL, "checkpoint too short");
+    CkptHeader hd;
+    memcpy(&hd, buf, sizeof hd);
+    if (memcmp(hd.magic, CKPT_MAGIC, 8)) return fail(PT_EINVAL, "not a checkpoint of this format");
+    if (hd.n != n || hd.R != R || hd.bytes != ckpt_bytes(R, n) || bytes < hd.bytes)
+        return fail(PT_EINVAL, "checkpoint shape (n=%d, R=%d, %llu bytes) does not fit this context", hd.n, hd.R,
+                    (unsigned long long)hd.bytes);
+    if (hd.fingerprint != ckpt_fingerprint(c))
+        return fail(PT_EINVAL, "checkpoint was taken on a different problem, ladder, options, seed, bank sizes "
+                               "or proposal mode");
+    if (hd.t > sweep_limit(c)) return fail(PT_EINVAL, "checkpoint sweep counter out of range");
+    const char *q = (const char *)buf + sizeof hd;
+    std::vector<int32_t> E(R), cursor(R);
+    memcpy(E.data(), q, 4 * (size_t)R);
+    memcpy(cursor.data(), q + 4 * (size_t)R, 4 * (size_t)R);
+    const char *counters = q + 8 * (size_t)R;
+    const size_t counter_bytes = 16 * P + 24 * (size_t)R;
+    const int8_t *spins = (const int8_t *)(counters + counter_bytes);
+    const int8_t *bspins = spins + (size_t)R * n;
+    for (int r = 0; r < R; ++r)
+        if (c->h_bank_n[r] ? (cursor[r] < 0 || cursor[r] >= c->h_bank_n[r]) : cursor[r] < 0)
+            return fail(PT_EINVAL, "checkpoint cursor of slot %d out of range", r);
+    for (size_t k = 0; k < (size_t)R * n + n; ++k) {
+        int v = spins[k];
+        int i = (int)(k % n);
+        if ((v != 1 && v != -1) || (c->clamp[i] && v != c->clamp[i]))
+            return fail(PT_EINVAL, "checkpoint spin %zu is invalid", k);
+    }
+    // the energies must be those of the spins: recompute them aside first,
+    // so that a corrupt checkpoint leaves the context as it was
+    hipStream_t s = c->stream;
+    DevBuf tmp_spins, tmp_E;
+    HIPCHK(tmp_spins.alloc((size_t)R * n));
+    HIPCHK(tmp_E.alloc(4 * (size_t)R));
+    HIPCHK(hipMemcpyAsync(tmp_spins.p, spins, (size_t)R * n, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_energy(c->inst.as<InstDev>(), tmp_spins.as<int8_t>(), R, tmp_E.as<int32_t>(), s));
+    std::vector<int32_t> E_dev(R);
+    HIPCHK(hipMemcpyAsync(E_dev.data(), tmp_E.p, 4 * (size_t)R, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (E_dev != E) return fail(PT_EINVAL, "checkpoint energies do not match its spins");
+    unsigned long long tt = hd.t;
+    const char *cq = counters;
+    auto put = [&](DevBuf &b, size_t nbytes) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(b.p, cq, nbytes, hipMemcpyHostToDevice, s);
+        cq += nbytes;
+        return e;
+    };
+    hipError_t e = hipMemcpyAsync(c->spins.p, tmp_spins.p, (size_t)R * n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->E.p, tmp_E.p, 4 * (size_t)R, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->cursor.p, cursor.data(), 4 * (size_t)R, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = put(c->swap_att, 8 * P);
+    if (e == hipSuccess) e = put(c->swap_acc, 8 * P);
+    if (e == hipSuccess) e = put(c->prop_att, 8 * (size_t)R);
+    if (e == hipSuccess) e = put(c->prop_acc, 8 * (size_t)R);
+    if (e == hipSuccess) e = put(c->flips, 8 * (size_t)R);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->best_spins.p, bspins, (size_t)n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->best.p, &hd.best, sizeof(BestRec), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->t.p, &tt, 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        c->hI.epoch += 1;       // batches clear their exchange words for the new state
+        e = hipMemcpyAsync(c->inst.p, &c->hI, sizeof(InstDev), hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        c->broken = true;
+        return fail(PT_EDEVICE, "restore: %s", hipGetErrorString(e));
+    }
+    c->t_host = hd.t;
     return PT_OK;
 }
 

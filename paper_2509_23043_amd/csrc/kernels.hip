@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(256) plain_tail_kernel(const InstDev *Ip, uint
 }
 
 // ---------------------------------------------------------------------------
-// Initialization ("Initialize replica states randomly", Algorithm 1): spin i
+// Initialization (Algorithm 1, random initial replica states): spin i
 // of slot r is +1 iff word (i & 3) of Philox(i >> 2, 0, r, INIT) >= 2^31;
 // clamped sites take their clamp value.
 __global__ void init_kernel(const InstDev *Ip)

@@ -55,3 +55,20 @@ def test_product_does_not_import_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "oracle.c" not in text and "liboracle" not in text, f
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libtapt.so not built")
+def test_overlong_acceptance_table_is_refused_not_truncated():
+    """A swap table longer than the library's cap (a ladder spaced by 1e-6,
+    whose Eq. 1 table runs to about 2.2e7 entries) makes pt_create fail with
+    PT_EUNSUPPORTED. The tables are built on the host before any device call,
+    so this runs without a GPU."""
+    import numpy as np
+
+    from paper_2509_23043_amd import binding, inputs
+    g = inputs.ea_lattice(4, 1)
+    betas = 1.0 + 1e-6 * np.arange(4)
+    with pytest.raises(binding.TaptError) as e:
+        binding.Context(g, betas, seed=1)
+    assert e.value.code == binding.PT_EUNSUPPORTED
+    assert "swap table of pair (0, 1)" in str(e.value)
