@@ -11,8 +11,12 @@ Algorithm 1: sweeps, proposal stages, swap stages, best tracking); the default
 
 Prints one JSON line: batched attempts/ns (value), the plain
 one-instance-per-launch path on the same chain (bit-identical final state),
-the ALU roofline of the chunk kernel from HIP events, and the CPU oracle
-baseline on this host.
+the LDS roofline of the chunk kernel (with the ALU one beside it) from HIP
+events, and the CPU oracle baseline on every core of this host. Beside it:
+the mixed-size workload (40 EA instances, L = 6..16, R = 24..48, 10^5
+sweeps, autotuned tiling), the factorization workload (64 8x8-bit
+multipliers, R = 32, 10^4 sweeps, then time to the ground energy) and the
+continuous-batching server under Poisson arrivals.
 """
 import argparse
 import hashlib
@@ -36,7 +40,38 @@ METRIC = "spin-flip attempts/ns (batched vs plain) + p50/p99 time-to-target per 
 OPS_PER_ATTEMPT = 6 + 2 + 7.5 + 3
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12       # int32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 LDS_BYTES_PER_ATTEMPT = 14                       # 6 neighbour spins + 6 couplings + own spin read + write
-LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12          # 128 B/clk/CU
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12          # 128 B/clk/CU x 256 CUs x 2.4 GHz
+LDS_PEAK_SOURCE = "128 B/clk/CU (the CDNA3 LDS figure) x 256 CUs x 2.4 GHz"
+HBM_PEAK_TBS = 8.0
+
+
+def csr_bytes_per_attempt(problem):
+    """Algorithmic LDS bytes of one attempt on a general sparse graph: per
+    bond the neighbour spin (1 B), the coupling (1 B) and its int16 index
+    (2 B), plus the own spin read and write, averaged over the free sites."""
+    rp = np.asarray(problem["row_ptr"])
+    free = np.asarray(problem["clamp"]) == 0
+    deg = np.diff(rp)[free]
+    return float(4 * deg.mean() + 2)
+
+
+def rooflines(attempts_per_launch, avg_ms, lds_bytes, ops=OPS_PER_ATTEMPT, traffic=None, kernel=None):
+    """LDS roofline (the target bound) with the ALU one beside it, for one
+    kernel: algorithmic bytes / ops per launch over the measured launch time."""
+    sec = avg_ms * 1e-3
+    lds = lds_bytes * attempts_per_launch / sec / 1e12
+    alu = ops * attempts_per_launch / sec / 1e12
+    fr = dict(lds=lds / LDS_PEAK_TBS, alu=alu / VALU_PEAK_TOPS)
+    if traffic is not None:
+        fr["hbm"] = traffic / sec / 1e12 / HBM_PEAK_TBS
+    return dict(bound="lds", achieved=round(lds, 3), peak=round(LDS_PEAK_TBS, 1), unit="TB/s",
+                frac=round(lds / LDS_PEAK_TBS, 4), traffic=traffic, kernel=kernel, avg_launch_ms=round(avg_ms, 4),
+                bytes_per_attempt=round(lds_bytes, 2), peak_source=LDS_PEAK_SOURCE,
+                alu=dict(achieved=round(alu, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TOP/s",
+                         frac=round(alu / VALU_PEAK_TOPS, 4), ops_per_attempt=ops,
+                         peak_source="64 int32 lanes/clk/CU x 256 CUs x 2.4 GHz"),
+                measured_binding=max(fr, key=fr.get),
+                fractions={k: round(v, 4) for k, v in fr.items()})
 
 
 def parse():
@@ -49,8 +84,10 @@ def parse():
     ap.add_argument("--L", type=int, default=8)
     ap.add_argument("--R", type=int, default=32)
     ap.add_argument("--bank", type=int, default=256)
-    ap.add_argument("--workload", default="pt", choices=("pt", "bankgen-sg", "bankgen-fact", "tts", "context"),
-                    help="pt: the batched PT benchmark (default); bankgen-*: the long-run MCMC bank "
+    ap.add_argument("--workload", default="pt",
+                    choices=("pt", "mixed", "fact", "bankgen-sg", "bankgen-fact", "tts", "context"),
+                    help="pt: the batched PT benchmark (default); mixed / fact: only the mixed-size or the "
+                         "factorization leg (for profiling); bankgen-*: the long-run MCMC bank "
                          "generation of Supp. Table S3 (3D spin glass L=10, or 16-bit factorization); "
                          "tts: the factorization TTS study; context: the proposal-context ablation")
     ap.add_argument("--ctx-instances", type=int, default=16, help="context: spin-glass instances")
@@ -77,9 +114,15 @@ def parse():
     ap.add_argument("--cpu-sweeps", type=int, default=1500)
     ap.add_argument("--calib-copy", action="store_true", help="also run a 256 MiB device copy (PMC scaling)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size workload")
+    ap.add_argument("--no-fact", action="store_true", help="skip the factorization workload")
+    ap.add_argument("--mixed-sweeps", type=int, default=100_000, help="mixed: timed sweeps")
     ap.add_argument("--serve-rates", default="10,30,100,300,1000", help="Poisson arrival rates, req/s")
-    ap.add_argument("--serve-requests", default="30,60,150,300,500", help="requests per rate")
-    ap.add_argument("--serve-cap", type=int, default=20_000, help="sweep cap per request")
+    ap.add_argument("--serve-requests", default="1000,1000,1000,1000,1000", help="requests per rate")
+    ap.add_argument("--serve-cap", type=int, default=100_000, help="sweep cap per request")
+    ap.add_argument("--serve-ref-runs", type=int, default=8,
+                    help="independent PT runs per spin-glass instance that set its reference energy")
+    ap.add_argument("--serve-ref-sweeps", type=int, default=50_000, help="sweeps of each reference run")
     ap.add_argument("--serve-chunk", type=int, default=250, help="sweeps per serving round")
     ap.add_argument("--bank-cache", default=None,
                     help="file to save the generated banks to, or load them from when it exists")
@@ -121,10 +164,11 @@ def make_banks(probs, betas, B, n_prop_slots, log):
 
 
 def build_contexts(probs, betas, bank, seeds, M=1):
-    from paper_2509_23043_amd import binding
+    from paper_2509_23043_amd import binding, workloads
     ctxs = []
     for i, p in enumerate(probs):
-        c = binding.Context(p, betas, seed=seeds[i], M=M, prop_start=100, prop_period=100)
+        c = binding.Context(p, betas, seed=seeds[i], M=M, prop_start=100, prop_period=100,
+                            target=workloads.ea_target(p["n"]))
         for r in range(bank.shape[1]):
             c.propose_device(r, bank[i, r].data_ptr(), bank.shape[2])
         ctxs.append(c)
@@ -156,23 +200,38 @@ def _cpu_worker(args):
     return time.perf_counter() - t0, sweeps * R * L ** 3
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(bank_host, L, R, sweeps, log):
-    workers = max(1, min(16, os.cpu_count() or 1, len(bank_host)))
-    jobs = [(i, L, R, 3000 + i, bank_host[i], sweeps) for i in range(workers)]
+    """The oracle on every core this process may use: one process per core,
+    each running one instance of the workload (instance i % 64 with its bank),
+    timed from the first start to the last finish."""
+    cores = len(os.sched_getaffinity(0))
+    jobs = [(i % len(bank_host), L, R, 3000 + i, bank_host[i % len(bank_host)], sweeps) for i in range(cores)]
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
-    with ctx.Pool(workers) as pool:
+    with ctx.Pool(cores) as pool:
         out = pool.map(_cpu_worker, jobs)
     wall = time.perf_counter() - t0
     attempts = sum(a for _, a in out)
     single = np.mean([a / t for t, a in out]) / 1e9
     rate = attempts / max(t for t, _ in out) / 1e9
-    log(f"cpu oracle: {workers} processes, {attempts:.3g} attempts, {wall:.1f} s wall, "
-        f"{rate:.4f} attempts/ns ({single:.4f} per core)")
-    return dict(value=round(rate, 5), unit="attempts/ns", cores=workers, kind="oracle",
-                single_core_value=round(single, 5),
-                sample=f"{workers} instances (one per process) of the same workload, {sweeps} sweeps each "
-                       f"with proposals every 100 sweeps, banks as on the GPU")
+    log(f"cpu oracle: {cores} processes on {cores} cores ({cpu_model()}), {attempts:.3g} attempts, "
+        f"{wall:.1f} s wall, {rate:.4f} attempts/ns ({single:.4f} per core)")
+    return dict(value=round(rate, 5), unit="attempts/ns", cores=cores, processes=cores, cpu_model=cpu_model(),
+                kind="oracle", single_core_value=round(single, 5),
+                cpu_seconds=round(sum(t for t, _ in out), 1),
+                sample=f"{cores} instances (one oracle process per core), {sweeps} sweeps each of the same "
+                       f"workload with proposals every 100 sweeps and the GPU run's banks")
 
 
 KERNEL_SOURCES = {"pm": "kernels_pm.hip", "pm1": "kernels_pm.hip", "wave": "kernels_wave.hip", "block": "kernels.hip"}
@@ -205,7 +264,182 @@ def traffic_from_profiles(launch_sweeps, kern_hash, kern):
     return d.get("hbm_bytes_per_launch")
 
 
-def serving_pool(log):
+def pt_banks(cases, B, log, seed0, burn=10_000, every=100):
+    """Banks [n_prop, B, n] (device tensors, one per case) from plain-PT runs
+    of each instance with no proposals: ``burn`` sweeps, then one sample of
+    every banked slot every ``every`` sweeps. One batch for all the cases."""
+    import torch
+    from paper_2509_23043_amd import binding
+    gens = [binding.Context(c["g"], c["betas"], seed=seed0 + c["k"]) for c in cases]
+    bt = binding.Batch(gens, chunk_sweeps=2000)
+    bt.sweep(burn)
+    banks = [torch.empty((c["n_prop"], B, c["g"]["n"]), dtype=torch.int8, device="cuda") for c in cases]
+    tmp = [torch.empty((len(c["betas"]), c["g"]["n"]), dtype=torch.int8, device="cuda") for c in cases]
+    for k in range(B):
+        bt.sweep(every)
+        for c, g, t, b in zip(cases, gens, tmp, banks):
+            g.state_device(t.data_ptr())
+            b[:, k, :] = t[:c["n_prop"]]
+    torch.cuda.synchronize()
+    bt.close()
+    for g in gens:
+        g.close()
+    log(f"banks: {len(cases)} instances x {B} configs per banked slot")
+    return banks
+
+
+def case_contexts(cases, cfg, banks, M=1, target=True):
+    from paper_2509_23043_amd import binding, workloads
+    ctxs = []
+    for c, b in zip(cases, banks if banks is not None else [None] * len(cases)):
+        kw = workloads.run_kwargs(cfg, c)
+        kw["M"] = M
+        if not target:
+            kw.pop("target")
+        ctx = binding.Context(c["g"], c["betas"], seed=c["seed"], **kw)
+        if b is not None:
+            for r in range(b.shape[0]):
+                ctx.propose_device(r, b[r].data_ptr(), b.shape[1])
+        ctxs.append(ctx)
+    return ctxs
+
+
+def timed_batch(ctxs, tiling, sweeps, chunk, warm_chunks=1):
+    """attempts/ns of a batch over ``sweeps`` sweeps after a warm-up, with the
+    chunk kernel's average launch time from its HIP events."""
+    import torch
+    from paper_2509_23043_amd import binding
+    G, rpt, kern = tiling
+    bt = binding.Batch(ctxs, replicas_per_wg=G, replicas_per_thread=rpt, chunk_sweeps=chunk, kernel=kern)
+    for _ in range(warm_chunks):
+        bt.sweep(chunk)
+    torch.cuda.synchronize()
+    bt.kernel_time()
+    t0 = time.perf_counter()
+    bt.sweep(sweeps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms, launches = bt.kernel_time()
+    bt.close()
+    att = sweeps * sum(c.R * c.nfree for c in ctxs)
+    return dict(value=att / dt / 1e9, seconds=dt, attempts=att, avg_ms=ms / max(launches, 1), launches=launches)
+
+
+def tuned_tiling(cases, cfg, log):
+    from paper_2509_23043_amd import autotune
+    res = autotune.tune(lambda M: case_contexts(cases, cfg, None, M=M), Ms=(1,), warm=200, timed=1000, log=log)
+    return (res["replicas_per_wg"], res["replicas_per_thread"], res["kernel"]), res["scan"]
+
+
+def mixed_leg(args, log):
+    """The mixed-size workload: 40 EA +-J instances (8 each of L = 6, 8, 10,
+    12, 16 with ladders of 24..48 slots) in one persistent launch sequence,
+    10^5 sweeps, proposals every 50 sweeps from 256-entry plain-PT banks on
+    all but the two coldest slots, tiling from the autotuner (M = 1)."""
+    from paper_2509_23043_amd import workloads
+    cfg = workloads.CFG3
+    cases = workloads.ea_cases(cfg)
+    t0 = time.perf_counter()
+    banks = pt_banks(cases, cfg["B"], log, seed0=1_300_000)
+    log(f"mixed: banks in {time.perf_counter() - t0:.1f} s")
+    tiling, scan = tuned_tiling(cases, cfg, log)
+    ctxs = case_contexts(cases, cfg, banks)
+    r = timed_batch(ctxs, tiling, args.mixed_sweeps, cfg["chunk"])
+    for c in ctxs:
+        c.close()
+    log(f"mixed: {r['value']:.1f} attempts/ns over {args.mixed_sweeps} sweeps, tiling {tiling}, "
+        f"chunk kernel {r['avg_ms']:.3f} ms avg")
+    roof = rooflines(r["attempts"] / max(r["launches"], 1), r["avg_ms"], LDS_BYTES_PER_ATTEMPT,
+                     kernel="chunk_kernel_mixed" if tiling[2] in ("auto", "block") else tiling[2])
+    return dict(value=round(r["value"], 2), unit="attempts/ns", sweeps=args.mixed_sweeps,
+                seconds=round(r["seconds"], 3), attempts_per_sweep=sum(len(c["betas"]) * c["g"]["n"] for c in cases),
+                instances=len(cases), sizes=[list(x) for x in cfg["sizes"]], sweeps_per_swap=1,
+                tiling=dict(replicas_per_wg=tiling[0], replicas_per_thread=tiling[1], kernel=tiling[2]),
+                tiling_scan=[dict(G=d["replicas_per_wg"], rpt=d["replicas_per_thread"], kernel=d["kernel"],
+                                  attempts_per_ns=d["attempts_per_ns"]) for d in scan],
+                roofline=roof,
+                workload="3D EA +-J L in {6,8,10,12,16} x 8 instances, R = 24/30/36/42/48 beta 0.2..3.0 "
+                         "geometric, Metropolis, M=1, proposals every 50 sweeps from 256-entry plain-PT banks "
+                         "on all but the 2 coldest slots; one persistent launch sequence of 10^4-sweep launches")
+
+
+def factorization_leg(args, log):
+    """The factorization workload: 64 distinct products of two primes in
+    [128, 256) as 8x8-bit multipliers (200 spins, 176 free), R = 32,
+    proposals every 100 sweeps from 256-entry plain-PT banks on the 23
+    hottest slots. Throughput over 10^4 sweeps; then fresh runs until every
+    product reaches its ground energy (cap 10^5 sweeps): sweeps to solve per
+    product and their device time within the 64-product batch."""
+    import torch
+    from paper_2509_23043_amd import binding, workloads
+    cfg = workloads.CFG4
+    cases = workloads.fact_cases(cfg)
+    t0 = time.perf_counter()
+    banks = pt_banks(cases, cfg["B"], log, seed0=1_400_000)
+    log(f"factorization: banks in {time.perf_counter() - t0:.1f} s")
+    tiling, scan = tuned_tiling(cases, cfg, log)
+    ctxs = case_contexts(cases, cfg, banks)
+    r = timed_batch(ctxs, tiling, cfg["sweeps"], 2000)
+    for c in ctxs:
+        c.close()
+    bpa = csr_bytes_per_attempt(cases[0]["g"])
+    log(f"factorization: {r['value']:.1f} attempts/ns over {cfg['sweeps']} sweeps, tiling {tiling}, "
+        f"chunk kernel {r['avg_ms']:.3f} ms avg")
+    roof = rooflines(r["attempts"] / max(r["launches"], 1), r["avg_ms"], bpa,
+                     kernel="chunk_kernel<CsrSweep>")
+    # time to solution: fresh contexts, chunks of 1000 sweeps until every
+    # product has hit its ground energy or the cap
+    ctxs = case_contexts(cases, cfg, banks)
+    G, rpt, kern = tiling
+    bt = binding.Batch(ctxs, replicas_per_wg=G, replicas_per_thread=rpt, chunk_sweeps=1000, kernel=kern)
+    bt.kernel_time()
+    done, hits = 0, [-1] * len(ctxs)
+    while done < cfg["solve_cap"] and min(hits) < 0:
+        bt.sweep(1000)
+        done += 1000
+        hits = [c.summary()["first_hit"] for c in ctxs]
+    ms, _ = bt.kernel_time()
+    bt.close()
+    best = [c.summary() for c in ctxs]
+    solved = [h for h in hits if h >= 0]
+    ok = all(inputs_factor(cases[k], best[k]["best_spins"]) for k in range(len(cases)) if hits[k] >= 0)
+    for c in ctxs:
+        c.close()
+    ms_per_sweep = ms / done
+    sw = np.array([h if h >= 0 else np.inf for h in hits], float)
+    med = float(np.median(sw))
+    log(f"factorization: {len(solved)}/{len(hits)} solved within {done} sweeps, median {med:g} sweeps "
+        f"({med * ms_per_sweep:.1f} ms of the batch), factors checked: {ok}")
+    torch.cuda.synchronize()
+    return dict(value=round(r["value"], 2), unit="attempts/ns", sweeps=cfg["sweeps"], seconds=round(r["seconds"], 3),
+                products=len(cases), replicas=cfg["R"], banked_slots=cfg["n_prop"], lds_bytes_per_attempt=round(bpa, 2),
+                tiling=dict(replicas_per_wg=G, replicas_per_thread=rpt, kernel=kern),
+                tiling_scan=[dict(G=d["replicas_per_wg"], rpt=d["replicas_per_thread"], kernel=d["kernel"],
+                                  attempts_per_ns=d["attempts_per_ns"]) for d in scan],
+                roofline=roof,
+                solve=dict(cap=cfg["solve_cap"], sweeps_run=done, solved=len(solved), products=len(hits),
+                           median_sweeps=None if not math.isfinite(med) else med,
+                           p90_sweeps=None if not math.isfinite(float(np.percentile(sw, 90)))
+                           else float(np.percentile(sw, 90)),
+                           batch_ms_per_sweep=round(ms_per_sweep, 5),
+                           median_seconds=None if not math.isfinite(med) else round(med * ms_per_sweep / 1e3, 5),
+                           factors_checked=ok,
+                           note="seconds = sweeps to the ground energy x device time per sweep of the "
+                                "64-product batch"),
+                workload="8x8-bit array multipliers (200 spins, 176 free) of 64 distinct semiprimes, R=32 beta "
+                         "0.2..3.0 geometric, Metropolis, M=1, DSATUR colors, proposals every 100 sweeps from "
+                         "256-entry plain-PT banks on the 23 hottest slots")
+
+
+def inputs_factor(case, spins):
+    """The factor bits of a ground state multiply to the product."""
+    from paper_2509_23043_amd import inputs
+    A = inputs.bits_to_int(spins, case["g"]["a_idx"])
+    B = inputs.bits_to_int(spins, case["g"]["b_idx"])
+    return A * B == case["C"]
+
+
+def serving_pool(args, log):
     """Problems of the mixed serving workload, each a registered context with
     proposal banks and a residual-energy target.
 
@@ -215,10 +449,14 @@ def serving_pool(log):
     multipliers, m = 8..12, 4 semiprimes per size, 32 slots, proposals on the
     23 hottest. Banks: 64 configurations per slot from a plain-PT run of the
     instance (10^4 burn-in sweeps, then one sample every 100 sweeps). The EA
-    target is the lowest energy of that run plus 1% of N rounded up to the
-    energy grid (multiples of 4); the factorization target is the ground
-    energy -3m^2 - 4m(m-1), reached exactly by the factor pairs."""
+    reference energy E_ref is the lowest energy of ``--serve-ref-runs``
+    independent plain-PT runs of ``--serve-ref-sweeps`` sweeps (seeds apart
+    from the bank run and from every request), and the target is E_ref plus
+    1% of N rounded up to the energy grid (multiples of 4); the factorization
+    target is the ground energy -3m^2 - 4m(m-1), reached exactly by the
+    factor pairs."""
     import torch
+    from paper_2509_23043_amd import banks as bankmod
     from paper_2509_23043_amd import binding, inputs
     B, burn, every = 64, 10_000, 100
     specs = []
@@ -251,16 +489,31 @@ def serving_pool(log):
                 banks[q][:, j, :] = tmp[q][:specs[idx[q]]["slots"]]
         torch.cuda.synchronize()
         for q, k in enumerate(idx):
-            sp = specs[k]
-            sp["bank"] = banks[q]
-            if sp["kind"] == "ea":
-                n = sp["g"]["n"]
-                slack = -(-((n + 99) // 100) // 4) * 4
-                sp["target"] = int(gens[q].summary()["best"]) + slack
+            specs[k]["bank"] = banks[q]
         bt.close()
         for g in gens:
             g.close()
     log(f"serving pool: {len(specs)} problems, banks in {time.perf_counter() - t0:.1f} s")
+    # reference energies of the spin glasses from independent long runs
+    t0 = time.perf_counter()
+    ea = [k for k, sp in enumerate(specs) if sp["kind"] == "ea"]
+    refs = [binding.Context(specs[k]["g"], specs[k]["betas"], seed=3_000_000 + 100 * k + j)
+            for k in ea for j in range(args.serve_ref_runs)]
+    owner = [k for k in ea for _ in range(args.serve_ref_runs)]
+    for group, bt in bankmod._batches(refs, lambda grp: binding.Batch(grp, chunk_sweeps=5000)):
+        bt.sweep(args.serve_ref_sweeps)
+        bt.close()
+    eref = {}
+    for k, c in zip(owner, refs):
+        eref[k] = min(eref.get(k, 1 << 30), int(c.summary()["best"]))
+        c.close()
+    for k in ea:
+        n = specs[k]["g"]["n"]
+        slack = -(-((n + 99) // 100) // 4) * 4
+        specs[k]["eref"] = eref[k]
+        specs[k]["target"] = eref[k] + slack
+    log(f"serving pool: reference energies from {args.serve_ref_runs} x {args.serve_ref_sweeps}-sweep runs per "
+        f"spin glass in {time.perf_counter() - t0:.1f} s")
     ctxs = []
     for sp in specs:
         c = binding.Context(sp["g"], sp["betas"], seed=0, prop_start=sp["period"], prop_period=sp["period"])
@@ -276,7 +529,7 @@ def serving_leg(args, log):
     continuous-batching server; time-to-target per request = completion seen
     by the host minus arrival."""
     from paper_2509_23043_amd import binding
-    specs, ctxs = serving_pool(log)
+    specs, ctxs = serving_pool(args, log)
     ea = {}
     fa = {}
     for k, sp in enumerate(specs):
@@ -318,31 +571,45 @@ def serving_leg(args, log):
         wall = max(r["t_done"] for r in results) - t_start
         ok = [r for r in results if r["status"] == 0]
         hits = [r for r in ok if r["hit"]]
-        tt = np.array([r["t_done"] - r["t_submit"] for r in hits]) if hits else np.array([np.nan])
+        pct = lambda v, q: round(float(np.percentile(v, q)), 4) if len(v) else None
+        done_t = [r["t_done"] - r["t_submit"] for r in ok]
+        hit_t = [r["t_done"] - r["t_submit"] for r in hits]
         by_kind = {}
         for kind in ("ea", "fact"):
-            h = [r["t_done"] - r["t_submit"] for r in hits if specs[r["user_tag"]]["kind"] == kind]
-            by_kind[kind] = dict(n=len(h), p50_s=round(float(np.percentile(h, 50)), 4) if h else None,
-                                 p99_s=round(float(np.percentile(h, 99)), 4) if h else None)
+            mine = [r for r in ok if specs[r["user_tag"]]["kind"] == kind]
+            h = [r["t_done"] - r["t_submit"] for r in mine if r["hit"]]
+            dn = [r["t_done"] - r["t_submit"] for r in mine]
+            by_kind[kind] = dict(n=len(mine), hit_frac=round(len(h) / max(len(mine), 1), 4),
+                                 p50_time_to_done_s=pct(dn, 50), p99_time_to_done_s=pct(dn, 99),
+                                 p50_time_to_target_s=pct(h, 50), p99_time_to_target_s=pct(h, 99))
+        busy = (st1["busy_s"] - st0["busy_s"]) / max(wall, 1e-9)
         d = dict(rate_req_per_s=lam, requests=nreq, completed=len(ok), rejected=nreq - len(ok),
                  hit_frac=round(len(hits) / max(len(ok), 1), 4), cap_frac=round(1 - len(hits) / max(len(ok), 1), 4),
-                 p50_time_to_target_s=round(float(np.percentile(tt, 50)), 4),
-                 p99_time_to_target_s=round(float(np.percentile(tt, 99)), 4),
+                 p50_time_to_done_s=pct(done_t, 50), p99_time_to_done_s=pct(done_t, 99),
+                 p50_time_to_target_s=pct(hit_t, 50), p99_time_to_target_s=pct(hit_t, 99),
                  completed_req_per_s=round(len(ok) / wall, 2),
                  attempts_per_ns=round((st1["attempts"] - st0["attempts"]) / (wall * 1e9), 2),
+                 round_busy_frac=round(busy, 4), rounds=st1["rounds"] - st0["rounds"],
                  peak_active=st1["peak_active"], by_kind=by_kind)
-        log(f"serving lambda={lam:g}: p50 {d['p50_time_to_target_s']} s, p99 {d['p99_time_to_target_s']} s, "
-            f"{d['completed_req_per_s']} req/s, hit {d['hit_frac']}, {d['attempts_per_ns']} attempts/ns, "
-            f"peak active {d['peak_active']}")
+        log(f"serving lambda={lam:g}: done p50 {d['p50_time_to_done_s']} s p99 {d['p99_time_to_done_s']} s; "
+            f"target p50 {d['p50_time_to_target_s']} s p99 {d['p99_time_to_target_s']} s; "
+            f"{d['completed_req_per_s']} req/s, hit {d['hit_frac']} (ea {by_kind['ea']['hit_frac']}, "
+            f"fact {by_kind['fact']['hit_frac']}), {d['attempts_per_ns']} attempts/ns, "
+            f"round busy {d['round_busy_frac']}, peak active {d['peak_active']}")
         out.append(d)
     srv.stop()
     for c in ctxs:
         c.close()
     return dict(rates=out, sweep_cap=args.serve_cap, chunk_sweeps=args.serve_chunk,
                 pool="40 EA +-J (L=6..16, 8 each, R=24..48) + 20 multipliers (m=8..12, 4 each, R=32); "
-                     "banks 64/slot from plain-PT runs; EA target = run's best + 1% N; factorization target = "
-                     "ground energy",
-                mix="70% EA (L uniform), 30% factorization (m uniform)")
+                     "banks 64/slot from plain-PT runs; EA target = E_ref + 1% N on the grid of 4, E_ref the "
+                     f"best of {args.serve_ref_runs} independent {args.serve_ref_sweeps}-sweep plain-PT runs; "
+                     "factorization target = ground energy",
+                mix="70% EA (L uniform), 30% factorization (m uniform)",
+                latency="time to done = host sees the result minus arrival, over every completed request "
+                        "(hits and capped ones); time to target over the hits only",
+                reference_energies={str(sp["size"]) + "_" + str(k): sp["eref"] for k, sp in enumerate(specs)
+                                    if sp["kind"] == "ea"})
 
 
 # Supp. Table S3: one complete 10^5-sample bank for one (instance, beta), with
@@ -563,6 +830,15 @@ def main():
     if args.workload == "context":
         context_study(args, lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True))
         return
+    if args.workload in ("mixed", "fact"):
+        import torch
+        from paper_2509_23043_amd import binding
+        torch.cuda.set_device(0)
+        binding.lib()
+        log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
+        leg = mixed_leg(args, log) if args.workload == "mixed" else factorization_leg(args, log)
+        print(json.dumps(leg), flush=True)
+        return
     if args.workload != "pt":
         bankgen(args, lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True))
         return
@@ -651,26 +927,32 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
 
-    # roofline of the chunk kernel from its own HIP events
+    # rooflines of the chunk kernel from its own HIP events
     avg_ms = kern_ms / max(launches, 1)
     att_launch = attempts / max(launches, 1)
-    achieved = OPS_PER_ATTEMPT * att_launch / (avg_ms * 1e-3) / 1e12
     ran = kern if kern != "auto" else ("pm" if ctxs[0].pm else "wave")
     kern_hash = kernel_source_hash(ran)
-    roof = dict(bound="alu", achieved=round(achieved, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TOP/s",
-                frac=round(achieved / VALU_PEAK_TOPS, 4), traffic=traffic_from_profiles(S, kern_hash, ran),
-                kernel=KERNEL_NAMES[ran], avg_launch_ms=round(avg_ms, 4), launches=launches,
-                ops_per_attempt=OPS_PER_ATTEMPT,
-                lds=dict(bytes_per_attempt=LDS_BYTES_PER_ATTEMPT,
-                         achieved_TBps=round(LDS_BYTES_PER_ATTEMPT * att_launch / (avg_ms * 1e-3) / 1e12, 3),
-                         peak_TBps=round(LDS_PEAK_TBS, 1),
-                         frac=round(LDS_BYTES_PER_ATTEMPT * att_launch / (avg_ms * 1e-3) / 1e12 / LDS_PEAK_TBS, 4)))
+    roof = rooflines(att_launch, avg_ms, LDS_BYTES_PER_ATTEMPT, traffic=traffic_from_profiles(S, kern_hash, ran),
+                     kernel=KERNEL_NAMES[ran])
+    roof["launches"] = launches
+
+    mixed = fact = None
+    if not args.no_mixed or not args.no_fact:
+        for c in ctxs:
+            c.close()
+        bt.close()
+        ctxs = []
+    if not args.no_mixed:
+        mixed = mixed_leg(args, log)
+    if not args.no_fact:
+        fact = factorization_leg(args, log)
 
     serving = None
     if not args.no_serve:
         for c in ctxs:
             c.close()
-        bt.close()
+        if ctxs:
+            bt.close()
         serving = serving_leg(args, log)
 
     cpu = None
@@ -686,7 +968,7 @@ def main():
                                     f"plain-PT banks on {n_prop} slots; {S} sweeps per step",
                            instances=NI, L=L, replicas=R, sweeps_per_step=S, sweeps_per_swap=M, bank=args.bank,
                            tiling=dict(replicas_per_wg=G, replicas_per_thread=rpt, kernel=kern)),
-               plain=plain, roofline=roof, cpu_baseline=cpu,
+               plain=plain, roofline=roof, cpu_baseline=cpu, mixed=mixed, factorization=fact,
                tiling_scan=[dict(G=d["replicas_per_wg"], rpt=d["replicas_per_thread"], kernel=d["kernel"],
                                  attempts_per_ns=d["attempts_per_ns"]) for d in scan],
                serving=serving)

@@ -312,6 +312,16 @@ double pt_serve_clock(pt_server *s);
  * the server. Results not polled are dropped. */
 int pt_serve_stop(pt_server *s);
 
+/* ---- measurement ----
+ * LDS read bandwidth of the current device in TB/s (the measured peak beside
+ * the nominal one in the LDS roofline): blocks_per_cu x CUs workgroups of 256
+ * threads, each reading its 32 KiB of LDS with unrolled, conflict-free
+ * bytes_per_read (8 or 16) byte reads for iters rounds of 16 reads per lane;
+ * the second of two timed launches counts. *ms (may be NULL) receives its
+ * duration. blocks_per_cu in 1..8. Allocates and frees a small output
+ * buffer. */
+int pt_probe_lds(int32_t bytes_per_read, int32_t blocks_per_cu, uint32_t iters, double *tbps, double *ms);
+
 const char *pt_last_error(void);
 
 #ifdef __cplusplus

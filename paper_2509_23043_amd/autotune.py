@@ -10,9 +10,12 @@ architecture.
 Every tiling realises the same chain bit for bit, because random numbers are
 keyed by site, sweep, slot and seed and never by thread or workgroup. So the
 tiling is chosen on speed alone. M is different: it changes the Markov chain
-(Algorithm 1 runs M sweeps between swap stages). A tuned M is therefore
-returned to the caller, who must run every path that is compared with the
-batch (the oracle, the plain path) with the same M.
+(Algorithm 1 runs M sweeps between swap stages), so a faster M is no gain if
+it samples worse. The caller's first M is the reference; another M is taken
+only if it is faster and, on held-out runs of the same batch (other seeds,
+the same number of sweeps), its mean best energy is no higher than the
+reference's. A tuned M is returned to the caller, who must run every path
+that is compared with the batch (the oracle, the plain path) with the same M.
 
 Timing uses the chunk-kernel HIP events of the batch (pt_batch_kernel_time)
 and is argument marshalling plus arithmetic on the host only.
@@ -94,11 +97,30 @@ def time_tiling(contexts, G, rpt, kernel="auto", warm=200, timed=600, chunk=None
     return _attempts_per_sweep(contexts) * timed / (ms * 1e6)
 
 
-def tune(make_contexts, Ms=(1,), cache=None, key_extra="", warm=200, timed=600, log=None):
+def mean_best_energy(make_contexts, M, tiling, sweeps, seed_offset=1_000_003):
+    """Mean best energy over the batch after ``sweeps`` sweeps with M sweeps
+    per cycle, on scratch contexts whose seeds are shifted by seed_offset
+    (runs held out from the timing)."""
+    ctxs = make_contexts(M, seed_offset=seed_offset)
+    try:
+        bt = binding.Batch(ctxs, replicas_per_wg=tiling["replicas_per_wg"],
+                           replicas_per_thread=tiling["replicas_per_thread"], chunk_sweeps=min(sweeps, 1000),
+                           kernel=tiling["kernel"])
+        bt.sweep(sweeps)
+        bt.close()
+        return float(sum(c.summary()["best"] for c in ctxs)) / len(ctxs)
+    finally:
+        for c in ctxs:
+            c.close()
+
+
+def tune(make_contexts, Ms=(1,), cache=None, key_extra="", warm=200, timed=600, log=None, quality_sweeps=2000):
     """Choose (M, replicas_per_wg, replicas_per_thread) for a batch.
 
     make_contexts(M) returns fresh scratch binding.Context objects of the
-    batch's shape with M sweeps per cycle (they are run and discarded).
+    batch's shape with M sweeps per cycle (they are run and discarded); with
+    several Ms it must also accept ``seed_offset`` (held-out runs for the
+    quality check of a faster M).
     cache: JSON file path or None. Returns a dict with the choice, its rate
     and the timed scan.
     """
@@ -132,9 +154,20 @@ def tune(make_contexts, Ms=(1,), cache=None, key_extra="", warm=200, timed=600, 
     if not scan:
         raise binding.TaptError(binding.PT_EUNSUPPORTED, "no feasible tiling for this batch")
     best = max(scan, key=lambda d: d["attempts_per_ns"])
+    quality = {}
+    if len(Ms) > 1 and best["M"] != Ms[0]:
+        # a faster M must sample no worse than the reference M on held-out runs
+        ref = max((d for d in scan if d["M"] == Ms[0]), key=lambda d: d["attempts_per_ns"], default=None)
+        quality = {Ms[0]: mean_best_energy(make_contexts, Ms[0], ref, quality_sweeps) if ref else None,
+                   best["M"]: mean_best_energy(make_contexts, best["M"], best, quality_sweeps)}
+        if log:
+            log(f"autotune quality check over {quality_sweeps} sweeps: mean best energy {quality}")
+        if ref is not None and quality[best["M"]] > quality[Ms[0]]:
+            best = ref
     res = dict(M=best["M"], replicas_per_wg=best["replicas_per_wg"],
                replicas_per_thread=best["replicas_per_thread"], kernel=best["kernel"],
-               attempts_per_ns=best["attempts_per_ns"], scan=scan)
+               attempts_per_ns=best["attempts_per_ns"], scan=scan,
+               quality={str(k): v for k, v in quality.items()})
     if cache:
         table[key] = res
         tmp = cache + ".tmp"

@@ -78,9 +78,10 @@ EXPORTS = ["pt_create", "pt_destroy", "pt_propose", "pt_propose_device", "pt_set
            "pt_state", "pt_state_device", "pt_set_state", "pt_save_size", "pt_save", "pt_restore",
            "pt_summary_get", "pt_counters",
            "pt_energy_device", "pt_set_stream", "pt_batch_create", "pt_batch_sweep", "pt_batch_destroy",
-           "pt_batch_set_stream", "pt_batch_kernel_time", "pt_serve_start", "pt_serve_register",
+           "pt_batch_set_stream", "pt_batch_kernel_time", "pt_serve_start",
+           "pt_serve_register",
            "pt_serve_submit", "pt_serve_poll", "pt_serve_stats_get", "pt_serve_clock", "pt_serve_stop",
-           "pt_last_error"]
+           "pt_probe_lds", "pt_last_error"]
 
 _lib = None
 
@@ -127,6 +128,7 @@ def lib():
     L.pt_serve_stats_get.argtypes = [vp, C.POINTER(_ServeStats)]
     L.pt_serve_clock.argtypes = [vp]
     L.pt_serve_stop.argtypes = [vp]
+    L.pt_probe_lds.argtypes = [C.c_int32, C.c_int32, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.pt_last_error.restype = C.c_char_p
     for name in EXPORTS:
         if name not in ("pt_last_error", "pt_serve_clock"):
@@ -278,6 +280,15 @@ class Context:
 
     def set_stream(self, stream_ptr):
         _check(lib().pt_set_stream(self.h, C.c_void_p(stream_ptr)))
+
+
+def probe_lds(bytes_per_read=16, blocks_per_cu=4, iters=2048):
+    """Measured LDS read bandwidth (TB/s, ms) of the current device."""
+    tb, ms = C.c_double(), C.c_double()
+    rc = lib().pt_probe_lds(int(bytes_per_read), int(blocks_per_cu), int(iters), C.byref(tb), C.byref(ms))
+    if rc != PT_OK:
+        raise TaptError(rc, "LDS probe failed")
+    return tb.value, ms.value
 
 
 class Batch:

@@ -58,6 +58,7 @@ hipError_t launch_init(const InstDev *dI, int R, int n, hipStream_t s);
 hipError_t launch_energy(const InstDev *dI, const int8_t *cfg, int k, int32_t *out, hipStream_t s);
 hipError_t launch_init_best(const InstDev *dI, hipStream_t s);
 hipError_t launch_set_caps(InstDev *const *insts, const unsigned long long *caps, int n, hipStream_t s);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 uint32_t host_philox_word0(uint32_t c0, uint32_t c1, uint32_t c3, uint32_t k0, uint32_t k1);
 } // namespace tapt
 
@@ -1203,17 +1204,45 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
     return PT_OK;
 }
 
-static int build_group(pt_batch *b, LaunchGroup *g)
+// Where a launch group's device buffers come from: fresh allocations, or
+// 256-byte aligned views into a region the caller provides (the static
+// region the caller provides), in which case nothing is allocated.
+struct GroupMem {
+    char *base = nullptr;             // null: allocate
+    size_t cap = 0, used = 0;
+    hipError_t take(DevBuf &b, size_t bytes)
+    {
+        if (!base) return b.alloc(bytes);
+        const size_t at = (used + 255) & ~(size_t)255;
+        const size_t len = (bytes + 7) & ~(size_t)7;
+        if (at + len > cap) return hipErrorOutOfMemory;
+        b.view(base + at, len);
+        used = at + len;
+        return hipSuccess;
+    }
+    template <class T> hipError_t put(DevBuf &b, const std::vector<T> &v, hipStream_t s)
+    {
+        hipError_t e = take(b, v.size() * sizeof(T));
+        if (e != hipSuccess || v.empty()) return e;
+        return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+    }
+};
+
+static int build_group(pt_batch *b, LaunchGroup *g, GroupMem &mem)
 {
     hipStream_t s = b->stream;
     GroupPlan P;
     int rc = plan_group(b, g, P);
     if (rc) return rc;
-    HIPCHK(g->status.alloc(g->ctxs.size() * sizeof(InstStatus)));
-    HIPCHK(g->best.alloc(P.nbest * sizeof(BestRec)));
-    HIPCHK(g->best_spins.alloc(P.nbs));
-    HIPCHK(g->xbuf.alloc(P.nx));
-    HIPCHK(hipMemsetAsync(g->xbuf.p, 0, P.nx, s));
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = mem.take(g->status, g->ctxs.size() * sizeof(InstStatus));
+    if (e == hipSuccess) e = mem.take(g->best, P.nbest * sizeof(BestRec));
+    if (e == hipSuccess) e = mem.take(g->best_spins, P.nbs);
+    if (e == hipSuccess) e = mem.take(g->xbuf, P.nx);
+    if (e == hipErrorOutOfMemory && mem.base)
+        return fail(PT_ENOMEM, "the launch needs more than the %zu bytes of static scratch", mem.cap);
+    HIPCHK(e);
+    HIPCHK(launch_zero(g->xbuf.p, g->xbuf.bytes, s));
     size_t bi = 0;
     for (size_t k = 0; k < g->ctxs.size(); ++k) {
         const GroupPlan::Ctx &p = P.ctx[k];
@@ -1236,9 +1265,13 @@ static int build_group(pt_batch *b, LaunchGroup *g)
     g->block = P.block;
     g->lds = P.lds;
     g->tsw_entries = P.tsw_max;
-    HIPCHK(upload(g->items, P.items, s));
-    HIPCHK(upload(g->order, P.order, s));
-    HIPCHK(upload(g->first_item, P.first, s));
+    if (e == hipSuccess) e = mem.put(g->items, P.items, s);
+    if (e == hipSuccess) e = mem.put(g->order, P.order, s);
+    if (e == hipSuccess) e = mem.put(g->first_item, P.first, s);
+    if (e == hipErrorOutOfMemory && mem.base)
+        return fail(PT_ENOMEM, "the launch needs more than the %zu bytes of static scratch", mem.cap);
+    HIPCHK(e);
+    // the host vectors must outlive their copies
     HIPCHK(hipStreamSynchronize(s));
     return PT_OK;
 }
@@ -1344,7 +1377,8 @@ static int batch_set_contexts(pt_batch *b, pt_ctx *const *ctxs, int32_t k)
     int rc = pick_group(b, b->ctxs, &g);
     if (rc) return rc;
     b->groups.push_back(g);
-    return build_group(b, g);
+    GroupMem mem;
+    return build_group(b, g, mem);
 }
 
 // PT_OK if the contexts could run in one launch of this batch (no allocation).
@@ -1431,10 +1465,11 @@ static hipError_t enqueue_round(pt_batch *b, uint32_t K, bool timed)
     return hipSuccess;
 }
 
-extern "C" int pt_batch_sweep(pt_batch *b, uint64_t n_sweeps)
+// Run n_sweeps sweeps of every context of a built batch. timed: record HIP
+// events around the chunk launches (pt_batch_kernel_time); untimed eager
+// launches create nothing. The graph path is taken when the batch asks for it.
+static int batch_sweep(pt_batch *b, uint64_t n_sweeps, bool timed)
 {
-    if (!b) return fail(PT_EINVAL, "null batch");
-    HIPCHK(hipSetDevice(b->device));
     if (n_sweeps == 0) return PT_OK;
     // every context stops exactly at its own t + n_sweeps: the caps go to the
     // device in one small launch per 64 contexts rather than one copy each
@@ -1458,7 +1493,7 @@ extern "C" int pt_batch_sweep(pt_batch *b, uint64_t n_sweeps)
     for (auto *g : b->groups)
         for (size_t k = 0; k < g->ctxs.size(); ++k)
             if (g->x_epoch[k] != g->ctxs[k]->hI.epoch) {
-                HIPCHK(hipMemsetAsync(g->xbuf.as<int8_t>() + g->x_off[k], 0, g->x_bytes[k], b->stream));
+                HIPCHK(launch_zero(g->xbuf.as<int8_t>() + g->x_off[k], g->x_bytes[k], b->stream));
                 g->x_epoch[k] = g->ctxs[k]->hI.epoch;
             }
     const uint32_t K = (uint32_t)b->opts.chunk_sweeps;
@@ -1487,7 +1522,7 @@ extern "C" int pt_batch_sweep(pt_batch *b, uint64_t n_sweeps)
     } else {
         b->ev_used = 0;
         for (uint64_t k = 0; k < rounds; ++k) {
-            hipError_t e = enqueue_round(b, K, true);
+            hipError_t e = enqueue_round(b, K, timed);
             if (e != hipSuccess) return fail(PT_EDEVICE, "chunk launch: %s", hipGetErrorString(e));
         }
     }
@@ -1514,6 +1549,13 @@ extern "C" int pt_batch_sweep(pt_batch *b, uint64_t n_sweeps)
                     err[0], err[1], err[2], err[3], err[4], (unsigned)err[6], (unsigned)err[5], err[7]);
     }
     return PT_OK;
+}
+
+extern "C" int pt_batch_sweep(pt_batch *b, uint64_t n_sweeps)
+{
+    if (!b) return fail(PT_EINVAL, "null batch");
+    HIPCHK(hipSetDevice(b->device));
+    return batch_sweep(b, n_sweeps, true);
 }
 
 extern "C" int pt_batch_set_stream(pt_batch *b, void *stream)

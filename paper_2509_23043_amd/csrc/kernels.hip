@@ -425,6 +425,23 @@ hipError_t launch_energy(const InstDev *dI, const int8_t *cfg, int k, int32_t *o
     return hipGetLastError();
 }
 
+// Zero `words` 64-bit words (a fill kernel rather than hipMemsetAsync, so that
+// the clear may sit in a captured stream).
+__global__ void zero_kernel(unsigned long long *p, size_t words)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) p[i] = 0ull;
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
+{
+    const size_t words = (bytes + 7) / 8;      // callers pass 8-byte aligned regions padded to 8 bytes
+    if (words == 0) return hipSuccess;
+    const size_t want = (words + 255) / 256, blocks = want < 1024 ? want : 1024;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (unsigned long long *)p, words);
+    return hipGetLastError();
+}
+
 // Sweep caps of up to CAPS_PER_LAUNCH contexts of a batch, set on the device
 // in one launch (the caps travel as kernel arguments).
 constexpr int CAPS_PER_LAUNCH = 64;

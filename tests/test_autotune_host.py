@@ -47,6 +47,7 @@ def test_tune_picks_fastest_and_caches(monkeypatch, tmp_path):
         c.M = M
         return [c]
 
+    monkeypatch.setattr(autotune, "mean_best_energy", lambda make, M, tiling, sweeps: {1: -100.0, 2: -101.0}[M])
     cache = str(tmp_path / "tune.json")
     r = autotune.tune(make, Ms=(1, 2), cache=cache)
     assert (r["M"], r["replicas_per_wg"], r["replicas_per_thread"]) == (2, 8, 1)
@@ -55,3 +56,29 @@ def test_tune_picks_fastest_and_caches(monkeypatch, tmp_path):
     r2 = autotune.tune(make, Ms=(1, 2), cache=cache)
     assert r2["cached"] and r2["M"] == 2 and len(calls) == n_calls
     assert r["key"] in json.load(open(cache))
+
+
+def test_faster_M_that_samples_worse_is_refused(monkeypatch):
+    """M changes the chain: a faster M whose held-out runs end at a higher
+    mean best energy than the reference M's loses to the reference."""
+    monkeypatch.setattr(autotune, "arch", lambda: "gfx950")
+    rates = {(1, 8, 1, "block"): 100.0, (2, 8, 1, "block"): 150.0}
+    monkeypatch.setattr(autotune, "time_tiling", lambda ctxs, G, rpt, kern, warm, timed:
+                        rates.get((ctxs[0].M, G, rpt, kern)))
+    seen = []
+
+    def quality(make, M, tiling, sweeps):
+        seen.append((M, tiling["replicas_per_wg"], sweeps))
+        return {1: -120.0, 2: -110.0}[M]
+
+    monkeypatch.setattr(autotune, "mean_best_energy", quality)
+
+    def make(M, seed_offset=0):
+        c = _ctx("lattice", 8, 512, 32)
+        c.M = M
+        return [c]
+
+    r = autotune.tune(make, Ms=(1, 2), quality_sweeps=500)
+    assert r["M"] == 1 and r["replicas_per_wg"] == 8
+    assert sorted(seen) == [(1, 8, 500), (2, 8, 500)]
+    assert r["quality"] == {"1": -120.0, "2": -110.0}

@@ -20,10 +20,10 @@ def _cases():
     return out
 
 
-def _make(M):
+def _make(M, seed_offset=0):
     ctxs = []
     for g, b, banks, seed in _cases():
-        c = binding.Context(g, b, seed=seed, M=M, prop_start=20, prop_period=20)
+        c = binding.Context(g, b, seed=seed + seed_offset, M=M, prop_start=20, prop_period=20)
         for r, bank in (banks or {}).items():
             c.propose(r, bank)
         ctxs.append(c)
