@@ -40,8 +40,10 @@ METRIC = "spin-flip attempts/ns (batched vs plain) + p50/p99 time-to-target per 
 OPS_PER_ATTEMPT = 6 + 2 + 7.5 + 3
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12       # int32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 LDS_BYTES_PER_ATTEMPT = 14                       # 6 neighbour spins + 6 couplings + own spin read + write
-LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12          # 128 B/clk/CU x 256 CUs x 2.4 GHz
-LDS_PEAK_SOURCE = "128 B/clk/CU (the CDNA3 LDS figure) x 256 CUs x 2.4 GHz"
+LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12          # 256 B/clk/CU x 256 CUs x 2.4 GHz
+LDS_PEAK_SOURCE = ("256 B/clk/CU (CDNA4 LDS reads, twice CDNA3's 128) x 256 CUs x 2.4 GHz; the LDS probe "
+                   "(bench.py --workload lds-probe) reads 137 TB/s with ds_read_b128, above the 78.6 TB/s "
+                   "a 128 B/clk LDS could give")
 HBM_PEAK_TBS = 8.0
 
 
@@ -85,9 +87,10 @@ def parse():
     ap.add_argument("--R", type=int, default=32)
     ap.add_argument("--bank", type=int, default=256)
     ap.add_argument("--workload", default="pt",
-                    choices=("pt", "mixed", "fact", "bankgen-sg", "bankgen-fact", "tts", "context"),
+                    choices=("pt", "mixed", "fact", "lds-probe", "bankgen-sg", "bankgen-fact", "tts", "context"),
                     help="pt: the batched PT benchmark (default); mixed / fact: only the mixed-size or the "
-                         "factorization leg (for profiling); bankgen-*: the long-run MCMC bank "
+                         "factorization leg (for profiling); lds-probe: LDS read bandwidth of the device; "
+                         "bankgen-*: the long-run MCMC bank "
                          "generation of Supp. Table S3 (3D spin glass L=10, or 16-bit factorization); "
                          "tts: the factorization TTS study; context: the proposal-context ablation")
     ap.add_argument("--ctx-instances", type=int, default=16, help="context: spin-glass instances")
@@ -583,19 +586,21 @@ def serving_leg(args, log):
                                  p50_time_to_done_s=pct(dn, 50), p99_time_to_done_s=pct(dn, 99),
                                  p50_time_to_target_s=pct(h, 50), p99_time_to_target_s=pct(h, 99))
         busy = (st1["busy_s"] - st0["busy_s"]) / max(wall, 1e-9)
+        gpu_busy = (st1["gpu_busy_s"] - st0["gpu_busy_s"]) / max(wall, 1e-9)
         d = dict(rate_req_per_s=lam, requests=nreq, completed=len(ok), rejected=nreq - len(ok),
                  hit_frac=round(len(hits) / max(len(ok), 1), 4), cap_frac=round(1 - len(hits) / max(len(ok), 1), 4),
                  p50_time_to_done_s=pct(done_t, 50), p99_time_to_done_s=pct(done_t, 99),
                  p50_time_to_target_s=pct(hit_t, 50), p99_time_to_target_s=pct(hit_t, 99),
                  completed_req_per_s=round(len(ok) / wall, 2),
                  attempts_per_ns=round((st1["attempts"] - st0["attempts"]) / (wall * 1e9), 2),
-                 round_busy_frac=round(busy, 4), rounds=st1["rounds"] - st0["rounds"],
+                 round_busy_frac=round(busy, 4), gpu_busy_frac=round(gpu_busy, 4),
+                 rounds=st1["rounds"] - st0["rounds"],
                  peak_active=st1["peak_active"], by_kind=by_kind)
         log(f"serving lambda={lam:g}: done p50 {d['p50_time_to_done_s']} s p99 {d['p99_time_to_done_s']} s; "
             f"target p50 {d['p50_time_to_target_s']} s p99 {d['p99_time_to_target_s']} s; "
             f"{d['completed_req_per_s']} req/s, hit {d['hit_frac']} (ea {by_kind['ea']['hit_frac']}, "
             f"fact {by_kind['fact']['hit_frac']}), {d['attempts_per_ns']} attempts/ns, "
-            f"round busy {d['round_busy_frac']}, peak active {d['peak_active']}")
+            f"round busy {d['round_busy_frac']}, GPU busy {d['gpu_busy_frac']}, peak active {d['peak_active']}")
         out.append(d)
     srv.stop()
     for c in ctxs:
@@ -829,6 +834,23 @@ def main():
         return
     if args.workload == "context":
         context_study(args, lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True))
+        return
+    if args.workload == "lds-probe":
+        import torch
+        from paper_2509_23043_amd import binding
+        torch.cuda.set_device(0)
+        binding.lib()
+        rows = []
+        for nbytes in (16, 8):
+            for bpc in (1, 2, 3, 4, 5):
+                tb, ms = binding.probe_lds(nbytes, bpc, 4096)
+                rows.append(dict(read=f"ds_read_b{8 * nbytes}", workgroups_per_cu=bpc, threads=256,
+                                 TBps=round(tb, 2), ms=round(ms, 3)))
+                print(f"[bench] ds_read_b{8 * nbytes}, {bpc} workgroups of 256 per CU: {tb:.2f} TB/s", file=sys.stderr,
+                      flush=True)
+        best = max(r["TBps"] for r in rows)
+        print(json.dumps(dict(metric="LDS read bandwidth", value=best, unit="TB/s", peak=round(LDS_PEAK_TBS, 1),
+                              frac=round(best / LDS_PEAK_TBS, 4), rows=rows)), flush=True)
         return
     if args.workload in ("mixed", "fact"):
         import torch

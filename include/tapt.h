@@ -125,9 +125,10 @@ int pt_propose_device(pt_ctx *c, double beta, const int8_t *configs_dev, int32_t
 /* Contextual proposals (Supp., ablation of proposal context, Fig. S4b):
  * with fraction > 0 or sweeps > 0, the proposal of a slot at cycle n is
  * built on the device rather than taken from the bank as is. It starts from
- * the slot's bank entry; each free site joins the context with probability
- * `fraction` (Philox tag 7, ctr (i>>2, n, r, 7), word i&3, against the
- * threshold T(fraction)) and takes the slot's current value; `sweeps` colored
+ * the slot's bank entry; K = round(fraction * n_free) free sites join the
+ * context and take the slot's current values: the K of smallest key, site i's
+ * key being word i&3 of Philox tag 7, ctr (i>>2, n, r, 7), ties to the lower
+ * index (a uniformly random K-subset); `sweeps` colored
  * sweeps at the slot's beta, with the context's rule, update the other free
  * sites (Philox tag 8, ctr (i>>2, n, r + 65536 j, 8) for sweep j = 1..sweeps,
  * word i&3 as the 32-bit uniform); its energy is recomputed and the Delta-E
@@ -292,6 +293,7 @@ typedef struct {
     int32_t active, waiting, peak_active;
     int32_t pad;
     uint64_t mem_used, mem_peak;
+    double gpu_busy_s;           /* device time of the rounds' sweep launches (HIP events) */
 } pt_serve_stats;
 
 int pt_serve_start(const pt_serve_opts *o, pt_server **out);

@@ -45,7 +45,7 @@ class _Problem(C.Structure):
         ("has_target", C.c_int32),
         ("target", C.c_int64),
         ("check_energy", C.c_int32),
-        ("ctx_T", C.c_uint32),
+        ("ctx_fraction", C.c_double),
         ("ctx_sweeps", C.c_int32),
     ]
 
@@ -135,9 +135,9 @@ class Run:
     problem: dict from ``paper_2509_23043_amd.inputs`` (n, row_ptr, col, J, h,
     clamp, color). banks: optional {slot: int8 [B, n]} proposal banks; a slot
     is proposal-enabled iff it has a bank. ctx_fraction / ctx_sweeps: the
-    contextual proposals of the context ablation (each free site joins the
-    context with probability ctx_fraction; the rest is completed by
-    ctx_sweeps sweeps from the bank entry).
+    contextual proposals of the context ablation (a random choice of
+    round(ctx_fraction * n_free) free sites is the context; the rest is
+    completed by ctx_sweeps sweeps from the bank entry).
     """
 
     def __init__(self, problem, betas, seed, M=1, rule="metropolis", banks=None,
@@ -189,7 +189,7 @@ class Run:
         P.has_target = 0 if target is None else 1
         P.target = 0 if target is None else int(target)
         P.check_energy = 1 if check_energy else 0
-        P.ctx_T = threshold(ctx_fraction) if ctx_fraction > 0 else 0
+        P.ctx_fraction = float(ctx_fraction)
         P.ctx_sweeps = int(ctx_sweeps)
         self.P = P
 

@@ -27,9 +27,9 @@
  *     SWAP   (5): swap at cycle n of pair (r, r+1): word 0 of ctr (r, n, 0, 5).
  *     BANK   (6): start cursor of a B-entry bank on slot r:
  *                 word 0 of ctr (r, 0, 0, 6) mod B.
- *     CONTEXT(7): contextual proposal at cycle n on slot r: site i is a context
- *                 site iff word (i&3) of ctr (i>>2, n, r, 7) passes the
- *                 fraction's threshold.
+ *     CONTEXT(7): contextual proposal at cycle n on slot r: the key of site i
+ *                 is word (i&3) of ctr (i>>2, n, r, 7); the context is the
+ *                 round(f n_free) free sites of smallest (key, index).
  *     CTXSWEEP(8): attempt on site i in completion sweep j (1-based) of that
  *                 proposal: u = word (i&3) of ctr (i>>2, n, r + 65536 j, 8).
  *   An event with probability p is accepted iff T(p) == 0xFFFFFFFF or u < T(p),
@@ -151,12 +151,13 @@ typedef struct {
     int32_t has_target;
     int64_t target;
     int32_t check_energy;   /* 1: compare incremental and recomputed energies */
-    /* contextual proposals (Supp. context ablation): when ctx_T or ctx_sweeps
-     * is nonzero, a proposal starts from its bank entry, takes the slot's
-     * current spins on the context sites (probability T/2^32 each, every site
-     * when T = 0xFFFFFFFF) and completes the other free sites by ctx_sweeps
-     * MCMC sweeps at the slot's beta (1..65535, or 0 for none) */
-    uint32_t ctx_T;
+    /* contextual proposals (Supp. context ablation): when ctx_fraction or
+     * ctx_sweeps is nonzero, a proposal starts from its bank entry, takes the
+     * slot's current spins on the context sites -- a random choice of
+     * round(ctx_fraction * n_free) of the free sites -- and completes the
+     * other free sites by ctx_sweeps MCMC sweeps at the slot's beta
+     * (1..65535, or 0 for none) */
+    double ctx_fraction;
     int32_t ctx_sweeps;
 } orc_problem;
 
@@ -273,22 +274,55 @@ static void sweep_slot(const orc_problem *P, orc_state *S, int32_t r, uint32_t t
     }
 }
 
+/* Number of context sites: the fraction f of the free spins, rounded to the
+ * nearest count (halves up). */
+static int32_t context_count(const orc_problem *P)
+{
+    int32_t nfree = 0;
+    for (int32_t i = 0; i < P->n; ++i) nfree += P->clamp[i] ? 0 : 1;
+    return (int32_t)floor(P->ctx_fraction * (double)nfree + 0.5);
+}
+
+typedef struct {
+    uint32_t key;
+    int32_t site;
+} ctx_key;
+
+static int ctx_key_order(const void *a, const void *b)
+{
+    const ctx_key *x = (const ctx_key *)a, *y = (const ctx_key *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->site < y->site ? -1 : (x->site > y->site ? 1 : 0);
+}
+
 /* Contextual proposal of slot r at cycle cyc (Supp. context ablation): a
- * random subset of the spins is clamped to the slot's current values and the
- * remaining spins are generated by MCMC under those clamps. The generation
- * starts from the bank entry (a sample of the unconstrained long-run MCMC at
- * beta_r) and runs ctx_sweeps sweeps at beta_r with the run's rule, color
- * classes in increasing color and sites in increasing index, as in
- * sweep_slot. ctx_mask[i] = 1 marks the context sites. */
+ * randomly chosen fraction of the spins is clamped to the slot's current
+ * values and the remaining spins are generated by MCMC under those clamps.
+ * The context is the K = round(f n_free) free sites whose CONTEXT keys
+ * (word i&3 of Philox ctr (i>>2, cyc, r, 7)) are smallest, ties going to the
+ * lower index: with independent uniform keys, a uniformly random K-subset.
+ * The generation starts from the bank entry (a sample of the unconstrained
+ * long-run MCMC at beta_r) and runs ctx_sweeps sweeps at beta_r with the
+ * run's rule, color classes in increasing color and sites in increasing
+ * index, as in sweep_slot. ctx_mask[i] = 1 marks the context sites. */
 void orc_context_candidate(const orc_problem *P, int32_t r, uint32_t cyc, const int8_t *start,
                            const int8_t *current, int8_t *out, uint8_t *ctx_mask)
 {
     const int32_t n = P->n;
+    ctx_key *keys = (ctx_key *)malloc(sizeof(ctx_key) * (size_t)(n > 0 ? n : 1));
+    int32_t nfree = 0;
     for (int32_t i = 0; i < n; ++i) {
-        uint32_t u = philox_word((uint32_t)i >> 2, cyc, (uint32_t)r, TAG_CONTEXT, P->seed, i & 3);
-        ctx_mask[i] = (!P->clamp[i] && accept(P->ctx_T, u)) ? 1 : 0;
-        out[i] = ctx_mask[i] ? current[i] : start[i];
+        ctx_mask[i] = 0;
+        if (P->clamp[i]) continue;
+        keys[nfree].key = philox_word((uint32_t)i >> 2, cyc, (uint32_t)r, TAG_CONTEXT, P->seed, i & 3);
+        keys[nfree].site = i;
+        ++nfree;
     }
+    qsort(keys, (size_t)nfree, sizeof(ctx_key), ctx_key_order);
+    const int32_t K = context_count(P);
+    for (int32_t k = 0; k < K && k < nfree; ++k) ctx_mask[keys[k].site] = 1;
+    free(keys);
+    for (int32_t i = 0; i < n; ++i) out[i] = ctx_mask[i] ? current[i] : start[i];
     for (int32_t j = 1; j <= P->ctx_sweeps; ++j) {
         for (int32_t c = 0; c < P->ncolors; ++c) {
             for (int32_t i = 0; i < n; ++i) {
@@ -319,7 +353,7 @@ int orc_run(const orc_problem *P, orc_state *S, uint64_t n_sweeps)
     int8_t *tmp = (int8_t *)malloc((size_t)n);
     int8_t *cand = (int8_t *)malloc((size_t)n);
     uint8_t *mask = (uint8_t *)malloc((size_t)n);
-    const int contextual = P->ctx_T != 0 || P->ctx_sweeps != 0;
+    const int contextual = P->ctx_fraction > 0.0 || P->ctx_sweeps != 0;
     if (!tmp || !cand || !mask) {
         free(tmp);
         free(cand);

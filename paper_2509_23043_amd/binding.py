@@ -71,7 +71,7 @@ class _ServeStats(C.Structure):
                 ("rejected", C.c_uint64), ("rounds", C.c_uint64), ("busy_s", C.c_double),
                 ("attempts", C.c_double), ("active", C.c_int32), ("waiting", C.c_int32),
                 ("peak_active", C.c_int32), ("pad", C.c_int32), ("mem_used", C.c_uint64),
-                ("mem_peak", C.c_uint64)]
+                ("mem_peak", C.c_uint64), ("gpu_busy_s", C.c_double)]
 
 
 EXPORTS = ["pt_create", "pt_destroy", "pt_propose", "pt_propose_device", "pt_set_context", "pt_sweep", "pt_energies",

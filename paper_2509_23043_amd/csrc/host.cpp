@@ -32,9 +32,10 @@ bool lattice_supported(int L);
 int lattice_max_threads();
 int lattice_threads(int L, int G, int rpt);
 size_t chunk_lds_bytes(int kind, int n, int G, int stride, int tsw_entries, int nnz, int nfree, int ncolors,
-                       bool contextual);
-hipError_t launch_chunk(int kind, int L, int rpt, bool wide, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
-hipError_t chunk_occupancy(int kind, int L, int rpt, bool wide, int block, size_t lds, int *blocks_per_cu);
+                       bool contextual, bool quad);
+hipError_t launch_chunk(int kind, int L, int rpt, bool wide, bool quad, const ChunkArgs &a, int block, size_t lds,
+                        hipStream_t s);
+hipError_t chunk_occupancy(int kind, int L, int rpt, bool wide, bool quad, int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_chunk_ctx(int kind, int L, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t chunk_occupancy_ctx(int kind, int L, int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_finish(const WorkItem *items, const int *first_item, int n_inst, uint32_t K, InstStatus *status,
@@ -206,6 +207,7 @@ struct pt_ctx {
     int device = 0;
     bool pmJ = false;                 // 8^3 lattice with every coupling +-1 (the +-J kernel applies)
     DevBuf arena;                     // a served request's state, carved into the views above
+    std::vector<int32_t> h_cursor0;   // a served request's start cursors (source of an async copy)
 };
 
 static int push_inst(pt_ctx *c)
@@ -226,7 +228,7 @@ static uint64_t sweep_limit(const pt_ctx *c)
 
 // Proposals of this context are contextual (built on the device from the
 // bank entry and the slot's current state) rather than plain bank entries.
-static bool contextual(const pt_ctx *c) { return (c->hI.ctx_T | (uint32_t)c->hI.ctx_sweeps) != 0; }
+static bool contextual(const pt_ctx *c) { return c->hI.ctx_on != 0; }
 
 static int check_ctx(pt_ctx *c)
 {
@@ -432,18 +434,23 @@ static void fill_inst_pointers(pt_ctx *c)
     I.best_spins = c->best_spins.as<int8_t>();
 }
 
-// zero counters, initialise spins (or take them from `spins`), energies, best
-static int reset_state(pt_ctx *c, const int8_t *spins, uint64_t t)
+// zero counters, initialise spins (or take them from `spins`), energies, best.
+// sync = false (fresh spins at t = 0 only): everything is enqueued on the
+// context's stream and nothing waits, so that a server can set up many
+// requests at once; every host source then lives in the context.
+static int reset_state(pt_ctx *c, const int8_t *spins, uint64_t t, bool sync = true)
 {
     hipStream_t s = c->stream;
     const int R = c->R, n = c->n;
+    if (!sync && (spins || t)) return fail(PT_EINVAL, "an unsynchronised reset starts fresh chains at t = 0");
     HIPCHK(hipMemsetAsync(c->swap_att.p, 0, c->swap_att.bytes, s));
     HIPCHK(hipMemsetAsync(c->swap_acc.p, 0, c->swap_acc.bytes, s));
     HIPCHK(hipMemsetAsync(c->prop_att.p, 0, c->prop_att.bytes, s));
     HIPCHK(hipMemsetAsync(c->prop_acc.p, 0, c->prop_acc.bytes, s));
     HIPCHK(hipMemsetAsync(c->flips.p, 0, c->flips.bytes, s));
     unsigned long long tt = t;
-    HIPCHK(hipMemcpyAsync(c->t.p, &tt, 8, hipMemcpyHostToDevice, s));
+    if (sync) HIPCHK(hipMemcpyAsync(c->t.p, &tt, 8, hipMemcpyHostToDevice, s));
+    else HIPCHK(hipMemsetAsync(c->t.p, 0, 8, s));
     c->hI.epoch += 1;
     int rc = push_inst(c);
     if (rc) return rc;
@@ -453,7 +460,7 @@ static int reset_state(pt_ctx *c, const int8_t *spins, uint64_t t)
         HIPCHK(launch_init(c->inst.as<InstDev>(), R, n, s));
     HIPCHK(launch_energy(c->inst.as<InstDev>(), c->spins.as<int8_t>(), R, c->E.as<int32_t>(), s));
     HIPCHK(launch_init_best(c->inst.as<InstDev>(), s));
-    HIPCHK(hipStreamSynchronize(s));
+    if (sync) HIPCHK(hipStreamSynchronize(s));
     c->t_host = t;
     return PT_OK;
 }
@@ -725,7 +732,9 @@ extern "C" int pt_set_context(pt_ctx *c, double fraction, int32_t sweeps)
     if (rc) return rc;
     if (!(fraction >= 0.0 && fraction <= 1.0)) return fail(PT_EINVAL, "context fraction must lie in [0, 1]");
     if (sweeps < 0 || sweeps > 65535) return fail(PT_EINVAL, "completion sweeps must lie in 0..65535");
-    c->hI.ctx_T = fraction > 0.0 ? threshold(fraction) : 0u;
+    // the context is round(fraction * n_free) free sites (halves round up)
+    c->hI.ctx_K = (int32_t)std::floor(fraction * (double)c->nfree + 0.5);
+    c->hI.ctx_on = (fraction > 0.0 || sweeps > 0) ? 1 : 0;
     c->hI.ctx_sweeps = sweeps;
     return push_inst(c);
 }
@@ -872,7 +881,8 @@ static uint64_t ckpt_fingerprint(const pt_ctx *c)
     Fnv f;
     f.val(c->problem_fp);
     f.add(c->h_bank_n);
-    f.val(c->hI.ctx_T);
+    f.val(c->hI.ctx_K);
+    f.val(c->hI.ctx_on);
     f.val(c->hI.ctx_sweeps);
     return f.h;
 }
@@ -1025,6 +1035,7 @@ struct LaunchGroup {
     int spw = 2;                      // its slots per wavefront (1 or 2)
     bool ctx = false;                 // some context has contextual proposals (chunk_kernel_ctx)
     bool wide = false;                // sparse graphs at 512 threads: the lane-sharing sweeper
+    bool quad = false;                // sparse graphs, four storages per lane (CsrQuadSweep)
     size_t lds;
     std::vector<pt_ctx *> ctxs;
     std::vector<int> Gs;              // per context: slots per workgroup (max)
@@ -1042,6 +1053,7 @@ struct pt_batch {
     pt_batch_opts opts{};
     hipStream_t stream = nullptr;
     DevBuf err;
+    DevBuf gmem;                      // the launch group's device buffers (grows, never shrinks)
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     uint32_t graph_K = 0;
@@ -1109,7 +1121,7 @@ struct GroupPlan {
     std::vector<Ctx> ctx;
     size_t nbest = 0, nbs = 0, nx = 0, lds = 0;
     int block = 64, grid = 0, tsw_max = 0, per_cu = 0;
-    bool wide = false;
+    bool wide = false, quad = false;
 };
 
 static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
@@ -1165,6 +1177,15 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
     P.order.assign((size_t)per * nx8, -1);
     for (int idx = 0; idx < n_items; ++idx) P.order[(size_t)(idx % per) * nx8 + idx / per] = idx;
     P.grid = per * nx8;
+    // Sparse graphs in the throughput tilings (every workgroup at least 4
+    // slots, 256 threads, no contextual proposals, every site's field bound
+    // below 256) take the four-storages-per-lane sweeper.
+    P.quad = g->kind == KIND_CSR && !g->mixed && !g->ctx && P.block <= 256;
+    for (size_t k = 0; k < g->ctxs.size() && P.quad; ++k) {
+        if (g->ctxs[k]->D > 255) P.quad = false;
+        for (int w = 0; w < P.ctx[k].W; ++w)
+            if (P.items[P.ctx[k].first + w].G < 4) P.quad = false;
+    }
     // LDS: the largest carve-up over the items (every item lays out its own
     // region with the common swap-table capacity)
     for (size_t k = 0; k < g->ctxs.size(); ++k) {
@@ -1172,7 +1193,7 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         P.lds = std::max(P.lds, g->pm     ? pm_lds_bytes(P.ctx[k].gmax, P.tsw_max)
                                 : g->wave ? wave_lds_bytes(c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max)
                                           : chunk_lds_bytes(c->kind, c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max,
-                                                            c->hI.nnz, c->hI.nfree, c->ncolors, contextual(c)));
+                                                            c->hI.nnz, c->hI.nfree, c->ncolors, contextual(c), P.quad));
     }
     if (P.lds > 160 * 1024) return fail(PT_EUNSUPPORTED, "tiling needs %zu B of LDS per workgroup", P.lds);
     if (g->ctx && g->mixed)
@@ -1190,7 +1211,7 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
     else {
         // a specialised sparse-graph launch at 512 threads takes the lane-sharing sweeper
         P.wide = g->kind == KIND_CSR && P.block == 512;
-        HIPCHK(chunk_occupancy(g->kind, g->L, g->rpt, P.wide, P.block, P.lds, &P.per_cu));
+        HIPCHK(chunk_occupancy(g->kind, g->L, g->rpt, P.wide, P.quad, P.block, P.lds, &P.per_cu));
     }
     if (P.per_cu < 1) return fail(PT_EUNSUPPORTED, "kernel cannot run with block %d, LDS %zu", P.block, P.lds);
     // the cross-workgroup waits need every workgroup of the launch resident
@@ -1205,8 +1226,8 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
 }
 
 // Where a launch group's device buffers come from: fresh allocations, or
-// 256-byte aligned views into a region the caller provides (the static
-// region the caller provides), in which case nothing is allocated.
+// 256-byte aligned views into a region the caller provides, in which case
+// nothing is allocated.
 struct GroupMem {
     char *base = nullptr;             // null: allocate
     size_t cap = 0, used = 0;
@@ -1227,6 +1248,22 @@ struct GroupMem {
         return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
     }
 };
+
+// Bytes build_group takes from a GroupMem region for this plan (the same
+// sequence of 256-byte aligned, 8-byte padded parts).
+static size_t group_bytes(const LaunchGroup *g, const GroupPlan &P)
+{
+    size_t used = 0;
+    auto take = [&](size_t bytes) { used = ((used + 255) & ~(size_t)255) + ((bytes + 7) & ~(size_t)7); };
+    take(g->ctxs.size() * sizeof(InstStatus));
+    take(P.nbest * sizeof(BestRec));
+    take(P.nbs);
+    take(P.nx);
+    take(P.items.size() * sizeof(WorkItem));
+    take(P.order.size() * sizeof(int32_t));
+    take(P.first.size() * sizeof(int));
+    return used;
+}
 
 static int build_group(pt_batch *b, LaunchGroup *g, GroupMem &mem)
 {
@@ -1261,6 +1298,7 @@ static int build_group(pt_batch *b, LaunchGroup *g, GroupMem &mem)
     }
     g->n_items = (int)P.items.size();
     g->wide = P.wide;
+    g->quad = P.quad;
     g->grid = P.grid;
     g->block = P.block;
     g->lds = P.lds;
@@ -1377,7 +1415,20 @@ static int batch_set_contexts(pt_batch *b, pt_ctx *const *ctxs, int32_t k)
     int rc = pick_group(b, b->ctxs, &g);
     if (rc) return rc;
     b->groups.push_back(g);
+    // the buffers are views into the batch's region, which grows when a
+    // launch needs more (a rebuilt batch, as in serving, allocates nothing
+    // while its launches fit the region)
+    GroupPlan P;
+    rc = plan_group(b, g, P);
+    if (rc) return rc;
+    const size_t need = group_bytes(g, P);
+    if (b->gmem.bytes < need) {
+        HIPCHK(hipStreamSynchronize(b->stream));
+        HIPCHK(b->gmem.alloc(std::max(need, 2 * b->gmem.bytes)));
+    }
     GroupMem mem;
+    mem.base = b->gmem.as<char>();
+    mem.cap = b->gmem.bytes;
     return build_group(b, g, mem);
 }
 
@@ -1452,7 +1503,7 @@ static hipError_t enqueue_round(pt_batch *b, uint32_t K, bool timed)
                        : g->wave  ? launch_wave(g->L, a, g->block, g->lds, b->stream)
                        : g->mixed ? launch_chunk_mixed(a, g->block, g->lds, b->stream)
                        : g->ctx   ? launch_chunk_ctx(g->kind, g->L, a, g->block, g->lds, b->stream)
-                                  : launch_chunk(g->kind, g->L, g->rpt, g->wide, a, g->block, g->lds, b->stream);
+                                  : launch_chunk(g->kind, g->L, g->rpt, g->wide, g->quad, a, g->block, g->lds, b->stream);
         if (e != hipSuccess) return e;
         if (timed) {
             e = hipEventRecord(e1, b->stream);
@@ -1636,8 +1687,10 @@ ArenaLayout arena_layout(int R, int n)
 
 // A context that reads the problem, tables and banks of `tm` (device data the
 // template owns) and owns only its replica state, on stream s.
+// The state lives in `mem` (arena_layout(R, n).total bytes, owned by the
+// caller), and the setup is only enqueued on s: nothing waits for it.
 int clone_ctx(const pt_ctx *tm, uint64_t seed, int has_target, int32_t target, uint64_t cap, hipStream_t s,
-              pt_ctx **out)
+              void *mem, pt_ctx **out)
 {
     *out = nullptr;
     pt_ctx *c = new pt_ctx();
@@ -1665,11 +1718,8 @@ int clone_ctx(const pt_ctx *tm, uint64_t seed, int has_target, int32_t target, u
 #undef VIEW
     const int R = c->R, n = c->n;
     const ArenaLayout A = arena_layout(R, n);
-    hipError_t e = c->arena.alloc(A.total);
-    if (e != hipSuccess) {
-        delete c;
-        return fail(e == hipErrorOutOfMemory ? PT_ENOMEM : PT_EDEVICE, "request state: %s", hipGetErrorString(e));
-    }
+    hipError_t e = hipSuccess;
+    c->arena.view(mem, A.total);
     char *base = c->arena.as<char>();
     const size_t P = (size_t)std::max(R - 1, 1);
     c->spins.view(base + A.spins, (size_t)R * n);
@@ -1700,7 +1750,8 @@ int clone_ctx(const pt_ctx *tm, uint64_t seed, int has_target, int32_t target, u
     c->hI.epoch = 0;
     fill_inst_pointers(c);
     // the request's bank cursors start at its own seeded offsets
-    std::vector<int32_t> cur(R, 0);
+    std::vector<int32_t> &cur = c->h_cursor0;
+    cur.assign(R, 0);
     for (int r = 0; r < R; ++r)
         if (c->h_bank_n[r] > 0)
             cur[r] = (int32_t)(host_philox_word0((uint32_t)r, 0, TAG_BANK, c->hI.seed_lo, c->hI.seed_hi) %
@@ -1714,7 +1765,7 @@ int clone_ctx(const pt_ctx *tm, uint64_t seed, int has_target, int32_t target, u
         (e = hipMemcpyAsync(c->bank_n.p, c->h_bank_n.data(), (size_t)R * 4, hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(c->cursor.p, cur.data(), (size_t)R * 4, hipMemcpyHostToDevice, s)))
         return bail(e);
-    int rc = reset_state(c, nullptr, 0);   // ends with a stream synchronisation
+    int rc = reset_state(c, nullptr, 0, false);
     if (rc) {
         delete c;
         return rc;
@@ -1761,7 +1812,29 @@ struct pt_server {
     pt_batch *batch = nullptr;
     std::vector<SrvActive> active;
     std::vector<InstStatus> status;
+    // request-state arenas of retired requests, reused by later ones of the
+    // same size (no device allocation or free, and so no device-wide
+    // synchronisation, per request once the pool is warm)
+    std::vector<std::pair<size_t, void *>> pool;
+    ~pt_server()
+    {
+        for (auto &m : pool) (void)hipFree(m.second);
+    }
 };
+
+// An arena of `bytes` for a new request: from the pool, else allocated.
+static void *arena_take(pt_server *S, size_t bytes)
+{
+    for (size_t k = 0; k < S->pool.size(); ++k)
+        if (S->pool[k].first == bytes) {
+            void *p = S->pool[k].second;
+            S->pool[k] = S->pool.back();
+            S->pool.pop_back();
+            return p;
+        }
+    void *p = nullptr;
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
 
 static void serve_publish(pt_server *S, std::vector<pt_result> &res)
 {
@@ -1813,7 +1886,13 @@ static void serve_admit(pt_server *S, bool &dirty, std::vector<pt_result> &out)
         }
         if (rc && !S->active.empty()) return;   // wait for running requests to finish
         pt_ctx *c = nullptr;
-        if (!rc) rc = clone_ctx(tm, r.rq.seed, r.rq.has_target, r.rq.target, r.rq.sweep_cap, S->batch->stream, &c);
+        void *mem = nullptr;
+        if (!rc) {
+            mem = arena_take(S, need);
+            if (!mem) rc = fail(PT_ENOMEM, "request state of %zu bytes: device allocation failed", need);
+        }
+        if (!rc) rc = clone_ctx(tm, r.rq.seed, r.rq.has_target, r.rq.target, r.rq.sweep_cap, S->batch->stream, mem, &c);
+        if (rc && mem) S->pool.push_back({need, mem});
         const double now = seconds_since(S->t0);
         {
             std::lock_guard<std::mutex> lk(S->mu);
@@ -1852,7 +1931,8 @@ static int serve_round(pt_server *S, bool &dirty, std::vector<pt_result> &out)
     }
     const double ta = seconds_since(S->t0);
     const uint32_t K = (uint32_t)S->opts.chunk_sweeps;
-    hipError_t e = enqueue_round(b, K, false);
+    b->ev_used = 0;
+    hipError_t e = enqueue_round(b, K, true);
     if (e != hipSuccess) return fail(PT_EDEVICE, "serving round: %s", hipGetErrorString(e));
     LaunchGroup *g = b->groups[0];
     S->status.resize(g->ctxs.size());
@@ -1862,8 +1942,15 @@ static int serve_round(pt_server *S, bool &dirty, std::vector<pt_result> &out)
     HIPCHK(hipMemcpyAsync(err, b->err.p, 32, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     if (err[0]) return fail(PT_ETIMEOUT, "cross-workgroup exchange timed out in a serving round");
+    double gpu_ms = 0.0;
+    for (size_t k = 0; k + 1 < b->ev_used; k += 2) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, b->ev_pool[k], b->ev_pool[k + 1]));
+        gpu_ms += ms;
+    }
+    b->ev_used = 0;
     double attempts = 0.0;
-    std::vector<SrvActive> keep;
+    std::vector<SrvActive> keep, retired;
     for (size_t k = 0; k < S->active.size(); ++k) {
         SrvActive &a = S->active[k];
         const InstStatus &st = S->status[k];
@@ -1876,8 +1963,9 @@ static int serve_round(pt_server *S, bool &dirty, std::vector<pt_result> &out)
             continue;
         }
         if (a.r.rq.best_out)
-            HIPCHK(hipMemcpy(a.r.rq.best_out, a.c->best_spins.p, (size_t)a.c->n, hipMemcpyDeviceToHost));
-        pt_result o = serve_result(a.r, PT_OK, a.t_admit, seconds_since(S->t0));
+            HIPCHK(hipMemcpyAsync(a.r.rq.best_out, a.c->best_spins.p, (size_t)a.c->n, hipMemcpyDeviceToHost,
+                                  b->stream));
+        pt_result o = serve_result(a.r, PT_OK, a.t_admit, 0.0);
         o.hit = hit ? 1 : 0;
         o.first_hit = st.first_hit;
         o.best_energy = st.best_E;
@@ -1885,18 +1973,26 @@ static int serve_round(pt_server *S, bool &dirty, std::vector<pt_result> &out)
         o.best_t = st.best_t;
         o.sweeps = t;
         out.push_back(o);
-        pt_destroy(a.c);
-        {
-            std::lock_guard<std::mutex> lk(S->mu);
-            S->st.mem_used -= a.bytes;
-            S->st.completed += 1;
-        }
+        retired.push_back(a);
         dirty = true;
+    }
+    // the best configurations are on their way to the callers' buffers: wait
+    // once, then stamp the results and hand the arenas back to the pool
+    if (!retired.empty()) HIPCHK(hipStreamSynchronize(b->stream));
+    const double t_done = seconds_since(S->t0);
+    for (size_t k = out.size() - retired.size(); k < out.size(); ++k) out[k].t_done = t_done;
+    for (auto &a : retired) {
+        S->pool.push_back({a.bytes, a.c->arena.p});
+        delete a.c;                  // views only: frees no device memory
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->st.mem_used -= a.bytes;
+        S->st.completed += 1;
     }
     S->active.swap(keep);
     std::lock_guard<std::mutex> lk(S->mu);
     S->st.rounds += 1;
     S->st.busy_s += seconds_since(S->t0) - ta;
+    S->st.gpu_busy_s += gpu_ms * 1e-3;
     S->st.attempts += attempts;
     S->st.active = (int32_t)S->active.size();
     return PT_OK;
@@ -1927,6 +2023,7 @@ static void serve_worker(pt_server *S)
             for (auto &a : S->active) {
                 out.push_back(serve_result(a.r, rc, a.t_admit, now));
                 a.c->broken = true;
+                S->pool.push_back({a.bytes, a.c->arena.p});
                 pt_destroy(a.c);
             }
             S->active.clear();
@@ -2033,7 +2130,10 @@ extern "C" int pt_serve_stop(pt_server *s)
         s->cv_work.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
-    for (auto &a : s->active) pt_destroy(a.c);
+    for (auto &a : s->active) {
+        s->pool.push_back({a.bytes, a.c->arena.p});
+        pt_destroy(a.c);
+    }
     pt_batch_destroy(s->batch);
     delete s;
     return PT_OK;

@@ -55,6 +55,15 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x)
 }
 
 // Three-input XOR in one instruction (gfx950 v_bitop3_b32, truth table 0x96).
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// a * b + c on the two 16-bit halves of each word (v_pk_mad_u16)
+__device__ __forceinline__ uint32_t pk_mad_u16(uint32_t a, uint32_t b, uint32_t c)
+{
+    const u16x2 r = __builtin_bit_cast(u16x2, a) * __builtin_bit_cast(u16x2, b) + __builtin_bit_cast(u16x2, c);
+    return __builtin_bit_cast(uint32_t, r);
+}
+
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
@@ -549,6 +558,196 @@ using CsrSweep = CsrSweepT<false>;
 using CsrSweepWide = CsrSweepT<true>;
 
 // ---------------------------------------------------------------------------
+// General sparse graph, four storages per lane ("quad" sweeper). The storages
+// of a workgroup are interleaved: byte k of site i's GS-byte group (GS = G
+// rounded up to a multiple of 4) holds storage k's spin as a down-bit (1 for
+// -1). One dword read gives a site's spins in four storages, so a lane
+// updates one site of four storages at once:
+//   with u = b_i ^ b_j ^ [J_ij < 0] (1 when the bond is unsatisfied, per
+//   byte) and u_h = b_i ^ [h_i < 0], the four energy changes of flipping
+//   site i are 2 d, d = m_i I_i = D_i - 2 U, with D_i = sum_j |J_ij| + |h_i|
+//   and U = sum_j |J_ij| u_ij + |h_i| u_h (Methods, Eq. 4),
+// and U is summed byte-parallel by 24-bit multiply-adds (no byte carries
+// while D_i <= 255). The bond records hold the neighbour's byte offset, the
+// sign mask and |J|, so a bond costs an add, a three-input XOR and a
+// multiply-add. Each storage's decision then reads its own slot's flip
+// table. Used for throughput tilings of general graphs (G >= 4, n <= 4096,
+// every site bound D_i <= 255); random halves are staged per sweep as in
+// CsrSweepT, interleaved like the storages.
+struct QuadGraph {
+    uint4 *site;     // [n]: x, y bond range; z = D_i | |h_i| << 16; w = 0x01010101 if h_i < 0
+    uint4 *bond;     // [nnz]: x = j * GS, y = 0x01010101 if J < 0, z = |J| in both 16-bit halves
+    int16_t *cs;     // free sites sorted by colour [nfree]
+    int *coff;       // [ncolors + 1]
+};
+
+__host__ __device__ inline size_t quad_graph_bytes(int n, int nnz, int nfree, int ncolors)
+{
+    size_t o = 0;
+    o = (o + (size_t)n * 16 + 15) & ~(size_t)15;
+    o = (o + (size_t)(nnz > 0 ? nnz : 1) * 16 + 15) & ~(size_t)15;
+    o = (o + (size_t)(nfree > 0 ? nfree : 1) * 2 + 15) & ~(size_t)15;
+    o = (o + (size_t)(ncolors + 1) * 4 + 15) & ~(size_t)15;
+    return o;
+}
+
+struct CsrQuadSweep {
+    static constexpr int RPTV = 1;
+    static constexpr int MAXT = 256;
+    static constexpr int MINW = 4;      // at most 128 VGPRs: four waves per SIMD
+    static constexpr bool RND = true;
+    int n, G, GS, nr;
+    QuadGraph gr;
+
+    __host__ __device__ static int group_bytes(int G) { return (G + 3) & ~3; }
+    __device__ static size_t graph_bytes(const InstDev &I) { return quad_graph_bytes(I.n, I.nnz, I.nfree, I.ncolors); }
+
+    __device__ void setup(const InstDev &I, int G_)
+    {
+        n = I.n;
+        G = G_;
+        GS = group_bytes(G_);
+        nr = (n + 7) & ~7;
+    }
+
+    __device__ __forceinline__ void bind(const InstDev &I, unsigned char *base, int tid, int bs)
+    {
+        size_t o = 0;
+        gr.site = (uint4 *)(base + o); o = (o + (size_t)n * 16 + 15) & ~(size_t)15;
+        gr.bond = (uint4 *)(base + o); o = (o + (size_t)(I.nnz > 0 ? I.nnz : 1) * 16 + 15) & ~(size_t)15;
+        gr.cs = (int16_t *)(base + o); o = (o + (size_t)(I.nfree > 0 ? I.nfree : 1) * 2 + 15) & ~(size_t)15;
+        gr.coff = (int *)(base + o);
+        for (int i = tid; i < n; i += bs) {
+            const int e0 = I.row_ptr[i], e1 = I.row_ptr[i + 1];
+            int D = 0;
+            for (int e = e0; e < e1; ++e) D += abs((int)I.Jc[e]);
+            const int h = I.h[i];
+            D += abs(h);
+            gr.site[i] = make_uint4((uint32_t)e0, (uint32_t)e1, (uint32_t)D | ((uint32_t)abs(h) << 16),
+                                    h < 0 ? 0x01010101u : 0u);
+        }
+        for (int e = tid; e < I.nnz; e += bs) {
+            const int J = I.Jc[e];
+            gr.bond[e] = make_uint4((uint32_t)I.col[e] * (uint32_t)GS, J < 0 ? 0x01010101u : 0u,
+                                    (uint32_t)abs(J) * 0x10001u, 0u);
+        }
+        for (int k = tid; k < I.nfree; k += bs) gr.cs[k] = I.color_sites[k];
+        for (int c = tid; c <= I.ncolors; c += bs) gr.coff[c] = I.color_off[c];
+    }
+
+    __device__ __forceinline__ void sweep(const InstDev &I, int G_, int s0, uint32_t t, const int *slot_of,
+                                          int8_t *sp, const uint32_t *tab, int stride, int *Elds,
+                                          unsigned *flips_lds, uint16_t *rnd)
+    {
+        (void)G_;
+        const int tid = threadIdx.x, bs = blockDim.x;
+        const int ncall = nr >> 3;
+        // random halves of every (site, storage), interleaved like the spins
+        for (int idx = tid; idx < G * ncall; idx += bs) {
+            const int k = idx / ncall, q = idx - k * ncall;
+            const P4 r = philox_v((uint32_t)q, t, (uint32_t)(s0 + slot_of[k]), TAG_SWEEP, I.seed_lo, I.seed_hi);
+            uint16_t *dst = rnd + (size_t)(8 * q) * GS + k;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) dst[s * GS] = (uint16_t)(r.v[s >> 1] >> (16 * (s & 1)));
+        }
+        __syncthreads();
+        const int D = I.D;
+        const int nq = GS >> 2;                 // storage quads
+        const int qd = tid % nq, j0 = tid / nq, dj = bs / nq;
+        const bool lane_on = j0 < dj;           // threads past the last whole quad row idle
+        const int qo = 4 * qd;                  // byte offset of this lane's quad in a site group
+        int tb[4];
+        uint32_t vm = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int st = qo + k;
+            const bool ok = st < G;
+            tb[k] = ok ? slot_of[st] * stride + D : D;
+            vm |= ok ? (1u << (8 * k)) : 0u;
+        }
+        int e_acc[4] = {0, 0, 0, 0};
+        unsigned f_acc[4] = {0, 0, 0, 0};
+        const int ncol = I.ncolors;
+        for (int c = 0; c < ncol; ++c) {
+            const int off = gr.coff[c], cnt = gr.coff[c + 1] - off;
+            for (int s = lane_on ? j0 : cnt; s < cnt; s += dj) {
+                const int i = gr.cs[off + s];
+                const uint4 si = gr.site[i];
+                const uint32_t a_own = (uint32_t)i * (uint32_t)GS + (uint32_t)qo;
+                uint32_t own = *(const uint32_t *)(sp + a_own);
+                uint32_t U = pk_mad_u16(own ^ si.w, (si.z >> 16) * 0x10001u, 0u);
+                uint32_t e = si.x;
+                // four bonds a step: their records, then their neighbours, are
+                // independent reads (two LDS round trips per four bonds)
+                for (; e + 4 <= si.y; e += 4) {
+                    const uint4 b0 = gr.bond[e], b1 = gr.bond[e + 1], b2 = gr.bond[e + 2], b3 = gr.bond[e + 3];
+                    const uint32_t n0 = *(const uint32_t *)(sp + b0.x + (uint32_t)qo);
+                    const uint32_t n1 = *(const uint32_t *)(sp + b1.x + (uint32_t)qo);
+                    const uint32_t n2 = *(const uint32_t *)(sp + b2.x + (uint32_t)qo);
+                    const uint32_t n3 = *(const uint32_t *)(sp + b3.x + (uint32_t)qo);
+                    U = pk_mad_u16(xor3(own, n0, b0.y), b0.z, U);
+                    U = pk_mad_u16(xor3(own, n1, b1.y), b1.z, U);
+                    U = pk_mad_u16(xor3(own, n2, b2.y), b2.z, U);
+                    U = pk_mad_u16(xor3(own, n3, b3.y), b3.z, U);
+                }
+                for (; e < si.y; ++e) {
+                    const uint4 b = gr.bond[e];
+                    const uint32_t nb = *(const uint32_t *)(sp + b.x + (uint32_t)qo);
+                    U = pk_mad_u16(xor3(own, nb, b.y), b.z, U);
+                }
+                const int Dsite = (int)(si.z & 0xFFFFu);
+                const uint2 hh = *(const uint2 *)(rnd + a_own);
+                uint32_t T[4], hs[4];
+                int d[4];
+                bool acc[4], maybe[4];
+                bool any_maybe = false;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    d[k] = Dsite - 2 * (int)((U >> (8 * k)) & 0xFFu);   // m_i I_i of storage 4 qd + k
+                    T[k] = tab[tb[k] + d[k]];
+                    const uint32_t w = k < 2 ? hh.x : hh.y;
+                    hs[k] = (k & 1) ? (w & 0xFFFF0000u) : (w << 16);
+                    acc[k] = coarse_accept(T[k], hs[k], maybe[k]) && ((vm >> (8 * k)) & 1u);
+                    maybe[k] = maybe[k] && ((vm >> (8 * k)) & 1u);
+                    any_maybe |= maybe[k];
+                }
+                if (any_lane(any_maybe)) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if (maybe[k]) {
+                            const P4 r2 = philox(opaque((uint32_t)(i >> 3)), t, (uint32_t)(s0 + slot_of[qo + k]), TAG_REFINE,
+                                                 I.seed_lo, I.seed_hi);
+                            const int wq = (i & 7) >> 1;
+                            const uint32_t wd = wq == 0 ? r2.v[0] : wq == 1 ? r2.v[1] : wq == 2 ? r2.v[2] : r2.v[3];
+                            const uint32_t lo = ((i & 1) ? (wd >> 16) : wd) & 0xFFFFu;
+                            acc[k] = (T[k] == ALWAYS) || ((hs[k] | lo) < T[k]);
+                        }
+                    }
+                }
+                uint32_t F = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    F |= acc[k] ? (1u << (8 * k)) : 0u;
+                    e_acc[k] += acc[k] ? 2 * d[k] : 0;       // the flip changes E by 2 d
+                    f_acc[k] += acc[k] ? 1u : 0u;
+                }
+                *(uint32_t *)(sp + a_own) = own ^ F;
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int st = qo + k;
+            if (lane_on && st < G && (e_acc[k] != 0 || f_acc[k] != 0)) {
+                atomicAdd(&Elds[st], e_acc[k]);
+                atomicAdd(&flips_lds[slot_of[st]], f_acc[k]);
+            }
+        }
+        __syncthreads();
+    }
+};
+
+// ---------------------------------------------------------------------------
 // LDS carve-up shared by the persistent kernel and the host's size query.
 // tsw: swap-threshold rows of the pairs a workgroup decides, pair slot p for
 // global pair r = s0 - 1 + p (p = 0 and p = G are the cross-workgroup pairs).
@@ -566,10 +765,12 @@ struct ChunkLds {
     uint32_t *usw;             // [2][65] swap uniforms by cycle parity (lane l: pair s0+l; 64: pair s0-1)
     int8_t *cx;                // contextual proposal: candidate storage [SB]
     uint8_t *cm;               // and its context mask [SB], both in the storage layout
+    uint32_t *ckey;            // and the CONTEXT keys of its sites [n], site order
+    int *chist;                // radix-select histogram [256]
 };
 
 struct ChunkOff {
-    size_t sp, tab, ints, src, rnd, toff, tsw, xst, usw, graph, ctx, cmask, total;
+    size_t sp, tab, ints, src, rnd, toff, tsw, xst, usw, graph, ctx, cmask, ckey, chist, total;
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -591,6 +792,8 @@ __host__ __device__ __forceinline__ ChunkOff chunk_lds_offsets(int G, int SB, in
     f.graph = o; o = align16(o + graph_bytes);
     f.ctx = o; o = align16(o + (contextual ? (size_t)SB : 0));     // contextual candidate
     f.cmask = o; o = align16(o + (contextual ? (size_t)SB : 0));   // and its context mask
+    f.ckey = o; o = align16(o + (contextual ? (size_t)n * 4 : 0)); // context keys
+    f.chist = o; o = align16(o + (contextual ? (size_t)256 * 4 : 0));
     f.total = o;
     return f;
 }
@@ -615,7 +818,9 @@ __host__ __device__ __forceinline__ ChunkOff chunk_lds_offsets(int G, int SB, in
     c.xstage = (uint32_t *)((base) + (f).xst);                    \
     c.usw = (uint32_t *)((base) + (f).usw);                       \
     c.cx = (int8_t *)((base) + (f).ctx);                          \
-    c.cm = (uint8_t *)((base) + (f).cmask)
+    c.cm = (uint8_t *)((base) + (f).cmask);                       \
+    c.ckey = (uint32_t *)((base) + (f).ckey);                     \
+    c.chist = (int *)((base) + (f).chist)
 
 // Run parameters of one instance, read once per launch (kept in SGPRs).
 struct RunParams {
@@ -686,6 +891,11 @@ struct SweepCall<LatSweep<L, RPT>> {
     }
     static __device__ int SB(const LatSweep<L, RPT> &) { return LatSweep<L, RPT>::SB; }
     static __device__ int lidx(const LatSweep<L, RPT> &, int i) { return LatSweep<L, RPT>::lidx(i); }
+    // storages are consecutive blocks of SB bytes holding the spins as +-1
+    static __device__ int layout_g(const LatSweep<L, RPT> &, int G) { return G; }
+    static __device__ int pos(const LatSweep<L, RPT> &, int st, int p) { return st * LatSweep<L, RPT>::SB + p; }
+    static __device__ int8_t enc(int m) { return (int8_t)m; }
+    static __device__ int dec(int8_t v) { return v; }
     static __device__ size_t graph_bytes(const InstDev &) { return 0; }
     static __device__ void bind(LatSweep<L, RPT> &, const InstDev &, unsigned char *, int, int) {}
 
@@ -738,6 +948,10 @@ struct SweepCall<CsrSweepT<W>> {
     }
     static __device__ int SB(const CsrSweepT<W> &s) { return s.SB; }
     static __device__ int lidx(const CsrSweepT<W> &, int i) { return i; }
+    static __device__ int layout_g(const CsrSweepT<W> &, int G) { return G; }
+    static __device__ int pos(const CsrSweepT<W> &s, int st, int p) { return st * s.SB + p; }
+    static __device__ int8_t enc(int m) { return (int8_t)m; }
+    static __device__ int dec(int8_t v) { return v; }
     static __device__ size_t graph_bytes(const InstDev &I) { return CsrSweepT<W>::graph_bytes(I); }
     static __device__ void bind(CsrSweepT<W> &sw, const InstDev &I, unsigned char *base, int tid, int bs)
     {
@@ -776,6 +990,29 @@ struct SweepCall<CsrSweepT<W>> {
     }
 };
 
+template <>
+struct SweepCall<CsrQuadSweep> {
+    static __device__ __forceinline__ void run(CsrQuadSweep &sw, const InstDev &I, int G, int s0, uint32_t t, ChunkLds &c,
+                                               int stride)
+    {
+        sw.sweep(I, G, s0, t, c.slot_of, c.sp, c.tab, stride, c.Elds, c.flips, c.rnd);
+    }
+    // the carve-up takes GS slots of n bytes each: the interleaved storages
+    // fill GS * n bytes and the staged random halves GS * nr
+    static __device__ int SB(const CsrQuadSweep &s) { return s.n; }
+    static __device__ int lidx(const CsrQuadSweep &, int i) { return i; }
+    static __device__ size_t graph_bytes(const InstDev &I) { return CsrQuadSweep::graph_bytes(I); }
+    static __device__ void bind(CsrQuadSweep &sw, const InstDev &I, unsigned char *base, int tid, int bs)
+    {
+        sw.bind(I, base, tid, bs);
+    }
+    static __device__ int layout_g(const CsrQuadSweep &s, int) { return s.GS; }
+    static __device__ int pos(const CsrQuadSweep &s, int st, int p) { return p * s.GS + st; }
+    static __device__ int8_t enc(int m) { return m < 0 ? 1 : 0; }
+    static __device__ int dec(int8_t v) { return v ? -1 : 1; }
+    struct CtxView {};
+};
+
 __device__ __forceinline__ uint32_t pick4(const P4 &r, int k)
 {
     return k == 0 ? r.v[0] : k == 1 ? r.v[1] : k == 2 ? r.v[2] : r.v[3];
@@ -784,8 +1021,8 @@ __device__ __forceinline__ uint32_t pick4(const P4 &r, int k)
 // Contextual proposals of the slots this workgroup holds (Supp. context
 // ablation), at the proposal stage of cycle cyc. For each proposal-enabled
 // slot, in increasing order: the candidate starts from the slot's bank entry;
-// each free site joins the context with the probability behind ctx_T (Philox
-// CONTEXT) and then holds the slot's current value; ctx_sweeps colored sweeps
+// the ctx_K free sites of smallest CONTEXT key join the context and hold the
+// slot's current values; ctx_sweeps colored sweeps
 // at the slot's beta (Philox CTXSWEEP, one 32-bit word per attempt) update
 // the other free sites; the Delta-E rule of Eq. 2 judges the candidate's
 // recomputed energy. Every thread of the block takes part. Only the
@@ -796,8 +1033,9 @@ __device__ __forceinline__ void ctx_proposals(const typename SweepCall<Sw>::CtxV
                                               uint32_t cyc, ChunkLds &c, int SB, int stride)
 {
     const int tid = threadIdx.x, bs = blockDim.x, n = I.n, D = I.D;
-    const uint32_t k0 = I.seed_lo, k1 = I.seed_hi, cT = I.ctx_T;
+    const uint32_t k0 = I.seed_lo, k1 = I.seed_hi;
     const int K = I.ctx_sweeps;
+    const int KC = I.ctx_K;        // context sites per proposal
     for (int l = 0; l < G; ++l) {
         const int r = s0 + l;
         const int B = I.bank_n[r];
@@ -811,12 +1049,59 @@ __device__ __forceinline__ void ctx_proposals(const typename SweepCall<Sw>::CtxV
         const int st = c.stor_of[l];
         const int8_t *cur = c.sp + st * SB;
         const int8_t *src = I.bank[r] + (size_t)k * n;
+        // the context: the KC free sites of smallest (key, index), found by a
+        // radix select of the KC-th smallest key (8 bits a pass, highest first)
+        for (int i = tid; i < n; i += bs)
+            c.ckey[i] = pick4(philox((uint32_t)i >> 2, cyc, (uint32_t)r, TAG_CONTEXT, k0, k1), i & 3);
+        uint32_t tau = 0;
+        int take_eq = 0;                 // sites with key == tau that join, lowest index first
+        if (KC > 0 && KC < I.nfree) {
+            uint32_t prefix = 0;
+            int remaining = KC;
+            for (int pass = 0; pass < 4; ++pass) {
+                const int shift = 24 - 8 * pass;
+                for (int x = tid; x < 256; x += bs) c.chist[x] = 0;
+                __syncthreads();
+                for (int i = tid; i < n; i += bs) {
+                    const uint32_t key = c.ckey[i];
+                    if (I.clamp[i] == 0 && (pass == 0 || (key >> (shift + 8)) == prefix))
+                        atomicAdd(&c.chist[(key >> shift) & 255u], 1);
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    int below = 0, b = 0;
+                    while (below + c.chist[b] < remaining) below += c.chist[b++];
+                    c.misc[9] = b;
+                    c.misc[10] = remaining - below;
+                    c.misc[11] = c.chist[b];
+                }
+                __syncthreads();
+                prefix = (prefix << 8) | (uint32_t)c.misc[9];
+                remaining = c.misc[10];
+            }
+            tau = prefix;
+            take_eq = remaining;             // of the c.misc[11] sites whose key is tau
+        }
+        const bool all_eq = KC >= I.nfree || take_eq >= c.misc[11];
         for (int i = tid; i < n; i += bs) {
             const int li = SweepCall<Sw>::ctx_lidx(i);
-            const uint32_t u = pick4(philox((uint32_t)i >> 2, cyc, (uint32_t)r, TAG_CONTEXT, k0, k1), i & 3);
-            const bool ctx = I.clamp[i] == 0 && (cT == ALWAYS || u < cT);
+            const uint32_t key = c.ckey[i];
+            const bool ctx = I.clamp[i] == 0 && KC > 0 &&
+                             (KC >= I.nfree || key < tau || (key == tau && all_eq));
             c.cm[li] = ctx ? 1 : 0;
             c.cx[li] = ctx ? cur[li] : src[i];
+        }
+        __syncthreads();
+        if (!all_eq && tid == 0) {
+            // equal keys at the cut (rare): the lowest indices among them join
+            int left = take_eq;
+            for (int i = 0; i < n && left > 0; ++i) {
+                if (I.clamp[i] != 0 || c.ckey[i] != tau) continue;
+                const int li = SweepCall<Sw>::ctx_lidx(i);
+                c.cm[li] = 1;
+                c.cx[li] = cur[li];
+                --left;
+            }
         }
         __syncthreads();
         const uint32_t *trow = c.tab + l * stride + D;
@@ -891,18 +1176,21 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
     Sw sw;
     sw.setup(I, G);
     const int SB = SweepCall<Sw>::SB(sw);
+    const int GL = SweepCall<Sw>::layout_g(sw, G);   // slots the LDS carve-up is sized for
     const int stride = P.stride;
-    const bool contextual = CTX && (I.ctx_T | (uint32_t)I.ctx_sweeps) != 0;
-    const ChunkOff lof = chunk_lds_offsets(G, SB, stride, Sw::RND ? ((n + 7) & ~7) : 0, a.tsw_entries, n,
+    const bool contextual = CTX && I.ctx_on != 0;
+    const ChunkOff lof = chunk_lds_offsets(GL, SB, stride, Sw::RND ? ((n + 7) & ~7) : 0, a.tsw_entries, n,
                                            SweepCall<Sw>::graph_bytes(I), contextual);
-    CHUNK_LDS_POINTERS(c, lof, G, lds_raw);
+    CHUNK_LDS_POINTERS(c, lof, GL, lds_raw);
     SweepCall<Sw>::bind(sw, I, lds_raw + lof.graph, tid, bs);
 
     // stage tables and state
     for (int x = tid; x < G * stride; x += bs) c.tab[x] = I.tflip[(size_t)s0 * stride + x];
+    for (int x = tid; x < GL * SB; x += bs) c.sp[x] = SweepCall<Sw>::enc(1);   // padding storages too
+    __syncthreads();
     for (int x = tid; x < G * n; x += bs) {
         int l = x / n, i = x - l * n;
-        c.sp[l * SB + SweepCall<Sw>::lidx(sw, i)] = I.spins[(size_t)(s0 + l) * n + i];
+        c.sp[SweepCall<Sw>::pos(sw, l, SweepCall<Sw>::lidx(sw, i))] = SweepCall<Sw>::enc(I.spins[(size_t)(s0 + l) * n + i]);
     }
     if (tid == 0) {
         int o = 0;
@@ -1012,8 +1300,9 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
             for (int l = 0; l < G; ++l) {
                 const int8_t *src = (const int8_t *)c.src[l];
                 if (src) {
-                    int8_t *dst = c.sp + c.stor_of[l] * SB;
-                    for (int i = tid; i < n; i += bs) dst[SweepCall<Sw>::lidx(sw, i)] = src[i];
+                    const int st = c.stor_of[l];
+                    for (int i = tid; i < n; i += bs)
+                        c.sp[SweepCall<Sw>::pos(sw, st, SweepCall<Sw>::lidx(sw, i))] = SweepCall<Sw>::enc(src[i]);
                 }
             }
             __syncthreads();
@@ -1038,20 +1327,19 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
             for (int side = 0; side < 2; ++side) {
                 if (!(side == 0 ? down : up)) continue;
                 const int st = c.stor_of[side == 0 ? 0 : G - 1];
-                const int8_t *stor = c.sp + st * SB;
                 unsigned long long *out = it.xbuf + ((size_t)(it.w * 2 + side) * 2 + buf) * it.xwords;
                 for (int ch0 = wv; ch0 < nch; ch0 += 4 * nwv) {
                     int8_t v[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {   // four chunks' reads in flight
                         const int j = 64 * (ch0 + q * nwv) + lane;
-                        v[q] = stor[j < n ? j : n - 1];
+                        v[q] = c.sp[SweepCall<Sw>::pos(sw, st, j < n ? j : n - 1)];
                     }
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int ch = ch0 + q * nwv;
                         if (ch >= nch) break;
-                        const unsigned long long m = __ballot(64 * ch + lane < n && v[q] > 0);
+                        const unsigned long long m = __ballot(64 * ch + lane < n && SweepCall<Sw>::dec(v[q]) > 0);
                         const int wd = 2 * ch + lane;
                         if (lane < 2 && wd < nw)
                             __hip_atomic_store(out + wd, tag | (lane ? (m >> 32) : (m & 0xFFFFFFFFull)),
@@ -1199,8 +1487,9 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                     const int xs = side == 0 ? x0 : x1;
                     if (!xs) continue;
                     const uint32_t *stage = c.xstage + side * (nw + 1);
-                    int8_t *stor = c.sp + (xs - 1) * SB;
-                    for (int j = tid; j < n; j += bs) stor[j] = ((stage[j >> 5] >> (j & 31)) & 1u) ? 1 : -1;
+                    for (int j = tid; j < n; j += bs)
+                        c.sp[SweepCall<Sw>::pos(sw, xs - 1, j)] =
+                            SweepCall<Sw>::enc(((stage[j >> 5] >> (j & 31)) & 1u) ? 1 : -1);
                 }
                 __syncthreads();
                 if (tid == 0) {
@@ -1211,8 +1500,8 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
         }
         const int bst = c.misc[2];
         if (bst) {   // snapshot of the new best state, before the next sweep changes it
-            const int8_t *src = c.sp + (bst - 1) * SB;
-            for (int i = tid; i < n; i += bs) it.best_spins[i] = src[SweepCall<Sw>::lidx(sw, i)];
+            for (int i = tid; i < n; i += bs)
+                it.best_spins[i] = (int8_t)SweepCall<Sw>::dec(c.sp[SweepCall<Sw>::pos(sw, bst - 1, SweepCall<Sw>::lidx(sw, i))]);
             __syncthreads();
             if (tid == 0) c.misc[2] = 0;
         }
@@ -1226,7 +1515,8 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
     // write the state back by slot
     for (int x = tid; x < G * n; x += bs) {
         int l = x / n, i = x - l * n;
-        I.spins[(size_t)(s0 + l) * n + i] = c.sp[c.stor_of[l] * SB + SweepCall<Sw>::lidx(sw, i)];
+        I.spins[(size_t)(s0 + l) * n + i] =
+            (int8_t)SweepCall<Sw>::dec(c.sp[SweepCall<Sw>::pos(sw, c.stor_of[l], SweepCall<Sw>::lidx(sw, i))]);
     }
     for (int l = tid; l < G; l += bs) {
         I.E[s0 + l] = c.Elds[c.stor_of[l]];

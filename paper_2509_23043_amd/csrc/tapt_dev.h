@@ -29,7 +29,9 @@ struct InstDev {
     int32_t has_target, target, ncolors, nfree;
     int32_t nnz, ctx_sweeps;                // ctx_sweeps: completion sweeps of a contextual proposal
     uint32_t seed_lo, seed_hi;
-    uint32_t epoch, ctx_T;                  // epoch bumps when the state is replaced; ctx_T: context threshold
+    uint32_t epoch;                         // bumps when the state is replaced
+    int32_t ctx_K;                          // context sites of a contextual proposal
+    int32_t ctx_on, ctx_pad;                // 1: proposals are contextual
     int64_t prop_start, prop_period, prop_stop;
     uint64_t sweep_cap;                     // batched runs stop at this sweep count
 

@@ -106,3 +106,19 @@ def test_contextual_errors():
     binding.Batch([ctx], chunk_sweeps=10).sweep(10)
     ctx.set_context(0.0, 0)
     ctx.sweep(1)
+
+
+def test_exact_count_context_on_a_large_lattice():
+    """L = 10 (1000 free sites), fraction 0.125: every contextual proposal
+    clamps exactly 125 sites, selected on the device by a radix select of the
+    Philox keys, and the chain equals the oracle's."""
+    announce("contextual proposals, EA L=10 R=4, G=2, fraction 0.125, 2 completion sweeps, 48 sweeps")
+    g = inputs.ea_lattice(10, 23)
+    betas = inputs.geometric_ladder(4)
+    banks = {r: inputs.random_bank(1000, 3, seed=800 + r) for r in range(3)}
+    ctx, ref = _pair(g, betas, 29, banks, 0.125, 2, prop_start=4, prop_period=4)
+    bt = binding.Batch([ctx], replicas_per_wg=2, chunk_sweeps=24)
+    bt.sweep(48)
+    ref.run(48)
+    compare(ctx, ref)
+    assert ref.prop_att.sum() == 3 * 12
