@@ -228,6 +228,22 @@ int pt_batch_set_stream(pt_batch *b, void *stream);
  * Resets both. */
 int pt_batch_kernel_time(pt_batch *b, double *ms, uint64_t *launches);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): run the k
+ * contexts batched for n_sweeps sweeps exactly as pt_batch_create +
+ * pt_batch_sweep + pt_batch_destroy would (bit-identical results, same
+ * tilings and kernels; o as for pt_batch_create, use_graph ignored), with no
+ * pt_batch object and no device allocation: the launch's work items, block
+ * order, per-workgroup best records and snapshots, exchange words, status
+ * and error flag live in a static device array of 32 MiB that the library
+ * holds on each GPU it runs on until the process ends. A launch that needs
+ * more returns PT_ENOMEM. stream: hipStream_t as void*, or NULL for the
+ * stream of ctxs[0]; the call returns when the work is complete. Every call
+ * on one GPU shares that GPU's array, so calls that overlap on one GPU (from
+ * several threads) race and must be serialised by the caller. Host-side
+ * planning uses ordinary host memory. */
+int pt_batch_run_static(pt_ctx *const *ctxs, int32_t k, const pt_batch_opts *o, uint64_t n_sweeps, void *stream);
+
 /* ---- serving: continuous batching of solve requests ----
  *
  * A server owns a worker thread and a stream. Callers register problems

@@ -78,7 +78,7 @@ EXPORTS = ["pt_create", "pt_destroy", "pt_propose", "pt_propose_device", "pt_set
            "pt_state", "pt_state_device", "pt_set_state", "pt_save_size", "pt_save", "pt_restore",
            "pt_summary_get", "pt_counters",
            "pt_energy_device", "pt_set_stream", "pt_batch_create", "pt_batch_sweep", "pt_batch_destroy",
-           "pt_batch_set_stream", "pt_batch_kernel_time", "pt_serve_start",
+           "pt_batch_set_stream", "pt_batch_kernel_time", "pt_batch_run_static", "pt_serve_start",
            "pt_serve_register",
            "pt_serve_submit", "pt_serve_poll", "pt_serve_stats_get", "pt_serve_clock", "pt_serve_stop",
            "pt_probe_lds", "pt_last_error"]
@@ -121,6 +121,7 @@ def lib():
     L.pt_batch_destroy.argtypes = [vp]
     L.pt_batch_set_stream.argtypes = [vp, vp]
     L.pt_batch_kernel_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
+    L.pt_batch_run_static.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(_BatchOpts), C.c_uint64, vp]
     L.pt_serve_start.argtypes = [C.POINTER(_ServeOpts), C.POINTER(vp)]
     L.pt_serve_register.argtypes = [vp, vp, C.POINTER(C.c_int32)]
     L.pt_serve_submit.argtypes = [vp, C.POINTER(_Request), C.POINTER(C.c_uint64)]
@@ -289,6 +290,17 @@ def probe_lds(bytes_per_read=16, blocks_per_cu=4, iters=2048):
     if rc != PT_OK:
         raise TaptError(rc, "LDS probe failed")
     return tb.value, ms.value
+
+
+def run_static(contexts, n_sweeps, replicas_per_wg=0, replicas_per_thread=0, chunk_sweeps=0, kernel="auto",
+               stream_ptr=None):
+    """pt_batch_run_static: a batched run of the contexts that allocates no
+    device memory (the launch's buffers live in the library's static scratch)."""
+    contexts = list(contexts)
+    arr = (C.c_void_p * len(contexts))(*[c.h for c in contexts])
+    o = _BatchOpts(int(replicas_per_wg), int(replicas_per_thread), int(chunk_sweeps), 0, KERNELS[kernel])
+    _check(lib().pt_batch_run_static(arr, len(contexts), C.byref(o), int(n_sweeps),
+                                     C.c_void_p(stream_ptr) if stream_ptr else None))
 
 
 class Batch:

@@ -1226,8 +1226,8 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
 }
 
 // Where a launch group's device buffers come from: fresh allocations, or
-// 256-byte aligned views into a region the caller provides, in which case
-// nothing is allocated.
+// 256-byte aligned views into a region the caller provides (the static
+// scratch of pt_batch_run_static), in which case nothing is allocated.
 struct GroupMem {
     char *base = nullptr;             // null: allocate
     size_t cap = 0, used = 0;
@@ -1643,6 +1643,75 @@ extern "C" int pt_batch_destroy(pt_batch *b)
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     delete b;
     return PT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched runs that allocate nothing: the launch's device buffers live in a
+// file-scope static device array. In host code the array's name is only a
+// stand-in for it; its device address (one per GPU) comes from
+// hipGetSymbolAddress and is the only form in which host code uses it.
+
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES];
+
+// Device address of `scratch` on the current device `dev`, looked up once
+// per device.
+static int static_scratch(int dev, char **out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(PT_EUNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(PT_EDEVICE, "static scratch address: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = (char *)g_scratch_ptr[dev];
+    return PT_OK;
+}
+
+extern "C" int pt_batch_run_static(pt_ctx *const *ctxs, int32_t k, const pt_batch_opts *o, uint64_t n_sweeps,
+                                   void *stream)
+{
+    if (!ctxs || k < 1) return fail(PT_EINVAL, "need at least one context");
+    if (!ctxs[0]) return fail(PT_EINVAL, "context 0 missing");
+    const int dev = ctxs[0]->device;
+    HIPCHK(hipSetDevice(dev));
+    char *base = nullptr;
+    int rc = static_scratch(dev, &base);
+    if (rc) return rc;
+    pt_batch b;                        // on the stack: owns no stream and no device memory
+    if (o) b.opts = *o;
+    b.opts.use_graph = 0;
+    if (b.opts.chunk_sweeps <= 0) b.opts.chunk_sweeps = 1000;
+    b.device = dev;
+    HIPCHK(hipDeviceGetAttribute(&b.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    b.stream = stream ? (hipStream_t)stream : ctxs[0]->stream;
+    for (int i = 0; i < k; ++i) {
+        if (!ctxs[i] || ctxs[i]->broken) return fail(PT_EINVAL, "context %d missing or unusable", i);
+        if (ctxs[i]->device != dev) return fail(PT_EINVAL, "context %d lives on another device", i);
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(PT_EINVAL, "context %d appears twice", i);
+        b.ctxs.push_back(ctxs[i]);
+    }
+    LaunchGroup *g = nullptr;
+    rc = pick_group(&b, b.ctxs, &g);
+    if (rc) return rc;
+    b.groups.push_back(g);
+    GroupMem mem;
+    mem.base = base;
+    mem.cap = STATIC_SCRATCH_BYTES;
+    // the error flag, cleared: a previous call may have left it set
+    HIPCHK(mem.take(b.err, 32));
+    HIPCHK(launch_zero(b.err.p, 32, b.stream));
+    rc = build_group(&b, g, mem);
+    if (rc) return rc;
+    return batch_sweep(&b, n_sweeps, false);
 }
 
 // ---------------------------------------------------------------------------
