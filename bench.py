@@ -42,7 +42,7 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12       # int32 lane-ops/s: 256 CUs x 64 
 LDS_BYTES_PER_ATTEMPT = 14                       # 6 neighbour spins + 6 couplings + own spin read + write
 LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12          # 256 B/clk/CU x 256 CUs x 2.4 GHz
 LDS_PEAK_SOURCE = ("256 B/clk/CU (CDNA4 LDS reads, twice CDNA3's 128) x 256 CUs x 2.4 GHz; the LDS probe "
-                   "(bench.py --workload lds-probe) reads 137 TB/s with ds_read_b128, above the 78.6 TB/s "
+                   "(bench.py --workload probe) reads 137 TB/s with ds_read_b128, above the 78.6 TB/s "
                    "a 128 B/clk LDS could give")
 HBM_PEAK_TBS = 8.0
 
@@ -87,9 +87,11 @@ def parse():
     ap.add_argument("--R", type=int, default=32)
     ap.add_argument("--bank", type=int, default=256)
     ap.add_argument("--workload", default="pt",
-                    choices=("pt", "mixed", "fact", "lds-probe", "bankgen-sg", "bankgen-fact", "tts", "context"),
-                    help="pt: the batched PT benchmark (default); mixed / fact: only the mixed-size or the "
-                         "factorization leg (for profiling); lds-probe: LDS read bandwidth of the device; "
+                    choices=("pt", "mixed", "fact", "plain", "probe", "bankgen-sg", "bankgen-fact", "tts",
+                             "context"),
+                    help="pt: the batched PT benchmark (default); mixed / fact / plain: only the mixed-size, "
+                         "the factorization or the plain-path leg (for profiling); probe: LDS read "
+                         "bandwidth and VALU issue rates of the device; "
                          "bankgen-*: the long-run MCMC bank "
                          "generation of Supp. Table S3 (3D spin glass L=10, or 16-bit factorization); "
                          "tts: the factorization TTS study; context: the proposal-context ablation")
@@ -120,6 +122,11 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size workload")
     ap.add_argument("--no-fact", action="store_true", help="skip the factorization workload")
     ap.add_argument("--mixed-sweeps", type=int, default=100_000, help="mixed: timed sweeps")
+    ap.add_argument("--plain-sweeps", type=int, default=2000, help="plain: sweeps of the plain-path leg")
+    ap.add_argument("--leg-tiling", default=None,
+                    help="mixed / fact legs: G,rpt,kernel instead of the autotuner's choice (for profiling)")
+    ap.add_argument("--leg-bank", type=int, default=256,
+                    help="mixed / fact legs: bank entries per slot (the workloads' 256; fewer for profiling)")
     ap.add_argument("--serve-rates", default="10,30,100,300,1000", help="Poisson arrival rates, req/s")
     ap.add_argument("--serve-requests", default="1000,1000,1000,1000,1000", help="requests per rate")
     ap.add_argument("--serve-cap", type=int, default=100_000, help="sweep cap per request")
@@ -328,8 +335,12 @@ def timed_batch(ctxs, tiling, sweeps, chunk, warm_chunks=1):
     return dict(value=att / dt / 1e9, seconds=dt, attempts=att, avg_ms=ms / max(launches, 1), launches=launches)
 
 
-def tuned_tiling(cases, cfg, log):
+def tuned_tiling(cases, cfg, log, fixed=None):
+    """The autotuner's tiling, or a fixed G,rpt,kernel string (profiling)."""
     from paper_2509_23043_amd import autotune
+    if fixed:
+        G, rpt, kern = fixed.split(",")
+        return (int(G), int(rpt), kern), []
     res = autotune.tune(lambda M: case_contexts(cases, cfg, None, M=M), Ms=(1,), warm=200, timed=1000, log=log)
     return (res["replicas_per_wg"], res["replicas_per_thread"], res["kernel"]), res["scan"]
 
@@ -343,9 +354,9 @@ def mixed_leg(args, log):
     cfg = workloads.CFG3
     cases = workloads.ea_cases(cfg)
     t0 = time.perf_counter()
-    banks = pt_banks(cases, cfg["B"], log, seed0=1_300_000)
+    banks = pt_banks(cases, args.leg_bank, log, seed0=1_300_000)
     log(f"mixed: banks in {time.perf_counter() - t0:.1f} s")
-    tiling, scan = tuned_tiling(cases, cfg, log)
+    tiling, scan = tuned_tiling(cases, cfg, log, args.leg_tiling)
     ctxs = case_contexts(cases, cfg, banks)
     r = timed_batch(ctxs, tiling, args.mixed_sweeps, cfg["chunk"])
     for c in ctxs:
@@ -362,8 +373,8 @@ def mixed_leg(args, log):
                                   attempts_per_ns=d["attempts_per_ns"]) for d in scan],
                 roofline=roof,
                 workload="3D EA +-J L in {6,8,10,12,16} x 8 instances, R = 24/30/36/42/48 beta 0.2..3.0 "
-                         "geometric, Metropolis, M=1, proposals every 50 sweeps from 256-entry plain-PT banks "
-                         "on all but the 2 coldest slots; one persistent launch sequence of 10^4-sweep launches")
+                         f"geometric, Metropolis, M=1, proposals every 50 sweeps from {args.leg_bank}-entry plain-PT "
+                         "banks on all but the 2 coldest slots; one persistent launch sequence of 10^4-sweep launches")
 
 
 def factorization_leg(args, log):
@@ -378,9 +389,9 @@ def factorization_leg(args, log):
     cfg = workloads.CFG4
     cases = workloads.fact_cases(cfg)
     t0 = time.perf_counter()
-    banks = pt_banks(cases, cfg["B"], log, seed0=1_400_000)
+    banks = pt_banks(cases, args.leg_bank, log, seed0=1_400_000)
     log(f"factorization: banks in {time.perf_counter() - t0:.1f} s")
-    tiling, scan = tuned_tiling(cases, cfg, log)
+    tiling, scan = tuned_tiling(cases, cfg, log, args.leg_tiling)
     ctxs = case_contexts(cases, cfg, banks)
     r = timed_batch(ctxs, tiling, cfg["sweeps"], 2000)
     for c in ctxs:
@@ -431,7 +442,7 @@ def factorization_leg(args, log):
                                 "64-product batch"),
                 workload="8x8-bit array multipliers (200 spins, 176 free) of 64 distinct semiprimes, R=32 beta "
                          "0.2..3.0 geometric, Metropolis, M=1, DSATUR colors, proposals every 100 sweeps from "
-                         "256-entry plain-PT banks on the 23 hottest slots")
+                         f"{args.leg_bank}-entry plain-PT banks on the 23 hottest slots")
 
 
 def inputs_factor(case, spins):
@@ -835,7 +846,7 @@ def main():
     if args.workload == "context":
         context_study(args, lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True))
         return
-    if args.workload == "lds-probe":
+    if args.workload == "probe":
         import torch
         from paper_2509_23043_amd import binding
         torch.cuda.set_device(0)
@@ -848,9 +859,34 @@ def main():
                                  TBps=round(tb, 2), ms=round(ms, 3)))
                 print(f"[bench] ds_read_b{8 * nbytes}, {bpc} workgroups of 256 per CU: {tb:.2f} TB/s", file=sys.stderr,
                       flush=True)
+        valu = {}
+        for op, name in ((0, "v_xor_b32"), (1, "v_mul_hi_u32"), (2, "v_mul_lo_u32"), (3, "v_mad_u64_u32")):
+            rate, ms = binding.probe_valu(op, 4096)
+            valu[name] = round(rate, 4)
+            print(f"[bench] {name}: {rate:.3f} wave-instructions per clock per CU", file=sys.stderr, flush=True)
         best = max(r["TBps"] for r in rows)
         print(json.dumps(dict(metric="LDS read bandwidth", value=best, unit="TB/s", peak=round(LDS_PEAK_TBS, 1),
-                              frac=round(best / LDS_PEAK_TBS, 4), rows=rows)), flush=True)
+                              frac=round(best / LDS_PEAK_TBS, 4), rows=rows,
+                              valu_wave_instr_per_clk_per_cu=valu)), flush=True)
+        return
+    if args.workload == "plain":
+        import torch
+        from paper_2509_23043_amd import binding
+        torch.cuda.set_device(0)
+        binding.lib()
+        log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
+        probs, betas = problems(1, args.L, args.R)
+        bank = make_banks(probs, betas, args.bank, args.R - 2, log)
+        ctx = build_contexts(probs, betas, bank, [3000], M=args.sweeps_per_swap)[0]
+        ctx.sweep(100)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.sweep(args.plain_sweeps)
+        dt = time.perf_counter() - t0
+        v = args.plain_sweeps * args.R * args.L ** 3 / dt / 1e9
+        log(f"plain: {v:.4f} attempts/ns over {args.plain_sweeps} sweeps")
+        print(json.dumps(dict(metric="plain path attempts/ns", value=round(v, 4), unit="attempts/ns",
+                              sweeps=args.plain_sweeps)), flush=True)
         return
     if args.workload in ("mixed", "fact"):
         import torch

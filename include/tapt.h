@@ -339,6 +339,13 @@ int pt_serve_stop(pt_server *s);
  * duration. blocks_per_cu in 1..8. Allocates and frees a small output
  * buffer. */
 int pt_probe_lds(int32_t bytes_per_read, int32_t blocks_per_cu, uint32_t iters, double *tbps, double *ms);
+/* VALU issue rate of one instruction (op 0: v_xor_b32, 1: v_mul_hi_u32,
+ * 2: v_mul_lo_u32, 3: v_mad_u64_u32) in wave-instructions per clock per CU,
+ * from 4 (op 3) or 8 independent
+ * chains per lane, eight waves per SIMD; the clock is the device's
+ * reported peak. A full-rate 32-bit operation issues 1 per clock per CU (4
+ * SIMDs, 4 clocks per wave64 instruction). */
+int pt_probe_valu(int32_t op, uint32_t iters, double *instr_per_clk_per_cu, double *ms);
 
 const char *pt_last_error(void);
 

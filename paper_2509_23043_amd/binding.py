@@ -81,7 +81,7 @@ EXPORTS = ["pt_create", "pt_destroy", "pt_propose", "pt_propose_device", "pt_set
            "pt_batch_set_stream", "pt_batch_kernel_time", "pt_batch_run_static", "pt_serve_start",
            "pt_serve_register",
            "pt_serve_submit", "pt_serve_poll", "pt_serve_stats_get", "pt_serve_clock", "pt_serve_stop",
-           "pt_probe_lds", "pt_last_error"]
+           "pt_probe_lds", "pt_probe_valu", "pt_last_error"]
 
 _lib = None
 
@@ -130,6 +130,7 @@ def lib():
     L.pt_serve_clock.argtypes = [vp]
     L.pt_serve_stop.argtypes = [vp]
     L.pt_probe_lds.argtypes = [C.c_int32, C.c_int32, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.pt_probe_valu.argtypes = [C.c_int32, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.pt_last_error.restype = C.c_char_p
     for name in EXPORTS:
         if name not in ("pt_last_error", "pt_serve_clock"):
@@ -290,6 +291,16 @@ def probe_lds(bytes_per_read=16, blocks_per_cu=4, iters=2048):
     if rc != PT_OK:
         raise TaptError(rc, "LDS probe failed")
     return tb.value, ms.value
+
+
+def probe_valu(op, iters=4096):
+    """VALU issue rate (wave-instructions per clock per CU, ms) of op 0
+    (v_xor_b32), 1 (v_mul_hi_u32), 2 (v_mul_lo_u32) or 3 (v_mad_u64_u32)."""
+    r, ms = C.c_double(), C.c_double()
+    rc = lib().pt_probe_valu(int(op), int(iters), C.byref(r), C.byref(ms))
+    if rc != PT_OK:
+        raise TaptError(rc, "VALU probe failed")
+    return r.value, ms.value
 
 
 def run_static(contexts, n_sweeps, replicas_per_wg=0, replicas_per_thread=0, chunk_sweeps=0, kernel="auto",

@@ -1124,6 +1124,9 @@ struct GroupPlan {
     bool wide = false, quad = false;
 };
 
+// Fewest slots per workgroup for the four-storages-per-lane sparse sweeper.
+constexpr int QUAD_MIN_G = 12;
+
 static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
 {
     for (size_t k = 0; k < g->ctxs.size(); ++k) {
@@ -1177,14 +1180,17 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
     P.order.assign((size_t)per * nx8, -1);
     for (int idx = 0; idx < n_items; ++idx) P.order[(size_t)(idx % per) * nx8 + idx / per] = idx;
     P.grid = per * nx8;
-    // Sparse graphs in the throughput tilings (every workgroup at least 4
-    // slots, 256 threads, no contextual proposals, every site's field bound
-    // below 256) take the four-storages-per-lane sweeper.
+    // Sparse graphs in the coarse tilings (every workgroup at least
+    // QUAD_MIN_G slots, 256 threads, no contextual proposals, every site's
+    // field bound below 256) take the four-storages-per-lane sweeper. With
+    // fewer slots a colour class has too few (site, quad) items to fill a
+    // workgroup, and the sweep is bound by each item's chain of LDS reads,
+    // which the quad layout does not shorten.
     P.quad = g->kind == KIND_CSR && !g->mixed && !g->ctx && P.block <= 256;
     for (size_t k = 0; k < g->ctxs.size() && P.quad; ++k) {
         if (g->ctxs[k]->D > 255) P.quad = false;
         for (int w = 0; w < P.ctx[k].W; ++w)
-            if (P.items[P.ctx[k].first + w].G < 4) P.quad = false;
+            if (P.items[P.ctx[k].first + w].G < QUAD_MIN_G) P.quad = false;
     }
     // LDS: the largest carve-up over the items (every item lays out its own
     // region with the common swap-table capacity)

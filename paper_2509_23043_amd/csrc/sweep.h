@@ -54,7 +54,6 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x)
     return x;
 }
 
-// Three-input XOR in one instruction (gfx950 v_bitop3_b32, truth table 0x96).
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 // a * b + c on the two 16-bit halves of each word (v_pk_mad_u16)
@@ -64,6 +63,7 @@ __device__ __forceinline__ uint32_t pk_mad_u16(uint32_t a, uint32_t b, uint32_t 
     return __builtin_bit_cast(uint32_t, r);
 }
 
+// Three-input XOR in one instruction (gfx950 v_bitop3_b32, truth table 0x96).
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);

@@ -464,3 +464,35 @@ def test_ladder_acceptance_matches_oracle_and_adapts():
     b0 = np.linspace(0.2, 3.0, 12)
     b1, hist = ladder.adapt(g6, b0, rounds=4, sweeps=2000, runs=4, seed=7)
     assert hist[-1][1].std() < 0.7 * hist[0][1].std(), (hist[0][1], hist[-1][1])
+
+
+@pytest.mark.parametrize("R,G,M", [(32, 16, 1), (32, 32, 1), (26, 13, 1), (48, 24, 2), (64, 32, 0)])
+def test_multipliers_quad_sweeper(R, G, M):
+    """Coarse tilings of sparse graphs (at least 12 slots per workgroup) run
+    the four-storages-per-lane sweeper: interleaved storages, padding storages
+    when G is not a multiple of 4 (G = 13), six quads per site (G = 24),
+    independent chains (M = 0, the bank-generation runs); 8-bit multipliers
+    against the oracle."""
+    announce(f"quad sweeper: 3 x 8-bit multipliers, R={R} G={G} M={M}")
+    import oracle
+    betas = inputs.geometric_ladder(R) if M else np.full(R, 1.3)
+    egnd = -3 * 64 - 4 * 8 * 7
+    ctxs, cases = [], []
+    for i, (C, p, q) in enumerate(inputs.semiprimes(8, 3, seed=4700 + R)):
+        g = inputs.multiplier(8, C)
+        banks = ({r: inputs.random_bank(g["n"], 5, seed=4800 + 32 * i + r, clamp=g["clamp"]) for r in range(0, R - 4, 3)}
+                 if M else None)
+        kw = dict(M=M, target=egnd)
+        if M:
+            kw.update(prop_start=2 * M, prop_period=2 * M)
+        c = binding.Context(g, betas, seed=4900 + i, **kw)
+        for r, b in (banks or {}).items():
+            c.propose(r, b)
+        ctxs.append(c)
+        cases.append((g, banks, kw, 4900 + i))
+    bt = binding.Batch(ctxs, replicas_per_wg=G, chunk_sweeps=50)
+    bt.sweep(100)
+    for c, (g, banks, kw, seed) in zip(ctxs, cases):
+        ref = oracle.Run(g, betas, seed=seed, banks=banks, **kw)
+        ref.run(100)
+        compare(c, ref)
