@@ -33,12 +33,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "spin-flip attempts/ns (batched vs plain) + p50/p99 time-to-target per request"
-# algorithmic integer operations per single-spin attempt on the +-J cubic lattice:
-# 6 multiply-accumulates for the local field, 2 for dE/2 = m I and the table
-# index, 7.5 for one eighth of a Philox4x32-10 call (10 rounds of two 32x32->64
-# multiplies and four XORs, 8 uniforms per call), 3 for compare, flip, energy.
-OPS_PER_ATTEMPT = 6 + 2 + 7.5 + 3
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12       # int32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+# algorithmic integer VALU issue slots per single-spin attempt on the +-J cubic
+# lattice: 6 multiply-accumulates for the local field, 2 for dE/2 = m I and the
+# table index, 10 for one eighth of a Philox4x32-10 call (10 rounds of two
+# 32x32->64 multiplies, each at half rate so two slots, and four XORs; the key
+# schedule is uniform and runs on the scalar unit; 8 uniforms per call) and 3
+# for compare, flip and energy.
+OPS_PER_ATTEMPT = 6 + 2 + 10 + 3
+# int32 VALU lane slots/s: 128 lanes/clk/CU (two wave64 instructions per clock
+# per CU, the rate of the fp32 vector peak, 157.3 TFLOP/s = 2 x 128 x 256 x 2.4
+# GHz) x 256 CUs x 2.4 GHz. The probe issues 1.66 v_xor_b32 and 0.91
+# v_mul_hi_u32 / 0.87 v_mad_u64_u32 wave instructions per clock per CU.
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+VALU_PEAK_SOURCE = ("128 int32 lanes/clk/CU x 256 CUs x 2.4 GHz (32-bit multiplies issue at half rate and "
+                    "count two slots); the VALU probe (bench.py --workload probe) issues 1.66 v_xor_b32 "
+                    "wave instructions per clock per CU of the 2.0 this assumes")
 LDS_BYTES_PER_ATTEMPT = 14                       # 6 neighbour spins + 6 couplings + own spin read + write
 LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12          # 256 B/clk/CU x 256 CUs x 2.4 GHz
 LDS_PEAK_SOURCE = ("256 B/clk/CU (CDNA4 LDS reads, twice CDNA3's 128) x 256 CUs x 2.4 GHz; the LDS probe "
@@ -57,6 +66,16 @@ def csr_bytes_per_attempt(problem):
     return float(4 * deg.mean() + 2)
 
 
+def csr_ops_per_attempt(problem):
+    """Algorithmic VALU issue slots of one attempt on a general sparse graph:
+    one multiply-accumulate per bond (mean degree of the free sites), the
+    field term, and the 2 + 10 + 3 of the lattice count (dE and table index,
+    an eighth of a Philox call, compare / flip / energy)."""
+    rp = np.asarray(problem["row_ptr"])
+    free = np.asarray(problem["clamp"]) == 0
+    return float(np.diff(rp)[free].mean() + 1 + 2 + 10 + 3)
+
+
 def rooflines(attempts_per_launch, avg_ms, lds_bytes, ops=OPS_PER_ATTEMPT, traffic=None, kernel=None):
     """LDS roofline (the target bound) with the ALU one beside it, for one
     kernel: algorithmic bytes / ops per launch over the measured launch time."""
@@ -71,9 +90,75 @@ def rooflines(attempts_per_launch, avg_ms, lds_bytes, ops=OPS_PER_ATTEMPT, traff
                 bytes_per_attempt=round(lds_bytes, 2), peak_source=LDS_PEAK_SOURCE,
                 alu=dict(achieved=round(alu, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TOP/s",
                          frac=round(alu / VALU_PEAK_TOPS, 4), ops_per_attempt=ops,
-                         peak_source="64 int32 lanes/clk/CU x 256 CUs x 2.4 GHz"),
+                         peak_source=VALU_PEAK_SOURCE),
                 measured_binding=max(fr, key=fr.get),
                 fractions={k: round(v, 4) for k, v in fr.items()})
+
+
+SWEEP_KERNELS = ("chunk_kernel", "pm_kernel", "plain_", "wave_kernel")
+
+
+def rocprof_summary(d):
+    """Markdown tables of a rocprofv3 ``-f csv`` output directory: the kernel
+    statistics, the sweep-kernel dispatches grouped by (kernel, grid, block,
+    LDS, VGPRs), and each counter's mean per dispatch grouped by (kernel,
+    grid)."""
+    import collections
+    import csv
+    import glob
+
+    def files(pat):
+        return sorted(glob.glob(os.path.join(d, "**", pat), recursive=True))
+
+    def col(r, *names):
+        return next((r[n] for n in names if n in r), "")
+
+    def sweep(name):
+        return any(k in name for k in SWEEP_KERNELS)
+
+    out = []
+    for f in files("*kernel_stats.csv"):
+        out += ["### kernel stats\n", "| kernel | calls | total ms | avg ms | min ms | max ms | % |",
+                "|---|---|---|---|---|---|---|"]
+        for r in list(csv.DictReader(open(f)))[:12]:
+            out.append(f"| `{r['Name'][:100]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                       f"{float(r['AverageNs']) / 1e6:.4f} | {float(r['MinNs']) / 1e6:.4f} | "
+                       f"{float(r['MaxNs']) / 1e6:.4f} | {float(r['Percentage']):.2f} |")
+    for f in files("*kernel_trace.csv"):
+        g = collections.defaultdict(list)
+        for r in csv.DictReader(open(f)):
+            if not sweep(r["Kernel_Name"]):
+                continue
+            key = (r["Kernel_Name"][:100], col(r, "Grid_Size", "Grid_Size_X"),
+                   col(r, "Workgroup_Size", "Workgroup_Size_X"), col(r, "LDS_Block_Size", "Lds_Size"),
+                   col(r, "VGPR_Count", "Arch_VGPR_Count"))
+            g[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+        out += ["\n### sweep-kernel dispatches by launch shape\n",
+                "| kernel | grid | block | LDS B | VGPRs | dispatches | mean ms | min ms | max ms |",
+                "|---|---|---|---|---|---|---|---|---|"]
+        for k, v in sorted(g.items(), key=lambda kv: -sum(kv[1]))[:12]:
+            out.append(f"| `{k[0]}` | {k[1]} | {k[2]} | {k[3]} | {k[4]} | {len(v)} | {sum(v) / len(v):.4f} | "
+                       f"{min(v):.4f} | {max(v):.4f} |")
+    for f in files("*counter_collection.csv"):
+        g = collections.defaultdict(lambda: collections.defaultdict(float))
+        ids = collections.defaultdict(set)
+        for r in csv.DictReader(open(f)):
+            if not sweep(r["Kernel_Name"]):
+                continue
+            key = (r["Kernel_Name"][:100], col(r, "Grid_Size", "Grid_Size_X"))
+            did = col(r, "Dispatch_Id", "Correlation_Id")
+            g[key][(did, r["Counter_Name"])] += float(r["Counter_Value"])
+            ids[key].add(did)
+        out += ["\n### counters per dispatch (mean over the dispatches of each launch shape)\n",
+                "| kernel | grid | dispatches | counter | mean per dispatch |", "|---|---|---|---|---|"]
+        for key in sorted(g, key=lambda k: -len(ids[k]))[:6]:
+            per = collections.defaultdict(list)
+            for (_, cname), v in g[key].items():
+                per[cname].append(v)
+            for cname in sorted(per):
+                vals = per[cname]
+                out.append(f"| `{key[0]}` | {key[1]} | {len(ids[key])} | {cname} | {sum(vals) / len(vals):.4g} |")
+    return "\n".join(out)
 
 
 def parse():
@@ -118,6 +203,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=1500)
     ap.add_argument("--calib-copy", action="store_true", help="also run a 256 MiB device copy (PMC scaling)")
+    ap.add_argument("--rocprof-summary", default=None, metavar="DIR",
+                    help="print markdown tables of a rocprofv3 csv output directory (kernel stats, sweep-kernel "
+                         "dispatches by launch shape, counters per dispatch) and exit; uses no GPU")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size workload")
     ap.add_argument("--no-fact", action="store_true", help="skip the factorization workload")
@@ -399,7 +487,7 @@ def factorization_leg(args, log):
     bpa = csr_bytes_per_attempt(cases[0]["g"])
     log(f"factorization: {r['value']:.1f} attempts/ns over {cfg['sweeps']} sweeps, tiling {tiling}, "
         f"chunk kernel {r['avg_ms']:.3f} ms avg")
-    roof = rooflines(r["attempts"] / max(r["launches"], 1), r["avg_ms"], bpa,
+    roof = rooflines(r["attempts"] / max(r["launches"], 1), r["avg_ms"], bpa, ops=csr_ops_per_attempt(cases[0]["g"]),
                      kernel="chunk_kernel<CsrSweep>")
     # time to solution: fresh contexts, chunks of 1000 sweeps until every
     # product has hit its ground energy or the cap
@@ -836,6 +924,9 @@ def context_study(args, log):
 
 def main():
     args = parse()
+    if args.rocprof_summary:
+        print(rocprof_summary(args.rocprof_summary))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); instances would shard "
               f"across GPUs with no communication between them", file=sys.stderr)
