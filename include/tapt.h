@@ -227,6 +227,12 @@ int pt_batch_set_stream(pt_batch *b, void *stream);
  * stream (launches replayed from a hipGraph are not timed), and their count.
  * Resets both. */
 int pt_batch_kernel_time(pt_batch *b, double *ms, uint64_t *launches);
+/* The launch plan of the batch as text, one line per launch group (contexts
+ * that share a kernel): "kernel=K sweeper=S contexts=N grid=G block=B lds=L".
+ * K is chunk, ctx, mixed, wave, pm or pm1; S names the sweeper of a chunk or
+ * ctx launch (latticeLxRPT, csr, csr-wide, csr-quad, csr-row) or "-". The
+ * text is truncated to len - 1 bytes and NUL-terminated. */
+int pt_batch_describe(pt_batch *b, char *buf, int32_t len);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): run the k

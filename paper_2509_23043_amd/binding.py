@@ -78,7 +78,7 @@ EXPORTS = ["pt_create", "pt_destroy", "pt_propose", "pt_propose_device", "pt_set
            "pt_state", "pt_state_device", "pt_set_state", "pt_save_size", "pt_save", "pt_restore",
            "pt_summary_get", "pt_counters",
            "pt_energy_device", "pt_set_stream", "pt_batch_create", "pt_batch_sweep", "pt_batch_destroy",
-           "pt_batch_set_stream", "pt_batch_kernel_time", "pt_batch_run_static", "pt_serve_start",
+           "pt_batch_set_stream", "pt_batch_kernel_time", "pt_batch_describe", "pt_batch_run_static", "pt_serve_start",
            "pt_serve_register",
            "pt_serve_submit", "pt_serve_poll", "pt_serve_stats_get", "pt_serve_clock", "pt_serve_stop",
            "pt_probe_lds", "pt_probe_valu", "pt_last_error"]
@@ -121,6 +121,7 @@ def lib():
     L.pt_batch_destroy.argtypes = [vp]
     L.pt_batch_set_stream.argtypes = [vp, vp]
     L.pt_batch_kernel_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
+    L.pt_batch_describe.argtypes = [vp, C.c_char_p, C.c_int32]
     L.pt_batch_run_static.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(_BatchOpts), C.c_uint64, vp]
     L.pt_serve_start.argtypes = [C.POINTER(_ServeOpts), C.POINTER(vp)]
     L.pt_serve_register.argtypes = [vp, vp, C.POINTER(C.c_int32)]
@@ -338,6 +339,17 @@ class Batch:
         ms, n = C.c_double(), C.c_uint64()
         _check(lib().pt_batch_kernel_time(self.h, C.byref(ms), C.byref(n)))
         return float(ms.value), int(n.value)
+
+    def describe(self):
+        """The launch plan: one dict per launch group (kernel, sweeper,
+        contexts, grid, block, lds)."""
+        buf = C.create_string_buffer(4096)
+        _check(lib().pt_batch_describe(self.h, buf, len(buf)))
+        out = []
+        for line in buf.value.decode().splitlines():
+            d = dict(kv.split("=", 1) for kv in line.split())
+            out.append({k: (int(v) if v.isdigit() else v) for k, v in d.items()})
+        return out
 
     def close(self):
         if getattr(self, "h", None):

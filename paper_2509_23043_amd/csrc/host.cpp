@@ -32,10 +32,11 @@ bool lattice_supported(int L);
 int lattice_max_threads();
 int lattice_threads(int L, int G, int rpt);
 size_t chunk_lds_bytes(int kind, int n, int G, int stride, int tsw_entries, int nnz, int nfree, int ncolors,
-                       bool contextual, bool quad);
-hipError_t launch_chunk(int kind, int L, int rpt, bool wide, bool quad, const ChunkArgs &a, int block, size_t lds,
-                        hipStream_t s);
-hipError_t chunk_occupancy(int kind, int L, int rpt, bool wide, bool quad, int block, size_t lds, int *blocks_per_cu);
+                       bool contextual, bool quad, size_t row_graph);
+hipError_t launch_chunk(int kind, int L, int rpt, bool wide, bool quad, bool row, const ChunkArgs &a, int block,
+                        size_t lds, hipStream_t s);
+hipError_t chunk_occupancy(int kind, int L, int rpt, bool wide, bool quad, bool row, int block, size_t lds,
+                           int *blocks_per_cu);
 hipError_t launch_chunk_ctx(int kind, int L, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t chunk_occupancy_ctx(int kind, int L, int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_finish(const WorkItem *items, const int *first_item, int n_inst, uint32_t K, InstStatus *status,
@@ -277,6 +278,7 @@ struct Prepared {
     std::vector<int16_t> color_sites;
     std::vector<int32_t> color_off;
     int64_t nfree;
+    int maxdeg = 0, maxcnt = 0, maxabsj = 0;   // over free sites / colour classes / bonds
 };
 
 static int prepare(const pt_graph *g, Prepared &P)
@@ -383,6 +385,9 @@ static int prepare(const pt_graph *g, Prepared &P)
         D = std::max(D, (int)s);
     }
     P.D = D;
+    for (int i = 0; i < n; ++i)
+        if (!P.clamp[i]) P.maxdeg = std::max(P.maxdeg, rp[i + 1] - rp[i]);
+    for (int v : jv) P.maxabsj = std::max(P.maxabsj, std::abs(v));
     P.row_ptr = rp;
     P.col.resize(cl.size());
     P.Jc.resize(jv.size());
@@ -395,6 +400,7 @@ static int prepare(const pt_graph *g, Prepared &P)
         for (int i = 0; i < n; ++i)
             if (color[i] == c && !P.clamp[i]) P.color_sites.push_back((int16_t)i);
         P.color_off[c + 1] = (int32_t)P.color_sites.size();
+        P.maxcnt = std::max(P.maxcnt, P.color_off[c + 1] - P.color_off[c]);
     }
     if (P.color_sites.empty()) P.color_sites.push_back(0);
     return PT_OK;
@@ -613,6 +619,9 @@ extern "C" int pt_create(const pt_graph *g, const double *betas, int32_t R, cons
     I.ncolors = P.ncolors;
     I.nfree = (int32_t)P.nfree;
     I.nnz = (int32_t)P.col.size();
+    I.maxdeg = P.maxdeg;
+    I.maxcnt = P.maxcnt;
+    I.maxabsj = P.maxabsj;
     I.seed_lo = (uint32_t)o->seed;
     I.seed_hi = (uint32_t)(o->seed >> 32);
     I.epoch = 0;
@@ -1036,6 +1045,7 @@ struct LaunchGroup {
     bool ctx = false;                 // some context has contextual proposals (chunk_kernel_ctx)
     bool wide = false;                // sparse graphs at 512 threads: the lane-sharing sweeper
     bool quad = false;                // sparse graphs, four storages per lane (CsrQuadSweep)
+    bool row = false;                 // sparse graphs, packed rows (CsrRowSweep)
     size_t lds;
     std::vector<pt_ctx *> ctxs;
     std::vector<int> Gs;              // per context: slots per workgroup (max)
@@ -1121,7 +1131,7 @@ struct GroupPlan {
     std::vector<Ctx> ctx;
     size_t nbest = 0, nbs = 0, nx = 0, lds = 0;
     int block = 64, grid = 0, tsw_max = 0, per_cu = 0;
-    bool wide = false, quad = false;
+    bool wide = false, quad = false, row = false;
 };
 
 // Fewest slots per workgroup for the four-storages-per-lane sparse sweeper.
@@ -1129,6 +1139,15 @@ constexpr int QUAD_MIN_G = 12;
 
 static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
 {
+    // Sparse graphs take the packed-row sweeper where every context fits it:
+    // its block holds one thread per (site, storage) item and bond share of
+    // the largest colour class.
+    P.row = g->kind == KIND_CSR && !g->mixed && !g->ctx;
+    int row_block = 64;
+    for (size_t k = 0; k < g->ctxs.size() && P.row; ++k) {
+        const InstDev &I = g->ctxs[k]->hI;
+        if (I.n > CSR_ROW_MAXN || I.maxabsj > CSR_ROW_MAXJ || I.maxdeg > 2 * CSR_ROW_BPL || I.maxcnt < 1) P.row = false;
+    }
     for (size_t k = 0; k < g->ctxs.size(); ++k) {
         pt_ctx *c = g->ctxs[k];
         // the two-slot +-J kernel splits the ladder into whole slot pairs (even G, even s0)
@@ -1170,7 +1189,11 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
                              // threads, so that 2 or 4 lanes can share a site's bonds
                              : P.ctx[k].gmax <= 2 ? 512 : 256;
         P.block = std::max(P.block, (need + 63) & ~63);
+        if (P.row)
+            row_block = std::max(row_block, (c->hI.maxcnt * P.ctx[k].gmax * csr_row_lanes(c->hI.maxdeg) + 63) & ~63);
     }
+    if (P.row && row_block > 512) P.row = false;
+    if (P.row) P.block = row_block;
     // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
     // so blockIdx b runs on XCD b % 8. Each XCD gets a contiguous run of the
     // instance-ordered items (so the workgroups of one instance share an L2);
@@ -1186,7 +1209,7 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
     // fewer slots a colour class has too few (site, quad) items to fill a
     // workgroup, and the sweep is bound by each item's chain of LDS reads,
     // which the quad layout does not shorten.
-    P.quad = g->kind == KIND_CSR && !g->mixed && !g->ctx && P.block <= 256;
+    P.quad = !P.row && g->kind == KIND_CSR && !g->mixed && !g->ctx && P.block <= 256;
     for (size_t k = 0; k < g->ctxs.size() && P.quad; ++k) {
         if (g->ctxs[k]->D > 255) P.quad = false;
         for (int w = 0; w < P.ctx[k].W; ++w)
@@ -1199,7 +1222,10 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         P.lds = std::max(P.lds, g->pm     ? pm_lds_bytes(P.ctx[k].gmax, P.tsw_max)
                                 : g->wave ? wave_lds_bytes(c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max)
                                           : chunk_lds_bytes(c->kind, c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max,
-                                                            c->hI.nnz, c->hI.nfree, c->ncolors, contextual(c), P.quad));
+                                                            c->hI.nnz, c->hI.nfree, c->ncolors, contextual(c), P.quad,
+                                                            P.row ? csr_row_graph_bytes(c->ncolors, c->hI.maxcnt,
+                                                                                        csr_row_lanes(c->hI.maxdeg))
+                                                                  : 0));
     }
     if (P.lds > 160 * 1024) return fail(PT_EUNSUPPORTED, "tiling needs %zu B of LDS per workgroup", P.lds);
     if (g->ctx && g->mixed)
@@ -1216,8 +1242,8 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         HIPCHK(chunk_occupancy_ctx(g->kind, g->L, P.block, P.lds, &P.per_cu));
     else {
         // a specialised sparse-graph launch at 512 threads takes the lane-sharing sweeper
-        P.wide = g->kind == KIND_CSR && P.block == 512;
-        HIPCHK(chunk_occupancy(g->kind, g->L, g->rpt, P.wide, P.quad, P.block, P.lds, &P.per_cu));
+        P.wide = !P.row && g->kind == KIND_CSR && P.block == 512;
+        HIPCHK(chunk_occupancy(g->kind, g->L, g->rpt, P.wide, P.quad, P.row, P.block, P.lds, &P.per_cu));
     }
     if (P.per_cu < 1) return fail(PT_EUNSUPPORTED, "kernel cannot run with block %d, LDS %zu", P.block, P.lds);
     // the cross-workgroup waits need every workgroup of the launch resident
@@ -1305,6 +1331,7 @@ static int build_group(pt_batch *b, LaunchGroup *g, GroupMem &mem)
     g->n_items = (int)P.items.size();
     g->wide = P.wide;
     g->quad = P.quad;
+    g->row = P.row;
     g->grid = P.grid;
     g->block = P.block;
     g->lds = P.lds;
@@ -1509,7 +1536,8 @@ static hipError_t enqueue_round(pt_batch *b, uint32_t K, bool timed)
                        : g->wave  ? launch_wave(g->L, a, g->block, g->lds, b->stream)
                        : g->mixed ? launch_chunk_mixed(a, g->block, g->lds, b->stream)
                        : g->ctx   ? launch_chunk_ctx(g->kind, g->L, a, g->block, g->lds, b->stream)
-                                  : launch_chunk(g->kind, g->L, g->rpt, g->wide, g->quad, a, g->block, g->lds, b->stream);
+                                  : launch_chunk(g->kind, g->L, g->rpt, g->wide, g->quad, g->row, a, g->block, g->lds,
+                                                 b->stream);
         if (e != hipSuccess) return e;
         if (timed) {
             e = hipEventRecord(e1, b->stream);
@@ -1639,6 +1667,25 @@ extern "C" int pt_batch_kernel_time(pt_batch *b, double *ms, uint64_t *launches)
     if (launches) *launches = b->kernel_launches;
     b->kernel_ms = 0.0;
     b->kernel_launches = 0;
+    return PT_OK;
+}
+
+extern "C" int pt_batch_describe(pt_batch *b, char *buf, int32_t len)
+{
+    if (!b || !buf || len < 1) return fail(PT_EINVAL, "null batch or buffer");
+    std::string out;
+    for (const LaunchGroup *g : b->groups) {
+        const char *kern = g->pm ? (g->spw == 1 ? "pm1" : "pm") : g->wave ? "wave" : g->mixed ? "mixed" : g->ctx ? "ctx" : "chunk";
+        std::string sw;
+        if (g->pm || g->wave || g->mixed) sw = "-";
+        else if (g->kind == KIND_LATTICE) sw = "lattice" + std::to_string(g->L) + "x" + std::to_string(g->rpt);
+        else sw = g->row ? "csr-row" : g->quad ? "csr-quad" : g->wide ? "csr-wide" : "csr";
+        char line[256];
+        snprintf(line, sizeof line, "kernel=%s sweeper=%s contexts=%zu grid=%d block=%d lds=%zu\n", kern, sw.c_str(),
+                 g->ctxs.size(), g->grid, g->block, g->lds);
+        out += line;
+    }
+    snprintf(buf, (size_t)len, "%s", out.c_str());
     return PT_OK;
 }
 

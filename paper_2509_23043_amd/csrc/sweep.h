@@ -558,6 +558,161 @@ using CsrSweep = CsrSweepT<false>;
 using CsrSweepWide = CsrSweepT<true>;
 
 // ---------------------------------------------------------------------------
+// General sparse graph, packed rows ("row" sweeper). The same (site, storage)
+// items and storage layout as CsrSweepT, with a fixed item per thread: the
+// thread's storage k and rank s never change (item s * G + k of every colour
+// class), and the graph is laid out for that map. Record (c, s, sub) holds
+// the s-th site of class c and its bonds sub * BPL .. sub * BPL + BPL - 1 as
+// 16-bit words (neighbour in bits 0-11, J in bits 12-15), so that a thread
+// reads its class-c row with two 16-byte and one 4-byte LDS read at an index
+// it computes itself. The rows of class c + 1 are read while class c is
+// swept, which leaves two dependent LDS round trips per class on the critical
+// path (the neighbour spins with the own spin and random half; then the flip
+// threshold), where the CSR layout needs site -> row bounds -> bond words ->
+// neighbour spins first. A site's bonds are split over LP = 1 or 2 adjacent
+// lanes, summed by DPP; unused bond words are 0 (site 0 with J = 0), so every
+// lane reads all BPL neighbours without a branch.
+// Requirements (checked by the runtime): n <= CSR_ROW_MAXN, |J| <=
+// CSR_ROW_MAXJ, degree <= 2 BPL, and a block of at least (largest class) x G x
+// LP threads.
+struct RowGraph {
+    uint4 *bw;        // [ncolors][maxcnt][LP][2]: 16 bonds of 16 bits
+    uint32_t *info;   // [ncolors][maxcnt][LP]: site i | h_i << 16 (h on sub 0); 0xFFF: no site
+};
+
+struct CsrRowSweep {
+    static constexpr int RPTV = 1;
+    static constexpr int MAXT = 512;
+    static constexpr int MINW = 1;
+    static constexpr bool RND = true;
+    static constexpr int BPL = CSR_ROW_BPL;
+    int n, SB, nr, G, k, sub, lp, s, maxcnt;
+    RowGraph gr;
+
+    __device__ static size_t graph_bytes(const InstDev &I)
+    {
+        return csr_row_graph_bytes(I.ncolors, I.maxcnt, csr_row_lanes(I.maxdeg));
+    }
+
+    __device__ void setup(const InstDev &I, int G_)
+    {
+        n = I.n;
+        SB = CsrSweepT<false>::storage_bytes(n);
+        nr = (n + 7) & ~7;
+        G = G_;
+    }
+
+    __device__ __forceinline__ void bind(const InstDev &I, unsigned char *base, int tid, int bs)
+    {
+        lp = csr_row_lanes(I.maxdeg);
+        maxcnt = I.maxcnt;
+        sub = tid & (lp - 1);
+        const int it = tid / lp;
+        s = it / G;
+        k = it - s * G;
+        const int nrec = I.ncolors * maxcnt * lp;
+        gr.bw = (uint4 *)base;
+        gr.info = (uint32_t *)(base + (size_t)nrec * 32);
+        for (int x = tid; x < nrec; x += bs) {
+            const int c = x / (maxcnt * lp), rest = x - c * maxcnt * lp;
+            const int ss = rest / lp, sb = rest - ss * lp;
+            const int off = I.color_off[c], cnt = I.color_off[c + 1] - off;
+            uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            uint32_t info = 0xFFFu;
+            if (ss < cnt) {
+                const int i = I.color_sites[off + ss];
+                const int r1 = I.row_ptr[i + 1];
+                const int e0 = I.row_ptr[i] + sb * BPL;
+                for (int b = 0; b < BPL && e0 + b < r1; ++b)
+                    w[b >> 1] |= ((uint32_t)I.col[e0 + b] | (((uint32_t)I.Jc[e0 + b] & 15u) << 12)) << (16 * (b & 1));
+                info = (uint32_t)i | ((sb == 0 ? (uint32_t)(uint16_t)I.h[i] : 0u) << 16);
+            }
+            gr.bw[2 * x] = make_uint4(w[0], w[1], w[2], w[3]);
+            gr.bw[2 * x + 1] = make_uint4(w[4], w[5], w[6], w[7]);
+            gr.info[x] = info;
+        }
+    }
+
+    __device__ __forceinline__ void sweep(const InstDev &I, int G_, int s0, uint32_t t, const int *slot_of,
+                                          int8_t *sp, const uint32_t *tab, int stride, int *Elds,
+                                          unsigned *flips_lds, uint16_t *rnd)
+    {
+        (void)G_;
+        const int tid = threadIdx.x, bs = blockDim.x;
+        const int ncol = I.ncolors;
+        const bool on = s < maxcnt;             // threads past the last item only keep the barriers
+        const int xs = on ? s * lp + sub : 0;   // record of this thread in class 0
+        const int xstep = maxcnt * lp;          // records per class
+        // class 0's row, read while the random halves are drawn
+        uint4 w0 = gr.bw[2 * xs], w1 = gr.bw[2 * xs + 1];
+        uint32_t info = on ? gr.info[xs] : 0xFFFu;
+        const int ncall = nr >> 3;
+        for (int idx = tid; idx < G * ncall; idx += bs) {
+            const int kk = idx / ncall, q = idx - kk * ncall;
+            const P4 r = philox_v((uint32_t)q, t, (uint32_t)(s0 + slot_of[kk]), TAG_SWEEP, I.seed_lo, I.seed_hi);
+            *(uint4 *)(rnd + (size_t)kk * nr + 8 * q) = make_uint4(r.v[0], r.v[1], r.v[2], r.v[3]);
+        }
+        __syncthreads();
+        const int sl = slot_of[k];
+        const int tb = sl * stride + I.D;
+        int8_t *m_k = sp + k * SB;
+        const uint16_t *r_k = rnd + (size_t)k * nr;
+        int dE_acc = 0;
+        unsigned nf_acc = 0;
+        for (int c = 0; c < ncol; ++c) {
+            const int i = (int)(info & 0xFFFu);
+            const bool valid = i != 0xFFF;
+            int f = 0, m = 0;
+            uint32_t hs = 0;
+            if (valid) {
+                // the item's reads are independent: one LDS round trip
+                m = m_k[i];
+                hs = (uint32_t)r_k[i] << 16;
+                f = (int)info >> 16;
+                const uint32_t ws[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const uint32_t wq = ws[q];
+                    f += ((int)(wq << 16) >> 28) * (int)m_k[wq & 0xFFFu] + ((int)wq >> 28) * (int)m_k[(wq >> 16) & 0xFFFu];
+                }
+            }
+            // the next class's row, in flight while this class is decided
+            if (c + 1 < ncol) {
+                const int xn = xs + (c + 1) * xstep;
+                w0 = gr.bw[2 * xn];
+                w1 = gr.bw[2 * xn + 1];
+                info = on ? gr.info[xn] : 0xFFFu;
+            }
+            if (lp == 2) f += __builtin_amdgcn_update_dpp(0, f, 0xB1, 0xf, 0xf, false);   // quad_perm 1,0,3,2
+            if (valid) {
+                const int d = m * f;
+                const uint32_t T = tab[tb + d];
+                bool maybe;
+                bool acc = coarse_accept(T, hs, maybe);
+                if (any_lane(maybe)) {
+                    if (maybe) {
+                        P4 r2 = philox(opaque((uint32_t)(i >> 3)), t, (uint32_t)(s0 + sl), TAG_REFINE, I.seed_lo, I.seed_hi);
+                        const int wq = (i & 7) >> 1;
+                        const uint32_t wd = wq == 0 ? r2.v[0] : wq == 1 ? r2.v[1] : wq == 2 ? r2.v[2] : r2.v[3];
+                        const uint32_t lo = ((i & 1) ? (wd >> 16) : wd) & 0xFFFFu;
+                        acc = (T == ALWAYS) || ((hs | lo) < T);
+                    }
+                }
+                if (acc && sub == 0) {   // the lanes of an item agree; the first one writes
+                    m_k[i] = (int8_t)(-m);
+                    dE_acc += 2 * d;
+                    nf_acc += 1;
+                }
+            }
+            __syncthreads();
+        }
+        if (dE_acc) atomicAdd(&Elds[k], dE_acc);
+        if (nf_acc) atomicAdd(&flips_lds[sl], nf_acc);
+        __syncthreads();
+    }
+};
+
+// ---------------------------------------------------------------------------
 // General sparse graph, four storages per lane ("quad" sweeper). The storages
 // of a workgroup are interleaved: byte k of site i's GS-byte group (GS = G
 // rounded up to a multiple of 4) holds storage k's spin as a down-bit (1 for
@@ -988,6 +1143,27 @@ struct SweepCall<CsrSweepT<W>> {
         const int m = X[i];
         return -m * s - 2 * (int)g.h[i] * m;
     }
+};
+
+template <>
+struct SweepCall<CsrRowSweep> {
+    static __device__ __forceinline__ void run(CsrRowSweep &sw, const InstDev &I, int G, int s0, uint32_t t, ChunkLds &c,
+                                               int stride)
+    {
+        sw.sweep(I, G, s0, t, c.slot_of, c.sp, c.tab, stride, c.Elds, c.flips, c.rnd);
+    }
+    static __device__ int SB(const CsrRowSweep &s) { return s.SB; }
+    static __device__ int lidx(const CsrRowSweep &, int i) { return i; }
+    static __device__ size_t graph_bytes(const InstDev &I) { return CsrRowSweep::graph_bytes(I); }
+    static __device__ void bind(CsrRowSweep &sw, const InstDev &I, unsigned char *base, int tid, int bs)
+    {
+        sw.bind(I, base, tid, bs);
+    }
+    static __device__ int layout_g(const CsrRowSweep &, int G) { return G; }
+    static __device__ int pos(const CsrRowSweep &s, int st, int p) { return st * s.SB + p; }
+    static __device__ int8_t enc(int m) { return (int8_t)m; }
+    static __device__ int dec(int8_t v) { return v; }
+    struct CtxView {};
 };
 
 template <>

@@ -3,6 +3,7 @@
 // InstDev struct in device memory; a persistent launch is a list of WorkItems,
 // one per workgroup.
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace tapt {
@@ -14,6 +15,14 @@ enum : uint32_t {
 };
 constexpr uint32_t ALWAYS = 0xFFFFFFFFu;   // threshold meaning "accept unconditionally"
 constexpr int MAX_COLORS = 64;
+// packed-row sparse sweeper: bonds per lane, lanes per (site, storage) item
+// for a largest degree, limits, and the LDS bytes of its rows
+constexpr int CSR_ROW_BPL = 16, CSR_ROW_MAXN = 4095, CSR_ROW_MAXJ = 7;
+__host__ __device__ inline int csr_row_lanes(int maxdeg) { return maxdeg <= CSR_ROW_BPL ? 1 : 2; }
+__host__ __device__ inline size_t csr_row_graph_bytes(int ncolors, int maxcnt, int lanes)
+{
+    return (size_t)ncolors * maxcnt * lanes * 36 + 32;
+}
 
 struct BestRec {          // best min_r E_r seen; ordered by (E, t, slot)
     int32_t E;
@@ -31,7 +40,10 @@ struct InstDev {
     uint32_t seed_lo, seed_hi;
     uint32_t epoch;                         // bumps when the state is replaced
     int32_t ctx_K;                          // context sites of a contextual proposal
-    int32_t ctx_on, ctx_pad;                // 1: proposals are contextual
+    int32_t ctx_on;                         // 1: proposals are contextual
+    int32_t maxdeg;                         // largest degree of a free site
+    int32_t maxcnt, maxabsj;                // largest colour class (free sites); largest |J|
+    int32_t pad0;
     int64_t prop_start, prop_period, prop_stop;
     uint64_t sweep_cap;                     // batched runs stop at this sweep count
 
