@@ -1385,7 +1385,13 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
         c.satt[l] = 0;
         c.sacc[l] = 0;
     }
-    if (tid < 16) c.misc[tid] = 0;
+    // misc[12]: the cycle end's outcome for the whole block, written by
+    // wavefront 0 every sweep (bit 0: a wait timed out; bits 8-15 / 16-23:
+    // storage + 1 that takes the partner's state across the lower / upper
+    // boundary; bits 24-31: storage + 1 of a new best state). misc[13]: the
+    // storages of slots 0 and G - 1 (bits 0-7, 8-15), which the next cycle
+    // end publishes.
+    if (tid < 16) c.misc[tid] = tid == 13 ? (G - 1) << 8 : 0;
     __syncthreads();
     for (int p = 0; p <= G; ++p) {
         int r = s0 - 1 + p;
@@ -1425,6 +1431,7 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
     __syncthreads();
 
     bool failed = false;
+    int xst = c.misc[13];
     // cycle bookkeeping by counting (t0 / M once per launch)
     uint32_t cyc = (uint32_t)(t0 / (uint64_t)P.M), phase = (uint32_t)(t0 % (uint64_t)P.M);
     uint64_t prop_at = P.first_prop_from(t0 + 1);
@@ -1489,6 +1496,16 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
         const bool up = cyc_end && has_up && (((s0 + G - 1 - first) & 1) == 0);
         const int buf = (cyc >> 1) & 1;
         const unsigned long long tag = (unsigned long long)cyc << 32;
+        // wavefront 0's reads of the cycle end, in flight during the publish
+        int e = 0x7FFFFFFF;
+        uint32_t u_pair = 0, u_dn = 0;
+        if (tid < 64) {
+            if (lane < G) e = c.Elds[my_st];
+            if (cyc_end) {
+                u_pair = c.usw[(cyc & 1) * 65 + lane];
+                u_dn = c.usw[(cyc & 1) * 65 + 64];
+            }
+        }
         if (down || up) {
             // publish the boundary states, every wavefront a share of the 64-byte
             // chunks. A boundary slot in a cross pair is in no local pair this
@@ -1502,8 +1519,11 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
             const int nch = (n + 63) >> 6, wv = tid >> 6, nwv = bs >> 6;
             for (int side = 0; side < 2; ++side) {
                 if (!(side == 0 ? down : up)) continue;
-                const int st = c.stor_of[side == 0 ? 0 : G - 1];
+                const int st = side == 0 ? (xst & 0xFF) : ((xst >> 8) & 0xFF);
                 unsigned long long *out = it.xbuf + ((size_t)(it.w * 2 + side) * 2 + buf) * it.xwords;
+                if (tid == 0)
+                    __hip_atomic_store(out + nw, tag | (uint32_t)c.Elds[st], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
                 for (int ch0 = wv; ch0 < nch; ch0 += 4 * nwv) {
                     int8_t v[4];
 #pragma unroll
@@ -1522,9 +1542,6 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
-                if (tid == 0)
-                    __hip_atomic_store(out + nw, tag | (uint32_t)c.Elds[st], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         if (tid >= 64 && tid < 128 && cyc_end) {
@@ -1534,10 +1551,22 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
             if (lane == 0 && has_down) c.usw[(nx & 1) * 65 + 64] = philox_word0((uint32_t)(s0 - 1), nx, TAG_SWAP, P.k0, P.k1);
         }
         if (tid < 64) {
-            int e = lane < G ? c.Elds[my_st] : 0x7FFFFFFF;
+            int fl = 0;   // the block's outcome word (misc[12])
+            // first poll of the partners' words (three per lane: n <= 6112 in
+            // one round), issued before the local pairs are settled so that
+            // its memory latency overlaps them
+            unsigned long long pv[2][3] = {{0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                if (!(side == 0 ? down : up)) continue;
+                const int pw = side == 0 ? it.w - 1 : it.w + 1;
+                const unsigned long long *in = it.xbuf + ((size_t)(pw * 2 + (side == 0 ? 1 : 0)) * 2 + buf) * it.xwords;
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    if (lane + 64 * q <= nw)
+                        pv[side][q] = __hip_atomic_load(in + lane + 64 * q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             if (cyc_end) {
-                const uint32_t u_pair = c.usw[(cyc & 1) * 65 + lane];
-                const uint32_t u_dn = c.usw[(cyc & 1) * 65 + 64];
                 // ---- replica exchange (Eq. 1): the boundary states are published ----
                 // pairs inside the workgroup: exchange labels (lane l decides (l, l+1))
                 const int e_nx = from_next_lane(e), st_nx = from_next_lane(my_st);
@@ -1568,18 +1597,22 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                 // accepted states after the barrier
                 if (down || up) {
                     int timeout = 0;
-                    for (int side = 0; side < 2 && !timeout; ++side) {
-                        if (!(side == 0 ? down : up)) continue;
+#pragma unroll
+                    for (int side = 0; side < 2; ++side) {
+                        if (!(side == 0 ? down : up) || timeout) continue;
                         const int pw = side == 0 ? it.w - 1 : it.w + 1;
                         const unsigned long long *in =
                             it.xbuf + ((size_t)(pw * 2 + (side == 0 ? 1 : 0)) * 2 + buf) * it.xwords;
                         uint32_t *stage = c.xstage + side * (nw + 1);
                         uint32_t polls = 0;
-                        for (;;) {
+                        for (bool first = true;; first = false) {
                             bool ok = true;
                             unsigned long long bad = 0;
-                            for (int wd = lane; wd <= nw; wd += 64) {
-                                unsigned long long v = __hip_atomic_load(in + wd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            for (int wd = lane, q = 0; wd <= nw; wd += 64, ++q) {
+                                // the first round takes the words read above
+                                const unsigned long long v =
+                                    (first && q < 3) ? (q == 0 ? pv[side][0] : q == 1 ? pv[side][1] : pv[side][2])
+                                                     : __hip_atomic_load(in + wd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                                 if ((uint32_t)(v >> 32) == cyc) {
                                     stage[wd] = (uint32_t)v;
                                 } else {
@@ -1606,7 +1639,7 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                     }
                     timeout = __builtin_amdgcn_readlane(timeout, 0);
                     if (timeout) {
-                        if (lane == 0) c.misc[0] = 1;
+                        fl |= 1;
                     } else {
                         for (int side = 0; side < 2; ++side) {
                             if (!(side == 0 ? down : up)) continue;
@@ -1630,7 +1663,7 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                                     e = pE;
                                     c.Elds[st] = pE;
                                 }
-                                if (lane == 0) c.misc[4 + side] = st + 1;
+                                fl |= (st + 1) << (8 + 8 * side);
                             }
                         }
                     }
@@ -1651,13 +1684,19 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                 bestT = (int64_t)t;
                 bestSlot = s0 + lm;
                 const int st = __builtin_amdgcn_readlane(my_st, lm);
-                if (lane == 0) c.misc[2] = st + 1;   // the whole block copies it below
+                fl |= (st + 1) << 24;   // the whole block copies it below
+            }
+            if (lane == 0) {
+                c.misc[12] = fl;
+                c.misc[13] = __builtin_amdgcn_readlane(my_st, 0) | (__builtin_amdgcn_readlane(my_st, G - 1) << 8);
             }
         }
         __syncthreads();
-        if (cyc_end && (has_down || has_up)) failed = c.misc[0] != 0;
+        const int fl = c.misc[12];
+        xst = c.misc[13];
+        if (cyc_end && (has_down || has_up)) failed = (fl & 1) != 0;
         if (down || up) {   // accepted cross swaps: the partner's state into the storage
-            const int x0 = c.misc[4], x1 = c.misc[5];
+            const int x0 = (fl >> 8) & 0xFF, x1 = (fl >> 16) & 0xFF;
             if (x0 | x1) {
                 for (int side = 0; side < 2; ++side) {
                     const int xs = side == 0 ? x0 : x1;
@@ -1668,18 +1707,13 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
                             SweepCall<Sw>::enc(((stage[j >> 5] >> (j & 31)) & 1u) ? 1 : -1);
                 }
                 __syncthreads();
-                if (tid == 0) {
-                    c.misc[4] = 0;
-                    c.misc[5] = 0;
-                }
             }
         }
-        const int bst = c.misc[2];
+        const int bst = (fl >> 24) & 0xFF;
         if (bst) {   // snapshot of the new best state, before the next sweep changes it
             for (int i = tid; i < n; i += bs)
                 it.best_spins[i] = (int8_t)SweepCall<Sw>::dec(c.sp[SweepCall<Sw>::pos(sw, bst - 1, SweepCall<Sw>::lidx(sw, i))]);
             __syncthreads();
-            if (tid == 0) c.misc[2] = 0;
         }
     }
     if (tid < 64 && lane < G) {
