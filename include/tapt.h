@@ -205,12 +205,22 @@ typedef struct {
     int32_t replicas_per_thread; /* 1, 2 or 4 (0 = choose) */
     int32_t chunk_sweeps;        /* sweeps per persistent launch (0 = 1000) */
     int32_t use_graph;           /* 1: replay the chunk launches as a hipGraph */
-    int32_t kernel;              /* 0 = choose; 1 = workgroup-synchronous kernel;
+    int32_t kernel;              /* 0 = choose; 1 = workgroup-synchronous kernel (general
+                                        graphs with their LDS-resident CSR sweepers);
                                     2 = wave-per-replica kernel (lattices with n = 512);
                                     3 = +-J 8^3 kernel, two slots per wavefront (every
                                         coupling +-1, even R);
                                     4 = the same kernel with one slot per wavefront
-                                        (at most 8 slots per workgroup) */
+                                        (at most 8 slots per workgroup);
+                                    5 = workgroup-synchronous kernel, general graphs
+                                        swept from packed rows, one storage per lane;
+                                    6 = the same, four storages per lane. 5 and 6 fail
+                                        with PT_EUNSUPPORTED where the rows do not fit;
+                                        0 takes 6, else 5, where they fit;
+                                    7 = +-J row kernel, one slot per wavefront, lattices
+                                        of every even L in 6..16 in one launch (every
+                                        coupling +-1, no fields), at most 8 slots per
+                                        workgroup */
 } pt_batch_opts;
 
 /* Group contexts for batched execution. The contexts stay owned by the

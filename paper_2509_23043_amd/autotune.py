@@ -51,26 +51,36 @@ def candidates(contexts):
     """(replicas_per_wg, replicas_per_thread, kernel) triples worth timing:
     every cap on the slots per workgroup up to the longest ladder, with 1, 2
     or 4 slots per thread in the workgroup-synchronous kernel (the runtime
-    lowers the cap per context until it fits), the wave-per-replica kernel
-    where every context is an 8^3 lattice, and the +-J 8^3 kernel (two slots
-    or one slot per wavefront) where every coupling is +-1 and every ladder
-    has even length."""
+    lowers the cap per context until it fits; general graphs sweep one slot
+    per thread, from the LDS graph or from either packed-row layout), the
+    wave-per-replica kernel where every context is an 8^3 lattice, the +-J
+    8^3 kernel (two slots or one slot per wavefront) where every coupling is
+    +-1 and every ladder has even length, and the +-J row kernel (one slot
+    per wavefront, any even L in 6..16, sizes mixed) where every coupling is
+    +-1."""
     rmax = max(c.R for c in contexts)
     wave_ok = all(c.kind == "lattice" and c.L == 8 for c in contexts)
     pm_ok = all(getattr(c, "pm", False) for c in contexts)
+    csr_ok = all(c.kind != "lattice" for c in contexts)
+    pml_ok = all(getattr(c, "pml", False) for c in contexts)
     out = []
     for G in G_CANDIDATES:
         if G > 2 * rmax:
             continue
         for rpt in RPT_CANDIDATES:
-            if rpt <= G:
+            if rpt <= G and (rpt == 1 or not csr_ok):
                 out.append((G, rpt, "block"))
+        if csr_ok:
+            out.append((G, 1, "row"))
+            out.append((G, 1, "row4"))
         if wave_ok and G <= 8:
             out.append((G, 1, "wave"))
         if pm_ok and 2 <= G <= 16:
             out.append((G, 1, "pm"))
         if pm_ok and G <= 8:
             out.append((G, 1, "pm1"))
+        if pml_ok and G <= 8:
+            out.append((G, 1, "pml"))
     return out
 
 

@@ -45,7 +45,7 @@ class _BatchOpts(C.Structure):
                 ("chunk_sweeps", C.c_int32), ("use_graph", C.c_int32), ("kernel", C.c_int32)]
 
 
-KERNELS = {"auto": 0, "block": 1, "wave": 2, "pm": 3, "pm1": 4}
+KERNELS = {"auto": 0, "block": 1, "wave": 2, "pm": 3, "pm1": 4, "row": 5, "row4": 6, "pml": 7}
 
 
 class _ServeOpts(C.Structure):
@@ -173,11 +173,14 @@ class Context:
         g.n = n
         self.kind, self.L = "csr", 0
         self.pm = False     # the +-J 8^3 kernel applies (every coupling +-1, even ladder)
+        self.pml = False    # the +-J row kernel applies (even L in 6..16, every coupling +-1)
         if problem.get("lattice_L") and not np.any(problem.get("h", 0)) and not np.any(problem.get("clamp", 0)):
             g.lattice_L = int(problem["lattice_L"])
             self.kind = "lattice" if g.lattice_L <= 16 else "csr"
             self.L = g.lattice_L
-            self.pm = self.L == 8 and self.R % 2 == 0 and bool(np.all(np.abs(np.asarray(problem["J3"])) == 1))
+            pmj = bool(np.all(np.abs(np.asarray(problem["J3"])) == 1))
+            self.pm = self.L == 8 and self.R % 2 == 0 and pmj
+            self.pml = self.L % 2 == 0 and 6 <= self.L <= 16 and pmj
             g.J = _p(keep(np.asarray(problem["J3"]).reshape(-1), np.int32), C.c_int32)
             g.nnz = 0
         else:

@@ -32,11 +32,9 @@ bool lattice_supported(int L);
 int lattice_max_threads();
 int lattice_threads(int L, int G, int rpt);
 size_t chunk_lds_bytes(int kind, int n, int G, int stride, int tsw_entries, int nnz, int nfree, int ncolors,
-                       bool contextual, bool quad, size_t row_graph);
-hipError_t launch_chunk(int kind, int L, int rpt, bool wide, bool quad, bool row, const ChunkArgs &a, int block,
-                        size_t lds, hipStream_t s);
-hipError_t chunk_occupancy(int kind, int L, int rpt, bool wide, bool quad, bool row, int block, size_t lds,
-                           int *blocks_per_cu);
+                       bool contextual, int sparse, size_t row_graph);
+hipError_t launch_chunk(int kind, int L, int rpt, int sparse, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
+hipError_t chunk_occupancy(int kind, int L, int rpt, int sparse, int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_chunk_ctx(int kind, int L, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t chunk_occupancy_ctx(int kind, int L, int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_finish(const WorkItem *items, const int *first_item, int n_inst, uint32_t K, InstStatus *status,
@@ -54,6 +52,12 @@ int pm_max_storages(int spw);
 size_t pm_lds_bytes(int G, int tsw_entries);
 hipError_t launch_pm(int spw, const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t pm_occupancy(int spw, int block, size_t lds, int *blocks_per_cu);
+bool pml_supported(int L);
+int pml_max_storages();
+size_t pml_lds_bytes(int L, int G, int tsw_entries);
+int pml_xwords(int L);
+hipError_t launch_pml(const ChunkArgs &a, int block, size_t lds, hipStream_t s);
+hipError_t pml_occupancy(int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_plain(int kind, int L, const InstDev *dI, int R, int n, int stride, int nnz, int nfree, int ncolors,
                         uint32_t t, hipStream_t s);
 hipError_t launch_init(const InstDev *dI, int R, int n, hipStream_t s);
@@ -207,6 +211,7 @@ struct pt_ctx {
     uint64_t t_host = 0;
     int device = 0;
     bool pmJ = false;                 // 8^3 lattice with every coupling +-1 (the +-J kernel applies)
+    bool pmL = false;                 // even L in 6..16, every coupling +-1 (the +-J row kernel applies)
     DevBuf arena;                     // a served request's state, carved into the views above
     std::vector<int32_t> h_cursor0;   // a served request's start cursors (source of an async copy)
 };
@@ -518,8 +523,9 @@ extern "C" int pt_create(const pt_graph *g, const double *betas, int32_t R, cons
         c->problem_fp = f.h;
     }
     c->pmJ = P.kind == KIND_LATTICE && P.L == 8 && P.D == 6 && R % 2 == 0;
+    c->pmL = P.kind == KIND_LATTICE && pml_supported(P.L) && P.D == 6;
     for (int8_t j : P.J3)
-        if (j != 1 && j != -1) c->pmJ = false;
+        if (j != 1 && j != -1) c->pmJ = c->pmL = false;
     auto bail = [&](int code) {
         if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
         delete c;
@@ -1041,11 +1047,11 @@ struct LaunchGroup {
     bool mixed = false;               // one launch of chunk_kernel_mixed for several sweepers
     bool wave = false;                // wave-per-replica kernel
     bool pm = false;                  // +-J 8^3 kernel
+    bool pml = false;                 // +-J row kernel, even L in 6..16, one slot per wavefront
     int spw = 2;                      // its slots per wavefront (1 or 2)
     bool ctx = false;                 // some context has contextual proposals (chunk_kernel_ctx)
-    bool wide = false;                // sparse graphs at 512 threads: the lane-sharing sweeper
-    bool quad = false;                // sparse graphs, four storages per lane (CsrQuadSweep)
-    bool row = false;                 // sparse graphs, packed rows (CsrRowSweep)
+    int sparse = SPARSE_CSR;          // sparse graphs: the sweeper of the chunk kernel
+    int sparse_req = 0;               // the caller's choice: 0 any, -1 no packed rows, SPARSE_ROW, SPARSE_ROW4
     size_t lds;
     std::vector<pt_ctx *> ctxs;
     std::vector<int> Gs;              // per context: slots per workgroup (max)
@@ -1131,7 +1137,7 @@ struct GroupPlan {
     std::vector<Ctx> ctx;
     size_t nbest = 0, nbs = 0, nx = 0, lds = 0;
     int block = 64, grid = 0, tsw_max = 0, per_cu = 0;
-    bool wide = false, quad = false, row = false;
+    int sparse = SPARSE_CSR;
 };
 
 // Fewest slots per workgroup for the four-storages-per-lane sparse sweeper.
@@ -1139,21 +1145,25 @@ constexpr int QUAD_MIN_G = 12;
 
 static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
 {
-    // Sparse graphs take the packed-row sweeper where every context fits it:
-    // its block holds one thread per (site, storage) item and bond share of
+    // Sparse graphs take a packed-row sweeper where every context fits it
+    // (the four-storages-per-lane one first): its block holds one thread per
+    // item (site and storage, or site and four storages) and bond share of
     // the largest colour class.
-    P.row = g->kind == KIND_CSR && !g->mixed && !g->ctx;
-    int row_block = 64;
-    for (size_t k = 0; k < g->ctxs.size() && P.row; ++k) {
+    const bool sparse_sync = g->kind == KIND_CSR && !g->mixed && !g->ctx;
+    bool row_ok = sparse_sync, row4_ok = sparse_sync;
+    int row_block = 64, row4_block = 64;
+    for (size_t k = 0; k < g->ctxs.size() && sparse_sync; ++k) {
         const InstDev &I = g->ctxs[k]->hI;
-        if (I.n > CSR_ROW_MAXN || I.maxabsj > CSR_ROW_MAXJ || I.maxdeg > 2 * CSR_ROW_BPL || I.maxcnt < 1) P.row = false;
+        if (I.n > CSR_ROW_MAXN || I.maxdeg > 2 * CSR_ROW_BPL || I.maxcnt < 1) row_ok = row4_ok = false;
+        if (I.maxabsj > CSR_ROW_MAXJ) row_ok = false;
+        if (I.D > 255) row4_ok = false;
     }
     for (size_t k = 0; k < g->ctxs.size(); ++k) {
         pt_ctx *c = g->ctxs[k];
         // the two-slot +-J kernel splits the ladder into whole slot pairs (even G, even s0)
         const int unit = g->pm ? g->spw : 1;
         int R = c->R / unit, W = (R + g->Gs[k] / unit - 1) / (g->Gs[k] / unit);
-        int xwords = (((c->n + 31) >> 5) + 1 + 7) & ~7;
+        int xwords = ((g->pml ? pml_xwords(c->L) : ((c->n + 31) >> 5) + 1) + 7) & ~7;
         P.ctx.push_back({(int)P.items.size(), W, c->n, xwords, unit * ((R + W - 1) / W), P.nbs, P.nx});
         P.first.push_back((int)P.items.size());
         int base = R / W, extra = R % W, s0 = 0;
@@ -1166,10 +1176,10 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
             it.w = w;
             it.W = W;
             it.xwords = xwords;
-            it.variant = mixed_variant_of(c->kind, c->L, g->rpts[k]);
+            it.variant = g->pml ? c->L : mixed_variant_of(c->kind, c->L, g->rpts[k]);
             P.items.push_back(it);
             s0 += G;
-            P.nbs += (g->wave || g->pm) ? (size_t)G * c->n : (size_t)((c->n + 15) & ~15);   // one snapshot per slot
+            P.nbs += (g->wave || g->pm || g->pml) ? (size_t)G * c->n : (size_t)((c->n + 15) & ~15);   // one snapshot per slot
         }
         P.nbest += W;
         P.nx += (size_t)W * 4 * xwords * 8;
@@ -1183,17 +1193,34 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         }
         // a block covers the largest item's threads
         int need = g->pm     ? 64 * (P.ctx[k].gmax / g->spw)
-                   : g->wave ? 64 * P.ctx[k].gmax
+                   : (g->wave || g->pml) ? 64 * P.ctx[k].gmax
                              : c->kind == KIND_LATTICE ? lattice_threads(c->L, P.ctx[k].gmax, g->rpts[k])
                              // sparse graphs: a few slots per workgroup (the latency tilings) get 512
                              // threads, so that 2 or 4 lanes can share a site's bonds
                              : P.ctx[k].gmax <= 2 ? 512 : 256;
         P.block = std::max(P.block, (need + 63) & ~63);
-        if (P.row)
-            row_block = std::max(row_block, (c->hI.maxcnt * P.ctx[k].gmax * csr_row_lanes(c->hI.maxdeg) + 63) & ~63);
+        if (sparse_sync) {
+            const int gmax = P.ctx[k].gmax, gs = (gmax + 3) & ~3;
+            row_block = std::max(row_block, (c->hI.maxcnt * gmax * csr_row_lanes(c->hI.maxdeg) + 63) & ~63);
+            row4_block = std::max(row4_block, (c->hI.maxcnt * (gs / 4) * csr_row4_lanes(c->hI.maxdeg) + 63) & ~63);
+            if ((c->n - 1) * gs + 3 >= 65536) row4_ok = false;
+        }
     }
-    if (P.row && row_block > 512) P.row = false;
-    if (P.row) P.block = row_block;
+    if (row_block > 512) row_ok = false;
+    if (row4_block > 512) row4_ok = false;
+    if (g->sparse_req == SPARSE_ROW4 && !row4_ok)
+        return fail(PT_EUNSUPPORTED, "the four-storage packed-row sweeper does not fit this batch");
+    if (g->sparse_req == SPARSE_ROW && !row_ok)
+        return fail(PT_EUNSUPPORTED, "the packed-row sweeper does not fit this batch");
+    if (g->sparse_req == SPARSE_ROW || g->sparse_req < 0) row4_ok = false;
+    if (g->sparse_req == SPARSE_ROW4 || g->sparse_req < 0) row_ok = false;
+    if (row4_ok) {
+        P.sparse = SPARSE_ROW4;
+        P.block = row4_block;
+    } else if (row_ok) {
+        P.sparse = SPARSE_ROW;
+        P.block = row_block;
+    }
     // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
     // so blockIdx b runs on XCD b % 8. Each XCD gets a contiguous run of the
     // instance-ordered items (so the workgroups of one instance share an L2);
@@ -1209,23 +1236,29 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
     // fewer slots a colour class has too few (site, quad) items to fill a
     // workgroup, and the sweep is bound by each item's chain of LDS reads,
     // which the quad layout does not shorten.
-    P.quad = !P.row && g->kind == KIND_CSR && !g->mixed && !g->ctx && P.block <= 256;
-    for (size_t k = 0; k < g->ctxs.size() && P.quad; ++k) {
-        if (g->ctxs[k]->D > 255) P.quad = false;
+    bool quad = P.sparse == SPARSE_CSR && sparse_sync && P.block <= 256;
+    for (size_t k = 0; k < g->ctxs.size() && quad; ++k) {
+        if (g->ctxs[k]->D > 255) quad = false;
         for (int w = 0; w < P.ctx[k].W; ++w)
-            if (P.items[P.ctx[k].first + w].G < QUAD_MIN_G) P.quad = false;
+            if (P.items[P.ctx[k].first + w].G < QUAD_MIN_G) quad = false;
     }
+    if (quad) P.sparse = SPARSE_QUAD;
     // LDS: the largest carve-up over the items (every item lays out its own
     // region with the common swap-table capacity)
     for (size_t k = 0; k < g->ctxs.size(); ++k) {
         pt_ctx *c = g->ctxs[k];
         P.lds = std::max(P.lds, g->pm     ? pm_lds_bytes(P.ctx[k].gmax, P.tsw_max)
+                                : g->pml ? pml_lds_bytes(c->L, P.ctx[k].gmax, P.tsw_max)
                                 : g->wave ? wave_lds_bytes(c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max)
                                           : chunk_lds_bytes(c->kind, c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max,
-                                                            c->hI.nnz, c->hI.nfree, c->ncolors, contextual(c), P.quad,
-                                                            P.row ? csr_row_graph_bytes(c->ncolors, c->hI.maxcnt,
-                                                                                        csr_row_lanes(c->hI.maxdeg))
-                                                                  : 0));
+                                                            c->hI.nnz, c->hI.nfree, c->ncolors, contextual(c), P.sparse,
+                                                            P.sparse == SPARSE_ROW4
+                                                                ? csr_row4_graph_bytes(c->ncolors, c->hI.maxcnt,
+                                                                                       csr_row4_lanes(c->hI.maxdeg))
+                                                            : P.sparse == SPARSE_ROW
+                                                                ? csr_row_graph_bytes(c->ncolors, c->hI.maxcnt,
+                                                                                      csr_row_lanes(c->hI.maxdeg))
+                                                                : 0));
     }
     if (P.lds > 160 * 1024) return fail(PT_EUNSUPPORTED, "tiling needs %zu B of LDS per workgroup", P.lds);
     if (g->ctx && g->mixed)
@@ -1234,6 +1267,8 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         if (g->ctx && r != 1) return fail(PT_EUNSUPPORTED, "contextual proposals take one slot per thread");
     if (g->pm)
         HIPCHK(pm_occupancy(g->spw, P.block, P.lds, &P.per_cu));
+    else if (g->pml)
+        HIPCHK(pml_occupancy(P.block, P.lds, &P.per_cu));
     else if (g->wave)
         HIPCHK(wave_occupancy(g->L, P.block, P.lds, &P.per_cu));
     else if (g->mixed)
@@ -1242,8 +1277,8 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         HIPCHK(chunk_occupancy_ctx(g->kind, g->L, P.block, P.lds, &P.per_cu));
     else {
         // a specialised sparse-graph launch at 512 threads takes the lane-sharing sweeper
-        P.wide = !P.row && g->kind == KIND_CSR && P.block == 512;
-        HIPCHK(chunk_occupancy(g->kind, g->L, g->rpt, P.wide, P.quad, P.row, P.block, P.lds, &P.per_cu));
+        if (P.sparse == SPARSE_CSR && g->kind == KIND_CSR && P.block == 512) P.sparse = SPARSE_WIDE;
+        HIPCHK(chunk_occupancy(g->kind, g->L, g->rpt, P.sparse, P.block, P.lds, &P.per_cu));
     }
     if (P.per_cu < 1) return fail(PT_EUNSUPPORTED, "kernel cannot run with block %d, LDS %zu", P.block, P.lds);
     // the cross-workgroup waits need every workgroup of the launch resident
@@ -1320,7 +1355,7 @@ static int build_group(pt_batch *b, LaunchGroup *g, GroupMem &mem)
             WorkItem &it = P.items[p.first + w];
             it.best = g->best.as<BestRec>() + bi++;
             it.best_spins = g->best_spins.as<int8_t>() + bs_off;
-            bs_off += (g->wave || g->pm) ? (size_t)it.G * p.n : (size_t)((p.n + 15) & ~15);
+            bs_off += (g->wave || g->pm || g->pml) ? (size_t)it.G * p.n : (size_t)((p.n + 15) & ~15);
             it.xbuf = (unsigned long long *)(g->xbuf.as<int8_t>() + p.x_off);
         }
         g->x_off.push_back(p.x_off);
@@ -1329,9 +1364,7 @@ static int build_group(pt_batch *b, LaunchGroup *g, GroupMem &mem)
         g->ctx_mode.push_back(contextual(g->ctxs[k]) ? 1 : 0);
     }
     g->n_items = (int)P.items.size();
-    g->wide = P.wide;
-    g->quad = P.quad;
-    g->row = P.row;
+    g->sparse = P.sparse;
     g->grid = P.grid;
     g->block = P.block;
     g->lds = P.lds;
@@ -1372,7 +1405,13 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
         keys[std::make_tuple(c->kind, c->kind == KIND_LATTICE ? c->L : 0, rpt)] += 1;
     }
     LaunchGroup *g = new LaunchGroup();
-    g->mixed = keys.size() > 1;
+    // the +-J row kernel runs lattices of several sizes in one launch: asked
+    // for by the caller (kernel 7) where every context is a +-J lattice with
+    // even L in 6..16
+    bool all_pml = !any_ctx && o.kernel == 7;
+    for (pt_ctx *c : ctxs) all_pml = all_pml && c->pmL;
+    g->pml = all_pml;
+    g->mixed = keys.size() > 1 && !g->pml;
     g->kind = ctxs[0]->kind;
     g->L = g->kind == KIND_LATTICE ? ctxs[0]->L : 0;
     // the wave-per-replica kernel: one lattice size whose storage is exactly
@@ -1382,10 +1421,11 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
     // contextual proposals run in the workgroup-synchronous kernels only
     all_pm = all_pm && !any_ctx;
     g->ctx = any_ctx;
-    g->pm = all_pm && (o.kernel == 3 || o.kernel == 4 || (o.kernel == 0 && o.replicas_per_thread <= 1));
+    g->pm = !g->pml && all_pm && (o.kernel == 3 || o.kernel == 4 || (o.kernel == 0 && o.replicas_per_thread <= 1));
     g->spw = o.kernel == 4 ? 1 : 2;
-    g->wave = !g->pm && !g->mixed && !any_ctx && g->kind == KIND_LATTICE && wave_supported(g->L) && o.kernel != 1 &&
-              (o.kernel == 2 || o.replicas_per_thread <= 1);
+    g->sparse_req = o.kernel == 1 ? -1 : o.kernel == 5 ? SPARSE_ROW : o.kernel == 6 ? SPARSE_ROW4 : 0;
+    g->wave = !g->pm && !g->pml && !g->mixed && !any_ctx && g->kind == KIND_LATTICE && wave_supported(g->L) &&
+              o.kernel != 1 && o.kernel != 5 && o.kernel != 6 && (o.kernel == 2 || o.replicas_per_thread <= 1);
     for (pt_ctx *c : ctxs) {
         int G, rpt;
         if (g->pm) {
@@ -1393,6 +1433,10 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
             G = o.replicas_per_wg > 0 ? o.replicas_per_wg : 8;
             G = std::min(std::min(G, c->R), pm_max_storages(g->spw));
             if (g->spw == 2) G = std::max(G & ~1, 2);
+        } else if (g->pml) {
+            rpt = 1;
+            G = o.replicas_per_wg > 0 ? o.replicas_per_wg : pml_max_storages();
+            G = std::min(std::min(G, c->R), pml_max_storages());
         } else if (g->wave) {
             rpt = 1;
             G = o.replicas_per_wg > 0 ? o.replicas_per_wg : wave_max_storages();
@@ -1495,6 +1539,7 @@ extern "C" int pt_batch_create(pt_ctx *const *ctxs, int32_t k, const pt_batch_op
     *out = nullptr;
     if (!ctxs || k < 1) return fail(PT_EINVAL, "need at least one context");
     if (!ctxs[0]) return fail(PT_EINVAL, "context 0 missing");
+    if (o && (o->kernel < 0 || o->kernel > 7)) return fail(PT_EINVAL, "kernel must be in 0..7 (got %d)", o->kernel);
     pt_batch *b = new pt_batch();
     if (o) b->opts = *o;
     if (b->opts.chunk_sweeps <= 0) b->opts.chunk_sweeps = 1000;
@@ -1533,10 +1578,11 @@ static hipError_t enqueue_round(pt_batch *b, uint32_t K, bool timed)
         a.spin_limit = 1u << 22;
         a.tsw_entries = g->tsw_entries;
         hipError_t e = g->pm      ? launch_pm(g->spw, a, g->block, g->lds, b->stream)
+                       : g->pml   ? launch_pml(a, g->block, g->lds, b->stream)
                        : g->wave  ? launch_wave(g->L, a, g->block, g->lds, b->stream)
                        : g->mixed ? launch_chunk_mixed(a, g->block, g->lds, b->stream)
                        : g->ctx   ? launch_chunk_ctx(g->kind, g->L, a, g->block, g->lds, b->stream)
-                                  : launch_chunk(g->kind, g->L, g->rpt, g->wide, g->quad, g->row, a, g->block, g->lds,
+                                  : launch_chunk(g->kind, g->L, g->rpt, g->sparse, a, g->block, g->lds,
                                                  b->stream);
         if (e != hipSuccess) return e;
         if (timed) {
@@ -1675,11 +1721,20 @@ extern "C" int pt_batch_describe(pt_batch *b, char *buf, int32_t len)
     if (!b || !buf || len < 1) return fail(PT_EINVAL, "null batch or buffer");
     std::string out;
     for (const LaunchGroup *g : b->groups) {
-        const char *kern = g->pm ? (g->spw == 1 ? "pm1" : "pm") : g->wave ? "wave" : g->mixed ? "mixed" : g->ctx ? "ctx" : "chunk";
+        const char *kern = g->pm    ? (g->spw == 1 ? "pm1" : "pm")
+                           : g->pml ? "pml"
+                           : g->wave ? "wave"
+                           : g->mixed ? "mixed"
+                           : g->ctx ? "ctx"
+                                    : "chunk";
         std::string sw;
-        if (g->pm || g->wave || g->mixed) sw = "-";
+        if (g->pm || g->pml || g->wave || g->mixed) sw = "-";
         else if (g->kind == KIND_LATTICE) sw = "lattice" + std::to_string(g->L) + "x" + std::to_string(g->rpt);
-        else sw = g->row ? "csr-row" : g->quad ? "csr-quad" : g->wide ? "csr-wide" : "csr";
+        else sw = g->sparse == SPARSE_ROW4  ? "csr-row4"
+                  : g->sparse == SPARSE_ROW ? "csr-row"
+                  : g->sparse == SPARSE_QUAD ? "csr-quad"
+                  : g->sparse == SPARSE_WIDE ? "csr-wide"
+                                             : "csr";
         char line[256];
         snprintf(line, sizeof line, "kernel=%s sweeper=%s contexts=%zu grid=%d block=%d lds=%zu\n", kern, sw.c_str(),
                  g->ctxs.size(), g->grid, g->block, g->lds);
@@ -1831,6 +1886,7 @@ int clone_ctx(const pt_ctx *tm, uint64_t seed, int has_target, int32_t target, u
     c->clamp = tm->clamp;
     c->nfree = tm->nfree;
     c->pmJ = tm->pmJ;
+    c->pmL = tm->pmL;
     c->device = tm->device;
     c->stream = s;
     c->own_stream = false;

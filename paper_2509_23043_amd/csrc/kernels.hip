@@ -313,12 +313,15 @@ int lattice_max_threads() { return 512; }
 int lattice_threads(int L, int G, int rpt) { return ((G + rpt - 1) / rpt) * (L * L * L / 8); }
 
 size_t chunk_lds_bytes(int kind, int n, int G, int stride, int tsw_entries, int nnz, int nfree, int ncolors,
-                       bool contextual, bool quad, size_t row_graph)
+                       bool contextual, int sparse, size_t row_graph)
 {
-    if (kind == KIND_CSR && row_graph)   // the packed-row sweeper, its rows' bytes
+    if (kind == KIND_CSR && sparse == SPARSE_ROW4)   // interleaved storages, packed rows of row_graph bytes
+        return chunk_lds_offsets(CsrRowQuadSweep::group_bytes(G), n, stride, (n + 7) & ~7, tsw_entries, n, row_graph,
+                                 false).total;
+    if (kind == KIND_CSR && sparse == SPARSE_ROW)    // per-storage bytes, packed rows of row_graph bytes
         return chunk_lds_offsets(G, CsrSweep::storage_bytes(n), stride, (n + 7) & ~7, tsw_entries, n, row_graph,
                                  false).total;
-    if (kind == KIND_CSR && quad)
+    if (kind == KIND_CSR && sparse == SPARSE_QUAD)
         return chunk_lds_offsets(CsrQuadSweep::group_bytes(G), n, stride, (n + 7) & ~7, tsw_entries, n,
                                  quad_graph_bytes(n, nnz, nfree, ncolors), false).total;
     int SB = kind == KIND_LATTICE ? n : CsrSweep::storage_bytes(n);
@@ -342,12 +345,17 @@ static hipError_t launch_chunk_t(const ChunkArgs &a, int block, size_t lds, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_chunk(int kind, int L, int rpt, bool wide, bool quad, bool row, const ChunkArgs &a, int block,
-                        size_t lds, hipStream_t s)
+hipError_t launch_chunk(int kind, int L, int rpt, int sparse, const ChunkArgs &a, int block, size_t lds, hipStream_t s)
 {
-    if (kind == KIND_CSR && row) return launch_chunk_t<CsrRowSweep>(a, block, lds, s);
-    if (kind == KIND_CSR && quad) return launch_chunk_t<CsrQuadSweep>(a, block, lds, s);
-    if (kind == KIND_CSR) return wide ? launch_chunk_t<CsrSweepWide>(a, block, lds, s) : launch_chunk_t<CsrSweep>(a, block, lds, s);
+    if (kind == KIND_CSR) {
+        switch (sparse) {
+        case SPARSE_ROW4: return launch_chunk_t<CsrRowQuadSweep>(a, block, lds, s);
+        case SPARSE_ROW: return launch_chunk_t<CsrRowSweep>(a, block, lds, s);
+        case SPARSE_QUAD: return launch_chunk_t<CsrQuadSweep>(a, block, lds, s);
+        case SPARSE_WIDE: return launch_chunk_t<CsrSweepWide>(a, block, lds, s);
+        default: return launch_chunk_t<CsrSweep>(a, block, lds, s);
+        }
+    }
 #define X(LL)                                                                         \
     if (L == LL) {                                                                    \
         if (rpt == 1) return launch_chunk_t<LatSweep<LL, 1>>(a, block, lds, s);       \
@@ -367,13 +375,17 @@ static hipError_t occupancy_t(int block, size_t lds, int *blocks_per_cu)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, chunk_kernel<Sw>, block, lds);
 }
 
-hipError_t chunk_occupancy(int kind, int L, int rpt, bool wide, bool quad, bool row, int block, size_t lds,
-                           int *blocks_per_cu)
+hipError_t chunk_occupancy(int kind, int L, int rpt, int sparse, int block, size_t lds, int *blocks_per_cu)
 {
-    if (kind == KIND_CSR && row) return occupancy_t<CsrRowSweep>(block, lds, blocks_per_cu);
-    if (kind == KIND_CSR && quad) return occupancy_t<CsrQuadSweep>(block, lds, blocks_per_cu);
-    if (kind == KIND_CSR)
-        return wide ? occupancy_t<CsrSweepWide>(block, lds, blocks_per_cu) : occupancy_t<CsrSweep>(block, lds, blocks_per_cu);
+    if (kind == KIND_CSR) {
+        switch (sparse) {
+        case SPARSE_ROW4: return occupancy_t<CsrRowQuadSweep>(block, lds, blocks_per_cu);
+        case SPARSE_ROW: return occupancy_t<CsrRowSweep>(block, lds, blocks_per_cu);
+        case SPARSE_QUAD: return occupancy_t<CsrQuadSweep>(block, lds, blocks_per_cu);
+        case SPARSE_WIDE: return occupancy_t<CsrSweepWide>(block, lds, blocks_per_cu);
+        default: return occupancy_t<CsrSweep>(block, lds, blocks_per_cu);
+        }
+    }
 #define X(LL)                                                                      \
     if (L == LL) {                                                                 \
         if (rpt == 1) return occupancy_t<LatSweep<LL, 1>>(block, lds, blocks_per_cu); \
@@ -405,7 +417,7 @@ static hipError_t launch_plain_sweep_t(const InstDev *dI, int R, int block, size
 hipError_t launch_plain(int kind, int L, const InstDev *dI, int R, int n, int stride, int nnz, int nfree, int ncolors,
                         uint32_t t, hipStream_t s)
 {
-    size_t lds = chunk_lds_bytes(kind, n, 1, stride, 0, nnz, nfree, ncolors, false, false, 0);
+    size_t lds = chunk_lds_bytes(kind, n, 1, stride, 0, nnz, nfree, ncolors, false, SPARSE_CSR, 0);
     hipError_t e;
     if (kind == KIND_CSR) {
         e = launch_plain_sweep_t<CsrSweep>(dI, R, 256, lds, t, s);

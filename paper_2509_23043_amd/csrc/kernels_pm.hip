@@ -267,8 +267,15 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
         constexpr uint32_t UCYC = 64 / NP;
         uint32_t u_vec = 0, u_base = (uint32_t)-100;
         const uint32_t u_i = (uint32_t)lane % (uint32_t)NP, u_c = (uint32_t)lane / (uint32_t)NP;
+        // the sweep uniforms of the next sweep: slots are fixed per wavefront,
+        // so they are drawn ahead, where the cycle end waits for a partner
+        P4 rn[SPW];
+#pragma unroll
+        for (int k = 0; k < SPW; ++k)
+            rn[k] = philox_v((uint32_t)lane, (uint32_t)(t0 + 1), (uint32_t)(lab0 + k), TAG_SWEEP, P.k0, P.k1);
 
         for (uint64_t t = t0 + 1; t <= tend && !failed; ++t) {
+            bool drawn = false;   // rn holds sweep t + 1's uniforms
             const bool ends = phase + 1 == (uint32_t)P.M;
             // one Philox call per UCYC cycles, drawn before the sweep so that
             // its latency hides behind it
@@ -285,7 +292,7 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
             uint32_t a_me[SPW], a_yp[SPW], a_ym[SPW], a_zp[SPW], a_zm[SPW];   // row addresses in bufs
 #pragma unroll
             for (int k = 0; k < SPW; ++k) {
-                r[k] = philox_v((uint32_t)lane, (uint32_t)t, (uint32_t)(lab0 + k), TAG_SWEEP, P.k0, P.k1);
+                r[k] = rn[k];
                 const uint32_t B = (uint32_t)(buf[k] * N);
                 a_me[k] = B + rel_me;
                 a_yp[k] = B + rel_yp;
@@ -434,6 +441,11 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                         if (lane <= NWD)
                             __hip_atomic_store(out + lane, ((unsigned long long)cyc << 32) | pay, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    // next sweep's uniforms while the partners' words travel
+                    if (intra || cross) {
+                        rn[0] = philox_v((uint32_t)lane, (uint32_t)(t + 1), (uint32_t)lab0, TAG_SWEEP, P.k0, P.k1);
+                        drawn = true;
                     }
                     if (intra) {
                         uint32_t polls = 0;
@@ -714,6 +726,11 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
                 }
             } else {
                 ++phase;
+            }
+            if (!drawn) {
+#pragma unroll
+                for (int k = 0; k < SPW; ++k)
+                    rn[k] = philox_v((uint32_t)lane, (uint32_t)(t + 1), (uint32_t)(lab0 + k), TAG_SWEEP, P.k0, P.k1);
             }
             // ---- best energy and first hit, per slot ----
 #pragma unroll

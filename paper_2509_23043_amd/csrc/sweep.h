@@ -713,6 +713,217 @@ struct CsrRowSweep {
 };
 
 // ---------------------------------------------------------------------------
+// General sparse graph, packed rows and four storages per lane ("row-quad"
+// sweeper). The storages are interleaved as in CsrQuadSweep (byte k of site
+// i's GS-byte group is storage k's down-bit), so one dword read gives a
+// neighbour's spins in four storages and a lane decides one site of four
+// storages at once (U summed byte-parallel, d = D_i - 2 U per storage). The
+// rows are packed as in CsrRowSweep, for a fixed (site rank s, quad) item per
+// thread: record (c, s, sub) holds the s-th site of class c and 16 of its
+// bonds as words (neighbour byte offset j * GS in bits 0-15, 1 in byte 2 if
+// J < 0, |J| in byte 3), read with four 16-byte LDS reads and prefetched one
+// class ahead. A bond costs an add, a dword read, a byte permute, a shift and
+// a multiply, a three-input XOR and a packed multiply-add; unused bond words are 0 (the
+// dword at offset 0 with |J| = 0). Requirements (checked by the runtime):
+// every D_i <= 255, (n - 1) * GS + 3 < 65536, degree <= 32 (LP = 1 or 2
+// lanes per item, U partial sums added after DPP: no byte exceeds D_i), and a
+// block of at least (largest class) x GS / 4 x LP threads.
+struct RowQuadGraph {
+    uint4 *bw;        // [ncolors][maxcnt][LP][4]: 16 bond words
+    uint32_t *info;   // [ncolors][maxcnt][LP]: i | D_i << 12 | |h_i| << 20 | [h_i < 0] << 28 (h on sub 0); 0xFFF: none
+};
+
+struct CsrRowQuadSweep {
+    static constexpr int RPTV = 1;
+    static constexpr int MAXT = 512;
+    static constexpr int MINW = 1;
+    static constexpr bool RND = true;
+    static constexpr int BPL = CSR_ROW4_BPL;
+    int n, G, GS, nr, qd, sub, lp, s, maxcnt;
+    RowQuadGraph gr;
+
+    __host__ __device__ static int group_bytes(int G) { return (G + 3) & ~3; }
+    __device__ static size_t graph_bytes(const InstDev &I)
+    {
+        return csr_row4_graph_bytes(I.ncolors, I.maxcnt, csr_row4_lanes(I.maxdeg));
+    }
+
+    __device__ void setup(const InstDev &I, int G_)
+    {
+        n = I.n;
+        G = G_;
+        GS = group_bytes(G_);
+        nr = (n + 7) & ~7;
+    }
+
+    __device__ __forceinline__ void bind(const InstDev &I, unsigned char *base, int tid, int bs)
+    {
+        lp = csr_row4_lanes(I.maxdeg);
+        maxcnt = I.maxcnt;
+        const int nq = GS >> 2;
+        sub = tid & (lp - 1);
+        const int it = tid / lp;
+        s = it / nq;
+        qd = it - s * nq;
+        const int nrec = I.ncolors * maxcnt * lp;
+        gr.bw = (uint4 *)base;
+        gr.info = (uint32_t *)(base + (size_t)nrec * 64);
+        for (int x = tid; x < nrec; x += bs) {
+            const int c = x / (maxcnt * lp), rest = x - c * maxcnt * lp;
+            const int ss = rest / lp, sb = rest - ss * lp;
+            const int off = I.color_off[c], cnt = I.color_off[c + 1] - off;
+            uint32_t w[16];
+#pragma unroll
+            for (int b = 0; b < 16; ++b) w[b] = 0;
+            uint32_t info = 0xFFFu;
+            if (ss < cnt) {
+                const int i = I.color_sites[off + ss];
+                const int r0 = I.row_ptr[i], r1 = I.row_ptr[i + 1];
+                int D = 0;
+                for (int e = r0; e < r1; ++e) D += abs((int)I.Jc[e]);
+                const int h = sb == 0 ? (int)I.h[i] : 0;
+                D += abs((int)I.h[i]);
+                const int e0 = r0 + sb * BPL;
+#pragma unroll
+                for (int b = 0; b < 16; ++b) {
+                    if (e0 + b < r1) {
+                        const int J = I.Jc[e0 + b];
+                        w[b] = (uint32_t)I.col[e0 + b] * (uint32_t)GS | (J < 0 ? 0x10000u : 0u) |
+                               ((uint32_t)abs(J) << 24);
+                    }
+                }
+                info = (uint32_t)i | ((uint32_t)D << 12) | ((uint32_t)abs(h) << 20) | (h < 0 ? 1u << 28 : 0u);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) gr.bw[4 * x + q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+            gr.info[x] = info;
+        }
+    }
+
+    __device__ __forceinline__ void sweep(const InstDev &I, int G_, int s0, uint32_t t, const int *slot_of,
+                                          int8_t *sp, const uint32_t *tab, int stride, int *Elds,
+                                          unsigned *flips_lds, uint16_t *rnd)
+    {
+        (void)G_;
+        const int tid = threadIdx.x, bs = blockDim.x;
+        const int ncol = I.ncolors;
+        const bool on = s < maxcnt;             // threads past the last item only keep the barriers
+        const int xs = on ? s * lp + sub : 0;   // record of this thread in class 0
+        const int xstep = maxcnt * lp;          // records per class
+        uint4 w0 = gr.bw[4 * xs], w1 = gr.bw[4 * xs + 1], w2 = gr.bw[4 * xs + 2], w3 = gr.bw[4 * xs + 3];
+        uint32_t info = on ? gr.info[xs] : 0xFFFu;
+        // random halves of every (site, storage), interleaved like the spins
+        const int ncall = nr >> 3;
+        for (int idx = tid; idx < G * ncall; idx += bs) {
+            const int k = idx / ncall, q = idx - k * ncall;
+            const P4 r = philox_v((uint32_t)q, t, (uint32_t)(s0 + slot_of[k]), TAG_SWEEP, I.seed_lo, I.seed_hi);
+            uint16_t *dst = rnd + (size_t)(8 * q) * GS + k;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) dst[j * GS] = (uint16_t)(r.v[j >> 1] >> (16 * (j & 1)));
+        }
+        __syncthreads();
+        const int D = I.D;
+        const int qo = 4 * qd;                  // byte offset of this lane's quad in a site group
+        int tb[4];
+        uint32_t vm = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int st = qo + k;
+            const bool ok = st < G;
+            tb[k] = ok ? slot_of[st] * stride + D : D;
+            vm |= ok ? (1u << (8 * k)) : 0u;
+        }
+        int e_acc[4] = {0, 0, 0, 0};
+        unsigned f_acc[4] = {0, 0, 0, 0};
+        for (int c = 0; c < ncol; ++c) {
+            const int i = (int)(info & 0xFFFu);
+            const bool valid = i != 0xFFF;
+            uint32_t U = 0, own = 0;
+            uint2 hh = make_uint2(0, 0);
+            const uint32_t a_own = (uint32_t)i * (uint32_t)GS + (uint32_t)qo;
+            if (valid) {
+                // the item's reads are independent: one LDS round trip
+                own = *(const uint32_t *)(sp + a_own);
+                hh = *(const uint2 *)(rnd + a_own);
+                U = pk_mad_u16(own ^ ((info >> 28) * 0x01010101u), ((info >> 20) & 0xFFu) * 0x10001u, 0u);
+                const uint32_t ws[16] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w,
+                                         w2.x, w2.y, w2.z, w2.w, w3.x, w3.y, w3.z, w3.w};
+#pragma unroll
+                for (int b = 0; b < 16; ++b) {
+                    const uint32_t w = ws[b];
+                    const uint32_t nb = *(const uint32_t *)(sp + (w & 0xFFFFu) + (uint32_t)qo);
+                    // sign byte to all four bytes; |J| to both 16-bit halves
+                    const uint32_t sg = __builtin_amdgcn_perm(w, w, 0x02020202u);
+                    const uint32_t aj = (w >> 24) * 0x10001u;
+                    U = pk_mad_u16(xor3(own, nb, sg), aj, U);
+                }
+            }
+            const uint32_t info_c = info;
+            // the next class's row, in flight while this class is decided
+            if (c + 1 < ncol) {
+                const int xn = xs + (c + 1) * xstep;
+                w0 = gr.bw[4 * xn];
+                w1 = gr.bw[4 * xn + 1];
+                w2 = gr.bw[4 * xn + 2];
+                w3 = gr.bw[4 * xn + 3];
+                info = on ? gr.info[xn] : 0xFFFu;
+            }
+            if (lp == 2) U += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)U, 0xB1, 0xf, 0xf, false);   // quad_perm 1,0,3,2
+            if (valid) {
+                const int Dsite = (int)((info_c >> 12) & 0xFFu);
+                uint32_t T[4], hs[4];
+                int d[4];
+                bool acc[4], maybe[4];
+                bool any_maybe = false;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    d[k] = Dsite - 2 * (int)((U >> (8 * k)) & 0xFFu);   // m_i I_i of storage qo + k
+                    T[k] = tab[tb[k] + d[k]];
+                    const uint32_t wv = k < 2 ? hh.x : hh.y;
+                    hs[k] = (k & 1) ? (wv & 0xFFFF0000u) : (wv << 16);
+                    acc[k] = coarse_accept(T[k], hs[k], maybe[k]) && ((vm >> (8 * k)) & 1u);
+                    maybe[k] = maybe[k] && ((vm >> (8 * k)) & 1u);
+                    any_maybe |= maybe[k];
+                }
+                if (any_lane(any_maybe)) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if (maybe[k]) {
+                            const P4 r2 = philox(opaque((uint32_t)(i >> 3)), t, (uint32_t)(s0 + slot_of[qo + k]), TAG_REFINE,
+                                                 I.seed_lo, I.seed_hi);
+                            const int wq = (i & 7) >> 1;
+                            const uint32_t wd = wq == 0 ? r2.v[0] : wq == 1 ? r2.v[1] : wq == 2 ? r2.v[2] : r2.v[3];
+                            const uint32_t lo = ((i & 1) ? (wd >> 16) : wd) & 0xFFFFu;
+                            acc[k] = (T[k] == ALWAYS) || ((hs[k] | lo) < T[k]);
+                        }
+                    }
+                }
+                if (sub == 0) {   // the lanes of an item agree; the first one writes
+                    uint32_t F = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        F |= acc[k] ? (1u << (8 * k)) : 0u;
+                        e_acc[k] += acc[k] ? 2 * d[k] : 0;       // the flip changes E by 2 d
+                        f_acc[k] += acc[k] ? 1u : 0u;
+                    }
+                    if (F) *(uint32_t *)(sp + a_own) = own ^ F;
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int st = qo + k;
+            if (on && st < G && (e_acc[k] != 0 || f_acc[k] != 0)) {
+                atomicAdd(&Elds[st], e_acc[k]);
+                atomicAdd(&flips_lds[slot_of[st]], f_acc[k]);
+            }
+        }
+        __syncthreads();
+    }
+};
+
+// ---------------------------------------------------------------------------
 // General sparse graph, four storages per lane ("quad" sweeper). The storages
 // of a workgroup are interleaved: byte k of site i's GS-byte group (GS = G
 // rounded up to a multiple of 4) holds storage k's spin as a down-bit (1 for
@@ -1163,6 +1374,28 @@ struct SweepCall<CsrRowSweep> {
     static __device__ int pos(const CsrRowSweep &s, int st, int p) { return st * s.SB + p; }
     static __device__ int8_t enc(int m) { return (int8_t)m; }
     static __device__ int dec(int8_t v) { return v; }
+    struct CtxView {};
+};
+
+template <>
+struct SweepCall<CsrRowQuadSweep> {
+    static __device__ __forceinline__ void run(CsrRowQuadSweep &sw, const InstDev &I, int G, int s0, uint32_t t,
+                                               ChunkLds &c, int stride)
+    {
+        sw.sweep(I, G, s0, t, c.slot_of, c.sp, c.tab, stride, c.Elds, c.flips, c.rnd);
+    }
+    // the carve-up takes GS slots of n bytes each, as for CsrQuadSweep
+    static __device__ int SB(const CsrRowQuadSweep &s) { return s.n; }
+    static __device__ int lidx(const CsrRowQuadSweep &, int i) { return i; }
+    static __device__ size_t graph_bytes(const InstDev &I) { return CsrRowQuadSweep::graph_bytes(I); }
+    static __device__ void bind(CsrRowQuadSweep &sw, const InstDev &I, unsigned char *base, int tid, int bs)
+    {
+        sw.bind(I, base, tid, bs);
+    }
+    static __device__ int layout_g(const CsrRowQuadSweep &s, int) { return s.GS; }
+    static __device__ int pos(const CsrRowQuadSweep &s, int st, int p) { return p * s.GS + st; }
+    static __device__ int8_t enc(int m) { return m < 0 ? 1 : 0; }
+    static __device__ int dec(int8_t v) { return v ? -1 : 1; }
     struct CtxView {};
 };
 

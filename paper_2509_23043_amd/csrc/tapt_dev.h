@@ -15,6 +15,8 @@ enum : uint32_t {
 };
 constexpr uint32_t ALWAYS = 0xFFFFFFFFu;   // threshold meaning "accept unconditionally"
 constexpr int MAX_COLORS = 64;
+// sparse-graph sweepers of the workgroup-synchronous kernel
+enum : int32_t { SPARSE_CSR = 0, SPARSE_WIDE = 1, SPARSE_QUAD = 2, SPARSE_ROW = 3, SPARSE_ROW4 = 4 };
 // packed-row sparse sweeper: bonds per lane, lanes per (site, storage) item
 // for a largest degree, limits, and the LDS bytes of its rows
 constexpr int CSR_ROW_BPL = 16, CSR_ROW_MAXN = 4095, CSR_ROW_MAXJ = 7;
@@ -22,6 +24,13 @@ __host__ __device__ inline int csr_row_lanes(int maxdeg) { return maxdeg <= CSR_
 __host__ __device__ inline size_t csr_row_graph_bytes(int ncolors, int maxcnt, int lanes)
 {
     return (size_t)ncolors * maxcnt * lanes * 36 + 32;
+}
+// the same for the four-storages-per-lane variant (16 bonds of 32 bits per record)
+constexpr int CSR_ROW4_BPL = 16;
+__host__ __device__ inline int csr_row4_lanes(int maxdeg) { return maxdeg <= CSR_ROW4_BPL ? 1 : 2; }
+__host__ __device__ inline size_t csr_row4_graph_bytes(int ncolors, int maxcnt, int lanes)
+{
+    return (size_t)ncolors * maxcnt * lanes * 68 + 64;
 }
 
 struct BestRec {          // best min_r E_r seen; ordered by (E, t, slot)
