@@ -220,7 +220,9 @@ typedef struct {
                                     7 = +-J row kernel, one slot per wavefront, lattices
                                         of every even L in 6..16 in one launch (every
                                         coupling +-1, no fields), at most 8 slots per
-                                        workgroup */
+                                        workgroup. 0 takes 7 where every context fits
+                                        it and not all are 8^3 lattices (those take 3),
+                                        else the other kernels */
 } pt_batch_opts;
 
 /* Group contexts for batched execution. The contexts stay owned by the

@@ -79,8 +79,9 @@ def candidates(contexts):
             out.append((G, 1, "pm"))
         if pm_ok and G <= 8:
             out.append((G, 1, "pm1"))
-        if pml_ok and G <= 8:
-            out.append((G, 1, "pml"))
+
+    if pml_ok:   # one slot per wavefront: every workgroup size up to 8 wavefronts
+        out += [(G, 1, "pml") for G in range(1, 9) if G <= rmax]
     return out
 
 

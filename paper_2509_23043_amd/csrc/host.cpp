@@ -1394,7 +1394,7 @@ static void clear_groups(pt_batch *b)
 // The launch group for a set of contexts (host fields only). Contexts that
 // share one sweeper instantiation run in the specialised kernel; a set that
 // needs several sweepers runs as a single launch of the mixed kernel.
-static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx *> &ctxs, int level)
+static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx *> &ctxs, int level, bool pml_auto)
 {
     bool any_ctx = false;
     for (pt_ctx *c : ctxs) any_ctx = any_ctx || contextual(c);
@@ -1405,12 +1405,17 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
         keys[std::make_tuple(c->kind, c->kind == KIND_LATTICE ? c->L : 0, rpt)] += 1;
     }
     LaunchGroup *g = new LaunchGroup();
-    // the +-J row kernel runs lattices of several sizes in one launch: asked
-    // for by the caller (kernel 7) where every context is a +-J lattice with
-    // even L in 6..16
-    bool all_pml = !any_ctx && o.kernel == 7;
-    for (pt_ctx *c : ctxs) all_pml = all_pml && c->pmL;
-    g->pml = all_pml;
+    // the +-J row kernel runs lattices of several sizes in one launch: where
+    // every context is a +-J lattice with even L in 6..16, when the caller
+    // asks for it (kernel 7) or leaves the kernel open (kernel 0, one slot
+    // per thread) and the batch is not one of 8^3 lattices only (the +-J 8^3
+    // kernel's)
+    bool all_pml = !any_ctx, all_pm8 = true;
+    for (pt_ctx *c : ctxs) {
+        all_pml = all_pml && c->pmL;
+        all_pm8 = all_pm8 && c->pmJ;
+    }
+    g->pml = all_pml && (o.kernel == 7 || (pml_auto && o.kernel == 0 && !all_pm8 && o.replicas_per_thread <= 1));
     g->mixed = keys.size() > 1 && !g->pml;
     g->kind = ctxs[0]->kind;
     g->L = g->kind == KIND_LATTICE ? ctxs[0]->L : 0;
@@ -1464,15 +1469,24 @@ static int pick_group(const pt_batch *b, const std::vector<pt_ctx *> &ctxs, Laun
     int rc = PT_OK;
     bool waits = false;
     for (pt_ctx *c : ctxs) waits = waits || c->opts.sweeps_per_cycle != 0;
-    for (int level = waits ? 0 : TILING_LEVELS - 1; level < TILING_LEVELS; ++level) {
-        LaunchGroup *g = make_group(b->opts, ctxs, level);
-        GroupPlan P;
-        rc = plan_group(b, g, P);
-        if (rc == PT_OK) {
-            *out = g;
-            return PT_OK;
+    // first the +-J row kernel where the caller leaves the kernel open (its
+    // tiling does not depend on the level), then the others
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int level = waits ? 0 : TILING_LEVELS - 1; level < TILING_LEVELS; ++level) {
+            LaunchGroup *g = make_group(b->opts, ctxs, level, pass == 0);
+            if (pass == 0 && !(g->pml && b->opts.kernel == 0)) {
+                delete g;
+                break;
+            }
+            GroupPlan P;
+            rc = plan_group(b, g, P);
+            if (rc == PT_OK) {
+                *out = g;
+                return PT_OK;
+            }
+            delete g;
+            if (pass == 0) break;
         }
-        delete g;
     }
     return rc;
 }
