@@ -222,7 +222,10 @@ typedef struct {
                                         coupling +-1, no fields), at most 8 slots per
                                         workgroup. 0 takes 7 where every context fits
                                         it and not all are 8^3 lattices (those take 3),
-                                        else the other kernels */
+                                        else the other kernels;
+                                    8 = general graphs, one slot per wavefront (n <= 4095,
+                                        |J| <= 7, degree <= 16, colour classes of at most
+                                        256 sites), at most 8 slots per workgroup */
 } pt_batch_opts;
 
 /* Group contexts for batched execution. The contexts stay owned by the

@@ -57,7 +57,7 @@ def candidates(contexts):
     8^3 kernel (two slots or one slot per wavefront) where every coupling is
     +-1 and every ladder has even length, and the +-J row kernel (one slot
     per wavefront, any even L in 6..16, sizes mixed) where every coupling is
-    +-1."""
+    +-1, and the one-slot-per-wavefront sparse kernel for general graphs."""
     rmax = max(c.R for c in contexts)
     wave_ok = all(c.kind == "lattice" and c.L == 8 for c in contexts)
     pm_ok = all(getattr(c, "pm", False) for c in contexts)
@@ -82,6 +82,8 @@ def candidates(contexts):
 
     if pml_ok:   # one slot per wavefront: every workgroup size up to 8 wavefronts
         out += [(G, 1, "pml") for G in range(1, 9) if G <= rmax]
+    if csr_ok:   # the same for general graphs
+        out += [(G, 1, "csrw") for G in range(1, 9) if G <= rmax]
     return out
 
 

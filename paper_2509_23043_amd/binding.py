@@ -45,7 +45,7 @@ class _BatchOpts(C.Structure):
                 ("chunk_sweeps", C.c_int32), ("use_graph", C.c_int32), ("kernel", C.c_int32)]
 
 
-KERNELS = {"auto": 0, "block": 1, "wave": 2, "pm": 3, "pm1": 4, "row": 5, "row4": 6, "pml": 7}
+KERNELS = {"auto": 0, "block": 1, "wave": 2, "pm": 3, "pm1": 4, "row": 5, "row4": 6, "pml": 7, "csrw": 8}
 
 
 class _ServeOpts(C.Structure):

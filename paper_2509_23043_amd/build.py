@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtapt.so")
-SOURCES = ["kernels.hip", "kernels_mixed.hip", "kernels_wave.hip", "kernels_pm.hip", "kernels_pml.hip", "kernels_ctx.hip",
+SOURCES = ["kernels.hip", "kernels_mixed.hip", "kernels_wave.hip", "kernels_pm.hip", "kernels_pml.hip", "kernels_csrw.hip",
+           "kernels_ctx.hip",
            "probe.hip", "host.cpp"]
 
 

@@ -58,6 +58,12 @@ size_t pml_lds_bytes(int L, int G, int tsw_entries);
 int pml_xwords(int L);
 hipError_t launch_pml(const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t pml_occupancy(int block, size_t lds, int *blocks_per_cu);
+int csrw_max_storages();
+bool csrw_supported(int n, int maxabsj, int maxdeg, int maxcnt);
+size_t csrw_lds_bytes(int n, int ncolors, int maxcnt, int G, int stride, int tsw_entries);
+int csrw_xwords(int n);
+hipError_t launch_csrw(const ChunkArgs &a, int block, size_t lds, hipStream_t s);
+hipError_t csrw_occupancy(int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_plain(int kind, int L, const InstDev *dI, int R, int n, int stride, int nnz, int nfree, int ncolors,
                         uint32_t t, hipStream_t s);
 hipError_t launch_init(const InstDev *dI, int R, int n, hipStream_t s);
@@ -1048,6 +1054,7 @@ struct LaunchGroup {
     bool wave = false;                // wave-per-replica kernel
     bool pm = false;                  // +-J 8^3 kernel
     bool pml = false;                 // +-J row kernel, even L in 6..16, one slot per wavefront
+    bool csrw = false;                // sparse graphs, one slot per wavefront
     int spw = 2;                      // its slots per wavefront (1 or 2)
     bool ctx = false;                 // some context has contextual proposals (chunk_kernel_ctx)
     int sparse = SPARSE_CSR;          // sparse graphs: the sweeper of the chunk kernel
@@ -1149,7 +1156,7 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
     // (the four-storages-per-lane one first): its block holds one thread per
     // item (site and storage, or site and four storages) and bond share of
     // the largest colour class.
-    const bool sparse_sync = g->kind == KIND_CSR && !g->mixed && !g->ctx;
+    const bool sparse_sync = g->kind == KIND_CSR && !g->mixed && !g->ctx && !g->csrw;
     bool row_ok = sparse_sync, row4_ok = sparse_sync;
     int row_block = 64, row4_block = 64;
     for (size_t k = 0; k < g->ctxs.size() && sparse_sync; ++k) {
@@ -1163,7 +1170,7 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         // the two-slot +-J kernel splits the ladder into whole slot pairs (even G, even s0)
         const int unit = g->pm ? g->spw : 1;
         int R = c->R / unit, W = (R + g->Gs[k] / unit - 1) / (g->Gs[k] / unit);
-        int xwords = ((g->pml ? pml_xwords(c->L) : ((c->n + 31) >> 5) + 1) + 7) & ~7;
+        int xwords = ((g->pml ? pml_xwords(c->L) : g->csrw ? csrw_xwords(c->n) : ((c->n + 31) >> 5) + 1) + 7) & ~7;
         P.ctx.push_back({(int)P.items.size(), W, c->n, xwords, unit * ((R + W - 1) / W), P.nbs, P.nx});
         P.first.push_back((int)P.items.size());
         int base = R / W, extra = R % W, s0 = 0;
@@ -1179,7 +1186,7 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
             it.variant = g->pml ? c->L : mixed_variant_of(c->kind, c->L, g->rpts[k]);
             P.items.push_back(it);
             s0 += G;
-            P.nbs += (g->wave || g->pm || g->pml) ? (size_t)G * c->n : (size_t)((c->n + 15) & ~15);   // one snapshot per slot
+            P.nbs += (g->wave || g->pm || g->pml || g->csrw) ? (size_t)G * c->n : (size_t)((c->n + 15) & ~15);   // one snapshot per slot
         }
         P.nbest += W;
         P.nx += (size_t)W * 4 * xwords * 8;
@@ -1193,7 +1200,7 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         }
         // a block covers the largest item's threads
         int need = g->pm     ? 64 * (P.ctx[k].gmax / g->spw)
-                   : (g->wave || g->pml) ? 64 * P.ctx[k].gmax
+                   : (g->wave || g->pml || g->csrw) ? 64 * P.ctx[k].gmax
                              : c->kind == KIND_LATTICE ? lattice_threads(c->L, P.ctx[k].gmax, g->rpts[k])
                              // sparse graphs: a few slots per workgroup (the latency tilings) get 512
                              // threads, so that 2 or 4 lanes can share a site's bonds
@@ -1249,6 +1256,8 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         pt_ctx *c = g->ctxs[k];
         P.lds = std::max(P.lds, g->pm     ? pm_lds_bytes(P.ctx[k].gmax, P.tsw_max)
                                 : g->pml ? pml_lds_bytes(c->L, P.ctx[k].gmax, P.tsw_max)
+                                : g->csrw ? csrw_lds_bytes(c->n, c->ncolors, c->hI.maxcnt, P.ctx[k].gmax, 2 * c->D + 1,
+                                                           P.tsw_max)
                                 : g->wave ? wave_lds_bytes(c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max)
                                           : chunk_lds_bytes(c->kind, c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max,
                                                             c->hI.nnz, c->hI.nfree, c->ncolors, contextual(c), P.sparse,
@@ -1269,6 +1278,8 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         HIPCHK(pm_occupancy(g->spw, P.block, P.lds, &P.per_cu));
     else if (g->pml)
         HIPCHK(pml_occupancy(P.block, P.lds, &P.per_cu));
+    else if (g->csrw)
+        HIPCHK(csrw_occupancy(P.block, P.lds, &P.per_cu));
     else if (g->wave)
         HIPCHK(wave_occupancy(g->L, P.block, P.lds, &P.per_cu));
     else if (g->mixed)
@@ -1355,7 +1366,7 @@ static int build_group(pt_batch *b, LaunchGroup *g, GroupMem &mem)
             WorkItem &it = P.items[p.first + w];
             it.best = g->best.as<BestRec>() + bi++;
             it.best_spins = g->best_spins.as<int8_t>() + bs_off;
-            bs_off += (g->wave || g->pm || g->pml) ? (size_t)it.G * p.n : (size_t)((p.n + 15) & ~15);
+            bs_off += (g->wave || g->pm || g->pml || g->csrw) ? (size_t)it.G * p.n : (size_t)((p.n + 15) & ~15);
             it.xbuf = (unsigned long long *)(g->xbuf.as<int8_t>() + p.x_off);
         }
         g->x_off.push_back(p.x_off);
@@ -1416,6 +1427,14 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
         all_pm8 = all_pm8 && c->pmJ;
     }
     g->pml = all_pml && (o.kernel == 7 || (pml_auto && o.kernel == 0 && !all_pm8 && o.replicas_per_thread <= 1));
+    // the one-slot-per-wavefront sparse kernel where the caller asks for it
+    // (kernel 8) and every context is a general graph that fits it (its
+    // mailbox carries energies of 24 bits)
+    bool all_csrw = !any_ctx && o.kernel == 8;
+    for (pt_ctx *c : ctxs)
+        all_csrw = all_csrw && c->kind == KIND_CSR &&
+                   csrw_supported(c->n, c->hI.maxabsj, c->hI.maxdeg, c->hI.maxcnt) && (long long)c->n * c->D < (1 << 23);
+    g->csrw = all_csrw;
     g->mixed = keys.size() > 1 && !g->pml;
     g->kind = ctxs[0]->kind;
     g->L = g->kind == KIND_LATTICE ? ctxs[0]->L : 0;
@@ -1442,6 +1461,10 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
             rpt = 1;
             G = o.replicas_per_wg > 0 ? o.replicas_per_wg : pml_max_storages();
             G = std::min(std::min(G, c->R), pml_max_storages());
+        } else if (g->csrw) {
+            rpt = 1;
+            G = o.replicas_per_wg > 0 ? o.replicas_per_wg : csrw_max_storages();
+            G = std::min(std::min(G, c->R), csrw_max_storages());
         } else if (g->wave) {
             rpt = 1;
             G = o.replicas_per_wg > 0 ? o.replicas_per_wg : wave_max_storages();
@@ -1553,7 +1576,7 @@ extern "C" int pt_batch_create(pt_ctx *const *ctxs, int32_t k, const pt_batch_op
     *out = nullptr;
     if (!ctxs || k < 1) return fail(PT_EINVAL, "need at least one context");
     if (!ctxs[0]) return fail(PT_EINVAL, "context 0 missing");
-    if (o && (o->kernel < 0 || o->kernel > 7)) return fail(PT_EINVAL, "kernel must be in 0..7 (got %d)", o->kernel);
+    if (o && (o->kernel < 0 || o->kernel > 8)) return fail(PT_EINVAL, "kernel must be in 0..8 (got %d)", o->kernel);
     pt_batch *b = new pt_batch();
     if (o) b->opts = *o;
     if (b->opts.chunk_sweeps <= 0) b->opts.chunk_sweeps = 1000;
@@ -1593,6 +1616,7 @@ static hipError_t enqueue_round(pt_batch *b, uint32_t K, bool timed)
         a.tsw_entries = g->tsw_entries;
         hipError_t e = g->pm      ? launch_pm(g->spw, a, g->block, g->lds, b->stream)
                        : g->pml   ? launch_pml(a, g->block, g->lds, b->stream)
+                       : g->csrw  ? launch_csrw(a, g->block, g->lds, b->stream)
                        : g->wave  ? launch_wave(g->L, a, g->block, g->lds, b->stream)
                        : g->mixed ? launch_chunk_mixed(a, g->block, g->lds, b->stream)
                        : g->ctx   ? launch_chunk_ctx(g->kind, g->L, a, g->block, g->lds, b->stream)
@@ -1737,12 +1761,13 @@ extern "C" int pt_batch_describe(pt_batch *b, char *buf, int32_t len)
     for (const LaunchGroup *g : b->groups) {
         const char *kern = g->pm    ? (g->spw == 1 ? "pm1" : "pm")
                            : g->pml ? "pml"
+                           : g->csrw ? "csrw"
                            : g->wave ? "wave"
                            : g->mixed ? "mixed"
                            : g->ctx ? "ctx"
                                     : "chunk";
         std::string sw;
-        if (g->pm || g->pml || g->wave || g->mixed) sw = "-";
+        if (g->pm || g->pml || g->csrw || g->wave || g->mixed) sw = "-";
         else if (g->kind == KIND_LATTICE) sw = "lattice" + std::to_string(g->L) + "x" + std::to_string(g->rpt);
         else sw = g->sparse == SPARSE_ROW4  ? "csr-row4"
                   : g->sparse == SPARSE_ROW ? "csr-row"
