@@ -225,7 +225,8 @@ typedef struct {
                                         else the other kernels;
                                     8 = general graphs, one slot per wavefront (n <= 4095,
                                         |J| <= 7, degree <= 16, colour classes of at most
-                                        256 sites), at most 8 slots per workgroup */
+                                        256 sites), at most 8 slots per workgroup; 0 takes
+                                        8 where every context fits it */
 } pt_batch_opts;
 
 /* Group contexts for batched execution. The contexts stay owned by the

@@ -1427,10 +1427,10 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
         all_pm8 = all_pm8 && c->pmJ;
     }
     g->pml = all_pml && (o.kernel == 7 || (pml_auto && o.kernel == 0 && !all_pm8 && o.replicas_per_thread <= 1));
-    // the one-slot-per-wavefront sparse kernel where the caller asks for it
-    // (kernel 8) and every context is a general graph that fits it (its
-    // mailbox carries energies of 24 bits)
-    bool all_csrw = !any_ctx && o.kernel == 8;
+    // the one-slot-per-wavefront sparse kernel where every context is a
+    // general graph that fits it (its mailbox carries energies of 24 bits),
+    // when the caller asks for it (kernel 8) or leaves the kernel open
+    bool all_csrw = !any_ctx && (o.kernel == 8 || (pml_auto && o.kernel == 0));
     for (pt_ctx *c : ctxs)
         all_csrw = all_csrw && c->kind == KIND_CSR &&
                    csrw_supported(c->n, c->hI.maxabsj, c->hI.maxdeg, c->hI.maxcnt) && (long long)c->n * c->D < (1 << 23);
@@ -1492,12 +1492,13 @@ static int pick_group(const pt_batch *b, const std::vector<pt_ctx *> &ctxs, Laun
     int rc = PT_OK;
     bool waits = false;
     for (pt_ctx *c : ctxs) waits = waits || c->opts.sweeps_per_cycle != 0;
-    // first the +-J row kernel where the caller leaves the kernel open (its
-    // tiling does not depend on the level), then the others
+    // first the one-slot-per-wavefront kernels (+-J rows, general graphs)
+    // where the caller leaves the kernel open (their tiling does not depend on
+    // the level), then the others
     for (int pass = 0; pass < 2; ++pass) {
         for (int level = waits ? 0 : TILING_LEVELS - 1; level < TILING_LEVELS; ++level) {
             LaunchGroup *g = make_group(b->opts, ctxs, level, pass == 0);
-            if (pass == 0 && !(g->pml && b->opts.kernel == 0)) {
+            if (pass == 0 && !((g->pml || g->csrw) && b->opts.kernel == 0)) {
                 delete g;
                 break;
             }

@@ -490,7 +490,8 @@ def test_multipliers_quad_sweeper(R, G, M):
             c.propose(r, b)
         ctxs.append(c)
         cases.append((g, banks, kw, 4900 + i))
-    bt = binding.Batch(ctxs, replicas_per_wg=G, chunk_sweeps=50)
+    bt = binding.Batch(ctxs, replicas_per_wg=G, chunk_sweeps=50, kernel="block")
+    assert [d["sweeper"] for d in bt.describe()] == ["csr-quad"], bt.describe()
     bt.sweep(100)
     for c, (g, banks, kw, seed) in zip(ctxs, cases):
         ref = oracle.Run(g, betas, seed=seed, banks=banks, **kw)

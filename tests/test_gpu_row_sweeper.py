@@ -1,8 +1,10 @@
-"""GPU vs oracle parity of the packed-row sparse sweeper (CsrRowSweep): the
-fine tilings of general graphs, where each thread keeps one (site, storage)
-item per colour class. Bit-exact spins, energies, counters and best record
-against the oracle; the launch plan is checked so that each case runs the
-sweeper it names."""
+"""GPU vs oracle parity of the packed-row sparse sweepers: one storage per
+lane (CsrRowSweep, kernel "row") and four interleaved storages per lane
+(CsrRowQuadSweep, kernel "row4"), where each thread keeps one item per colour
+class for the whole launch; and of the runtime's choice among all sparse
+sweepers. Bit-exact spins, energies, counters and best record against the
+oracle; the launch plan is checked so that each case runs the sweeper it
+names."""
 import numpy as np
 import pytest
 
@@ -38,7 +40,7 @@ def _plan(bt):
     return [(d["kernel"], d["sweeper"], d["block"]) for d in bt.describe()]
 
 
-def _run_and_compare(problems, betas, G, sweeps, M=1, chunk=50, bank_every=3, expect="csr-row"):
+def _run_and_compare(problems, betas, G, sweeps, M=1, chunk=50, bank_every=3, expect="csr-row", kernel="row"):
     import oracle
     R = len(betas)
     ctxs, cases = [], []
@@ -53,7 +55,7 @@ def _run_and_compare(problems, betas, G, sweeps, M=1, chunk=50, bank_every=3, ex
             c.propose(r, b)
         ctxs.append(c)
         cases.append((g, banks, kw, 5900 + i))
-    bt = binding.Batch(ctxs, replicas_per_wg=G, chunk_sweeps=chunk)
+    bt = binding.Batch(ctxs, replicas_per_wg=G, chunk_sweeps=chunk, kernel=kernel)
     plan = _plan(bt)
     assert all(p[1] == expect for p in plan), plan
     bt.sweep(sweeps)
@@ -66,44 +68,79 @@ def _run_and_compare(problems, betas, G, sweeps, M=1, chunk=50, bank_every=3, ex
     return plan
 
 
-@pytest.mark.parametrize("m,R,G", [(8, 32, 4), (8, 29, 8), (8, 24, 1), (10, 24, 4), (6, 16, 3)])
-def test_multipliers_row_sweeper(m, R, G):
+SWEEPER = {"row": "csr-row", "row4": "csr-row4"}
+
+
+@pytest.mark.parametrize("kernel", ["row", "row4"])
+@pytest.mark.parametrize("m,R,G", [(8, 32, 4), (8, 29, 8), (8, 24, 1), (10, 24, 4), (6, 16, 3), (8, 26, 13),
+                                   (8, 32, 32)])
+def test_multipliers_row_sweepers(kernel, m, R, G):
     """Multipliers: one lane per item (m = 6, 8: degree <= 16) and two lanes
-    per item (m = 10: degree 20, bonds summed by DPP); an uneven split of the
-    ladder (R = 29 over workgroups of 8 and 7 slots); one slot per workgroup."""
-    announce(f"row sweeper: 2 x {m}-bit multipliers, R={R} G={G}")
+    per item (m = 10: degree 20, sums combined by DPP); an uneven split of
+    the ladder (R = 29 over workgroups of 8 and 7 slots); one slot per
+    workgroup; slot counts that leave padding storages in the last quad
+    (G = 1, 3, 13); a whole ladder in one workgroup (G = 32)."""
+    if kernel == "row" and G > 12:
+        pytest.skip("one storage per lane: 40 sites x 32 slots exceed a block")
+    announce(f"{kernel} sweeper: 2 x {m}-bit multipliers, R={R} G={G}")
     betas = inputs.geometric_ladder(R)
     probs = [inputs.multiplier(m, C) for C, _, _ in inputs.semiprimes(m, 2, seed=6100 + m)]
-    plan = _run_and_compare(probs, betas, G, 120)
+    plan = _run_and_compare(probs, betas, G, 120, expect=SWEEPER[kernel], kernel=kernel)
     announce(f"plan {plan}")
 
 
+@pytest.mark.parametrize("kernel", ["row", "row4"])
 @pytest.mark.parametrize("seed", [1, 2])
-def test_random_graphs_row_sweeper(seed):
+def test_random_graphs_row_sweepers(kernel, seed):
     """Random sparse graphs with |J| up to 7, fields, clamped sites, hub sites
     of degree about 25 (two lanes per item) and DSATUR colourings."""
     probs = [_random_graph(150, 6200 + 10 * seed + k) for k in range(2)]
     for g in probs:
         deg = np.diff(g["row_ptr"])[g["clamp"] == 0]
         assert 16 < deg.max() <= 32 and np.abs(g["J"]).max() <= 7
-    announce(f"row sweeper: random graphs n=150 seed={seed}, max degree "
+    announce(f"{kernel} sweeper: random graphs n=150 seed={seed}, max degree "
              f"{max(int(np.diff(g['row_ptr']).max()) for g in probs)}, colours {[int(g['color'].max()) + 1 for g in probs]}")
-    _run_and_compare(probs, inputs.geometric_ladder(12), 4, 150)
+    _run_and_compare(probs, inputs.geometric_ladder(12), 5, 150, expect=SWEEPER[kernel], kernel=kernel)
 
 
-def test_row_sweeper_independent_chains():
+@pytest.mark.parametrize("kernel", ["row", "row4"])
+def test_row_sweepers_independent_chains(kernel):
     """Independent chains (M = 0: no exchange, the bank-generation runs)."""
-    announce("row sweeper: independent chains, 2 x 8-bit multipliers, R=16 G=4")
+    announce(f"{kernel} sweeper: independent chains, 2 x 8-bit multipliers, R=16 G=4")
     probs = [inputs.multiplier(8, C) for C, _, _ in inputs.semiprimes(8, 2, seed=6300)]
-    _run_and_compare(probs, np.full(16, 1.3), 4, 100, M=0)
+    _run_and_compare(probs, np.full(16, 1.3), 4, 100, M=0, expect=SWEEPER[kernel], kernel=kernel)
 
 
-def test_coarse_tiling_and_large_couplings_leave_row_sweeper():
-    """Where the packed rows do not apply the runtime keeps the other
-    sweepers, with the same chain: 16 slots per workgroup of an 8-bit
-    multiplier need 640 threads (the four-storages-per-lane sweeper runs), and
-    a coupling of 9 does not fit the 4-bit field (the CSR sweeper runs)."""
-    announce("row sweeper: fallbacks (G=16 multiplier, |J| = 9 graph)")
-    probs = [inputs.multiplier(8, C) for C, _, _ in inputs.semiprimes(8, 1, seed=6400)]
-    _run_and_compare(probs, inputs.geometric_ladder(32), 16, 60, expect="csr-quad")
-    _run_and_compare([_random_graph(100, 6450, hubs=0, jmax=9)], inputs.geometric_ladder(8), 4, 60, expect="csr")
+def test_runtime_sparse_sweeper_choice():
+    """The runtime's choice among the sweepers of the workgroup-synchronous
+    kernel, each against the oracle (general graphs that fit it take the
+    one-slot-per-wavefront kernel first): that kernel for an 8-bit multiplier
+    (auto); the four-storage rows for a graph of degree 20 (a 10-bit
+    multiplier, 4 slots per workgroup); the one-storage rows where a site's bound exceeds
+    255 (a hub with field 200); the four-storages-per-lane LDS sweeper where no
+    packed rows fit a block (a 10-bit multiplier, two lanes per item, 20
+    slots per workgroup); the LDS-resident CSR
+    sweepers when the caller asks for the workgroup-synchronous kernel (the
+    lane-sharing one at 512 threads for 2 slots per workgroup); and a
+    coupling of 9 refused by the one-storage rows."""
+    announce("sparse sweeper choice: row4 / row / quad / csr / csr-wide, refusal")
+    mult = [inputs.multiplier(8, C) for C, _, _ in inputs.semiprimes(8, 1, seed=6400)]
+    plan = _run_and_compare(mult, inputs.geometric_ladder(32), 8, 60, expect="-", kernel="auto")
+    assert plan[0][0] == "csrw", plan
+    m10a = [inputs.multiplier(10, C) for C, _, _ in inputs.semiprimes(10, 1, seed=6405)]
+    _run_and_compare(m10a, inputs.geometric_ladder(16), 4, 60, expect="csr-row4", kernel="auto")
+    big = _random_graph(120, 6470)
+    big["h"] = big["h"].copy()
+    hub = int(np.argmax(np.diff(big["row_ptr"]) * (big["clamp"] == 0)))
+    big["h"][hub] = 200
+    _run_and_compare([big], inputs.geometric_ladder(8), 4, 60, expect="csr-row", kernel="auto")
+    m10 = [inputs.multiplier(10, C) for C, _, _ in inputs.semiprimes(10, 1, seed=6410)]
+    _run_and_compare(m10, inputs.geometric_ladder(20), 20, 40, expect="csr-quad", kernel="auto")
+    _run_and_compare(mult, inputs.geometric_ladder(16), 4, 60, expect="csr", kernel="block")
+    _run_and_compare(mult, inputs.geometric_ladder(16), 2, 60, expect="csr-wide", kernel="block")
+    g9 = _random_graph(100, 6450, hubs=0, jmax=9)
+    c = binding.Context(g9, inputs.geometric_ladder(8), seed=1)
+    with pytest.raises(binding.TaptError):
+        binding.Batch([c], replicas_per_wg=4, kernel="row")
+    c.close()
+    _run_and_compare([g9], inputs.geometric_ladder(8), 4, 60, expect="csr-row4", kernel="auto")   # |J| = 9
