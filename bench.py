@@ -452,7 +452,8 @@ def mixed_leg(args, log):
     log(f"mixed: {r['value']:.1f} attempts/ns over {args.mixed_sweeps} sweeps, tiling {tiling}, "
         f"chunk kernel {r['avg_ms']:.3f} ms avg")
     roof = rooflines(r["attempts"] / max(r["launches"], 1), r["avg_ms"], LDS_BYTES_PER_ATTEMPT,
-                     kernel="chunk_kernel_mixed" if tiling[2] in ("auto", "block") else tiling[2])
+                     kernel={"pml": "pml_kernel", "auto": "chunk_kernel_mixed", "block": "chunk_kernel_mixed"}.get(
+                         tiling[2], tiling[2]))
     return dict(value=round(r["value"], 2), unit="attempts/ns", sweeps=args.mixed_sweeps,
                 seconds=round(r["seconds"], 3), attempts_per_sweep=sum(len(c["betas"]) * c["g"]["n"] for c in cases),
                 instances=len(cases), sizes=[list(x) for x in cfg["sizes"]], sweeps_per_swap=1,
@@ -488,7 +489,8 @@ def factorization_leg(args, log):
     log(f"factorization: {r['value']:.1f} attempts/ns over {cfg['sweeps']} sweeps, tiling {tiling}, "
         f"chunk kernel {r['avg_ms']:.3f} ms avg")
     roof = rooflines(r["attempts"] / max(r["launches"], 1), r["avg_ms"], bpa, ops=csr_ops_per_attempt(cases[0]["g"]),
-                     kernel="chunk_kernel<CsrSweep>")
+                     kernel={"csrw": "csrw_kernel", "row": "chunk_kernel<CsrRowSweep>",
+                             "row4": "chunk_kernel<CsrRowQuadSweep>"}.get(tiling[2], "chunk_kernel<CsrSweep>"))
     # time to solution: fresh contexts, chunks of 1000 sweeps until every
     # product has hit its ground energy or the cap
     ctxs = case_contexts(cases, cfg, banks)

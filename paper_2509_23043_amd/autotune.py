@@ -80,8 +80,8 @@ def candidates(contexts):
         if pm_ok and G <= 8:
             out.append((G, 1, "pm1"))
 
-    if pml_ok:   # one slot per wavefront: every workgroup size up to 8 wavefronts
-        out += [(G, 1, "pml") for G in range(1, 9) if G <= rmax]
+    if pml_ok:   # one slot per wavefront: every workgroup size up to 8 wavefronts, or the runtime's per size
+        out += [(G, 1, "pml") for G in range(0, 9) if G <= rmax]
     if csr_ok:   # the same for general graphs
         out += [(G, 1, "csrw") for G in range(1, 9) if G <= rmax]
     return out

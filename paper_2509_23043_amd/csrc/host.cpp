@@ -1458,8 +1458,11 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
             G = std::min(std::min(G, c->R), pm_max_storages(g->spw));
             if (g->spw == 2) G = std::max(G & ~1, 2);
         } else if (g->pml) {
+            // left open, a large lattice takes 4 slots per workgroup: its
+            // wavefronts keep a SIMD's issue slots busy alone, so a workgroup
+            // of 4 gives each its own SIMD; smaller ones take 8
             rpt = 1;
-            G = o.replicas_per_wg > 0 ? o.replicas_per_wg : pml_max_storages();
+            G = o.replicas_per_wg > 0 ? o.replicas_per_wg : (c->n > 2000 ? 4 : pml_max_storages());
             G = std::min(std::min(G, c->R), pml_max_storages());
         } else if (g->csrw) {
             rpt = 1;
