@@ -1405,7 +1405,8 @@ static void clear_groups(pt_batch *b)
 // The launch group for a set of contexts (host fields only). Contexts that
 // share one sweeper instantiation run in the specialised kernel; a set that
 // needs several sweepers runs as a single launch of the mixed kernel.
-static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx *> &ctxs, int level, bool pml_auto)
+static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx *> &ctxs, int level, bool pml_auto,
+                               bool force_mixed = false)
 {
     bool any_ctx = false;
     for (pt_ctx *c : ctxs) any_ctx = any_ctx || contextual(c);
@@ -1435,7 +1436,7 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
         all_csrw = all_csrw && c->kind == KIND_CSR &&
                    csrw_supported(c->n, c->hI.maxabsj, c->hI.maxdeg, c->hI.maxcnt) && (long long)c->n * c->D < (1 << 23);
     g->csrw = all_csrw;
-    g->mixed = keys.size() > 1 && !g->pml;
+    g->mixed = (keys.size() > 1 || force_mixed) && !g->pml;
     g->kind = ctxs[0]->kind;
     g->L = g->kind == KIND_LATTICE ? ctxs[0]->L : 0;
     // the wave-per-replica kernel: one lattice size whose storage is exactly
@@ -1497,20 +1498,30 @@ static int pick_group(const pt_batch *b, const std::vector<pt_ctx *> &ctxs, Laun
     for (pt_ctx *c : ctxs) waits = waits || c->opts.sweeps_per_cycle != 0;
     // first the one-slot-per-wavefront kernels (+-J rows, general graphs)
     // where the caller leaves the kernel open (their tiling does not depend on
-    // the level), then the others
-    for (int pass = 0; pass < 2; ++pass) {
+    // the level), then the others, then the mixed kernel for any set. A set
+    // that fits the mixed kernel keeps fitting it when contexts leave it
+    // (fewer workgroups, no more LDS), so a server that admitted a set can
+    // always run what remains of it.
+    const bool open = b->opts.kernel == 0 || b->opts.kernel == 1;
+    for (int pass = 0; pass < 3; ++pass) {
+        if (pass == 2 && !open) break;
         for (int level = waits ? 0 : TILING_LEVELS - 1; level < TILING_LEVELS; ++level) {
-            LaunchGroup *g = make_group(b->opts, ctxs, level, pass == 0);
+            LaunchGroup *g = make_group(b->opts, ctxs, level, pass == 0, pass == 2);
             if (pass == 0 && !((g->pml || g->csrw) && b->opts.kernel == 0)) {
                 delete g;
                 break;
             }
+            if (pass == 2 && (!g->mixed || g->ctx)) {   // the mixed kernel takes no contextual proposals
+                delete g;
+                break;
+            }
             GroupPlan P;
-            rc = plan_group(b, g, P);
-            if (rc == PT_OK) {
+            const int r = plan_group(b, g, P);
+            if (r == PT_OK) {
                 *out = g;
                 return PT_OK;
             }
+            rc = r;
             delete g;
             if (pass == 0) break;
         }
@@ -2026,6 +2037,7 @@ struct pt_server {
     std::deque<SrvReq> pending;
     std::deque<pt_result> done;
     bool stopping = false;
+    std::string fail_msg;             // why a failed round stopped the server
     uint64_t next_id = 1;
     pt_serve_stats st{};
     std::thread worker;
@@ -2248,7 +2260,9 @@ static void serve_worker(pt_server *S)
                 pt_destroy(a.c);
             }
             S->active.clear();
+            const std::string why = pt_last_error();
             std::lock_guard<std::mutex> lk(S->mu);
+            S->fail_msg = why;
             for (auto &r : S->pending) out.push_back(serve_result(r, rc, now, now));
             S->st.rejected += S->pending.size();
             S->pending.clear();
@@ -2302,7 +2316,9 @@ extern "C" int pt_serve_submit(pt_server *s, const pt_request *rq, uint64_t *id)
 {
     if (!s || !rq) return fail(PT_EINVAL, "null argument");
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stopping) return fail(PT_ESTATE, "server is stopping");
+    if (s->stopping)
+        return fail(PT_ESTATE, s->fail_msg.empty() ? "server is stopping" : "server stopped after a failed round: %s",
+                    s->fail_msg.c_str());
     if (rq->problem < 0 || rq->problem >= (int32_t)s->problems.size()) return fail(PT_EINVAL, "unknown problem %d", rq->problem);
     if (rq->sweep_cap < 1 || rq->sweep_cap > 0xFFFFFFFFull) return fail(PT_EINVAL, "sweep_cap must be in 1..2^32-1");
     SrvReq r;
