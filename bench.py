@@ -95,7 +95,7 @@ def rooflines(attempts_per_launch, avg_ms, lds_bytes, ops=OPS_PER_ATTEMPT, traff
                 fractions={k: round(v, 4) for k, v in fr.items()})
 
 
-SWEEP_KERNELS = ("chunk_kernel", "pm_kernel", "plain_", "wave_kernel")
+SWEEP_KERNELS = ("chunk_kernel", "pm_kernel", "pml_kernel", "csrw_kernel", "plain_", "wave_kernel")
 
 
 def rocprof_summary(d):
