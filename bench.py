@@ -696,7 +696,7 @@ def serving_leg(args, log):
                  attempts_per_ns=round((st1["attempts"] - st0["attempts"]) / (wall * 1e9), 2),
                  round_busy_frac=round(busy, 4), gpu_busy_frac=round(gpu_busy, 4),
                  rounds=st1["rounds"] - st0["rounds"],
-                 peak_active=st1["peak_active"], by_kind=by_kind)
+                 peak_active=st1["peak_active"], peak_lanes=st1["peak_lanes"], by_kind=by_kind)
         log(f"serving lambda={lam:g}: done p50 {d['p50_time_to_done_s']} s p99 {d['p99_time_to_done_s']} s; "
             f"target p50 {d['p50_time_to_target_s']} s p99 {d['p99_time_to_target_s']} s; "
             f"{d['completed_req_per_s']} req/s, hit {d['hit_frac']} (ea {by_kind['ea']['hit_frac']}, "

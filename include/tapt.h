@@ -224,9 +224,10 @@ typedef struct {
                                         it and not all are 8^3 lattices (those take 3),
                                         else the other kernels;
                                     8 = general graphs, one slot per wavefront (n <= 4095,
-                                        |J| <= 7, degree <= 16, colour classes of at most
-                                        256 sites), at most 8 slots per workgroup; 0 takes
-                                        8 where every context fits it */
+                                        |J| <= 7, degree <= 64, colour classes of at most
+                                        256 sites, at most 64 groups of 64 sites of one
+                                        class), at most 8 slots per workgroup; 0 takes 8
+                                        where every context fits it */
 } pt_batch_opts;
 
 /* Group contexts for batched execution. The contexts stay owned by the
@@ -276,12 +277,15 @@ int pt_batch_run_static(pt_ctx *const *ctxs, int32_t k, const pt_batch_opts *o, 
  * cap. It shares the problem's couplings, tables and banks in device memory
  * and owns only its replica state, which stays resident until it finishes.
  *
- * The worker runs rounds. Each round is one persistent launch of
- * chunk_sweeps sweeps over every admitted request (they overlap on the
- * device). Between rounds it retires the requests that reached their target or
- * their cap and admits waiting ones, first come first served, while their
- * state fits the device-memory budget and every workgroup of the next launch
- * can be co-resident.
+ * The worker runs rounds of chunk_sweeps sweeps over every admitted request.
+ * Running requests are grouped in launch lanes: each lane is one persistent
+ * launch, co-resident on its own, of the fastest kernel for its requests
+ * (requests of one kind share a lane while it has room, so their work
+ * overlaps on the device); a round runs the lanes' launches in turn. Between
+ * rounds the worker retires the requests that reached their target or their
+ * cap and admits waiting ones, first come first served, while their state
+ * fits the device-memory budget (and max_active); a request that fits no
+ * launch even alone is rejected with that launch's error.
  *
  * Results do not depend on co-tenants or arrival times. A request admitted at
  * sweep 0 stops at the first multiple of chunk_sweeps at or after its first
@@ -329,7 +333,7 @@ typedef struct {
     double busy_s;               /* wall time of the rounds (launch to results) */
     double attempts;             /* spin-flip attempts run for requests */
     int32_t active, waiting, peak_active;
-    int32_t pad;
+    int32_t peak_lanes;          /* most launches in one round */
     uint64_t mem_used, mem_peak;
     double gpu_busy_s;           /* device time of the rounds' sweep launches (HIP events) */
 } pt_serve_stats;

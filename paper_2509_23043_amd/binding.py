@@ -70,7 +70,7 @@ class _ServeStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("completed", C.c_uint64),
                 ("rejected", C.c_uint64), ("rounds", C.c_uint64), ("busy_s", C.c_double),
                 ("attempts", C.c_double), ("active", C.c_int32), ("waiting", C.c_int32),
-                ("peak_active", C.c_int32), ("pad", C.c_int32), ("mem_used", C.c_uint64),
+                ("peak_active", C.c_int32), ("peak_lanes", C.c_int32), ("mem_used", C.c_uint64),
                 ("mem_peak", C.c_uint64), ("gpu_busy_s", C.c_double)]
 
 
@@ -421,7 +421,7 @@ class Server:
     def stats(self):
         st = _ServeStats()
         _check(lib().pt_serve_stats_get(self.h, C.byref(st)))
-        return {f: getattr(st, f) for f, _ in _ServeStats._fields_ if f != "pad"}
+        return {f: getattr(st, f) for f, _ in _ServeStats._fields_}
 
     def clock(self):
         return float(lib().pt_serve_clock(self.h))

@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <set>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -59,8 +60,8 @@ int pml_xwords(int L);
 hipError_t launch_pml(const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t pml_occupancy(int block, size_t lds, int *blocks_per_cu);
 int csrw_max_storages();
-bool csrw_supported(int n, int maxabsj, int maxdeg, int maxcnt);
-size_t csrw_lds_bytes(int n, int ncolors, int maxcnt, int G, int stride, int tsw_entries);
+bool csrw_supported(int n, int maxabsj, int chunks, int maxcnt);
+size_t csrw_lds_bytes(int n, int ncolors, int maxcnt, int chunks, int G, int stride, int tsw_entries);
 int csrw_xwords(int n);
 hipError_t launch_csrw(const ChunkArgs &a, int block, size_t lds, hipStream_t s);
 hipError_t csrw_occupancy(int block, size_t lds, int *blocks_per_cu);
@@ -200,7 +201,7 @@ struct pt_ctx {
     uint64_t problem_fp = 0;          // FNV-1a of the problem, ladder, options and seed
 
     // device allocations
-    DevBuf J3, row_ptr, col, Jc, h, clampd, color_sites, color_off;
+    DevBuf J3, row_ptr, col, Jc, h, clampd, color_sites, color_off, csrw_grp;
     DevBuf tflip, tprop, tprop_off, tprop_len, tswap, tswap_off, tswap_len;
     DevBuf spins, E, t, cursor, bank_ptrs, bankE_ptrs, bank_n;
     DevBuf swap_att, swap_acc, prop_att, prop_acc, flips, best, best_spins;
@@ -288,6 +289,8 @@ struct Prepared {
     std::vector<int8_t> clamp;
     std::vector<int16_t> color_sites;
     std::vector<int32_t> color_off;
+    std::vector<int32_t> csrw_groups;       // rank groups of the one-slot-per-wavefront sparse kernel
+    int csrw_chunks = 0;
     int64_t nfree;
     int maxdeg = 0, maxcnt = 0, maxabsj = 0;   // over free sites / colour classes / bonds
 };
@@ -406,12 +409,36 @@ static int prepare(const pt_graph *g, Prepared &P)
         P.col[k] = (int16_t)cl[k];
         P.Jc[k] = (int8_t)jv[k];
     }
+    // the free sites of each colour, largest degree first (sites of one colour
+    // share no bond, so their order within the class changes no result; this
+    // one lets the one-slot-per-wavefront kernel give the few high-degree
+    // sites their own rank groups)
     P.color_off.assign(nc + 1, 0);
     for (int c = 0; c < nc; ++c) {
+        const size_t from = P.color_sites.size();
         for (int i = 0; i < n; ++i)
             if (color[i] == c && !P.clamp[i]) P.color_sites.push_back((int16_t)i);
+        std::stable_sort(P.color_sites.begin() + from, P.color_sites.end(), [&](int16_t a, int16_t b) {
+            return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
+        });
         P.color_off[c + 1] = (int32_t)P.color_sites.size();
         P.maxcnt = std::max(P.maxcnt, P.color_off[c + 1] - P.color_off[c]);
+    }
+    // rank groups (c, k) of 64 sites: chunks of CSRW_CHUNK bonds for the
+    // largest degree in the group, numbered in group order
+    const int ipl = (P.maxcnt + 63) / 64;
+    if (P.maxdeg <= CSRW_MAXDEG && P.maxcnt >= 1 && nc * ipl <= CSRW_MAXGROUPS) {
+        int base = 0;
+        for (int c = 0; c < nc; ++c)
+            for (int k = 0; k < ipl; ++k) {
+                int md = 1;
+                for (int s = P.color_off[c] + 64 * k; s < std::min(P.color_off[c + 1], P.color_off[c] + 64 * k + 64); ++s)
+                    md = std::max(md, rp[P.color_sites[s] + 1] - rp[P.color_sites[s]]);
+                const int nch = (md + CSRW_CHUNK - 1) / CSRW_CHUNK;
+                P.csrw_groups.push_back((base << 8) | nch);
+                base += nch;
+            }
+        P.csrw_chunks = base;
     }
     if (P.color_sites.empty()) P.color_sites.push_back(0);
     return PT_OK;
@@ -428,6 +455,7 @@ static void fill_inst_pointers(pt_ctx *c)
     I.clamp = c->clampd.as<int8_t>();
     I.color_sites = c->color_sites.as<int16_t>();
     I.color_off = c->color_off.as<int32_t>();
+    I.csrw_groups = c->csrw_grp.as<int32_t>();
     I.tflip = c->tflip.as<uint32_t>();
     I.tprop = c->tprop.as<uint32_t>();
     I.tprop_off = c->tprop_off.as<int32_t>();
@@ -581,6 +609,7 @@ extern "C" int pt_create(const pt_graph *g, const double *betas, int32_t R, cons
     UP(clampd, P.clamp);
     UP(color_sites, colsites);
     UP(color_off, P.color_off);
+    UP(csrw_grp, P.csrw_groups.empty() ? std::vector<int32_t>(1, 0) : P.csrw_groups);
     UP(tflip, tflip);
     UP(tprop, tprop);
     UP(tprop_off, tprop_off);
@@ -634,6 +663,7 @@ extern "C" int pt_create(const pt_graph *g, const double *betas, int32_t R, cons
     I.maxdeg = P.maxdeg;
     I.maxcnt = P.maxcnt;
     I.maxabsj = P.maxabsj;
+    I.csrw_chunks = P.csrw_chunks;
     I.seed_lo = (uint32_t)o->seed;
     I.seed_hi = (uint32_t)(o->seed >> 32);
     I.epoch = 0;
@@ -1256,7 +1286,7 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
         pt_ctx *c = g->ctxs[k];
         P.lds = std::max(P.lds, g->pm     ? pm_lds_bytes(P.ctx[k].gmax, P.tsw_max)
                                 : g->pml ? pml_lds_bytes(c->L, P.ctx[k].gmax, P.tsw_max)
-                                : g->csrw ? csrw_lds_bytes(c->n, c->ncolors, c->hI.maxcnt, P.ctx[k].gmax, 2 * c->D + 1,
+                                : g->csrw ? csrw_lds_bytes(c->n, c->ncolors, c->hI.maxcnt, c->hI.csrw_chunks, P.ctx[k].gmax, 2 * c->D + 1,
                                                            P.tsw_max)
                                 : g->wave ? wave_lds_bytes(c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max)
                                           : chunk_lds_bytes(c->kind, c->n, P.ctx[k].gmax, 2 * c->D + 1, P.tsw_max,
@@ -1434,7 +1464,7 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
     bool all_csrw = !any_ctx && (o.kernel == 8 || (pml_auto && o.kernel == 0));
     for (pt_ctx *c : ctxs)
         all_csrw = all_csrw && c->kind == KIND_CSR &&
-                   csrw_supported(c->n, c->hI.maxabsj, c->hI.maxdeg, c->hI.maxcnt) && (long long)c->n * c->D < (1 << 23);
+                   csrw_supported(c->n, c->hI.maxabsj, c->hI.csrw_chunks, c->hI.maxcnt) && (long long)c->n * c->D < (1 << 23);
     g->csrw = all_csrw;
     g->mixed = (keys.size() > 1 || force_mixed) && !g->pml;
     g->kind = ctxs[0]->kind;
@@ -1518,6 +1548,7 @@ static int pick_group(const pt_batch *b, const std::vector<pt_ctx *> &ctxs, Laun
             GroupPlan P;
             const int r = plan_group(b, g, P);
             if (r == PT_OK) {
+                g->sparse = P.sparse;   // the sweeper it would run (build_group sets it again)
                 *out = g;
                 return PT_OK;
             }
@@ -1570,16 +1601,21 @@ static int batch_fits(const pt_batch *b, const std::vector<pt_ctx *> &ctxs)
     return rc;
 }
 
-static int batch_init(pt_batch *b, int device)
+// shared: run on that stream (not owned), else on a stream of the batch's own
+static int batch_init(pt_batch *b, int device, hipStream_t shared = nullptr)
 {
     b->device = device;
     if (hipSetDevice(b->device) != hipSuccess) return fail(PT_EDEVICE, "hipSetDevice");
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) return fail(PT_EDEVICE, "device properties");
     b->cus = prop.multiProcessorCount;
-    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
-        return fail(PT_EDEVICE, "stream creation failed");
-    b->own_stream = b->stream;
+    if (shared) {
+        b->stream = shared;
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+            return fail(PT_EDEVICE, "stream creation failed");
+        b->own_stream = b->stream;
+    }
     if (b->err.alloc(32) != hipSuccess) return fail(PT_ENOMEM, "error flag");
     if (hipMemset(b->err.p, 0, 32) != hipSuccess) return fail(PT_EDEVICE, "memset");
     return PT_OK;
@@ -1769,28 +1805,34 @@ extern "C" int pt_batch_kernel_time(pt_batch *b, double *ms, uint64_t *launches)
     return PT_OK;
 }
 
+// The kernel and sweeper a launch group runs, as pt_batch_describe names them.
+static std::string group_identity(const LaunchGroup *g)
+{
+    const char *kern = g->pm    ? (g->spw == 1 ? "pm1" : "pm")
+                       : g->pml ? "pml"
+                       : g->csrw ? "csrw"
+                       : g->wave ? "wave"
+                       : g->mixed ? "mixed"
+                       : g->ctx ? "ctx"
+                                : "chunk";
+    std::string sw;
+    if (g->pm || g->pml || g->csrw || g->wave || g->mixed) sw = "-";
+    else if (g->kind == KIND_LATTICE) sw = "lattice" + std::to_string(g->L) + "x" + std::to_string(g->rpt);
+    else sw = g->sparse == SPARSE_ROW4  ? "csr-row4"
+              : g->sparse == SPARSE_ROW ? "csr-row"
+              : g->sparse == SPARSE_QUAD ? "csr-quad"
+              : g->sparse == SPARSE_WIDE ? "csr-wide"
+                                         : "csr";
+    return std::string("kernel=") + kern + " sweeper=" + sw;
+}
+
 extern "C" int pt_batch_describe(pt_batch *b, char *buf, int32_t len)
 {
     if (!b || !buf || len < 1) return fail(PT_EINVAL, "null batch or buffer");
     std::string out;
     for (const LaunchGroup *g : b->groups) {
-        const char *kern = g->pm    ? (g->spw == 1 ? "pm1" : "pm")
-                           : g->pml ? "pml"
-                           : g->csrw ? "csrw"
-                           : g->wave ? "wave"
-                           : g->mixed ? "mixed"
-                           : g->ctx ? "ctx"
-                                    : "chunk";
-        std::string sw;
-        if (g->pm || g->pml || g->csrw || g->wave || g->mixed) sw = "-";
-        else if (g->kind == KIND_LATTICE) sw = "lattice" + std::to_string(g->L) + "x" + std::to_string(g->rpt);
-        else sw = g->sparse == SPARSE_ROW4  ? "csr-row4"
-                  : g->sparse == SPARSE_ROW ? "csr-row"
-                  : g->sparse == SPARSE_QUAD ? "csr-quad"
-                  : g->sparse == SPARSE_WIDE ? "csr-wide"
-                                             : "csr";
         char line[256];
-        snprintf(line, sizeof line, "kernel=%s sweeper=%s contexts=%zu grid=%d block=%d lds=%zu\n", kern, sw.c_str(),
+        snprintf(line, sizeof line, "%s contexts=%zu grid=%d block=%d lds=%zu\n", group_identity(g).c_str(),
                  g->ctxs.size(), g->grid, g->block, g->lds);
         out += line;
     }
@@ -1945,7 +1987,7 @@ int clone_ctx(const pt_ctx *tm, uint64_t seed, int has_target, int32_t target, u
     c->stream = s;
     c->own_stream = false;
 #define VIEW(f) c->f.view(tm->f.p, tm->f.bytes)
-    VIEW(J3); VIEW(row_ptr); VIEW(col); VIEW(Jc); VIEW(h); VIEW(clampd); VIEW(color_sites); VIEW(color_off);
+    VIEW(J3); VIEW(row_ptr); VIEW(col); VIEW(Jc); VIEW(h); VIEW(clampd); VIEW(color_sites); VIEW(color_off); VIEW(csrw_grp);
     VIEW(tflip); VIEW(tprop); VIEW(tprop_off); VIEW(tprop_len); VIEW(tswap); VIEW(tswap_off); VIEW(tswap_len);
 #undef VIEW
     const int R = c->R, n = c->n;
@@ -2023,6 +2065,23 @@ struct SrvActive {
     size_t bytes;
     double t_admit;
     uint64_t t_last;
+    int lane;                         // the launch lane it runs in
+    int slot;                         // its index in that lane's launch group
+};
+
+// A launch lane of a server: a batch over some of the running requests whose
+// launch is co-resident on its own. A round runs every non-empty lane's launch
+// in turn on the server's stream, so each lane keeps the fastest kernel for
+// its requests (the +-J row kernel for lattices, the one-slot-per-wavefront
+// sparse kernel for general graphs) instead of one mixed launch over all.
+struct SrvLane {
+    pt_batch *b = nullptr;
+    std::string ident;                // kernel and sweeper of its launch (group_identity)
+    int members = 0;
+    bool dirty = false;               // membership changed since the last build
+    std::set<std::string> full_for;   // request kinds it had no room for (cleared when one leaves)
+    std::vector<InstStatus> status;
+    int err[8] = {0};
 };
 
 } // namespace
@@ -2042,16 +2101,21 @@ struct pt_server {
     pt_serve_stats st{};
     std::thread worker;
     // worker-only
-    pt_batch *batch = nullptr;
+    hipStream_t stream = nullptr;
+    pt_batch *probe = nullptr;        // plans single requests (no contexts of its own)
+    std::vector<SrvLane> lanes;
+    std::vector<std::string> solo;    // per problem: the kernel a request of it runs alone
     std::vector<SrvActive> active;
-    std::vector<InstStatus> status;
     // request-state arenas of retired requests, reused by later ones of the
     // same size (no device allocation or free, and so no device-wide
     // synchronisation, per request once the pool is warm)
     std::vector<std::pair<size_t, void *>> pool;
     ~pt_server()
     {
+        for (auto &l : lanes) pt_batch_destroy(l.b);
+        pt_batch_destroy(probe);
         for (auto &m : pool) (void)hipFree(m.second);
+        if (stream) (void)hipStreamDestroy(stream);
     }
 };
 
@@ -2094,8 +2158,87 @@ static pt_result serve_result(const SrvReq &r, int status, double t_admit, doubl
     return o;
 }
 
-// Admit waiting requests, first come first served, while they fit.
-static void serve_admit(pt_server *S, bool &dirty, std::vector<pt_result> &out)
+// A batch object on the server's stream with its tiling options and no
+// contexts: a lane, or the probe that plans single requests.
+static int serve_new_batch(pt_server *S, pt_batch **out)
+{
+    *out = nullptr;
+    pt_batch *b = new pt_batch();
+    b->opts.replicas_per_wg = S->opts.replicas_per_wg;
+    b->opts.replicas_per_thread = S->opts.replicas_per_thread;
+    b->opts.chunk_sweeps = S->opts.chunk_sweeps;
+    int rc = batch_init(b, S->device, S->stream);
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return PT_OK;
+}
+
+// The contexts of lane l in the order of the active list.
+static std::vector<pt_ctx *> lane_set(const pt_server *S, int l)
+{
+    std::vector<pt_ctx *> set;
+    for (auto &a : S->active)
+        if (a.lane == l) set.push_back(a.c);
+    return set;
+}
+
+// The kernel a request of problem p runs alone ("" with the error code in rc
+// if it fits no launch by itself).
+static const std::string &serve_solo(pt_server *S, int p, int &rc)
+{
+    static const std::string none;
+    rc = PT_OK;
+    if ((int)S->solo.size() <= p) S->solo.resize(p + 1);
+    if (S->solo[p].empty()) {
+        LaunchGroup *g = nullptr;
+        rc = pick_group(S->probe, {S->problems[p]}, &g);
+        if (rc) return none;
+        S->solo[p] = group_identity(g);
+        delete g;
+    }
+    return S->solo[p];
+}
+
+// The lane a request of template tm joins: the first lane of its kind whose
+// launch keeps its kernel and stays co-resident with it added, else an empty
+// lane (reused or new). -1 with the error code in rc when none can be had.
+static int serve_place(pt_server *S, pt_ctx *tm, const std::string &solo, int &rc)
+{
+    rc = PT_OK;
+    for (int l = 0; l < (int)S->lanes.size(); ++l) {
+        SrvLane &ln = S->lanes[l];
+        // 8^3 +-J lattices run in the row kernel's lanes beside other sizes
+        const bool kin = ln.ident == solo || (ln.ident.rfind("kernel=pml ", 0) == 0 && solo.rfind("kernel=pm ", 0) == 0);
+        if (ln.members == 0 || !kin || ln.full_for.count(solo)) continue;
+        std::vector<pt_ctx *> set = lane_set(S, l);
+        set.push_back(tm);
+        LaunchGroup *g = nullptr;
+        const bool ok = pick_group(ln.b, set, &g) == PT_OK && group_identity(g) == ln.ident;
+        delete g;
+        if (ok) return l;
+        ln.full_for.insert(solo);
+    }
+    for (int l = 0; l < (int)S->lanes.size(); ++l)
+        if (S->lanes[l].members == 0) {
+            S->lanes[l].ident = solo;
+            S->lanes[l].full_for.clear();
+            return l;
+        }
+    SrvLane ln;
+    rc = serve_new_batch(S, &ln.b);
+    if (rc) return -1;
+    ln.ident = solo;
+    S->lanes.push_back(ln);
+    return (int)S->lanes.size() - 1;
+}
+
+// Admit waiting requests, first come first served, while their state fits
+// the memory budget (and the cap on running requests). Each joins a launch
+// lane (serve_place); a request that fits no launch even alone is rejected.
+static void serve_admit(pt_server *S, std::vector<pt_result> &out)
 {
     for (;;) {
         SrvReq r;
@@ -2109,22 +2252,22 @@ static void serve_admit(pt_server *S, bool &dirty, std::vector<pt_result> &out)
         const size_t need = arena_layout(tm->R, tm->n).total;
         int rc = PT_OK;
         if (S->st.mem_used + need > S->opts.mem_budget) {
+            if (!S->active.empty()) return;   // wait for running requests to finish
             rc = fail(PT_ENOMEM, "request state of %zu bytes exceeds the memory budget", need);
-        } else {
-            // the template has the clone's shape: plan the next launch with it
-            std::vector<pt_ctx *> set;
-            for (auto &a : S->active) set.push_back(a.c);
-            set.push_back(tm);
-            rc = batch_fits(S->batch, set);
         }
-        if (rc && !S->active.empty()) return;   // wait for running requests to finish
+        int lane = -1;
+        if (!rc) {
+            // the template has the clone's shape: plan with it
+            const std::string solo = serve_solo(S, r.rq.problem, rc);
+            if (!rc) lane = serve_place(S, tm, solo, rc);
+        }
         pt_ctx *c = nullptr;
         void *mem = nullptr;
         if (!rc) {
             mem = arena_take(S, need);
             if (!mem) rc = fail(PT_ENOMEM, "request state of %zu bytes: device allocation failed", need);
         }
-        if (!rc) rc = clone_ctx(tm, r.rq.seed, r.rq.has_target, r.rq.target, r.rq.sweep_cap, S->batch->stream, mem, &c);
+        if (!rc) rc = clone_ctx(tm, r.rq.seed, r.rq.has_target, r.rq.target, r.rq.sweep_cap, S->stream, mem, &c);
         if (rc && mem) S->pool.push_back({need, mem});
         const double now = seconds_since(S->t0);
         {
@@ -2145,48 +2288,91 @@ static void serve_admit(pt_server *S, bool &dirty, std::vector<pt_result> &out)
             out.push_back(serve_result(r, rc, now, now));
             continue;
         }
-        S->active.push_back({r, c, need, now, 0});
-        dirty = true;
+        S->active.push_back({r, c, need, now, 0, lane, -1});
+        S->lanes[lane].members += 1;
+        S->lanes[lane].dirty = true;
     }
 }
 
-// One round: a persistent launch of chunk_sweeps sweeps over every active
-// request, then retire the ones that are done.
-static int serve_round(pt_server *S, bool &dirty, std::vector<pt_result> &out)
+// Build the launch of every lane whose membership changed. A lane whose
+// remaining requests no longer fit its launch (its kernel can change as
+// requests leave) gives its later half to a new lane, until every lane
+// builds; a single admitted request always fits alone.
+static int serve_build(pt_server *S)
 {
-    pt_batch *b = S->batch;
-    if (dirty) {
-        std::vector<pt_ctx *> set;
-        for (auto &a : S->active) set.push_back(a.c);
-        int rc = batch_set_contexts(b, set.data(), (int32_t)set.size());
+    for (int l = 0; l < (int)S->lanes.size(); ++l) {
+        SrvLane &ln = S->lanes[l];
+        if (!ln.dirty || ln.members == 0) {
+            ln.dirty = false;
+            continue;
+        }
+        std::vector<pt_ctx *> set = lane_set(S, l);
+        int rc = batch_set_contexts(ln.b, set.data(), (int32_t)set.size());
+        if (rc == PT_EUNSUPPORTED && set.size() > 1) {
+            SrvLane nl;
+            rc = serve_new_batch(S, &nl.b);
+            if (rc) return rc;
+            const int nidx = (int)S->lanes.size();
+            int k = 0, keep = (int)set.size() / 2;
+            for (auto &a : S->active)
+                if (a.lane == l && k++ >= keep) a.lane = nidx;
+            nl.members = (int)set.size() - keep;
+            nl.dirty = true;
+            S->lanes.push_back(nl);
+            S->lanes[l].members = keep;
+            --l;   // rebuild this lane with its first half
+            continue;
+        }
         if (rc) return rc;
-        dirty = false;
+        SrvLane &lb = S->lanes[l];
+        lb.ident = group_identity(lb.b->groups[0]);
+        lb.dirty = false;
+        int k = 0;
+        for (auto &a : S->active)
+            if (a.lane == l) a.slot = k++;
     }
+    return PT_OK;
+}
+
+// One round: each lane's persistent launch of chunk_sweeps sweeps over its
+// requests, in turn on the server's stream, then retire the requests that are
+// done.
+static int serve_round(pt_server *S, std::vector<pt_result> &out)
+{
+    int rc = serve_build(S);
+    if (rc) return rc;
     const double ta = seconds_since(S->t0);
     const uint32_t K = (uint32_t)S->opts.chunk_sweeps;
-    b->ev_used = 0;
-    hipError_t e = enqueue_round(b, K, true);
-    if (e != hipSuccess) return fail(PT_EDEVICE, "serving round: %s", hipGetErrorString(e));
-    LaunchGroup *g = b->groups[0];
-    S->status.resize(g->ctxs.size());
-    int err[8] = {0};
-    HIPCHK(hipMemcpyAsync(S->status.data(), g->status.p, S->status.size() * sizeof(InstStatus),
-                          hipMemcpyDeviceToHost, b->stream));
-    HIPCHK(hipMemcpyAsync(err, b->err.p, 32, hipMemcpyDeviceToHost, b->stream));
-    HIPCHK(hipStreamSynchronize(b->stream));
-    if (err[0]) return fail(PT_ETIMEOUT, "cross-workgroup exchange timed out in a serving round");
-    double gpu_ms = 0.0;
-    for (size_t k = 0; k + 1 < b->ev_used; k += 2) {
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, b->ev_pool[k], b->ev_pool[k + 1]));
-        gpu_ms += ms;
+    int lanes = 0;
+    for (auto &ln : S->lanes) {
+        if (ln.members == 0) continue;
+        ln.b->ev_used = 0;
+        hipError_t e = enqueue_round(ln.b, K, true);
+        if (e != hipSuccess) return fail(PT_EDEVICE, "serving round: %s", hipGetErrorString(e));
+        LaunchGroup *g = ln.b->groups[0];
+        ln.status.resize(g->ctxs.size());
+        HIPCHK(hipMemcpyAsync(ln.status.data(), g->status.p, ln.status.size() * sizeof(InstStatus),
+                              hipMemcpyDeviceToHost, S->stream));
+        HIPCHK(hipMemcpyAsync(ln.err, ln.b->err.p, 32, hipMemcpyDeviceToHost, S->stream));
+        lanes += 1;
     }
-    b->ev_used = 0;
+    HIPCHK(hipStreamSynchronize(S->stream));
+    double gpu_ms = 0.0;
+    for (auto &ln : S->lanes) {
+        if (ln.members == 0) continue;
+        if (ln.err[0]) return fail(PT_ETIMEOUT, "cross-workgroup exchange timed out in a serving round");
+        for (size_t k = 0; k + 1 < ln.b->ev_used; k += 2) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ln.b->ev_pool[k], ln.b->ev_pool[k + 1]));
+            gpu_ms += ms;
+        }
+        ln.b->ev_used = 0;
+    }
     double attempts = 0.0;
     std::vector<SrvActive> keep, retired;
     for (size_t k = 0; k < S->active.size(); ++k) {
         SrvActive &a = S->active[k];
-        const InstStatus &st = S->status[k];
+        const InstStatus &st = S->lanes[a.lane].status[a.slot];
         const uint64_t t = (uint64_t)st.t;
         attempts += (double)(t - a.t_last) * (double)a.c->R * (double)a.c->nfree;
         a.t_last = t;
@@ -2197,7 +2383,7 @@ static int serve_round(pt_server *S, bool &dirty, std::vector<pt_result> &out)
         }
         if (a.r.rq.best_out)
             HIPCHK(hipMemcpyAsync(a.r.rq.best_out, a.c->best_spins.p, (size_t)a.c->n, hipMemcpyDeviceToHost,
-                                  b->stream));
+                                  S->stream));
         pt_result o = serve_result(a.r, PT_OK, a.t_admit, 0.0);
         o.hit = hit ? 1 : 0;
         o.first_hit = st.first_hit;
@@ -2207,11 +2393,14 @@ static int serve_round(pt_server *S, bool &dirty, std::vector<pt_result> &out)
         o.sweeps = t;
         out.push_back(o);
         retired.push_back(a);
-        dirty = true;
+        SrvLane &ln = S->lanes[a.lane];
+        ln.members -= 1;
+        ln.dirty = true;
+        ln.full_for.clear();
     }
     // the best configurations are on their way to the callers' buffers: wait
     // once, then stamp the results and hand the arenas back to the pool
-    if (!retired.empty()) HIPCHK(hipStreamSynchronize(b->stream));
+    if (!retired.empty()) HIPCHK(hipStreamSynchronize(S->stream));
     const double t_done = seconds_since(S->t0);
     for (size_t k = out.size() - retired.size(); k < out.size(); ++k) out[k].t_done = t_done;
     for (auto &a : retired) {
@@ -2228,13 +2417,13 @@ static int serve_round(pt_server *S, bool &dirty, std::vector<pt_result> &out)
     S->st.gpu_busy_s += gpu_ms * 1e-3;
     S->st.attempts += attempts;
     S->st.active = (int32_t)S->active.size();
+    S->st.peak_lanes = std::max(S->st.peak_lanes, (int32_t)lanes);
     return PT_OK;
 }
 
 static void serve_worker(pt_server *S)
 {
     (void)hipSetDevice(S->device);
-    bool dirty = true;
     std::vector<pt_result> out;
     for (;;) {
         {
@@ -2245,10 +2434,10 @@ static void serve_worker(pt_server *S)
                 continue;
             }
         }
-        serve_admit(S, dirty, out);
+        serve_admit(S, out);
         serve_publish(S, out);
         if (S->active.empty()) continue;
-        int rc = serve_round(S, dirty, out);
+        int rc = serve_round(S, out);
         if (rc) {
             // a failed round fails every request in it; the device state of
             // the launch is unknown, so the server takes no more work
@@ -2260,6 +2449,7 @@ static void serve_worker(pt_server *S)
                 pt_destroy(a.c);
             }
             S->active.clear();
+            for (auto &ln : S->lanes) ln.members = 0;
             const std::string why = pt_last_error();
             std::lock_guard<std::mutex> lk(S->mu);
             S->fail_msg = why;
@@ -2284,13 +2474,11 @@ extern "C" int pt_serve_start(const pt_serve_opts *o, pt_server **out)
         delete S;
         return fail(PT_EDEVICE, "no HIP device");
     }
-    S->batch = new pt_batch();
-    S->batch->opts.replicas_per_wg = S->opts.replicas_per_wg;
-    S->batch->opts.replicas_per_thread = S->opts.replicas_per_thread;
-    S->batch->opts.chunk_sweeps = S->opts.chunk_sweeps;
-    int rc = batch_init(S->batch, S->device);
+    int rc = PT_OK;
+    if (hipSetDevice(S->device) != hipSuccess || hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess)
+        rc = fail(PT_EDEVICE, "stream creation failed");
+    if (!rc) rc = serve_new_batch(S, &S->probe);
     if (rc) {
-        delete S->batch;
         delete S;
         return rc;
     }
@@ -2371,7 +2559,6 @@ extern "C" int pt_serve_stop(pt_server *s)
         s->pool.push_back({a.bytes, a.c->arena.p});
         pt_destroy(a.c);
     }
-    pt_batch_destroy(s->batch);
     delete s;
     return PT_OK;
 }

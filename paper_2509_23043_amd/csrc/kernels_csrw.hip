@@ -9,11 +9,14 @@
 // (Methods, Graph coloring). Their rows are packed once per launch in LDS,
 // shared by the workgroup's slots of the instance: record (c, s) holds the
 // s-th site of class c with h_i, and its bonds as 16-bit words (neighbour in
-// bits 0-11, J in bits 12-15; unused words 0: site 0 with J = 0). A lane reads
-// the next item's record while it decides the current one, so an item costs
-// two dependent LDS round trips: the neighbour spins with the own spin and
-// random half, then the flip threshold of the slot (Eqs. 4-5 through the
-// slot's uint32 table). The slot's sweep uniforms (Philox call q serves sites
+// bits 0-11, J in bits 12-15; unused words 0: site 0 with J = 0) in chunks of
+// CSRW_CHUNK words. The 64 sites of a rank group (c, k) take the chunks their
+// largest degree needs; within a class the host orders sites by degree, so
+// the few high-degree sites of a circuit (a multiplier's input bits) share
+// groups and the rest take one chunk. A lane reads the next item's first two
+// chunks while it decides the current one, so an item costs two dependent LDS
+// round trips: the neighbour spins with the own spin and random half, then the
+// flip threshold of the slot (Eqs. 4-5 through the slot's uint32 table). The slot's sweep uniforms (Philox call q serves sites
 // 8q .. 8q + 7) are drawn at the start of the sweep and staged in LDS in site
 // order.
 //
@@ -30,14 +33,13 @@ namespace tapt {
 namespace csrw {
 
 constexpr int MAXG = 8;   // slots (wavefronts) per workgroup
-constexpr int BPL = 16;   // bonds per record
 
 struct Off {
     size_t sp, rnd, bw, info, tab, toff, tsw, mail, xst, total;
 };
 
-// n sites, ncolors classes of at most ipl * 64 sites, G slots
-__host__ __device__ inline Off offsets(int n, int ncolors, int ipl, int G, int stride, int tsw_entries)
+// n sites, ncolors classes of at most ipl * 64 sites, chunks bond chunks, G slots
+__host__ __device__ inline Off offsets(int n, int ncolors, int ipl, int chunks, int G, int stride, int tsw_entries)
 {
     const int SB = (n + 15) & ~15, nr = (n + 7) & ~7;
     const int wpl = (n + 64 * 32 - 1) / (64 * 32);        // exchange words per lane
@@ -46,7 +48,7 @@ __host__ __device__ inline Off offsets(int n, int ncolors, int ipl, int G, int s
     size_t o = 0;
     f.sp = o; o = align16(o + (size_t)G * SB);
     f.rnd = o; o = align16(o + (size_t)G * nr * 2);
-    f.bw = o; o = align16(o + nrec * 32);
+    f.bw = o; o = align16(o + (size_t)chunks * 64 * 16);
     f.info = o; o = align16(o + nrec * 4);
     f.tab = o; o = align16(o + (size_t)G * stride * 4);
     f.toff = o; o = align16(o + (size_t)(G + 2) * 4);
@@ -93,16 +95,16 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
     const uint64_t cap = I.sweep_cap;
     const uint64_t tend = (t0 + a.K < cap) ? t0 + a.K : cap;
     if (t0 >= tend) return;
-    const int ncol = I.ncolors, ipl = (I.maxcnt + 63) / 64;
+    const int ncol = I.ncolors, ipl = (I.maxcnt + 63) / 64, ngr = ncol * ipl;
     const int SB = (n + 15) & ~15, nr = (n + 7) & ~7;
     const int spl = (n + 63) / 64;                            // sites per lane
     const int wpl = (spl + 31) / 32;                          // exchange words per lane
     const int NXW = 64 * wpl;                                 // words of a state, before the energy word
     const int stride = P.stride, D = P.D;
-    const Off lof = offsets(n, ncol, ipl, G, stride, a.tsw_entries);
+    const Off lof = offsets(n, ncol, ipl, I.csrw_chunks, G, stride, a.tsw_entries);
     int8_t *sp = (int8_t *)(lds_raw + lof.sp);                 // [G][SB] spins +-1, site order
     uint16_t *rnd = (uint16_t *)(lds_raw + lof.rnd);          // [G][nr] sweep uniforms (upper halves)
-    uint4 *bw = (uint4 *)(lds_raw + lof.bw);                  // [ncol][64 ipl][2] bond words
+    uint4 *bw = (uint4 *)(lds_raw + lof.bw);                  // [chunks][64] bond words, CSRW_CHUNK per chunk
     uint32_t *info = (uint32_t *)(lds_raw + lof.info);        // [ncol][64 ipl] site | h << 16; 0xFFF: none
     uint32_t *tab = (uint32_t *)(lds_raw + lof.tab);          // [G][stride] flip thresholds
     int *tsw_off = (int *)(lds_raw + lof.toff);
@@ -115,23 +117,32 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
         const int l = x / n, i = x - l * n;
         sp[l * SB + i] = I.spins[(size_t)(s0 + l) * n + i];
     }
-    const int nrec = ncol * 64 * ipl;
-    for (int x = tid; x < nrec; x += bs) {
-        const int c = x / (64 * ipl), s = x - c * 64 * ipl;
+    // record x = 64 g + q: lane q of rank group g = (c, k), class c's site 64 k + q
+    for (int x = tid; x < 64 * ngr; x += bs) {
+        const int g = x >> 6, q = x & 63;
+        const int c = g / ipl, s = (g - c * ipl) * 64 + q;
+        const int gcb = I.csrw_groups[g], cb = gcb >> 8, nch = gcb & 255;
         const int off = I.color_off[c], cnt = I.color_off[c + 1] - off;
-        uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         uint32_t inf = 0xFFFu;
+        int e0 = 0, e1 = 0;
         if (s < cnt) {
             const int i = I.color_sites[off + s];
-            const int e0 = I.row_ptr[i], e1 = I.row_ptr[i + 1];
-            for (int b = 0; b < BPL && e0 + b < e1; ++b)
-                w[b >> 1] |= ((uint32_t)I.col[e0 + b] | (((uint32_t)I.Jc[e0 + b] & 15u) << 12)) << (16 * (b & 1));
+            e0 = I.row_ptr[i];
+            e1 = I.row_ptr[i + 1];
             inf = (uint32_t)i | ((uint32_t)(uint16_t)I.h[i] << 16);
         }
-        bw[2 * x] = make_uint4(w[0], w[1], w[2], w[3]);
-        bw[2 * x + 1] = make_uint4(w[4], w[5], w[6], w[7]);
+        for (int j = 0; j < nch; ++j) {
+            uint32_t w[4] = {0, 0, 0, 0};
+            for (int b = 0; b < CSRW_CHUNK; ++b) {
+                const int e = e0 + CSRW_CHUNK * j + b;
+                if (e < e1) w[b >> 1] |= ((uint32_t)I.col[e] | (((uint32_t)I.Jc[e] & 15u) << 12)) << (16 * (b & 1));
+            }
+            bw[(cb + j) * 64 + q] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
         info[x] = inf;
     }
+    // group g's first chunk << 8 | chunks, in lane g
+    const int gcb_v = lane < ngr ? I.csrw_groups[lane] : 0;
     for (int x = tid; x < G * stride; x += bs) tab[x] = I.tflip[(size_t)s0 * stride + x];
     if (tid == 0) {
         int o = 0;
@@ -202,8 +213,10 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                 u_base = cyc + 1;
                 u_vec = philox_v((uint32_t)(slot - 1) + u_i, u_base + u_c, 0, TAG_SWAP, P.k0, P.k1).v[0];
             }
-            // the first item's record, in flight while the uniforms are drawn
-            uint4 b0 = bw[2 * lane], b1 = bw[2 * lane + 1];
+            // the first group's first two chunks, in flight while the uniforms are drawn
+            int gcb = __builtin_amdgcn_readfirstlane(gcb_v);
+            uint4 b0 = bw[(gcb >> 8) * 64 + lane];
+            uint4 b1 = (gcb & 255) > 1 ? bw[((gcb >> 8) + 1) * 64 + lane] : make_uint4(0u, 0u, 0u, 0u);
             uint32_t inf = info[lane];
             // ---- the sweep's uniforms, staged in site order ----
             for (int q = lane; q < nr / 8; q += 64) {
@@ -218,15 +231,16 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
             int dE = 0, nf = 0;
             for (int c = 0; c < ncol; ++c) {
                 for (int k = 0; k < ipl; ++k) {
+                    const int g = c * ipl + k;
                     const uint32_t ci = inf;
+                    const int cb = gcb >> 8, nch = gcb & 255;
                     const uint32_t ws[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
-                    // the next item's record, in flight while this one is decided
-                    const int nk = k + 1 < ipl ? k + 1 : 0, nc = k + 1 < ipl ? c : c + 1;
-                    if (nc < ncol) {
-                        const int xn = nc * 64 * ipl + 64 * nk + lane;
-                        b0 = bw[2 * xn];
-                        b1 = bw[2 * xn + 1];
-                        inf = info[xn];
+                    // the next group's first chunks, in flight while this one is decided
+                    if (g + 1 < ngr) {
+                        gcb = __builtin_amdgcn_readlane(gcb_v, g + 1);
+                        b0 = bw[(gcb >> 8) * 64 + lane];
+                        b1 = (gcb & 255) > 1 ? bw[((gcb >> 8) + 1) * 64 + lane] : make_uint4(0u, 0u, 0u, 0u);
+                        inf = info[(g + 1) * 64 + lane];
                     }
                     const int i = (int)(ci & 0xFFFu);
                     if (i != 0xFFF) {
@@ -235,10 +249,27 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                         const uint32_t hs = (uint32_t)rnd_w[i] << 16;
                         int f = (int)ci >> 16;
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) {
+                        for (int q = 0; q < 4; ++q) {
                             const uint32_t wq = ws[q];
                             f += ((int)(wq << 16) >> 28) * (int)m_w[wq & 0xFFFu] +
                                  ((int)wq >> 28) * (int)m_w[(wq >> 16) & 0xFFFu];
+                        }
+                        if (nch > 1) {
+#pragma unroll
+                            for (int q = 4; q < 8; ++q) {
+                                const uint32_t wq = ws[q];
+                                f += ((int)(wq << 16) >> 28) * (int)m_w[wq & 0xFFFu] +
+                                     ((int)wq >> 28) * (int)m_w[(wq >> 16) & 0xFFFu];
+                            }
+                        }
+                        // chunks past the second: the rare high-degree groups
+                        for (int j = 2; j < nch; ++j) {
+                            const uint4 bj = bw[(cb + j) * 64 + lane];
+                            const uint32_t wj[4] = {bj.x, bj.y, bj.z, bj.w};
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                f += ((int)(wj[q] << 16) >> 28) * (int)m_w[wj[q] & 0xFFFu] +
+                                     ((int)wj[q] >> 28) * (int)m_w[(wj[q] >> 16) & 0xFFFu];
                         }
                         const int d = m * f;
                         const uint32_t T = tab_w[d];
@@ -507,15 +538,17 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
 
 int csrw_max_storages() { return csrw::MAXG; }
 
-// where the kernel applies: n <= 4095, |J| <= 7, degree <= 16, classes of at most 256 sites
-bool csrw_supported(int n, int maxabsj, int maxdeg, int maxcnt)
+// where the kernel applies: n <= 4095, |J| <= 7, classes of at most 256 sites,
+// and the host packed the rows (chunks > 0: degree <= CSRW_MAXDEG, at most
+// CSRW_MAXGROUPS rank groups)
+bool csrw_supported(int n, int maxabsj, int chunks, int maxcnt)
 {
-    return n >= 1 && n <= 4095 && maxabsj <= 7 && maxdeg <= csrw::BPL && maxcnt >= 1 && maxcnt <= 256;
+    return n >= 1 && n <= 4095 && maxabsj <= 7 && chunks > 0 && maxcnt >= 1 && maxcnt <= 256;
 }
 
-size_t csrw_lds_bytes(int n, int ncolors, int maxcnt, int G, int stride, int tsw_entries)
+size_t csrw_lds_bytes(int n, int ncolors, int maxcnt, int chunks, int G, int stride, int tsw_entries)
 {
-    return csrw::offsets(n, ncolors, (maxcnt + 63) / 64, G, stride, tsw_entries).total;
+    return csrw::offsets(n, ncolors, (maxcnt + 63) / 64, chunks, G, stride, tsw_entries).total;
 }
 
 // 64-bit exchange words of one state (bits and energy)

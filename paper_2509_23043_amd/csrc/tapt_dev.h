@@ -33,6 +33,12 @@ __host__ __device__ inline size_t csr_row4_graph_bytes(int ncolors, int maxcnt, 
     return (size_t)ncolors * maxcnt * lanes * 68 + 64;
 }
 
+// The one-slot-per-wavefront sparse kernel packs a site's bonds in chunks of
+// CSRW_CHUNK 16-bit words; a rank group of 64 sites takes as many chunks as
+// its largest degree needs. Graphs with larger degrees or more rank groups
+// run in the other kernels.
+constexpr int CSRW_CHUNK = 8, CSRW_MAXDEG = 64, CSRW_MAXGROUPS = 64;
+
 struct BestRec {          // best min_r E_r seen; ordered by (E, t, slot)
     int32_t E;
     int32_t slot;
@@ -52,7 +58,8 @@ struct InstDev {
     int32_t ctx_on;                         // 1: proposals are contextual
     int32_t maxdeg;                         // largest degree of a free site
     int32_t maxcnt, maxabsj;                // largest colour class (free sites); largest |J|
-    int32_t pad0;
+    int32_t csrw_chunks;                    // bond chunks of the packed rows of the one-slot-per-
+                                            // wavefront sparse kernel (0: the graph does not fit it)
     int64_t prop_start, prop_period, prop_stop;
     uint64_t sweep_cap;                     // batched runs stop at this sweep count
 
@@ -63,8 +70,12 @@ struct InstDev {
     const int8_t *Jc;          // CSR [nnz]
     const int16_t *h;          // [n]
     const int8_t *clamp;       // [n]
-    const int16_t *color_sites;// CSR: free sites sorted by (color, index) [nfree]
+    const int16_t *color_sites;// CSR: free sites by color, within a color by degree (largest
+                               // first), then index [nfree]
     const int32_t *color_off;  // [ncolors + 1]
+    const int32_t *csrw_groups;// CSR: rank group (c, k) of the one-slot-per-wavefront sparse
+                               // kernel (sites 64k .. 64k + 63 of class c): first chunk << 8 |
+                               // chunks, over ceil(largest degree in the group / CSRW_CHUNK)
 
     // acceptance tables (uint32 thresholds, built on the host in FP64)
     const uint32_t *tflip;     // [R][tflip_stride]

@@ -111,31 +111,44 @@ def test_row_sweepers_independent_chains(kernel):
     _run_and_compare(probs, np.full(16, 1.3), 4, 100, M=0, expect=SWEEPER[kernel], kernel=kernel)
 
 
+def _pad_isolated(g, k):
+    """g with k more free sites that have no bonds: they join colour 0,
+    which then holds more than the 256 sites of the one-slot-per-wavefront
+    sparse kernel's limit."""
+    n = g["n"] + k
+    rp = np.concatenate([g["row_ptr"], np.full(k, g["row_ptr"][-1])])
+    out = inputs.graph(n, rp, g["col"], g["J"], h=np.concatenate([g["h"], np.zeros(k, np.int64)]),
+                       clamp=np.concatenate([g["clamp"], np.zeros(k, np.int8)]))
+    return out
+
+
 def test_runtime_sparse_sweeper_choice():
     """The runtime's choice among the sweepers of the workgroup-synchronous
     kernel, each against the oracle (general graphs that fit it take the
-    one-slot-per-wavefront kernel first): that kernel for an 8-bit multiplier
-    (auto); the four-storage rows for a graph of degree 20 (a 10-bit
-    multiplier, 4 slots per workgroup); the one-storage rows where a site's bound exceeds
-    255 (a hub with field 200); the four-storages-per-lane LDS sweeper where no
-    packed rows fit a block (a 10-bit multiplier, two lanes per item, 20
-    slots per workgroup); the LDS-resident CSR
-    sweepers when the caller asks for the workgroup-synchronous kernel (the
-    lane-sharing one at 512 threads for 2 slots per workgroup); and a
-    coupling of 9 refused by the one-storage rows."""
-    announce("sparse sweeper choice: row4 / row / quad / csr / csr-wide, refusal")
+    one-slot-per-wavefront kernel first): that kernel for 8- and 10-bit
+    multipliers (auto; the 10-bit one has sites of degree 20); the one-storage
+    rows for a graph with a colour class of more than 256 sites where a site's
+    bound exceeds 255 (a field of 250); the four-storages-per-lane LDS sweeper
+    where no packed rows fit a block (|J| = 9, a large colour class, 20 slots
+    per workgroup); the LDS-resident CSR sweepers when the caller asks for the
+    workgroup-synchronous kernel (the lane-sharing one at 512 threads for 2
+    slots per workgroup); and a coupling of 9 refused by the one-storage rows
+    and run in the four-storage rows."""
+    announce("sparse sweeper choice: csrw / row / quad / csr / csr-wide / row4, refusal")
     mult = [inputs.multiplier(8, C) for C, _, _ in inputs.semiprimes(8, 1, seed=6400)]
     plan = _run_and_compare(mult, inputs.geometric_ladder(32), 8, 60, expect="-", kernel="auto")
     assert plan[0][0] == "csrw", plan
     m10a = [inputs.multiplier(10, C) for C, _, _ in inputs.semiprimes(10, 1, seed=6405)]
-    _run_and_compare(m10a, inputs.geometric_ladder(16), 4, 60, expect="csr-row4", kernel="auto")
-    big = _random_graph(120, 6470)
+    plan = _run_and_compare(m10a, inputs.geometric_ladder(16), 4, 60, expect="-", kernel="auto")
+    assert plan[0][0] == "csrw", plan
+    big = _random_graph(120, 6470, hubs=0)
     big["h"] = big["h"].copy()
-    hub = int(np.argmax(np.diff(big["row_ptr"]) * (big["clamp"] == 0)))
-    big["h"][hub] = 200
-    _run_and_compare([big], inputs.geometric_ladder(8), 4, 60, expect="csr-row", kernel="auto")
-    m10 = [inputs.multiplier(10, C) for C, _, _ in inputs.semiprimes(10, 1, seed=6410)]
-    _run_and_compare(m10, inputs.geometric_ladder(20), 20, 40, expect="csr-quad", kernel="auto")
+    big["h"][int(np.argmax(big["clamp"] == 0))] = 250
+    big = _pad_isolated(big, 260)
+    assert np.bincount(big["color"][big["clamp"] == 0]).max() > 256
+    _run_and_compare([big], inputs.geometric_ladder(8), 1, 60, expect="csr-row", kernel="auto")
+    g9q = _pad_isolated(_random_graph(100, 6460, hubs=0, jmax=9), 120)
+    _run_and_compare([g9q], inputs.geometric_ladder(20), 20, 40, expect="csr-quad", kernel="auto")
     _run_and_compare(mult, inputs.geometric_ladder(16), 4, 60, expect="csr", kernel="block")
     _run_and_compare(mult, inputs.geometric_ladder(16), 2, 60, expect="csr-wide", kernel="block")
     g9 = _random_graph(100, 6450, hubs=0, jmax=9)

@@ -78,6 +78,8 @@ def test_serving_alone_vs_mix_and_oracle():
     srv.stop()
     assert st["completed"] == len(rqs) and st["rejected"] == 0
     assert st["peak_active"] > 1
+    # lattices of L = 4, the row kernel's lattices and the multipliers run in lanes of their own
+    assert st["peak_lanes"] >= 2, st
     by_tag = {r["user_tag"]: r for r in mix.values()}
     # three of them alone, each on a fresh server
     for j in (0, 5, 11):
@@ -134,3 +136,35 @@ def test_serving_memory_admission():
     for r in res.values():
         assert r["status"] == 0 and r["sweeps"] == 150 + 50 * (r["id"] - 1)
         assert r["t_admit"] >= r["t_submit"] and r["t_done"] >= r["t_admit"]
+
+
+def test_serving_lanes_overflow():
+    """More requests of one kind than one co-resident launch holds: 40 +-J
+    L = 6 lattices of 64 slots (8 workgroups of the row kernel each) are
+    admitted together and run in several lanes per round; every result equals
+    the oracle's."""
+    announce("serving: 40 requests of L=6 R=64 over several launch lanes, 3 checked against the oracle")
+    g = inputs.ea_lattice(6, 640)
+    b = inputs.geometric_ladder(64)
+    banks = {r: inputs.random_bank(g["n"], 4, seed=960 + r) for r in range(0, 60, 4)}
+    kw = dict(prop_start=20, prop_period=20)
+    K, cap = 50, 150
+    srv = binding.Server(chunk_sweeps=K)
+    ctx = binding.Context(g, b, seed=0, **kw)
+    for r, bank in banks.items():
+        ctx.propose(r, bank)
+    pid = srv.register(ctx)
+    for j in range(40):
+        srv.submit(pid, 8000 + j, cap, user_tag=j)
+    res = {r["user_tag"]: r for r in _drain(srv, 40).values()}
+    st = srv.stats()
+    srv.stop()
+    assert st["completed"] == 40 and st["rejected"] == 0
+    assert st["peak_active"] > 32 and st["peak_lanes"] >= 2, st
+    for j in (0, 21, 39):
+        r = res[j]
+        assert r["status"] == 0 and r["sweeps"] == cap
+        ref = oracle.Run(g, b, seed=8000 + j, banks=banks, **kw)
+        ref.run(cap)
+        assert r["best_energy"] == ref.best and r["best_t"] == ref.best_t and r["best_slot"] == ref.best_slot
+        assert np.array_equal(r["best_spins"], ref.best_spins), j
