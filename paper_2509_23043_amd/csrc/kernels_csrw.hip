@@ -243,25 +243,27 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                         inf = info[(g + 1) * 64 + lane];
                     }
                     const int i = (int)(ci & 0xFFFu);
-                    if (i != 0xFFF) {
-                        // the item's reads are independent: one LDS round trip
+                    // the item, with the reads of its first NC chunks issued
+                    // before any is summed (one LDS round trip); a group takes
+                    // one straight-line body by its chunk count, so no read is
+                    // waited for at a branch
+                    auto decide = [&](auto nc_const) {
+                        constexpr int NC = decltype(nc_const)::value;
+                        if (i == 0xFFF) return;
                         const int m = m_w[i];
                         const uint32_t hs = (uint32_t)rnd_w[i] << 16;
+                        int v[8 * NC];                      // 4 words of 2 bonds per chunk
+#pragma unroll
+                        for (int q = 0; q < 4 * NC; ++q) {
+                            v[2 * q] = m_w[ws[q] & 0xFFFu];
+                            v[2 * q + 1] = m_w[(ws[q] >> 16) & 0xFFFu];
+                        }
+                        // keep the scheduler from splitting the reads around a wait
+                        __builtin_amdgcn_sched_barrier(0);
                         int f = (int)ci >> 16;
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const uint32_t wq = ws[q];
-                            f += ((int)(wq << 16) >> 28) * (int)m_w[wq & 0xFFFu] +
-                                 ((int)wq >> 28) * (int)m_w[(wq >> 16) & 0xFFFu];
-                        }
-                        if (nch > 1) {
-#pragma unroll
-                            for (int q = 4; q < 8; ++q) {
-                                const uint32_t wq = ws[q];
-                                f += ((int)(wq << 16) >> 28) * (int)m_w[wq & 0xFFFu] +
-                                     ((int)wq >> 28) * (int)m_w[(wq >> 16) & 0xFFFu];
-                            }
-                        }
+                        for (int q = 0; q < 4 * NC; ++q)
+                            f += ((int)(ws[q] << 16) >> 28) * v[2 * q] + ((int)ws[q] >> 28) * v[2 * q + 1];
                         // chunks past the second: the rare high-degree groups
                         for (int j = 2; j < nch; ++j) {
                             const uint4 bj = bw[(cb + j) * 64 + lane];
@@ -290,7 +292,9 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                             dE += 2 * d;
                             nf += 1;
                         }
-                    }
+                    };
+                    if (nch == 1) decide(std::integral_constant<int, 1>{});
+                    else decide(std::integral_constant<int, 2>{});
                 }
                 // the next class reads what this one wrote (in-order LDS within a wavefront)
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
