@@ -217,6 +217,8 @@ def parse():
                     help="mixed / fact legs: bank entries per slot (the workloads' 256; fewer for profiling)")
     ap.add_argument("--serve-rates", default="10,30,100,300,1000", help="Poisson arrival rates, req/s")
     ap.add_argument("--serve-requests", default="1000,1000,1000,1000,1000", help="requests per rate")
+    ap.add_argument("--serve-pipeline", action="store_true",
+                    help="serving: enqueue each round before retiring the last (one more round before a request joins)")
     ap.add_argument("--serve-cap", type=int, default=100_000, help="sweep cap per request")
     ap.add_argument("--serve-ref-runs", type=int, default=8,
                     help="independent PT runs per spin-glass instance that set its reference energy")
@@ -641,7 +643,7 @@ def serving_leg(args, log):
     rates = [float(x) for x in args.serve_rates.split(",")]
     counts = [int(x) for x in args.serve_requests.split(",")]
     out = []
-    srv = binding.Server(chunk_sweeps=args.serve_chunk, mem_budget=8 << 30)
+    srv = binding.Server(chunk_sweeps=args.serve_chunk, mem_budget=8 << 30, pipeline=args.serve_pipeline)
     pids = [srv.register(c) for c in ctxs]
     seed_base = 5000
     for lam, nreq in zip(rates, counts):
@@ -706,7 +708,7 @@ def serving_leg(args, log):
     srv.stop()
     for c in ctxs:
         c.close()
-    return dict(rates=out, sweep_cap=args.serve_cap, chunk_sweeps=args.serve_chunk,
+    return dict(rates=out, sweep_cap=args.serve_cap, chunk_sweeps=args.serve_chunk, pipelined=bool(args.serve_pipeline),
                 pool="40 EA +-J (L=6..16, 8 each, R=24..48) + 20 multipliers (m=8..12, 4 each, R=32); "
                      "banks 64/slot from plain-PT runs; EA target = E_ref + 1% N on the grid of 4, E_ref the "
                      f"best of {args.serve_ref_runs} independent {args.serve_ref_sweeps}-sweep plain-PT runs; "

@@ -299,6 +299,10 @@ typedef struct {
     int32_t max_active;          /* cap on concurrent requests (0 = none) */
     int32_t replicas_per_wg;     /* tiling as in pt_batch_opts (0 = choose) */
     int32_t replicas_per_thread;
+    int32_t pipeline;            /* 1: enqueue each round before retiring the requests
+                                    the previous one finished (the device does not wait
+                                    for the host between rounds; a new request joins one
+                                    round later); 0: one round at a time */
 } pt_serve_opts;
 
 typedef struct {

@@ -50,7 +50,7 @@ KERNELS = {"auto": 0, "block": 1, "wave": 2, "pm": 3, "pm1": 4, "row": 5, "row4"
 
 class _ServeOpts(C.Structure):
     _fields_ = [("mem_budget", C.c_uint64), ("chunk_sweeps", C.c_int32), ("max_active", C.c_int32),
-                ("replicas_per_wg", C.c_int32), ("replicas_per_thread", C.c_int32)]
+                ("replicas_per_wg", C.c_int32), ("replicas_per_thread", C.c_int32), ("pipeline", C.c_int32)]
 
 
 class _Request(C.Structure):
@@ -370,9 +370,10 @@ class Server:
     """Continuous-batching solve server (pt_serve_*). Problems are Contexts
     with their banks installed; requests are (problem, seed, target, cap)."""
 
-    def __init__(self, mem_budget=0, chunk_sweeps=0, max_active=0, replicas_per_wg=0, replicas_per_thread=0):
+    def __init__(self, mem_budget=0, chunk_sweeps=0, max_active=0, replicas_per_wg=0, replicas_per_thread=0,
+                 pipeline=False):
         o = _ServeOpts(int(mem_budget), int(chunk_sweeps), int(max_active), int(replicas_per_wg),
-                       int(replicas_per_thread))
+                       int(replicas_per_thread), 1 if pipeline else 0)
         h = C.c_void_p()
         _check(lib().pt_serve_start(C.byref(o), C.byref(h)))
         self.h = h

@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <set>
 #include <tuple>
 #include <string>
@@ -181,6 +182,32 @@ struct DevBuf {
         p = q;
         bytes = b;
         owned = false;
+    }
+    template <class T> T *as() const { return (T *)p; }
+};
+
+// Page-locked host memory (hipHostMalloc): the source or target of copies
+// that run after the call that enqueued them has returned.
+struct HostPinned {
+    void *p = nullptr;
+    size_t bytes = 0;
+    HostPinned() = default;
+    HostPinned(const HostPinned &) = delete;
+    HostPinned &operator=(const HostPinned &) = delete;
+    ~HostPinned()
+    {
+        if (p) (void)hipHostFree(p);
+    }
+    // at least b bytes (contents not kept when it grows)
+    hipError_t reserve(size_t b)
+    {
+        if (b <= bytes) return hipSuccess;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+        hipError_t e = hipHostMalloc(&p, b, hipHostMallocDefault);
+        if (e == hipSuccess) bytes = b;
+        return e;
     }
     template <class T> T *as() const { return (T *)p; }
 };
@@ -1115,6 +1142,12 @@ struct pt_batch {
     hipStream_t own_stream = nullptr;
     std::vector<hipEvent_t> ev_pool;  // start/stop pairs of timed launches
     size_t ev_used = 0;
+    // builds that do not wait for the stream: the work-item tables go to the
+    // device from pinned staging, alternating between two, so a build never
+    // overwrites the staging of the launch before the one still running
+    bool async_build = false;
+    unsigned build_gen = 0;
+    HostPinned stage[2];
     double kernel_ms = 0.0;
     uint64_t kernel_launches = 0;
     ~pt_batch()
@@ -1355,6 +1388,16 @@ struct GroupMem {
         if (e != hipSuccess || v.empty()) return e;
         return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
     }
+    // the same from a copy in pinned staging at *at (advanced past it)
+    template <class T> hipError_t put_staged(DevBuf &b, const std::vector<T> &v, char *&at, hipStream_t s)
+    {
+        hipError_t e = take(b, v.size() * sizeof(T));
+        if (e != hipSuccess || v.empty()) return e;
+        memcpy(at, v.data(), v.size() * sizeof(T));
+        e = hipMemcpyAsync(b.p, at, v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+        at += (v.size() * sizeof(T) + 15) & ~(size_t)15;
+        return e;
+    }
 };
 
 // Bytes build_group takes from a GroupMem region for this plan (the same
@@ -1410,14 +1453,26 @@ static int build_group(pt_batch *b, LaunchGroup *g, GroupMem &mem)
     g->block = P.block;
     g->lds = P.lds;
     g->tsw_entries = P.tsw_max;
-    if (e == hipSuccess) e = mem.put(g->items, P.items, s);
-    if (e == hipSuccess) e = mem.put(g->order, P.order, s);
-    if (e == hipSuccess) e = mem.put(g->first_item, P.first, s);
+    if (b->async_build) {
+        auto padded = [](size_t x) { return (x + 15) & ~(size_t)15; };
+        HostPinned &st = b->stage[b->build_gen++ & 1];
+        if (e == hipSuccess)
+            e = st.reserve(padded(P.items.size() * sizeof(WorkItem)) + padded(P.order.size() * sizeof(int32_t)) +
+                           padded(P.first.size() * sizeof(int)));
+        char *at = st.as<char>();
+        if (e == hipSuccess) e = mem.put_staged(g->items, P.items, at, s);
+        if (e == hipSuccess) e = mem.put_staged(g->order, P.order, at, s);
+        if (e == hipSuccess) e = mem.put_staged(g->first_item, P.first, at, s);
+    } else {
+        if (e == hipSuccess) e = mem.put(g->items, P.items, s);
+        if (e == hipSuccess) e = mem.put(g->order, P.order, s);
+        if (e == hipSuccess) e = mem.put(g->first_item, P.first, s);
+    }
     if (e == hipErrorOutOfMemory && mem.base)
         return fail(PT_ENOMEM, "the launch needs more than the %zu bytes of static scratch", mem.cap);
     HIPCHK(e);
-    // the host vectors must outlive their copies
-    HIPCHK(hipStreamSynchronize(s));
+    // the host vectors must outlive their copies (staged copies do not read them)
+    if (!b->async_build) HIPCHK(hipStreamSynchronize(s));
     return PT_OK;
 }
 
@@ -2022,6 +2077,7 @@ int clone_ctx(const pt_ctx *tm, uint64_t seed, int has_target, int32_t target, u
     c->hI.target = target;
     c->hI.sweep_cap = cap;
     c->hI.epoch = 0;
+    c->hI.stop_at_hit = 1;     // a request ends at its first hit: later rounds leave it as it is
     fill_inst_pointers(c);
     // the request's bank cursors start at its own seeded offsets
     std::vector<int32_t> &cur = c->h_cursor0;
@@ -2066,7 +2122,8 @@ struct SrvActive {
     double t_admit;
     uint64_t t_last;
     int lane;                         // the launch lane it runs in
-    int slot;                         // its index in that lane's launch group
+    int cur;                          // its index in that lane's launch group as last built
+    int slot[2];                      // its index in the round of each parity (-1: not in it)
 };
 
 // A launch lane of a server: a batch over some of the running requests whose
@@ -2080,8 +2137,18 @@ struct SrvLane {
     int members = 0;
     bool dirty = false;               // membership changed since the last build
     std::set<std::string> full_for;   // request kinds it had no room for (cleared when one leaves)
-    std::vector<InstStatus> status;
-    int err[8] = {0};
+    // by round parity: status records and error flag copied after its launch,
+    // and events around the launch
+    HostPinned status[2], err[2];
+    hipEvent_t ev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    bool ran[2] = {false, false};
+    ~SrvLane()
+    {
+        pt_batch_destroy(b);
+        for (auto &pe : ev)
+            for (hipEvent_t e : pe)
+                if (e) (void)hipEventDestroy(e);
+    }
 };
 
 } // namespace
@@ -2102,19 +2169,29 @@ struct pt_server {
     std::thread worker;
     // worker-only
     hipStream_t stream = nullptr;
+    hipStream_t copy_stream = nullptr; // best configurations to callers beside a running round
+    hipEvent_t round_end[2] = {nullptr, nullptr};   // after the status copies of the round of each parity
     pt_batch *probe = nullptr;        // plans single requests (no contexts of its own)
-    std::vector<SrvLane> lanes;
+    std::vector<std::unique_ptr<SrvLane>> lanes;
     std::vector<std::string> solo;    // per problem: the kernel a request of it runs alone
     std::vector<SrvActive> active;
     // request-state arenas of retired requests, reused by later ones of the
     // same size (no device allocation or free, and so no device-wide
-    // synchronisation, per request once the pool is warm)
-    std::vector<std::pair<size_t, void *>> pool;
+    // synchronisation, per request once the pool is warm); grave[q]: arenas
+    // of requests retired while the round of parity q still ran over them
+    // (no-ops there), pooled once it ends
+    std::vector<std::pair<size_t, void *>> pool, grave[2];
     ~pt_server()
     {
-        for (auto &l : lanes) pt_batch_destroy(l.b);
+        if (stream) (void)hipStreamSynchronize(stream);
+        lanes.clear();
         pt_batch_destroy(probe);
         for (auto &m : pool) (void)hipFree(m.second);
+        for (auto &g : grave)
+            for (auto &m : g) (void)hipFree(m.second);
+        for (hipEvent_t e : round_end)
+            if (e) (void)hipEventDestroy(e);
+        if (copy_stream) (void)hipStreamDestroy(copy_stream);
         if (stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -2159,7 +2236,8 @@ static pt_result serve_result(const SrvReq &r, int status, double t_admit, doubl
 }
 
 // A batch object on the server's stream with its tiling options and no
-// contexts: a lane, or the probe that plans single requests.
+// contexts: a lane (builds that do not wait for the running round), or the
+// probe that plans single requests.
 static int serve_new_batch(pt_server *S, pt_batch **out)
 {
     *out = nullptr;
@@ -2167,12 +2245,28 @@ static int serve_new_batch(pt_server *S, pt_batch **out)
     b->opts.replicas_per_wg = S->opts.replicas_per_wg;
     b->opts.replicas_per_thread = S->opts.replicas_per_thread;
     b->opts.chunk_sweeps = S->opts.chunk_sweeps;
+    b->async_build = true;
     int rc = batch_init(b, S->device, S->stream);
     if (rc) {
         delete b;
         return rc;
     }
     *out = b;
+    return PT_OK;
+}
+
+// A new empty lane, its events created.
+static int serve_new_lane(pt_server *S, const std::string &ident, int &index)
+{
+    std::unique_ptr<SrvLane> ln(new SrvLane());
+    int rc = serve_new_batch(S, &ln->b);
+    if (rc) return rc;
+    for (auto &pe : ln->ev)
+        for (hipEvent_t &e : pe)
+            if (hipEventCreate(&e) != hipSuccess) return fail(PT_EDEVICE, "event creation failed");
+    ln->ident = ident;
+    S->lanes.push_back(std::move(ln));
+    index = (int)S->lanes.size() - 1;
     return PT_OK;
 }
 
@@ -2185,17 +2279,16 @@ static std::vector<pt_ctx *> lane_set(const pt_server *S, int l)
     return set;
 }
 
-// The kernel a request of problem p runs alone ("" with the error code in rc
-// if it fits no launch by itself).
-static const std::string &serve_solo(pt_server *S, int p, int &rc)
+// The kernel a request of problem p runs alone (empty, with the error code in
+// rc, if it fits no launch by itself).
+static std::string serve_solo(pt_server *S, int p, int &rc)
 {
-    static const std::string none;
     rc = PT_OK;
     if ((int)S->solo.size() <= p) S->solo.resize(p + 1);
     if (S->solo[p].empty()) {
         LaunchGroup *g = nullptr;
         rc = pick_group(S->probe, {S->problems[p]}, &g);
-        if (rc) return none;
+        if (rc) return std::string();
         S->solo[p] = group_identity(g);
         delete g;
     }
@@ -2209,7 +2302,7 @@ static int serve_place(pt_server *S, pt_ctx *tm, const std::string &solo, int &r
 {
     rc = PT_OK;
     for (int l = 0; l < (int)S->lanes.size(); ++l) {
-        SrvLane &ln = S->lanes[l];
+        SrvLane &ln = *S->lanes[l];
         // 8^3 +-J lattices run in the row kernel's lanes beside other sizes
         const bool kin = ln.ident == solo || (ln.ident.rfind("kernel=pml ", 0) == 0 && solo.rfind("kernel=pm ", 0) == 0);
         if (ln.members == 0 || !kin || ln.full_for.count(solo)) continue;
@@ -2222,17 +2315,14 @@ static int serve_place(pt_server *S, pt_ctx *tm, const std::string &solo, int &r
         ln.full_for.insert(solo);
     }
     for (int l = 0; l < (int)S->lanes.size(); ++l)
-        if (S->lanes[l].members == 0) {
-            S->lanes[l].ident = solo;
-            S->lanes[l].full_for.clear();
+        if (S->lanes[l]->members == 0) {
+            S->lanes[l]->ident = solo;
+            S->lanes[l]->full_for.clear();
             return l;
         }
-    SrvLane ln;
-    rc = serve_new_batch(S, &ln.b);
-    if (rc) return -1;
-    ln.ident = solo;
-    S->lanes.push_back(ln);
-    return (int)S->lanes.size() - 1;
+    int l = -1;
+    rc = serve_new_lane(S, solo, l);
+    return rc ? -1 : l;
 }
 
 // Admit waiting requests, first come first served, while their state fits
@@ -2288,20 +2378,21 @@ static void serve_admit(pt_server *S, std::vector<pt_result> &out)
             out.push_back(serve_result(r, rc, now, now));
             continue;
         }
-        S->active.push_back({r, c, need, now, 0, lane, -1});
-        S->lanes[lane].members += 1;
-        S->lanes[lane].dirty = true;
+        S->active.push_back({r, c, need, now, 0, lane, -1, {-1, -1}});
+        S->lanes[lane]->members += 1;
+        S->lanes[lane]->dirty = true;
     }
 }
 
-// Build the launch of every lane whose membership changed. A lane whose
-// remaining requests no longer fit its launch (its kernel can change as
+// Build the launch of every lane whose membership changed (without waiting
+// for the running round: the new tables reach the device behind it). A lane
+// whose remaining requests no longer fit its launch (its kernel can change as
 // requests leave) gives its later half to a new lane, until every lane
 // builds; a single admitted request always fits alone.
 static int serve_build(pt_server *S)
 {
     for (int l = 0; l < (int)S->lanes.size(); ++l) {
-        SrvLane &ln = S->lanes[l];
+        SrvLane &ln = *S->lanes[l];
         if (!ln.dirty || ln.members == 0) {
             ln.dirty = false;
             continue;
@@ -2309,70 +2400,85 @@ static int serve_build(pt_server *S)
         std::vector<pt_ctx *> set = lane_set(S, l);
         int rc = batch_set_contexts(ln.b, set.data(), (int32_t)set.size());
         if (rc == PT_EUNSUPPORTED && set.size() > 1) {
-            SrvLane nl;
-            rc = serve_new_batch(S, &nl.b);
+            int nidx = -1;
+            rc = serve_new_lane(S, std::string(), nidx);
             if (rc) return rc;
-            const int nidx = (int)S->lanes.size();
-            int k = 0, keep = (int)set.size() / 2;
+            int k = 0;
+            const int keep = (int)set.size() / 2;
             for (auto &a : S->active)
                 if (a.lane == l && k++ >= keep) a.lane = nidx;
-            nl.members = (int)set.size() - keep;
-            nl.dirty = true;
-            S->lanes.push_back(nl);
-            S->lanes[l].members = keep;
+            S->lanes[nidx]->members = (int)set.size() - keep;
+            S->lanes[nidx]->dirty = true;
+            S->lanes[l]->members = keep;
             --l;   // rebuild this lane with its first half
             continue;
         }
         if (rc) return rc;
-        SrvLane &lb = S->lanes[l];
+        SrvLane &lb = *S->lanes[l];
         lb.ident = group_identity(lb.b->groups[0]);
         lb.dirty = false;
         int k = 0;
         for (auto &a : S->active)
-            if (a.lane == l) a.slot = k++;
+            if (a.lane == l) a.cur = k++;
     }
     return PT_OK;
 }
 
-// One round: each lane's persistent launch of chunk_sweeps sweeps over its
-// requests, in turn on the server's stream, then retire the requests that are
-// done.
-static int serve_round(pt_server *S, std::vector<pt_result> &out)
+// Enqueue the round of parity q: each lane's persistent launch of
+// chunk_sweeps sweeps over its requests, in turn on the server's stream,
+// with its status records and error flag copied to pinned memory behind it.
+static int serve_launch(pt_server *S, int q, int &lanes)
 {
-    int rc = serve_build(S);
-    if (rc) return rc;
-    const double ta = seconds_since(S->t0);
     const uint32_t K = (uint32_t)S->opts.chunk_sweeps;
-    int lanes = 0;
-    for (auto &ln : S->lanes) {
-        if (ln.members == 0) continue;
-        ln.b->ev_used = 0;
-        hipError_t e = enqueue_round(ln.b, K, true);
-        if (e != hipSuccess) return fail(PT_EDEVICE, "serving round: %s", hipGetErrorString(e));
+    lanes = 0;
+    for (auto &lp : S->lanes) {
+        SrvLane &ln = *lp;
+        ln.ran[q] = ln.members > 0;
+        if (!ln.ran[q]) continue;
         LaunchGroup *g = ln.b->groups[0];
-        ln.status.resize(g->ctxs.size());
-        HIPCHK(hipMemcpyAsync(ln.status.data(), g->status.p, ln.status.size() * sizeof(InstStatus),
-                              hipMemcpyDeviceToHost, S->stream));
-        HIPCHK(hipMemcpyAsync(ln.err, ln.b->err.p, 32, hipMemcpyDeviceToHost, S->stream));
+        const size_t sb = g->ctxs.size() * sizeof(InstStatus);
+        HIPCHK(ln.status[q].reserve(sb));
+        HIPCHK(ln.err[q].reserve(32));
+        HIPCHK(hipEventRecord(ln.ev[q][0], S->stream));
+        hipError_t e = enqueue_round(ln.b, K, false);
+        if (e != hipSuccess) return fail(PT_EDEVICE, "serving round: %s", hipGetErrorString(e));
+        HIPCHK(hipEventRecord(ln.ev[q][1], S->stream));
+        HIPCHK(hipMemcpyAsync(ln.status[q].p, g->status.p, sb, hipMemcpyDeviceToHost, S->stream));
+        HIPCHK(hipMemcpyAsync(ln.err[q].p, ln.b->err.p, 32, hipMemcpyDeviceToHost, S->stream));
         lanes += 1;
     }
-    HIPCHK(hipStreamSynchronize(S->stream));
+    HIPCHK(hipEventRecord(S->round_end[q], S->stream));
+    for (auto &a : S->active) a.slot[q] = a.cur;
+    return PT_OK;
+}
+
+// Wait for the round of parity q and retire the requests that are done. The
+// round of parity q ^ 1, if next_running, was enqueued before this wait and
+// runs over the retired requests as no-ops (they stop at their target or
+// cap), so their arenas wait in grave[q ^ 1] until it ends; their best
+// configurations go to the callers now, on the copy stream.
+static int serve_finish(pt_server *S, int q, bool next_running, std::vector<pt_result> &out)
+{
+    HIPCHK(hipEventSynchronize(S->round_end[q]));
+    for (auto &m : S->grave[q]) S->pool.push_back(m);
+    S->grave[q].clear();
     double gpu_ms = 0.0;
-    for (auto &ln : S->lanes) {
-        if (ln.members == 0) continue;
-        if (ln.err[0]) return fail(PT_ETIMEOUT, "cross-workgroup exchange timed out in a serving round");
-        for (size_t k = 0; k + 1 < ln.b->ev_used; k += 2) {
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, ln.b->ev_pool[k], ln.b->ev_pool[k + 1]));
-            gpu_ms += ms;
-        }
-        ln.b->ev_used = 0;
+    for (auto &lp : S->lanes) {
+        SrvLane &ln = *lp;
+        if (!ln.ran[q]) continue;
+        if (ln.err[q].as<int>()[0]) return fail(PT_ETIMEOUT, "cross-workgroup exchange timed out in a serving round");
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ln.ev[q][0], ln.ev[q][1]));
+        gpu_ms += ms;
     }
     double attempts = 0.0;
     std::vector<SrvActive> keep, retired;
-    for (size_t k = 0; k < S->active.size(); ++k) {
-        SrvActive &a = S->active[k];
-        const InstStatus &st = S->lanes[a.lane].status[a.slot];
+    for (auto &a : S->active) {
+        if (a.slot[q] < 0) {     // admitted after the round was enqueued
+            keep.push_back(a);
+            continue;
+        }
+        const InstStatus &st = S->lanes[a.lane]->status[q].as<InstStatus>()[a.slot[q]];
         const uint64_t t = (uint64_t)st.t;
         attempts += (double)(t - a.t_last) * (double)a.c->R * (double)a.c->nfree;
         a.t_last = t;
@@ -2383,7 +2489,7 @@ static int serve_round(pt_server *S, std::vector<pt_result> &out)
         }
         if (a.r.rq.best_out)
             HIPCHK(hipMemcpyAsync(a.r.rq.best_out, a.c->best_spins.p, (size_t)a.c->n, hipMemcpyDeviceToHost,
-                                  S->stream));
+                                  S->copy_stream));
         pt_result o = serve_result(a.r, PT_OK, a.t_admit, 0.0);
         o.hit = hit ? 1 : 0;
         o.first_hit = st.first_hit;
@@ -2393,54 +2499,76 @@ static int serve_round(pt_server *S, std::vector<pt_result> &out)
         o.sweeps = t;
         out.push_back(o);
         retired.push_back(a);
-        SrvLane &ln = S->lanes[a.lane];
+        SrvLane &ln = *S->lanes[a.lane];
         ln.members -= 1;
         ln.dirty = true;
         ln.full_for.clear();
     }
-    // the best configurations are on their way to the callers' buffers: wait
-    // once, then stamp the results and hand the arenas back to the pool
-    if (!retired.empty()) HIPCHK(hipStreamSynchronize(S->stream));
+    if (!retired.empty()) HIPCHK(hipStreamSynchronize(S->copy_stream));
     const double t_done = seconds_since(S->t0);
     for (size_t k = out.size() - retired.size(); k < out.size(); ++k) out[k].t_done = t_done;
     for (auto &a : retired) {
-        S->pool.push_back({a.bytes, a.c->arena.p});
+        (next_running ? S->grave[q ^ 1] : S->pool).push_back({a.bytes, a.c->arena.p});
         delete a.c;                  // views only: frees no device memory
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->st.mem_used -= a.bytes;
-        S->st.completed += 1;
     }
     S->active.swap(keep);
     std::lock_guard<std::mutex> lk(S->mu);
-    S->st.rounds += 1;
-    S->st.busy_s += seconds_since(S->t0) - ta;
+    for (auto &a : retired) {
+        S->st.mem_used -= a.bytes;
+        S->st.completed += 1;
+    }
     S->st.gpu_busy_s += gpu_ms * 1e-3;
     S->st.attempts += attempts;
     S->st.active = (int32_t)S->active.size();
-    S->st.peak_lanes = std::max(S->st.peak_lanes, (int32_t)lanes);
     return PT_OK;
 }
 
+// The worker. Each turn admits waiting requests, builds the lanes that
+// changed and enqueues a round. One round at a time (the default), it then
+// waits for that round and retires what it finished. Pipelined, it waits
+// instead for the round before, so the device runs the next round while the
+// host handles the last; a request is then in the round after the one that
+// finished it as a no-op, which changes nothing it reports, and a new request
+// joins one round later.
 static void serve_worker(pt_server *S)
 {
     (void)hipSetDevice(S->device);
     std::vector<pt_result> out;
+    int q = 0;                   // parity of the next round
+    bool running = false;        // the round of parity q ^ 1 is in flight
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            if (S->active.empty() && S->pending.empty()) {
+            if (S->active.empty() && S->pending.empty() && !running) {
                 if (S->stopping) break;
                 S->cv_work.wait(lk, [&] { return S->stopping || !S->pending.empty(); });
                 continue;
             }
         }
+        const double ta = seconds_since(S->t0);
         serve_admit(S, out);
         serve_publish(S, out);
-        if (S->active.empty()) continue;
-        int rc = serve_round(S, out);
+        int rc = PT_OK, lanes = 0;
+        bool launched = false;
+        if (!S->active.empty()) {
+            rc = serve_build(S);
+            if (!rc) rc = serve_launch(S, q, lanes);
+            launched = rc == PT_OK;
+        }
+        if (!rc && running) rc = serve_finish(S, q ^ 1, launched, out);
+        if (!rc && launched && !S->opts.pipeline) {   // one round at a time
+            rc = serve_finish(S, q, false, out);
+            launched = false;
+            if (!rc) {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->st.rounds += 1;
+                S->st.peak_lanes = std::max(S->st.peak_lanes, (int32_t)lanes);
+            }
+        }
         if (rc) {
             // a failed round fails every request in it; the device state of
             // the launch is unknown, so the server takes no more work
+            (void)hipStreamSynchronize(S->stream);
             const double now = seconds_since(S->t0);
             for (auto &a : S->active) {
                 out.push_back(serve_result(a.r, rc, a.t_admit, now));
@@ -2449,7 +2577,7 @@ static void serve_worker(pt_server *S)
                 pt_destroy(a.c);
             }
             S->active.clear();
-            for (auto &ln : S->lanes) ln.members = 0;
+            for (auto &ln : S->lanes) ln->members = 0;
             const std::string why = pt_last_error();
             std::lock_guard<std::mutex> lk(S->mu);
             S->fail_msg = why;
@@ -2457,6 +2585,16 @@ static void serve_worker(pt_server *S)
             S->st.rejected += S->pending.size();
             S->pending.clear();
             S->stopping = true;
+            running = false;
+        } else {
+            running = launched;
+            if (launched) q ^= 1;
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (launched) {
+                S->st.rounds += 1;
+                S->st.peak_lanes = std::max(S->st.peak_lanes, (int32_t)lanes);
+            }
+            S->st.busy_s += seconds_since(S->t0) - ta;
         }
         serve_publish(S, out);
     }
@@ -2475,8 +2613,11 @@ extern "C" int pt_serve_start(const pt_serve_opts *o, pt_server **out)
         return fail(PT_EDEVICE, "no HIP device");
     }
     int rc = PT_OK;
-    if (hipSetDevice(S->device) != hipSuccess || hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess)
-        rc = fail(PT_EDEVICE, "stream creation failed");
+    if (hipSetDevice(S->device) != hipSuccess || hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&S->round_end[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&S->round_end[1], hipEventDisableTiming) != hipSuccess)
+        rc = fail(PT_EDEVICE, "stream or event creation failed");
     if (!rc) rc = serve_new_batch(S, &S->probe);
     if (rc) {
         delete S;

@@ -46,6 +46,8 @@ __global__ void finish_kernel(const WorkItem *items, const int *first_item, int 
     __shared__ int win;
     if (threadIdx.x == 0) {
         BestRec cb = *I.best;
+        // as the round's sweep launch saw it (chunk_cap)
+        const bool stopped = I.stop_at_hit && cb.first_hit >= 0;
         int wbest = -1;
         long long hit = -1;
         for (int w = 0; w < W; ++w) {
@@ -63,7 +65,8 @@ __global__ void finish_kernel(const WorkItem *items, const int *first_item, int 
         *I.best = cb;
         win = wbest;
         uint64_t t0 = *I.t;
-        uint64_t t1 = t0 + K < I.sweep_cap ? t0 + K : I.sweep_cap;
+        const uint64_t cap = stopped ? t0 : I.sweep_cap;
+        uint64_t t1 = t0 + K < cap ? t0 + K : cap;
         if (t0 < t1) *I.t = t1;
         if (status) {
             InstStatus st;

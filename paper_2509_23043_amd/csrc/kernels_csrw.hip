@@ -92,9 +92,12 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
     const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint64_t t0 = *I.t;
-    const uint64_t cap = I.sweep_cap;
+    const uint64_t cap = chunk_cap(I, t0);
     const uint64_t tend = (t0 + a.K < cap) ? t0 + a.K : cap;
-    if (t0 >= tend) return;
+    if (t0 >= tend) {
+        if (tid == 0) idle_best(it.best);
+        return;
+    }
     const int ncol = I.ncolors, ipl = (I.maxcnt + 63) / 64, ngr = ncol * ipl;
     const int SB = (n + 15) & ~15, nr = (n + 7) & ~7;
     const int spl = (n + 63) / 64;                            // sites per lane

@@ -111,9 +111,12 @@ __global__ void __launch_bounds__(512) pm_kernel(ChunkArgs a)
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int NWV = G / SPW;
     const uint64_t t0 = *I.t;
-    const uint64_t cap = I.sweep_cap;
+    const uint64_t cap = chunk_cap(I, t0);
     const uint64_t tend = (t0 + a.K < cap) ? t0 + a.K : cap;
-    if (t0 >= tend) return;
+    if (t0 >= tend) {
+        if (tid == 0) idle_best(it.best);
+        return;
+    }
     const Off lof = offsets(G, a.tsw_entries);
     uint8_t *bufs = (uint8_t *)(lds_raw + lof.buf);
     uint32_t *tabu = (uint32_t *)(lds_raw + lof.tabu);          // [G][8] threshold by U

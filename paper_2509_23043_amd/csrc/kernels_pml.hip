@@ -153,9 +153,12 @@ __device__ __forceinline__ void pml_body(const ChunkArgs a, const int item)
     const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint64_t t0 = *I.t;
-    const uint64_t cap = I.sweep_cap;
+    const uint64_t cap = chunk_cap(I, t0);
     const uint64_t tend = (t0 + a.K < cap) ? t0 + a.K : cap;
-    if (t0 >= tend) return;
+    if (t0 >= tend) {
+        if (tid == 0) idle_best(it.best);
+        return;
+    }
     const Off lof = offsets<L>(G, a.tsw_entries);
     uint8_t *bufs = (uint8_t *)(lds_raw + lof.buf);
     uint32_t *jn = (uint32_t *)(lds_raw + lof.jn);              // [NR][2 colours][NCH][6 directions]

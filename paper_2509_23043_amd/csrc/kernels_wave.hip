@@ -168,9 +168,12 @@ __global__ void __launch_bounds__(512) wave_kernel(ChunkArgs a)
     const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // storage of this wavefront
     const uint64_t t0 = *I.t;
-    const uint64_t cap = I.sweep_cap;
+    const uint64_t cap = chunk_cap(I, t0);
     const uint64_t tend = (t0 + a.K < cap) ? t0 + a.K : cap;
-    if (t0 >= tend) return;
+    if (t0 >= tend) {
+        if (tid == 0) idle_best(it.best);
+        return;
+    }
     const int stride = P.stride;
     const WaveOff lof = wave_lds_offsets(G, N, stride, a.tsw_entries);
     int8_t *sp = (int8_t *)(lds_raw + lof.sp);

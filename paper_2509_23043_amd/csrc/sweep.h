@@ -1578,9 +1578,12 @@ __device__ __forceinline__ void chunk_body(const ChunkArgs &a, const int item)
     const int G = it.G, s0 = it.s0, n = P.n;
     const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63;
     const uint64_t t0 = *I.t;
-    const uint64_t cap = I.sweep_cap;
+    const uint64_t cap = chunk_cap(I, t0);
     const uint64_t tend = (t0 + a.K < cap) ? t0 + a.K : cap;
-    if (t0 >= tend) return;
+    if (t0 >= tend) {
+        if (tid == 0) idle_best(it.best);
+        return;
+    }
 
     Sw sw;
     sw.setup(I, G);

@@ -60,6 +60,8 @@ struct InstDev {
     int32_t maxcnt, maxabsj;                // largest colour class (free sites); largest |J|
     int32_t csrw_chunks;                    // bond chunks of the packed rows of the one-slot-per-
                                             // wavefront sparse kernel (0: the graph does not fit it)
+    int32_t stop_at_hit;                    // 1: chunk launches sweep no more once the target is
+                                            // reached (serving requests)
     int64_t prop_start, prop_period, prop_stop;
     uint64_t sweep_cap;                     // batched runs stop at this sweep count
 
@@ -103,6 +105,25 @@ struct InstDev {
     BestRec *best;             // canonical record
     int8_t *best_spins;        // [n]
 };
+
+// The sweep count a chunk launch may take an instance to: its cap, or where it
+// stands if it stops at its target and has reached it (the canonical record
+// changes only in the finish kernel, so every launch of a round sees the same).
+__device__ inline uint64_t chunk_cap(const InstDev &I, uint64_t t0)
+{
+    return (I.stop_at_hit && I.best->first_hit >= 0) ? t0 : I.sweep_cap;
+}
+
+// The record of a workgroup that sweeps nothing in a launch: it merges as
+// nothing in the finish kernel (its buffer may hold another layout's record).
+__device__ inline void idle_best(BestRec *b)
+{
+    b->E = 0x7FFFFFFF;
+    b->slot = -1;
+    b->t = -1;
+    b->first_hit = -1;
+    b->pad = 0;
+}
 
 struct WorkItem {              // one workgroup of a persistent chunk launch
     const InstDev *inst;

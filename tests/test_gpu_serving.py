@@ -62,13 +62,17 @@ def _key(r):
     return (r["status"], r["hit"], r["first_hit"], r["best_energy"], r["best_slot"], r["best_t"], r["sweeps"])
 
 
-def test_serving_alone_vs_mix_and_oracle():
-    announce("serving: 14 mixed requests (EA L=4,6,8 + 4-bit factorization), alone vs mix vs oracle")
+@pytest.mark.parametrize("pipeline", [False, True])
+def test_serving_alone_vs_mix_and_oracle(pipeline):
+    """The mix one round at a time and pipelined (each round enqueued before
+    the last is retired: finished requests ride along as no-ops)."""
+    announce(f"serving: 14 mixed requests (EA L=4,6,8 + 4-bit factorization), alone vs mix vs oracle, "
+             f"pipeline={pipeline}")
     pool = _problems()
     rqs = _requests()
     K = 100
     # the mix: everything submitted at once
-    srv = binding.Server(chunk_sweeps=K)
+    srv = binding.Server(chunk_sweeps=K, pipeline=pipeline)
     ids, _ctxs = _register(srv, pool)
     sub = {}
     for j, (p, seed, cap, with_t) in enumerate(rqs):
@@ -141,15 +145,15 @@ def test_serving_memory_admission():
 def test_serving_lanes_overflow():
     """More requests of one kind than one co-resident launch holds: 40 +-J
     L = 6 lattices of 64 slots (8 workgroups of the row kernel each) are
-    admitted together and run in several lanes per round; every result equals
-    the oracle's."""
+    admitted together and run in several lanes per round, pipelined; every
+    result equals the oracle's."""
     announce("serving: 40 requests of L=6 R=64 over several launch lanes, 3 checked against the oracle")
     g = inputs.ea_lattice(6, 640)
     b = inputs.geometric_ladder(64)
     banks = {r: inputs.random_bank(g["n"], 4, seed=960 + r) for r in range(0, 60, 4)}
     kw = dict(prop_start=20, prop_period=20)
     K, cap = 50, 150
-    srv = binding.Server(chunk_sweeps=K)
+    srv = binding.Server(chunk_sweeps=K, pipeline=True)
     ctx = binding.Context(g, b, seed=0, **kw)
     for r, bank in banks.items():
         ctx.propose(r, bank)
