@@ -30,8 +30,8 @@
 // buffers. A pair that spans two wavefronts meets in an LDS mailbox carrying
 // the energy and the buffer index, and an accepted swap (Eq. 1) trades buffer
 // indices. A pair across a workgroup boundary exchanges cycle-tagged words
-// through global memory (the state as bits, one ballot per row block and x,
-// and the energy) and copies the state on acceptance. Proposals (Eq. 2) read
+// through global memory (the state as bits, each lane its own rows, and the
+// energy) and copies the state on acceptance. Proposals (Eq. 2) read
 // the bank configuration into the slot's buffer. Best energy, first hit and
 // every counter are per slot and live in registers.
 #include "sweep.h"
@@ -53,7 +53,11 @@ struct Geo {
     static constexpr int RPL = (NR + 63) / 64;       // rows per lane
     static constexpr int SBUF = NR * RB;             // bytes per state buffer
     static constexpr int JW = 2 * NCH * 6;           // bond-sign words per row
-    static constexpr int NXW = 2 * RPL * L;          // exchange words of a state, before the energy word
+    // A state crosses a workgroup boundary as XW words per lane (lane q's
+    // rows, RB bits each: bit x of row j at bit RB j + x of its bit stream),
+    // word k of lane q at q + 64 k; the energy word follows at NXW.
+    static constexpr int XW = (RPL * RB + 31) / 32;
+    static constexpr int NXW = 64 * XW;
     // A row's first site L r sits at half (L r) mod 8 of Philox call (L r) / 8;
     // L is even, so that offset is a whole 32-bit word, TOFF words at most,
     // and the row's uniforms are NCALL consecutive calls' words from there.
@@ -76,7 +80,7 @@ __device__ __forceinline__ uint32_t sel_fhi(int p) { return p ? 0x030c020cu : 0x
 
 // LDS carve-up of one workgroup of G slots of an L^3 lattice
 struct Off {
-    size_t buf, jn, tabu, toff, tsw, mail, xst, total;
+    size_t buf, jn, tabu, toff, tsw, mail, total;
 };
 
 template <int L>
@@ -91,7 +95,6 @@ __host__ __device__ inline Off offsets(int G, int tsw_entries)
     f.toff = o; o = align16(o + (size_t)(G + 2) * 4);
     f.tsw = o; o = align16(o + (size_t)tsw_entries * 4);
     f.mail = o; o = align16(o + (size_t)4 * G * 8);
-    f.xst = o; o = align16(o + (size_t)2 * G * (Gm::NXW + 1) * 4);
     f.total = o;
     return f;
 }
@@ -166,7 +169,6 @@ __device__ __forceinline__ void pml_body(const ChunkArgs a, const int item)
     int *tsw_off = (int *)(lds_raw + lof.toff);
     uint32_t *tsw = (uint32_t *)(lds_raw + lof.tsw);
     unsigned long long *mail = (unsigned long long *)(lds_raw + lof.mail);   // [4][G]
-    uint32_t *xstage = (uint32_t *)(lds_raw + lof.xst);         // [G][2 sides][NXW + 1]
 
     // ---- stage: states as down-bits in row layout (slot l in buffer l), bond signs, tables ----
     for (int x = tid; x < G * SBUF / 4; x += bs) ((uint32_t *)bufs)[x] = 0u;
@@ -481,21 +483,19 @@ __device__ __forceinline__ void pml_body(const ChunkArgs a, const int item)
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 const int buf_x = (cyc >> 1) & 1;
                 if (cross) {
-                    // the state as bits: word 2 (j L + x) + h holds bit (lane - 32 h) =
-                    // down-bit of site x of row lane + 64 j, for the lanes 32 h .. 32 h + 31;
-                    // word NXW the energy. Lane w % 64 stores word w.
+                    // the state as bits, each lane its own rows: a row's down-bytes
+                    // (0 or 1) fold four at a time into bits by a dot product with
+                    // 1, 2, 4, 8 (bit x of the row is site x)
                     unsigned long long *out = it.xbuf + ((size_t)(it.w * 2 + side) * 2 + buf_x) * it.xwords;
-                    uint32_t pay[3] = {0u, 0u, 0u};
-                    // the lane index made opaque here: otherwise the compiler keeps
-                    // every lane mask lane == w % 64 in SGPRs for the whole launch
-                    const int ln = (int)opaque((uint32_t)lane);
+                    uint32_t pay[Gm::XW];
+#pragma unroll
+                    for (int k = 0; k < Gm::XW; ++k) pay[k] = 0u;
 #pragma unroll
                     for (int j = 0; j < RPL; ++j) {
                         const int r = lane + 64 * j;
-                        uint32_t o[NW];
-#pragma unroll
-                        for (int w = 0; w < NW; ++w) o[w] = 0;
+                        uint32_t bits = 0;
                         if (NR % 64 == 0 || r < NR) {
+                            uint32_t o[NW];
                             if constexpr (NW == 2) {
                                 const uint2 v = *(const uint2 *)(bufs + buf * SBUF + r * RB);
                                 o[0] = v.x; o[1] = v.y;
@@ -503,21 +503,17 @@ __device__ __forceinline__ void pml_body(const ChunkArgs a, const int item)
                                 const uint4 v = *(const uint4 *)(bufs + buf * SBUF + r * RB);
                                 o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
                             }
-                        }
 #pragma unroll
-                        for (int x = 0; x < L; ++x) {
-                            const unsigned long long bal = __ballot(((o[x >> 2] >> (8 * (x & 3))) & 1u) != 0);
-                            const int w = 2 * (j * L + x);
-                            pay[w >> 6] = ln == (w & 63) ? (uint32_t)bal : pay[w >> 6];
-                            pay[(w + 1) >> 6] = ln == ((w + 1) & 63) ? (uint32_t)(bal >> 32) : pay[(w + 1) >> 6];
+                            for (int w = 0; w < NW; ++w) bits |= __builtin_amdgcn_udot4(o[w], 0x08040201u, 0u, false) << (4 * w);
                         }
+                        pay[(j * RB) >> 5] |= bits << ((j * RB) & 31);
                     }
-                    pay[NXW >> 6] = ln == (NXW & 63) ? (uint32_t)E : pay[NXW >> 6];
+                    const unsigned long long tg = (unsigned long long)cyc << 32;
 #pragma unroll
-                    for (int k = 0; k < 3; ++k)
-                        if (lane + 64 * k <= NXW)
-                            __hip_atomic_store(out + lane + 64 * k, ((unsigned long long)cyc << 32) | pay[k],
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    for (int k = 0; k < Gm::XW; ++k)
+                        __hip_atomic_store(out + lane + 64 * k, tg | pay[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (lane == 0)
+                        __hip_atomic_store(out + NXW, tg | (uint32_t)E, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
                 if (intra) {
                     uint32_t polls = 0;
@@ -553,23 +549,21 @@ __device__ __forceinline__ void pml_body(const ChunkArgs a, const int item)
                 if (cross && !failed) {
                     const int pw = lower ? it.w + 1 : it.w - 1;
                     const unsigned long long *in = it.xbuf + ((size_t)(pw * 2 + (1 - side)) * 2 + buf_x) * it.xwords;
-                    uint32_t *stage = xstage + (size_t)(wv * 2 + side) * (NXW + 1);
+                    uint32_t got[Gm::XW + 1];   // this lane's words, and the energy (lane 0)
                     uint32_t polls = 0;
                     bool ok_all = false;
                     unsigned long long bad = 0;
                     for (;;) {
                         bool ok = true;
 #pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            const int w = lane + 64 * k;
-                            if (w <= NXW) {
-                                const unsigned long long v =
-                                    __hip_atomic_load(in + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                if ((uint32_t)(v >> 32) == cyc) stage[w] = (uint32_t)v;
-                                else {
-                                    ok = false;
-                                    bad = v;
-                                }
+                        for (int k = 0; k <= Gm::XW; ++k) {
+                            if (k == Gm::XW && lane != 0) continue;
+                            const unsigned long long v = __hip_atomic_load(in + (k == Gm::XW ? NXW : lane + 64 * k),
+                                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            if ((uint32_t)(v >> 32) == cyc) got[k] = (uint32_t)v;
+                            else {
+                                ok = false;
+                                bad = v;
                             }
                         }
                         if (__all(ok)) {
@@ -585,9 +579,7 @@ __device__ __forceinline__ void pml_body(const ChunkArgs a, const int item)
                         }
                         failed = true;
                     } else {
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        const int pE = __builtin_amdgcn_readfirstlane((int)stage[NXW]);
+                        const int pE = __builtin_amdgcn_readfirstlane((int)got[Gm::XW]);
                         const int dEs = lower ? pE - E : E - pE;
                         const bool okx = swap_ok(dEs, __builtin_amdgcn_readlane(u_vec, NP * (cyc - u_base) + pi),
                                                  __builtin_amdgcn_readlane(row_off_v, pi),
@@ -598,17 +590,17 @@ __device__ __forceinline__ void pml_body(const ChunkArgs a, const int item)
                         }
                         E = okx ? pE : E;
                         if (okx) {
-                            const int h = lane >> 5, bit = lane & 31;
+                            // bits back to down-bytes: a nibble times 1 + 2^7 + 2^14 + 2^21
+                            // puts bit i at bit 8 i (the copies do not overlap)
 #pragma unroll
                             for (int j = 0; j < RPL; ++j) {
                                 const int r = lane + 64 * j;
                                 if (NR % 64 != 0 && r >= NR) continue;
+                                const uint32_t bits = got[(j * RB) >> 5] >> ((j * RB) & 31);
                                 uint32_t o[NW];
 #pragma unroll
-                                for (int w = 0; w < NW; ++w) o[w] = 0;
-#pragma unroll
-                                for (int x = 0; x < L; ++x)
-                                    o[x >> 2] |= ((stage[2 * (j * L + x) + h] >> bit) & 1u) << (8 * (x & 3));
+                                for (int w = 0; w < NW; ++w)
+                                    o[w] = (((bits >> (4 * w)) & 15u) * 0x00204081u) & 0x01010101u;
                                 if constexpr (NW == 2) *(uint2 *)(bufs + buf * SBUF + r * RB) = make_uint2(o[0], o[1]);
                                 else *(uint4 *)(bufs + buf * SBUF + r * RB) = make_uint4(o[0], o[1], o[2], o[3]);
                             }
@@ -742,7 +734,12 @@ size_t pml_lds_bytes(int L, int G, int tsw_entries)
 }
 
 // 64-bit exchange words of one state (bits and energy)
-int pml_xwords(int L) { return 2 * ((L * L + 63) / 64) * L + 1; }
+// 64-bit exchange words of one state: XW per lane and the energy
+int pml_xwords(int L)
+{
+    const int rpl = (L * L + 63) / 64, rb = L <= 8 ? 8 : 16;
+    return 64 * ((rpl * rb + 31) / 32) + 1;
+}
 
 hipError_t launch_pml(const ChunkArgs &a, int block, size_t lds, hipStream_t s)
 {
