@@ -321,43 +321,70 @@ __device__ __forceinline__ void pml_body(const ChunkArgs a, const int item)
             int nf = 0, su = 0;
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-#pragma unroll
-                for (int j = 0; j < RPL; ++j) {
+                // a row's reads (its own row, the four y and z neighbour rows, its
+                // bond-sign words): issued for row j + 1 before row j is decided and
+                // written back, which they never alias (row j + 1's neighbours are
+                // rows r + 64 +- 1 and +- L, none of them r)
+                struct RowIn {
+                    uint32_t o[NW], yp[NW], ym[NW], zp[NW], zm[NW], jw[NCH * 6];
+                };
+                auto row_in = [&](int j, RowIn &v) {
                     const int r = lane + 64 * j;
-                    if (NR % 64 != 0 && r >= NR) continue;
+                    if (NR % 64 != 0 && r >= NR) return;
                     const int y = r % L, z = r / L;
-                    const int p = (c + y + z) & 1;
                     const uint32_t a_me = B + r * RB;
                     const uint32_t a_yp = B + (((y + 1) % L) + L * z) * RB, a_ym = B + (((y + L - 1) % L) + L * z) * RB;
                     const uint32_t a_zp = B + (y + L * ((z + 1) % L)) * RB, a_zm = B + (y + L * ((z + L - 1) % L)) * RB;
-                    uint32_t o[NW], yp[NW], ym[NW], zp[NW], zm[NW], rw[2 * NW], jw[NCH * 6];
-#pragma unroll
-                    for (int k = 0; k < RB / 2; ++k) rw[k] = rwr[j][k];
                     if constexpr (NW == 2) {
                         const uint2 v0 = *(const uint2 *)(bufs + a_me), v1 = *(const uint2 *)(bufs + a_yp);
                         const uint2 v2 = *(const uint2 *)(bufs + a_ym), v3 = *(const uint2 *)(bufs + a_zp);
                         const uint2 v4 = *(const uint2 *)(bufs + a_zm);
-                        o[0] = v0.x; o[1] = v0.y; yp[0] = v1.x; yp[1] = v1.y; ym[0] = v2.x; ym[1] = v2.y;
-                        zp[0] = v3.x; zp[1] = v3.y; zm[0] = v4.x; zm[1] = v4.y;
+                        v.o[0] = v0.x; v.o[1] = v0.y; v.yp[0] = v1.x; v.yp[1] = v1.y; v.ym[0] = v2.x; v.ym[1] = v2.y;
+                        v.zp[0] = v3.x; v.zp[1] = v3.y; v.zm[0] = v4.x; v.zm[1] = v4.y;
                     } else {
                         const uint4 v0 = *(const uint4 *)(bufs + a_me), v1 = *(const uint4 *)(bufs + a_yp);
                         const uint4 v2 = *(const uint4 *)(bufs + a_ym), v3 = *(const uint4 *)(bufs + a_zp);
                         const uint4 v4 = *(const uint4 *)(bufs + a_zm);
-                        o[0] = v0.x; o[1] = v0.y; o[2] = v0.z; o[3] = v0.w;
-                        yp[0] = v1.x; yp[1] = v1.y; yp[2] = v1.z; yp[3] = v1.w;
-                        ym[0] = v2.x; ym[1] = v2.y; ym[2] = v2.z; ym[3] = v2.w;
-                        zp[0] = v3.x; zp[1] = v3.y; zp[2] = v3.z; zp[3] = v3.w;
-                        zm[0] = v4.x; zm[1] = v4.y; zm[2] = v4.z; zm[3] = v4.w;
+                        v.o[0] = v0.x; v.o[1] = v0.y; v.o[2] = v0.z; v.o[3] = v0.w;
+                        v.yp[0] = v1.x; v.yp[1] = v1.y; v.yp[2] = v1.z; v.yp[3] = v1.w;
+                        v.ym[0] = v2.x; v.ym[1] = v2.y; v.ym[2] = v2.z; v.ym[3] = v2.w;
+                        v.zp[0] = v3.x; v.zp[1] = v3.y; v.zp[2] = v3.z; v.zp[3] = v3.w;
+                        v.zm[0] = v4.x; v.zm[1] = v4.y; v.zm[2] = v4.z; v.zm[3] = v4.w;
                     }
-                    {
-                        const uint32_t *js = jn + r * JW + c * NCH * 6;
+                    const uint32_t *js = jn + r * JW + c * NCH * 6;
 #pragma unroll
-                        for (int q = 0; q < NCH * 6; q += 2) {
-                            const uint2 v = *(const uint2 *)(js + q);
-                            jw[q] = v.x;
-                            jw[q + 1] = v.y;
-                        }
+                    for (int q = 0; q < NCH * 6; q += 2) {
+                        const uint2 w = *(const uint2 *)(js + q);
+                        v.jw[q] = w.x;
+                        v.jw[q + 1] = w.y;
                     }
+                };
+                RowIn nxt;
+                row_in(0, nxt);
+#pragma unroll
+                for (int j = 0; j < RPL; ++j) {
+                    const int r = lane + 64 * j;
+                    if (NR % 64 != 0 && r >= NR) continue;
+                    const RowIn cur = nxt;
+                    if (j + 1 < RPL) row_in(j + 1, nxt);
+                    // keep the scheduler from sinking those reads below row j's work
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int y = r % L, z = r / L;
+                    const int p = (c + y + z) & 1;
+                    const uint32_t a_me = B + r * RB;
+                    uint32_t o[NW], yp[NW], ym[NW], zp[NW], zm[NW], rw[2 * NW], jw[NCH * 6];
+#pragma unroll
+                    for (int k = 0; k < RB / 2; ++k) rw[k] = rwr[j][k];
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        o[w] = cur.o[w];
+                        yp[w] = cur.yp[w];
+                        ym[w] = cur.ym[w];
+                        zp[w] = cur.zp[w];
+                        zm[w] = cur.zm[w];
+                    }
+#pragma unroll
+                    for (int q = 0; q < NCH * 6; ++q) jw[q] = cur.jw[q];
                     uint32_t xp[NW], xm[NW];
                     rotate_row<L>(o, xp, xm);
                     const uint32_t S = sel_sites(p), Hp = sel_pair(p);
