@@ -224,7 +224,7 @@ typedef struct {
                                         it and not all are 8^3 lattices (those take 3),
                                         else the other kernels;
                                     8 = general graphs, one slot per wavefront (n <= 4095,
-                                        |J| <= 7, degree <= 64, colour classes of at most
+                                        |J| <= 127, degree <= 64, colour classes of at most
                                         256 sites, at most 64 groups of 64 sites of one
                                         class), at most 8 slots per workgroup; 0 takes 8
                                         where every context fits it */

@@ -8,9 +8,11 @@
 // Sweep. Lane q takes the sites of rank q, q + 64, ... of every colour class
 // (Methods, Graph coloring). Their rows are packed once per launch in LDS,
 // shared by the workgroup's slots of the instance: record (c, s) holds the
-// s-th site of class c with h_i, and its bonds as 16-bit words (neighbour in
-// bits 0-11, J in bits 12-15; unused words 0: site 0 with J = 0) in chunks of
-// CSRW_CHUNK words. The 64 sites of a rank group (c, k) take the chunks their
+// s-th site of class c with h_i, and its bonds in chunks of CSRW_CHUNK: the
+// neighbours as 16-bit words and the couplings as bytes (unused bonds: site
+// 0 with J = 0). A neighbour's LDS address is one add of a 16-bit half to the
+// slot's base, and four spins packed by v_perm meet their four couplings in
+// one 8-bit dot product. The 64 sites of a rank group (c, k) take the chunks their
 // largest degree needs; within a class the host orders sites by degree, so
 // the few high-degree sites of a circuit (a multiplier's input bits) share
 // groups and the rest take one chunk. A lane reads the next item's first two
@@ -35,7 +37,7 @@ namespace csrw {
 constexpr int MAXG = 8;   // slots (wavefronts) per workgroup
 
 struct Off {
-    size_t sp, rnd, bw, info, tab, toff, tsw, mail, xst, total;
+    size_t sp, rnd, bw, bj, info, tab, toff, tsw, mail, xst, total;
 };
 
 // n sites, ncolors classes of at most ipl * 64 sites, chunks bond chunks, G slots
@@ -49,6 +51,7 @@ __host__ __device__ inline Off offsets(int n, int ncolors, int ipl, int chunks, 
     f.sp = o; o = align16(o + (size_t)G * SB);
     f.rnd = o; o = align16(o + (size_t)G * nr * 2);
     f.bw = o; o = align16(o + (size_t)chunks * 64 * 16);
+    f.bj = o; o = align16(o + (size_t)chunks * 64 * 8);
     f.info = o; o = align16(o + nrec * 4);
     f.tab = o; o = align16(o + (size_t)G * stride * 4);
     f.toff = o; o = align16(o + (size_t)(G + 2) * 4);
@@ -63,6 +66,13 @@ struct Rec {
     int E, slot;
     long long t, hit;
 };
+
+// The low bytes of four values (spins +-1) as one word, a in byte 0.
+__device__ __forceinline__ uint32_t pack4(int a, int b, int c, int d)
+{
+    return __builtin_amdgcn_perm((uint32_t)b, (uint32_t)a, 0x0c0c0400u) |
+           (__builtin_amdgcn_perm((uint32_t)d, (uint32_t)c, 0x0c0c0400u) << 16);
+}
 
 // Swap acceptance (Eq. 1) for dE = E_{r+1} - E_r with the pair's LDS table
 // row (off, len); every input is wave-uniform and the result is a scalar.
@@ -107,7 +117,8 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
     const Off lof = offsets(n, ncol, ipl, I.csrw_chunks, G, stride, a.tsw_entries);
     int8_t *sp = (int8_t *)(lds_raw + lof.sp);                 // [G][SB] spins +-1, site order
     uint16_t *rnd = (uint16_t *)(lds_raw + lof.rnd);          // [G][nr] sweep uniforms (upper halves)
-    uint4 *bw = (uint4 *)(lds_raw + lof.bw);                  // [chunks][64] bond words, CSRW_CHUNK per chunk
+    uint4 *bw = (uint4 *)(lds_raw + lof.bw);                  // [chunks][64] neighbours, CSRW_CHUNK 16-bit words
+    uint2 *bj = (uint2 *)(lds_raw + lof.bj);                  // [chunks][64] couplings, CSRW_CHUNK bytes
     uint32_t *info = (uint32_t *)(lds_raw + lof.info);        // [ncol][64 ipl] site | h << 16; 0xFFF: none
     uint32_t *tab = (uint32_t *)(lds_raw + lof.tab);          // [G][stride] flip thresholds
     int *tsw_off = (int *)(lds_raw + lof.toff);
@@ -135,12 +146,16 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
             inf = (uint32_t)i | ((uint32_t)(uint16_t)I.h[i] << 16);
         }
         for (int j = 0; j < nch; ++j) {
-            uint32_t w[4] = {0, 0, 0, 0};
+            uint32_t w[4] = {0, 0, 0, 0}, jv[2] = {0, 0};
             for (int b = 0; b < CSRW_CHUNK; ++b) {
                 const int e = e0 + CSRW_CHUNK * j + b;
-                if (e < e1) w[b >> 1] |= ((uint32_t)I.col[e] | (((uint32_t)I.Jc[e] & 15u) << 12)) << (16 * (b & 1));
+                if (e < e1) {
+                    w[b >> 1] |= (uint32_t)(uint16_t)I.col[e] << (16 * (b & 1));
+                    jv[b >> 2] |= (uint32_t)(uint8_t)I.Jc[e] << (8 * (b & 3));
+                }
             }
             bw[(cb + j) * 64 + q] = make_uint4(w[0], w[1], w[2], w[3]);
+            bj[(cb + j) * 64 + q] = make_uint2(jv[0], jv[1]);
         }
         info[x] = inf;
     }
@@ -220,6 +235,8 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
             int gcb = __builtin_amdgcn_readfirstlane(gcb_v);
             uint4 b0 = bw[(gcb >> 8) * 64 + lane];
             uint4 b1 = (gcb & 255) > 1 ? bw[((gcb >> 8) + 1) * 64 + lane] : make_uint4(0u, 0u, 0u, 0u);
+            uint2 j0 = bj[(gcb >> 8) * 64 + lane];
+            uint2 j1 = (gcb & 255) > 1 ? bj[((gcb >> 8) + 1) * 64 + lane] : make_uint2(0u, 0u);
             uint32_t inf = info[lane];
             // ---- the sweep's uniforms, staged in site order ----
             for (int q = lane; q < nr / 8; q += 64) {
@@ -238,11 +255,14 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                     const uint32_t ci = inf;
                     const int cb = gcb >> 8, nch = gcb & 255;
                     const uint32_t ws[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+                    const uint32_t jz[4] = {j0.x, j0.y, j1.x, j1.y};
                     // the next group's first chunks, in flight while this one is decided
                     if (g + 1 < ngr) {
                         gcb = __builtin_amdgcn_readlane(gcb_v, g + 1);
                         b0 = bw[(gcb >> 8) * 64 + lane];
                         b1 = (gcb & 255) > 1 ? bw[((gcb >> 8) + 1) * 64 + lane] : make_uint4(0u, 0u, 0u, 0u);
+                        j0 = bj[(gcb >> 8) * 64 + lane];
+                        j1 = (gcb & 255) > 1 ? bj[((gcb >> 8) + 1) * 64 + lane] : make_uint2(0u, 0u);
                         inf = info[(g + 1) * 64 + lane];
                     }
                     const int i = (int)(ci & 0xFFFu);
@@ -255,26 +275,32 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                         if (i == 0xFFF) return;
                         const int m = m_w[i];
                         const uint32_t hs = (uint32_t)rnd_w[i] << 16;
-                        int v[8 * NC];                      // 4 words of 2 bonds per chunk
+                        int v[8 * NC];                      // 4 words of 2 neighbours per chunk
 #pragma unroll
                         for (int q = 0; q < 4 * NC; ++q) {
-                            v[2 * q] = m_w[ws[q] & 0xFFFu];
-                            v[2 * q + 1] = m_w[(ws[q] >> 16) & 0xFFFu];
+                            v[2 * q] = m_w[ws[q] & 0xFFFFu];
+                            v[2 * q + 1] = m_w[ws[q] >> 16];
                         }
                         // keep the scheduler from splitting the reads around a wait
                         __builtin_amdgcn_sched_barrier(0);
                         int f = (int)ci >> 16;
 #pragma unroll
-                        for (int q = 0; q < 4 * NC; ++q)
-                            f += ((int)(ws[q] << 16) >> 28) * v[2 * q] + ((int)ws[q] >> 28) * v[2 * q + 1];
+                        for (int q = 0; q < 2 * NC; ++q)
+                            f = __builtin_amdgcn_sdot4((int)pack4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]),
+                                                       (int)jz[q], f, false);
                         // chunks past the second: the rare high-degree groups
                         for (int j = 2; j < nch; ++j) {
-                            const uint4 bj = bw[(cb + j) * 64 + lane];
-                            const uint32_t wj[4] = {bj.x, bj.y, bj.z, bj.w};
+                            const uint4 wc = bw[(cb + j) * 64 + lane];
+                            const uint2 jc = bj[(cb + j) * 64 + lane];
+                            const uint32_t wj[4] = {wc.x, wc.y, wc.z, wc.w};
+                            int u[8];
 #pragma unroll
-                            for (int q = 0; q < 4; ++q)
-                                f += ((int)(wj[q] << 16) >> 28) * (int)m_w[wj[q] & 0xFFFu] +
-                                     ((int)wj[q] >> 28) * (int)m_w[(wj[q] >> 16) & 0xFFFu];
+                            for (int q = 0; q < 4; ++q) {
+                                u[2 * q] = m_w[wj[q] & 0xFFFFu];
+                                u[2 * q + 1] = m_w[wj[q] >> 16];
+                            }
+                            f = __builtin_amdgcn_sdot4((int)pack4(u[0], u[1], u[2], u[3]), (int)jc.x, f, false);
+                            f = __builtin_amdgcn_sdot4((int)pack4(u[4], u[5], u[6], u[7]), (int)jc.y, f, false);
                         }
                         const int d = m * f;
                         const uint32_t T = tab_w[d];
@@ -545,12 +571,12 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
 
 int csrw_max_storages() { return csrw::MAXG; }
 
-// where the kernel applies: n <= 4095, |J| <= 7, classes of at most 256 sites,
+// where the kernel applies: n <= 4095, |J| <= 127, classes of at most 256 sites,
 // and the host packed the rows (chunks > 0: degree <= CSRW_MAXDEG, at most
 // CSRW_MAXGROUPS rank groups)
 bool csrw_supported(int n, int maxabsj, int chunks, int maxcnt)
 {
-    return n >= 1 && n <= 4095 && maxabsj <= 7 && chunks > 0 && maxcnt >= 1 && maxcnt <= 256;
+    return n >= 1 && n <= 4095 && maxabsj <= 127 && chunks > 0 && maxcnt >= 1 && maxcnt <= 256;
 }
 
 size_t csrw_lds_bytes(int n, int ncolors, int maxcnt, int chunks, int G, int stride, int tsw_entries)

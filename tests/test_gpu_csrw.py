@@ -6,7 +6,7 @@ import pytest
 
 from paper_2509_23043_amd import binding, inputs
 from tests.gpu_util import announce
-from tests.test_gpu_row_sweeper import _random_graph, _run_and_compare
+from tests.test_gpu_row_sweeper import _pad_isolated, _random_graph, _run_and_compare
 
 pytestmark = pytest.mark.gpu
 
@@ -36,28 +36,32 @@ def test_multipliers_csrw(m, R, G):
     _run_and_compare(probs, inputs.geometric_ladder(R), G, 120, expect="-", kernel="csrw")
 
 
-@pytest.mark.parametrize("seed,hubs", [(1, 0), (2, 0), (3, 4)])
-def test_random_graphs_csrw(seed, hubs):
-    """Random sparse graphs with |J| up to 7, fields, clamped sites and DSATUR
-    colourings, 6 slots per workgroup: degree <= 16, and with hub sites of
-    degree above 16 (up to four bond chunks)."""
-    probs = [_random_graph(150, 6600 + 10 * seed + k, hubs=hubs) for k in range(2)]
+@pytest.mark.parametrize("seed,hubs,jmax", [(1, 0, 7), (2, 0, 7), (3, 4, 7), (4, 3, 40)])
+def test_random_graphs_csrw(seed, hubs, jmax):
+    """Random sparse graphs with fields, clamped sites and DSATUR colourings,
+    6 slots per workgroup: |J| up to 7 and degree <= 16; hub sites of degree
+    above 16 (up to four bond chunks); couplings up to 40 (bytes in the dot
+    products)."""
+    probs = [_random_graph(150, 6600 + 10 * seed + k, hubs=hubs, jmax=jmax) for k in range(2)]
     for g in probs:
         dmax = np.diff(g["row_ptr"])[g["clamp"] == 0].max()
         assert (dmax <= 16) if hubs == 0 else (16 < dmax <= 64), dmax
-    announce(f"csrw: random graphs n=150 seed={seed} hubs={hubs}, colours {[int(g['color'].max()) + 1 for g in probs]}")
+        assert np.abs(g["J"]).max() <= jmax
+    announce(f"csrw: random graphs n=150 seed={seed} hubs={hubs} |J|<={jmax}, "
+             f"colours {[int(g['color'].max()) + 1 for g in probs]}")
     _run_and_compare(probs, inputs.geometric_ladder(12), 6, 150, expect="-", kernel="csrw")
 
 
 def test_csrw_independent_chains_and_refusal():
-    """Independent chains (M = 0); a graph with |J| = 9 is refused."""
-    announce("csrw: independent chains, 2 x 8-bit multipliers, R=16 G=8; refusal at |J| = 9")
+    """Independent chains (M = 0); a graph with a colour class of more than
+    256 sites is refused."""
+    announce("csrw: independent chains, 2 x 8-bit multipliers, R=16 G=8; refusal at a class of 300+ sites")
     probs = [inputs.multiplier(8, C) for C, _, _ in inputs.semiprimes(8, 2, seed=6700)]
     _run_and_compare(probs, np.full(16, 1.3), 8, 100, M=0, expect="-", kernel="csrw")
-    g9 = _random_graph(120, 6710, hubs=0, jmax=9)
-    assert np.abs(g9["J"]).max() == 9
-    c = binding.Context(g9, inputs.geometric_ladder(8), seed=1)
-    bt = binding.Batch([c], replicas_per_wg=4, kernel="csrw")   # falls back: |J| > 7
+    big = _pad_isolated(_random_graph(120, 6710, hubs=0), 280)
+    assert np.bincount(big["color"][big["clamp"] == 0]).max() > 256
+    c = binding.Context(big, inputs.geometric_ladder(8), seed=1)
+    bt = binding.Batch([c], replicas_per_wg=4, kernel="csrw")   # falls back: a class of more than 256 sites
     assert [d["kernel"] for d in bt.describe()] != ["csrw"], bt.describe()
     bt.close()
     c.close()

@@ -129,11 +129,12 @@ def test_runtime_sparse_sweeper_choice():
     multipliers (auto; the 10-bit one has sites of degree 20); the one-storage
     rows for a graph with a colour class of more than 256 sites where a site's
     bound exceeds 255 (a field of 250); the four-storages-per-lane LDS sweeper
-    where no packed rows fit a block (|J| = 9, a large colour class, 20 slots
-    per workgroup); the LDS-resident CSR sweepers when the caller asks for the
-    workgroup-synchronous kernel (the lane-sharing one at 512 threads for 2
-    slots per workgroup); and a coupling of 9 refused by the one-storage rows
-    and run in the four-storage rows."""
+    where no packed rows fit a block (|J| = 9, a colour class of more than 256
+    sites, 20 slots per workgroup); the LDS-resident CSR sweepers when the
+    caller asks for the workgroup-synchronous kernel (the lane-sharing one at
+    512 threads for 2 slots per workgroup); and a coupling of 9 refused by the
+    one-storage rows and run in the four-storage rows (with a class of more
+    than 256 sites)."""
     announce("sparse sweeper choice: csrw / row / quad / csr / csr-wide / row4, refusal")
     mult = [inputs.multiplier(8, C) for C, _, _ in inputs.semiprimes(8, 1, seed=6400)]
     plan = _run_and_compare(mult, inputs.geometric_ladder(32), 8, 60, expect="-", kernel="auto")
@@ -147,7 +148,8 @@ def test_runtime_sparse_sweeper_choice():
     big = _pad_isolated(big, 260)
     assert np.bincount(big["color"][big["clamp"] == 0]).max() > 256
     _run_and_compare([big], inputs.geometric_ladder(8), 1, 60, expect="csr-row", kernel="auto")
-    g9q = _pad_isolated(_random_graph(100, 6460, hubs=0, jmax=9), 120)
+    g9q = _pad_isolated(_random_graph(100, 6460, hubs=0, jmax=9), 240)
+    assert np.bincount(g9q["color"][g9q["clamp"] == 0]).max() > 256
     _run_and_compare([g9q], inputs.geometric_ladder(20), 20, 40, expect="csr-quad", kernel="auto")
     _run_and_compare(mult, inputs.geometric_ladder(16), 4, 60, expect="csr", kernel="block")
     _run_and_compare(mult, inputs.geometric_ladder(16), 2, 60, expect="csr-wide", kernel="block")
@@ -156,4 +158,6 @@ def test_runtime_sparse_sweeper_choice():
     with pytest.raises(binding.TaptError):
         binding.Batch([c], replicas_per_wg=4, kernel="row")
     c.close()
-    _run_and_compare([g9], inputs.geometric_ladder(8), 4, 60, expect="csr-row4", kernel="auto")   # |J| = 9
+    g9p = _pad_isolated(g9, 260)   # a class of more than 256 sites: not the one-slot-per-wavefront kernel
+    assert np.bincount(g9p["color"][g9p["clamp"] == 0]).max() > 256
+    _run_and_compare([g9p], inputs.geometric_ladder(8), 4, 60, expect="csr-row4", kernel="auto")   # |J| = 9
