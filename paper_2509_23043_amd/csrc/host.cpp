@@ -2124,6 +2124,8 @@ struct SrvActive {
     int lane;                         // the launch lane it runs in
     int cur;                          // its index in that lane's launch group as last built
     int slot[2];                      // its index in the round of each parity (-1: not in it)
+    int lane_at[2];                   // its lane in the round of each parity
+    int pace;                         // rank groups per sweep (sparse one-slot-per-wavefront requests), else 0
 };
 
 // A launch lane of a server: a batch over some of the running requests whose
@@ -2135,6 +2137,7 @@ struct SrvLane {
     pt_batch *b = nullptr;
     std::string ident;                // kernel and sweeper of its launch (group_identity)
     int members = 0;
+    int pace = -2;                    // its members' pace (SrvActive::pace); -1 mixed, -2 none yet
     bool dirty = false;               // membership changed since the last build
     std::set<std::string> full_for;   // request kinds it had no room for (cleared when one leaves)
     // by round parity: status records and error flag copied after its launch,
@@ -2295,25 +2298,38 @@ static std::string serve_solo(pt_server *S, int p, int &rc)
     return S->solo[p];
 }
 
-// The lane a request of template tm joins: the first lane of its kind whose
-// launch keeps its kernel and stays co-resident with it added, else an empty
-// lane (reused or new). -1 with the error code in rc when none can be had.
-static int serve_place(pt_server *S, pt_ctx *tm, const std::string &solo, int &rc)
+// A request's pace in the sparse one-slot-per-wavefront kernel: the rank
+// groups it sweeps per colour pass (colour classes of more than 64 sites take
+// two or more). A launch lasts as long as its slowest request, so lanes keep
+// requests of one pace apart where that costs no extra launch. 0 elsewhere.
+static int serve_pace(const pt_ctx *c, const std::string &solo)
+{
+    if (solo.rfind("kernel=csrw ", 0) != 0) return 0;
+    return c->ncolors * ((c->hI.maxcnt + 63) / 64);
+}
+
+// The lane a request of template tm joins: the first lane of its kind, of its
+// pace first, whose launch keeps its kernel and stays co-resident with it
+// added, else an empty lane (reused or new). -1 with the error code in rc
+// when none can be had.
+static int serve_place(pt_server *S, pt_ctx *tm, const std::string &solo, int pace, int &rc)
 {
     rc = PT_OK;
-    for (int l = 0; l < (int)S->lanes.size(); ++l) {
-        SrvLane &ln = *S->lanes[l];
-        // 8^3 +-J lattices run in the row kernel's lanes beside other sizes
-        const bool kin = ln.ident == solo || (ln.ident.rfind("kernel=pml ", 0) == 0 && solo.rfind("kernel=pm ", 0) == 0);
-        if (ln.members == 0 || !kin || ln.full_for.count(solo)) continue;
-        std::vector<pt_ctx *> set = lane_set(S, l);
-        set.push_back(tm);
-        LaunchGroup *g = nullptr;
-        const bool ok = pick_group(ln.b, set, &g) == PT_OK && group_identity(g) == ln.ident;
-        delete g;
-        if (ok) return l;
-        ln.full_for.insert(solo);
-    }
+    for (int pass = 0; pass < 2; ++pass)
+        for (int l = 0; l < (int)S->lanes.size(); ++l) {
+            SrvLane &ln = *S->lanes[l];
+            // 8^3 +-J lattices run in the row kernel's lanes beside other sizes
+            const bool kin = ln.ident == solo || (ln.ident.rfind("kernel=pml ", 0) == 0 && solo.rfind("kernel=pm ", 0) == 0);
+            if (ln.members == 0 || !kin || ln.full_for.count(solo)) continue;
+            if (pass == 0 && ln.pace != pace) continue;
+            std::vector<pt_ctx *> set = lane_set(S, l);
+            set.push_back(tm);
+            LaunchGroup *g = nullptr;
+            const bool ok = pick_group(ln.b, set, &g) == PT_OK && group_identity(g) == ln.ident;
+            delete g;
+            if (ok) return l;
+            ln.full_for.insert(solo);
+        }
     for (int l = 0; l < (int)S->lanes.size(); ++l)
         if (S->lanes[l]->members == 0) {
             S->lanes[l]->ident = solo;
@@ -2345,11 +2361,12 @@ static void serve_admit(pt_server *S, std::vector<pt_result> &out)
             if (!S->active.empty()) return;   // wait for running requests to finish
             rc = fail(PT_ENOMEM, "request state of %zu bytes exceeds the memory budget", need);
         }
-        int lane = -1;
+        int lane = -1, pace = 0;
         if (!rc) {
             // the template has the clone's shape: plan with it
             const std::string solo = serve_solo(S, r.rq.problem, rc);
-            if (!rc) lane = serve_place(S, tm, solo, rc);
+            pace = serve_pace(tm, solo);
+            if (!rc) lane = serve_place(S, tm, solo, pace, rc);
         }
         pt_ctx *c = nullptr;
         void *mem = nullptr;
@@ -2378,9 +2395,74 @@ static void serve_admit(pt_server *S, std::vector<pt_result> &out)
             out.push_back(serve_result(r, rc, now, now));
             continue;
         }
-        S->active.push_back({r, c, need, now, 0, lane, -1, {-1, -1}});
-        S->lanes[lane]->members += 1;
-        S->lanes[lane]->dirty = true;
+        S->active.push_back({r, c, need, now, 0, lane, -1, {-1, -1}, {-1, -1}, pace});
+        SrvLane &ln = *S->lanes[lane];
+        ln.pace = ln.members == 0 ? pace : ln.pace == pace ? pace : -1;
+        ln.members += 1;
+        ln.dirty = true;
+    }
+}
+
+// Keep the paces of the sparse one-slot-per-wavefront requests apart: when
+// lanes of that kernel mix paces and their membership changed, refill them
+// pace by pace (each lane filled to its co-resident limit) if that takes no
+// more lanes than they now are. Which lane a request runs in changes none of
+// its results.
+static void serve_rebalance(pt_server *S)
+{
+    std::vector<int> ls;
+    bool mixed = false, dirty = false;
+    for (int l = 0; l < (int)S->lanes.size(); ++l) {
+        const SrvLane &ln = *S->lanes[l];
+        if (ln.members == 0 || ln.ident.rfind("kernel=csrw ", 0) != 0) continue;
+        ls.push_back(l);
+        mixed = mixed || ln.pace == -1;
+        dirty = dirty || ln.dirty;
+    }
+    if (ls.size() < 2 || !mixed || !dirty) return;
+    std::map<int, std::vector<int>> by_pace;   // active indices, in arrival order
+    for (int k = 0; k < (int)S->active.size(); ++k)
+        if (std::find(ls.begin(), ls.end(), S->active[k].lane) != ls.end()) by_pace[S->active[k].pace].push_back(k);
+    std::vector<std::pair<int, std::vector<int>>> fill;   // (pace, members) per lane
+    for (auto &kv : by_pace) {
+        // the co-resident work items of a lane of this pace: a plan of one request
+        LaunchGroup *g = nullptr;
+        GroupPlan P;
+        if (pick_group(S->probe, {S->active[kv.second[0]].c}, &g) != PT_OK) return;
+        const int prc = g->csrw ? plan_group(S->probe, g, P) : PT_EUNSUPPORTED;
+        delete g;
+        if (prc) return;
+        const long cap = (long)P.per_cu * S->probe->cus / 8 * 8;
+        std::vector<int> cur;
+        long items = 0;
+        for (int k : kv.second) {
+            const pt_ctx *c = S->active[k].c;
+            int G = S->opts.replicas_per_wg > 0 ? S->opts.replicas_per_wg : csrw_max_storages();
+            G = std::min(std::min(G, c->R), csrw_max_storages());
+            const long w = (c->R + G - 1) / G;
+            if (!cur.empty() && items + w > cap) {
+                fill.push_back({kv.first, cur});
+                cur.clear();
+                items = 0;
+            }
+            cur.push_back(k);
+            items += w;
+        }
+        if (!cur.empty()) fill.push_back({kv.first, cur});
+    }
+    if (fill.size() > ls.size()) return;   // keeping paces apart would take another launch
+    for (int l : ls) {
+        SrvLane &ln = *S->lanes[l];
+        ln.members = 0;
+        ln.pace = -2;
+        ln.dirty = true;
+        ln.full_for.clear();
+    }
+    for (size_t i = 0; i < fill.size(); ++i) {
+        SrvLane &ln = *S->lanes[ls[i]];
+        for (int k : fill[i].second) S->active[k].lane = ls[i];
+        ln.members = (int)fill[i].second.size();
+        ln.pace = fill[i].first;
     }
 }
 
@@ -2391,6 +2473,7 @@ static void serve_admit(pt_server *S, std::vector<pt_result> &out)
 // builds; a single admitted request always fits alone.
 static int serve_build(pt_server *S)
 {
+    serve_rebalance(S);
     for (int l = 0; l < (int)S->lanes.size(); ++l) {
         SrvLane &ln = *S->lanes[l];
         if (!ln.dirty || ln.members == 0) {
@@ -2408,6 +2491,7 @@ static int serve_build(pt_server *S)
             for (auto &a : S->active)
                 if (a.lane == l && k++ >= keep) a.lane = nidx;
             S->lanes[nidx]->members = (int)set.size() - keep;
+            S->lanes[nidx]->pace = S->lanes[l]->pace;
             S->lanes[nidx]->dirty = true;
             S->lanes[l]->members = keep;
             --l;   // rebuild this lane with its first half
@@ -2448,7 +2532,10 @@ static int serve_launch(pt_server *S, int q, int &lanes)
         lanes += 1;
     }
     HIPCHK(hipEventRecord(S->round_end[q], S->stream));
-    for (auto &a : S->active) a.slot[q] = a.cur;
+    for (auto &a : S->active) {
+        a.slot[q] = a.cur;
+        a.lane_at[q] = a.lane;
+    }
     return PT_OK;
 }
 
@@ -2478,7 +2565,7 @@ static int serve_finish(pt_server *S, int q, bool next_running, std::vector<pt_r
             keep.push_back(a);
             continue;
         }
-        const InstStatus &st = S->lanes[a.lane]->status[q].as<InstStatus>()[a.slot[q]];
+        const InstStatus &st = S->lanes[a.lane_at[q]]->status[q].as<InstStatus>()[a.slot[q]];
         const uint64_t t = (uint64_t)st.t;
         attempts += (double)(t - a.t_last) * (double)a.c->R * (double)a.c->nfree;
         a.t_last = t;

@@ -172,3 +172,40 @@ def test_serving_lanes_overflow():
         ref.run(cap)
         assert r["best_energy"] == ref.best and r["best_t"] == ref.best_t and r["best_slot"] == ref.best_slot
         assert np.array_equal(r["best_spins"], ref.best_spins), j
+
+
+def test_serving_sparse_lanes_by_pace():
+    """Sparse requests of two paces (6-bit multipliers: one rank group per
+    colour class; 12-bit: two) beyond one co-resident launch (64 slots each,
+    8 workgroups): admitted together into mixed lanes, then refilled pace by
+    pace. Every result equals the oracle's for the sweeps it ran."""
+    announce("serving: 24 + 24 multiplier requests (m = 6 and 12, R = 64) over several lanes")
+    K, cap = 50, 100
+    probs = []
+    for m in (6, 12):
+        C, _p, _q = inputs.semiprimes(m, 1, seed=7700 + m)[0]
+        g = inputs.multiplier(m, C)
+        b = inputs.geometric_ladder(64)
+        banks = {r: inputs.random_bank(g["n"], 4, seed=7800 + 10 * m + r, clamp=g["clamp"]) for r in range(0, 48, 6)}
+        probs.append((g, b, banks, dict(prop_start=25, prop_period=25)))
+    srv = binding.Server(chunk_sweeps=K)
+    pids = []
+    for g, b, banks, kw in probs:
+        ctx = binding.Context(g, b, seed=0, **kw)
+        for r, bank in banks.items():
+            ctx.propose(r, bank)
+        pids.append(srv.register(ctx))
+    for j in range(48):
+        srv.submit(pids[j % 2], 9100 + j, cap, user_tag=j)
+    res = {r["user_tag"]: r for r in _drain(srv, 48).values()}
+    st = srv.stats()
+    srv.stop()
+    assert st["completed"] == 48 and st["rejected"] == 0 and st["peak_lanes"] >= 2, st
+    for j in (0, 1, 46, 47):
+        g, b, banks, kw = probs[j % 2]
+        r = res[j]
+        assert r["status"] == 0 and r["sweeps"] == cap
+        ref = oracle.Run(g, b, seed=9100 + j, banks=banks, **kw)
+        ref.run(cap)
+        assert r["best_energy"] == ref.best and r["best_t"] == ref.best_t and r["best_slot"] == ref.best_slot
+        assert np.array_equal(r["best_spins"], ref.best_spins), j
