@@ -174,12 +174,14 @@ def test_serving_lanes_overflow():
         assert np.array_equal(r["best_spins"], ref.best_spins), j
 
 
-def test_serving_sparse_lanes_by_pace():
+@pytest.mark.parametrize("pipeline", [False, True])
+def test_serving_sparse_lanes_by_pace(pipeline):
     """Sparse requests of two paces (6-bit multipliers: one rank group per
     colour class; 12-bit: two) beyond one co-resident launch (64 slots each,
     8 workgroups): admitted together into mixed lanes, then refilled pace by
-    pace. Every result equals the oracle's for the sweeps it ran."""
-    announce("serving: 24 + 24 multiplier requests (m = 6 and 12, R = 64) over several lanes")
+    pace (pipelined: while a round over the old lanes runs). Every result
+    equals the oracle's for the sweeps it ran."""
+    announce(f"serving: 24 + 24 multiplier requests (m = 6 and 12, R = 64) over several lanes, pipeline={pipeline}")
     K, cap = 50, 100
     probs = []
     for m in (6, 12):
@@ -188,7 +190,7 @@ def test_serving_sparse_lanes_by_pace():
         b = inputs.geometric_ladder(64)
         banks = {r: inputs.random_bank(g["n"], 4, seed=7800 + 10 * m + r, clamp=g["clamp"]) for r in range(0, 48, 6)}
         probs.append((g, b, banks, dict(prop_start=25, prop_period=25)))
-    srv = binding.Server(chunk_sweeps=K)
+    srv = binding.Server(chunk_sweeps=K, pipeline=pipeline)
     pids = []
     for g, b, banks, kw in probs:
         ctx = binding.Context(g, b, seed=0, **kw)
