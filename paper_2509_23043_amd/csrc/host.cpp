@@ -1278,6 +1278,12 @@ static int plan_group(const pt_batch *b, const LaunchGroup *g, GroupPlan &P)
     }
     if (row_block > 512) row_ok = false;
     if (row4_block > 512) row4_ok = false;
+    // independent chains (bank generation) take the coarsest tiling, where the
+    // four-storages-per-lane LDS sweeper outruns the packed rows; the rows
+    // only where the caller asks for them
+    bool any_waits = false;
+    for (pt_ctx *c : g->ctxs) any_waits = any_waits || c->opts.sweeps_per_cycle != 0;
+    if (!any_waits && g->sparse_req == 0) row_ok = row4_ok = false;
     if (g->sparse_req == SPARSE_ROW4 && !row4_ok)
         return fail(PT_EUNSUPPORTED, "the four-storage packed-row sweeper does not fit this batch");
     if (g->sparse_req == SPARSE_ROW && !row_ok)
@@ -1515,8 +1521,12 @@ static LaunchGroup *make_group(const pt_batch_opts &o, const std::vector<pt_ctx 
     g->pml = all_pml && (o.kernel == 7 || (pml_auto && o.kernel == 0 && !all_pm8 && o.replicas_per_thread <= 1));
     // the one-slot-per-wavefront sparse kernel where every context is a
     // general graph that fits it (its mailbox carries energies of 24 bits),
-    // when the caller asks for it (kernel 8) or leaves the kernel open
-    bool all_csrw = !any_ctx && (o.kernel == 8 || (pml_auto && o.kernel == 0));
+    // when the caller asks for it (kernel 8) or leaves the kernel open for
+    // chains that exchange (independent chains never wait, and wide
+    // workgroups of the workgroup-synchronous kernel sweep them faster)
+    bool waits = false;
+    for (pt_ctx *c : ctxs) waits = waits || c->opts.sweeps_per_cycle != 0;
+    bool all_csrw = !any_ctx && (o.kernel == 8 || (pml_auto && o.kernel == 0 && waits));
     for (pt_ctx *c : ctxs)
         all_csrw = all_csrw && c->kind == KIND_CSR &&
                    csrw_supported(c->n, c->hI.maxabsj, c->hI.csrw_chunks, c->hI.maxcnt) && (long long)c->n * c->D < (1 << 23);
