@@ -161,3 +161,17 @@ def test_runtime_sparse_sweeper_choice():
     g9p = _pad_isolated(g9, 260)   # a class of more than 256 sites: not the one-slot-per-wavefront kernel
     assert np.bincount(g9p["color"][g9p["clamp"] == 0]).max() > 256
     _run_and_compare([g9p], inputs.geometric_ladder(8), 4, 60, expect="csr-row4", kernel="auto")   # |J| = 9
+
+
+def test_independent_chains_auto_choice():
+    """Independent chains (M = 0) of multipliers with the kernel left open take
+    the workgroup-synchronous kernel at its coarsest tiling and the
+    four-storages-per-lane LDS sweeper (neither the packed rows nor the
+    one-slot-per-wavefront kernel); with exchanges (M = 1) the same circuits
+    take the one-slot-per-wavefront kernel. Both against the oracle."""
+    announce("sparse auto choice: independent chains -> csr-quad, exchanging chains -> csrw")
+    probs = [inputs.multiplier(8, C) for C, _, _ in inputs.semiprimes(8, 2, seed=6480)]
+    plan = _run_and_compare(probs, np.full(32, 1.1), 0, 60, M=0, expect="csr-quad", kernel="auto")
+    assert plan[0][0] == "chunk", plan
+    plan = _run_and_compare(probs, inputs.geometric_ladder(16), 0, 60, M=1, expect="-", kernel="auto")
+    assert plan[0][0] == "csrw", plan
