@@ -593,11 +593,17 @@ extern "C" int pt_create(const pt_graph *g, const double *betas, int32_t R, cons
         return code;
     };
     // tables (on the host, before any device call)
+    // Flip thresholds [R][stride], then per slot the FP32 bits of 2 beta / ln 2,
+    // from which the sparse one-slot-per-wavefront kernel evaluates the flip
+    // probability itself and reads a threshold only near a uniform's edge.
     const int stride = 2 * P.D + 1;
-    std::vector<uint32_t> tflip((size_t)R * stride);
-    for (int r = 0; r < R; ++r)
+    std::vector<uint32_t> tflip((size_t)R * stride + R);
+    for (int r = 0; r < R; ++r) {
         for (int k = 0; k < stride; ++k)
             tflip[(size_t)r * stride + k] = threshold(flip_probability(o->rule, betas[r], 2LL * (k - P.D)));
+        const float cf = (float)(2.0 * betas[r] / std::log(2.0));
+        memcpy(&tflip[(size_t)R * stride + r], &cf, 4);
+    }
     std::vector<uint32_t> tprop, tswap;
     std::vector<int32_t> tprop_off(R), tprop_len(R), tswap_off(std::max(R - 1, 1)), tswap_len(std::max(R - 1, 1));
     for (int r = 0; r < R; ++r) {

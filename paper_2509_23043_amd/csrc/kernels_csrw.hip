@@ -16,9 +16,12 @@
 // largest degree needs; within a class the host orders sites by degree, so
 // the few high-degree sites of a circuit (a multiplier's input bits) share
 // groups and the rest take one chunk. A lane reads the next item's first two
-// chunks while it decides the current one, so an item costs two dependent LDS
-// round trips: the neighbour spins with the own spin and random half, then the
-// flip threshold of the slot (Eqs. 4-5 through the slot's uint32 table). The slot's sweep uniforms (Philox call q serves sites
+// chunks while it decides the current one, so an item costs one LDS round
+// trip: the neighbour spins with the own spin and random half. The flip
+// decision (Eqs. 4-5) comes from the flip probability evaluated in FP32 with a
+// relative margin, which settles it as the slot's uint32 threshold table would
+// for all but about one uniform in 10^4; only those items read the table (a
+// second round trip). The slot's sweep uniforms (Philox call q serves sites
 // 8q .. 8q + 7) are drawn at the start of the sweep and staged in LDS in site
 // order.
 //
@@ -35,6 +38,8 @@ namespace tapt {
 namespace csrw {
 
 constexpr int MAXG = 8;   // slots (wavefronts) per workgroup
+constexpr int RULE_GIBBS = 1;              // heat-bath rule (Methods Eq. 5); 0: Metropolis
+constexpr float MARGIN = 1.0f / 4096.0f;   // relative margin of the FP32 flip decision
 
 struct Off {
     size_t sp, rnd, bw, bj, info, tab, toff, tsw, mail, xst, total;
@@ -206,6 +211,8 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
     if (active) {
         const int slot = s0 + wv;
         const uint32_t *tab_w = tab + wv * stride + D;        // flip threshold by m_i I_i
+        const float cfl = __uint_as_float(__builtin_amdgcn_readfirstlane(I.tflip[(size_t)P.R * stride + slot]));   // 2 beta / ln 2
+        const bool gibbs = I.rule == RULE_GIBBS;
         uint16_t *rnd_w = rnd + (size_t)wv * nr;
         uint32_t cyc = (uint32_t)(t0 / (uint64_t)P.M), phase = (uint32_t)(t0 % (uint64_t)P.M);
         uint64_t prop_at = P.first_prop_from(t0 + 1);
@@ -274,7 +281,7 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                         constexpr int NC = decltype(nc_const)::value;
                         if (i == 0xFFF) return;
                         const int m = m_w[i];
-                        const uint32_t hs = (uint32_t)rnd_w[i] << 16;
+                        const uint32_t ur = rnd_w[i], hs = ur << 16;
                         int v[8 * NC];                      // 4 words of 2 neighbours per chunk
 #pragma unroll
                         for (int q = 0; q < 4 * NC; ++q) {
@@ -303,17 +310,34 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                             f = __builtin_amdgcn_sdot4((int)pack4(u[4], u[5], u[6], u[7]), (int)jc.y, f, false);
                         }
                         const int d = m * f;
-                        const uint32_t T = tab_w[d];
-                        bool maybe;
-                        bool acc = coarse_accept(T, hs, maybe);
-                        if (any_lane(maybe)) {
-                            if (maybe) {
-                                const P4 r2 = philox(opaque((uint32_t)(i >> 3)), (uint32_t)t, (uint32_t)slot, TAG_REFINE,
-                                                     P.k0, P.k1);
-                                const int wq = (i & 7) >> 1;
-                                const uint32_t wd = wq == 0 ? r2.v[0] : wq == 1 ? r2.v[1] : wq == 2 ? r2.v[2] : r2.v[3];
-                                const uint32_t lo = ((i & 1) ? (wd >> 16) : wd) & 0xFFFFu;
-                                acc = (T == ALWAYS) || ((hs | lo) < T);
+                        // The table's coarse test accepts iff floor(65536 p) > u_hi
+                        // and leaves u open iff floor(65536 p) == u_hi. X = 65536 p
+                        // in FP32 is within 3e-6 of the host's FP64 value wherever
+                        // X >= 1/2 (the exponent stays below 17), so X (1 - MARGIN)
+                        // >= u_hi + 1 accepts and X (1 + MARGIN) < u_hi rejects as the
+                        // table would; the rest (about one uniform in 10^4, and a
+                        // NaN X) read the slot's threshold.
+                        const float uf = (float)ur, y = (float)d * cfl;
+                        const float X = gibbs ? 65536.0f * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(y))
+                                              : __builtin_amdgcn_exp2f(16.0f - y);
+                        bool acc = (!gibbs && d <= 0) || X * (1.0f - MARGIN) >= uf + 1.0f;
+                        const bool open = !acc && !(X * (1.0f + MARGIN) < uf);
+                        if (any_lane(open)) {
+                            bool maybe = false;
+                            uint32_t T = 0;
+                            if (open) {
+                                T = tab_w[d];
+                                acc = coarse_accept(T, hs, maybe);
+                            }
+                            if (any_lane(maybe)) {
+                                if (maybe) {
+                                    const P4 r2 = philox(opaque((uint32_t)(i >> 3)), (uint32_t)t, (uint32_t)slot,
+                                                         TAG_REFINE, P.k0, P.k1);
+                                    const int wq = (i & 7) >> 1;
+                                    const uint32_t wd = wq == 0 ? r2.v[0] : wq == 1 ? r2.v[1] : wq == 2 ? r2.v[2] : r2.v[3];
+                                    const uint32_t lo = ((i & 1) ? (wd >> 16) : wd) & 0xFFFFu;
+                                    acc = (T == ALWAYS) || ((hs | lo) < T);
+                                }
                             }
                         }
                         if (acc) {

@@ -52,6 +52,20 @@ def test_random_graphs_csrw(seed, hubs, jmax):
     _run_and_compare(probs, inputs.geometric_ladder(12), 6, 150, expect="-", kernel="csrw")
 
 
+@pytest.mark.parametrize("rule", ["metropolis", "gibbs"])
+def test_csrw_rules_and_extreme_betas(rule):
+    """The flip decision from the flip probability in FP32, with the table read
+    only near a uniform's edge, under both rules and at the ends of the range
+    of beta: a slot that accepts almost everything (beta = 0.001), one that
+    accepts almost nothing uphill (beta = 40: the probability underflows FP32
+    for most fields), and couplings up to 40 (fields up to several hundred)."""
+    betas = np.array([0.001, 0.05, 0.2, 0.6, 1.5, 3.0, 8.0, 40.0])
+    probs = [inputs.multiplier(8, C) for C, _, _ in inputs.semiprimes(8, 1, seed=6750)]
+    probs.append(_random_graph(150, 6760, hubs=3, jmax=40))
+    announce(f"csrw: {rule}, betas {betas.tolist()}, 8-bit multiplier and a random graph with |J| <= 40")
+    _run_and_compare(probs, betas, 4, 150, expect="-", kernel="csrw", rule=rule)
+
+
 def test_csrw_independent_chains_and_refusal():
     """Independent chains (M = 0); a graph with a colour class of more than
     256 sites is refused."""

@@ -40,14 +40,15 @@ def _plan(bt):
     return [(d["kernel"], d["sweeper"], d["block"]) for d in bt.describe()]
 
 
-def _run_and_compare(problems, betas, G, sweeps, M=1, chunk=50, bank_every=3, expect="csr-row", kernel="row"):
+def _run_and_compare(problems, betas, G, sweeps, M=1, chunk=50, bank_every=3, expect="csr-row", kernel="row",
+                     rule="metropolis"):
     import oracle
     R = len(betas)
     ctxs, cases = [], []
     for i, g in enumerate(problems):
         banks = ({r: inputs.random_bank(g["n"], 5, seed=5800 + 32 * i + r, clamp=g["clamp"])
                   for r in range(0, R - 2, bank_every)} if M else None)
-        kw = dict(M=M)
+        kw = dict(M=M, rule=rule)
         if M:
             kw.update(prop_start=2 * M, prop_period=3 * M)
         c = binding.Context(g, betas, seed=5900 + i, **kw)
