@@ -232,6 +232,16 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
         uint32_t u_vec = 0, u_base = (uint32_t)-100;
         const uint32_t u_i = (uint32_t)lane % (uint32_t)NP, u_c = (uint32_t)lane / (uint32_t)NP;
 
+        // sweep tt's uniforms: Philox call q serves sites 8q .. 8q + 7
+        auto draw = [&](uint64_t tt) {
+            for (int q = lane; q < nr / 8; q += 64) {
+                const P4 rr = philox_v((uint32_t)q, (uint32_t)tt, (uint32_t)slot, TAG_SWEEP, P.k0, P.k1);
+                *(uint4 *)(rnd_w + 8 * q) = make_uint4(rr.v[0], rr.v[1], rr.v[2], rr.v[3]);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        };
+        bool drawn = false;
         for (uint64_t t = t0 + 1; t <= tend && !failed; ++t) {
             const bool ends = phase + 1 == (uint32_t)P.M;
             if (ends && cyc + 1 - u_base >= UCYC) {
@@ -245,13 +255,10 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
             uint2 j0 = bj[(gcb >> 8) * 64 + lane];
             uint2 j1 = (gcb & 255) > 1 ? bj[((gcb >> 8) + 1) * 64 + lane] : make_uint2(0u, 0u);
             uint32_t inf = info[lane];
-            // ---- the sweep's uniforms, staged in site order ----
-            for (int q = lane; q < nr / 8; q += 64) {
-                const P4 rr = philox_v((uint32_t)q, (uint32_t)t, (uint32_t)slot, TAG_SWEEP, P.k0, P.k1);
-                *(uint4 *)(rnd_w + 8 * q) = make_uint4(rr.v[0], rr.v[1], rr.v[2], rr.v[3]);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+            // ---- the sweep's uniforms, staged in site order (at a cycle end
+            // they were drawn while the slot waited for its partner) ----
+            if (!drawn) draw(t);
+            drawn = false;
 
             // ---- the sweep: colour classes in order, item ranks lane + 64 k ----
             int8_t *m_w = sp + buf * SB;
@@ -415,6 +422,12 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                     if (wpl > 1) __hip_atomic_store(out + 64 + lane, tg | w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (lane == 0)
                         __hip_atomic_store(out + NXW, tg | (uint32_t)E, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                // the next sweep's uniforms do not depend on the swap: draw
+                // them while the partner's word is on its way
+                if ((intra || cross) && t < tend) {
+                    draw(t + 1);
+                    drawn = true;
                 }
                 if (intra) {
                     uint32_t polls = 0;
