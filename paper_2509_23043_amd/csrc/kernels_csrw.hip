@@ -22,8 +22,8 @@
 // relative margin, which settles it as the slot's uint32 threshold table would
 // for all but about one uniform in 10^4; only those items read the table (a
 // second round trip). The slot's sweep uniforms (Philox call q serves sites
-// 8q .. 8q + 7) are drawn at the start of the sweep and staged in LDS in site
-// order.
+// 8q .. 8q + 7) are staged in LDS in site order, drawn at the start of the
+// sweep or, after a cycle end with a partner, while the slot waits for it.
 //
 // Slots and states as in the +-J row kernel: states move between LDS buffers,
 // pairs inside the workgroup meet in an LDS mailbox (energy, buffer index),
