@@ -52,6 +52,16 @@ def test_random_graphs_csrw(seed, hubs, jmax):
     _run_and_compare(probs, inputs.geometric_ladder(12), 6, 150, expect="-", kernel="csrw")
 
 
+@pytest.mark.parametrize("M,chunk", [(3, 50), (4, 30), (2, 7)])
+def test_csrw_cycle_lengths(M, chunk):
+    """Several sweeps per exchange cycle (M = 2, 3, 4), with launches of 50,
+    30 and 7 sweeps that end inside a cycle: the next sweep's uniforms are drawn
+    during a cycle end's wait only when that sweep belongs to the same launch."""
+    announce(f"csrw: M={M}, launches of {chunk} sweeps, 2 x 8-bit multipliers, R=16 G=4")
+    probs = [inputs.multiplier(8, C) for C, _, _ in inputs.semiprimes(8, 2, seed=6770)]
+    _run_and_compare(probs, inputs.geometric_ladder(16), 4, 130, M=M, chunk=chunk, expect="-", kernel="csrw")
+
+
 @pytest.mark.parametrize("rule", ["metropolis", "gibbs"])
 def test_csrw_rules_and_extreme_betas(rule):
     """The flip decision from the flip probability in FP32, with the table read
