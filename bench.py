@@ -441,7 +441,7 @@ def mixed_leg(args, log):
     10^5 sweeps, proposals every 50 sweeps from 256-entry plain-PT banks on
     all but the two coldest slots, tiling from the autotuner (M = 1)."""
     from paper_2509_23043_amd import workloads
-    cfg = workloads.CFG3
+    cfg = workloads.EA_MIXED
     cases = workloads.ea_cases(cfg)
     t0 = time.perf_counter()
     banks = pt_banks(cases, args.leg_bank, log, seed0=1_300_000)
@@ -477,7 +477,7 @@ def factorization_leg(args, log):
     product and their device time within the 64-product batch."""
     import torch
     from paper_2509_23043_amd import binding, workloads
-    cfg = workloads.CFG4
+    cfg = workloads.MULT8
     cases = workloads.fact_cases(cfg)
     t0 = time.perf_counter()
     banks = pt_banks(cases, args.leg_bank, log, seed0=1_400_000)

@@ -4,14 +4,14 @@ Shared by bench.py and the full-length parity tests, so that both run the same
 instances, ladders, seeds, schedules and targets. Like ``inputs``, this module
 only describes problems: it holds none of the sampler's arithmetic.
 
-- ``CFG2``: 64 synthetic 3D EA +-J instances, L=8 (512 spins), R=32 geometric
+- ``EA_L8``: 64 synthetic 3D EA +-J instances, L=8 (512 spins), R=32 geometric
   0.2..3.0, Metropolis, M=1, 10^5 sweeps, 256-entry banks on the 30 hottest
   slots, proposals every 100 sweeps.
-- ``CFG3``: EA +-J L in {6, 8, 10, 12, 16} x 8 instances with ladders of
+- ``EA_MIXED``: EA +-J L in {6, 8, 10, 12, 16} x 8 instances with ladders of
   24/30/36/42/48 slots, M=1, 10^5 sweeps, banks on all but the two coldest
   slots, proposals every 50 sweeps; one persistent launch under the
   autotuner's tiling.
-- ``CFG4``: 64 distinct products of two distinct primes in [128, 256) as 8x8-bit
+- ``MULT8``: 64 distinct products of two distinct primes in [128, 256) as 8x8-bit
   array multipliers (200 spins, 176 free, DSATUR colors), R=32, M=1, banks on
   the round(13 R / 18) = 23 hottest slots (the paper's 13 of 18), proposals
   every 100 sweeps, target the ground energy -3m^2 - 4m(m-1).
@@ -23,11 +23,11 @@ from __future__ import annotations
 
 from . import inputs
 
-CFG2 = dict(name="cfg2", sizes=((8, 32),), per_size=64, inst_seed=2000, run_seed=3000, B=256, period=100,
+EA_L8 = dict(name="ea_l8_x64", sizes=((8, 32),), per_size=64, inst_seed=2000, run_seed=3000, B=256, period=100,
             sweeps=100_000, chunk=10_000)
-CFG3 = dict(name="cfg3", sizes=((6, 24), (8, 30), (10, 36), (12, 42), (16, 48)), per_size=8, inst_seed=3000,
+EA_MIXED = dict(name="ea_mixed_x40", sizes=((6, 24), (8, 30), (10, 36), (12, 42), (16, 48)), per_size=8, inst_seed=3000,
             run_seed=3500, B=256, period=50, sweeps=100_000, chunk=10_000)
-CFG4 = dict(name="cfg4", m=8, count=64, prod_seed=4000, run_seed=4500, R=32, n_prop=23, B=256, period=100,
+MULT8 = dict(name="mult8x8_x64", m=8, count=64, prod_seed=4000, run_seed=4500, R=32, n_prop=23, B=256, period=100,
             sweeps=10_000, chunk=10_000, solve_cap=100_000)
 
 
@@ -52,7 +52,7 @@ def ea_cases(cfg):
     return out
 
 
-def fact_cases(cfg=CFG4):
+def fact_cases(cfg=MULT8):
     """Every product of the factorization workload: dicts as ea_cases plus
     C, p, q and m."""
     m = cfg["m"]

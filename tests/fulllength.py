@@ -8,9 +8,10 @@ after BANK_SWEEPS sweeps from its own random start. So no input and no
 expected value comes from the HIP path. The other instances of a batch carry
 seeded iid banks; they only fill the launch.
 
-Expected results of the 10^5-sweep runs (cfg 2, cfg 3) are stored under
+Expected results of the 10^5-sweep runs (the 8^3 and the mixed-size
+spin-glass batches) are stored under
 tests/golden/ by tests/golden/make_fulllength.py, which calls only the oracle
-and this module; the factorization batch (cfg 4, 10^4 sweeps) is short
+and this module; the factorization batch (10^4 sweeps) is short
 enough for the oracle to run beside the test on the host's cores.
 """
 from __future__ import annotations
@@ -24,14 +25,14 @@ import numpy as np
 
 from paper_2509_23043_amd import inputs
 
-from paper_2509_23043_amd.workloads import CFG2, CFG3, CFG4, ea_cases, fact_cases, run_kwargs  # noqa: F401
+from paper_2509_23043_amd.workloads import EA_L8, EA_MIXED, MULT8, ea_cases, fact_cases, run_kwargs  # noqa: F401
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 BANK_SWEEPS = 20
 BANK_SEED = 7_000_000
 
 # instances compared with the oracle (batch order)
-COMPARED = {"cfg2": (0, 9, 18, 27, 36, 45, 54, 63), "cfg3": (0, 8, 16, 24, 32)}
+COMPARED = {"ea_l8_x64": (0, 9, 18, 27, 36, 45, 54, 63), "ea_mixed_x40": (0, 8, 16, 24, 32)}
 
 
 def _bank_job(args):

@@ -7,7 +7,7 @@ compare: final spins and energies by slot, swap, proposal and flip counters,
 the best record and the first hit. One oracle process per instance, longest
 first.
 
-    python tests/golden/make_fulllength.py [--workers N] [cfg2 cfg3]
+    python tests/golden/make_fulllength.py [--workers N] [ea_l8_x64 ea_mixed_x40]
 """
 import argparse
 import json
@@ -26,9 +26,9 @@ from tests import fulllength as F  # noqa: E402
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workers", type=int, default=len(os.sched_getaffinity(0)))
-    ap.add_argument("cfgs", nargs="*", default=["cfg2", "cfg3"])
+    ap.add_argument("cfgs", nargs="*", default=["ea_l8_x64", "ea_mixed_x40"])
     args = ap.parse_args()
-    cfgs = {"cfg2": F.CFG2, "cfg3": F.CFG3}
+    cfgs = {"ea_l8_x64": F.EA_L8, "ea_mixed_x40": F.EA_MIXED}
     todo = []
     for name in args.cfgs:
         cfg = cfgs[name]

@@ -3,14 +3,14 @@ the launch configuration the benchmark times, compared with the oracle
 element by element (spins and energies by slot, every counter, the best
 record and the first hit).
 
-- cfg 2: 64 EA +-J L=8 instances, R=32, 10^5 sweeps in 10^4-sweep launches
+- 64 EA +-J L=8 instances, R=32, 10^5 sweeps in 10^4-sweep launches
   of the +-J kernel with one slot per wavefront and 8 slots per workgroup;
   8 instances compared with stored oracle runs of the same length.
-- cfg 3: the 40-instance mixed-size batch (L = 6..16, R = 24..48), 10^5
+- the 40-instance mixed-size batch (L = 6..16, R = 24..48), 10^5
   sweeps in one launch sequence under the autotuner's tiling (and the
   runtime's automatic tiling); one instance per size compared with stored
   oracle runs.
-- cfg 4: 64 8-bit factorization instances, R=32, 10^4 sweeps under the
+- 64 8-bit factorization instances, R=32, 10^4 sweeps under the
   autotuner's tiling; every instance compared with an oracle run made beside
   the test on the host's cores.
 
@@ -76,42 +76,42 @@ def _run_and_compare(cases, cfg, banks, refs, tiling, label):
         c.close()
 
 
-def test_cfg2_full_length_bench_launch():
-    cfg = F.CFG2
+def test_ea_l8_x64_full_length_bench_launch():
+    cfg = F.EA_L8
     golden, refs = F.load_golden(cfg)
     assert golden["sweeps"] == cfg["sweeps"] == 100_000 and len(refs) == 8
     cases = F.ea_cases(cfg)
-    announce("cfg2: oracle banks of the 8 compared instances")
+    announce("8^3 x 64: oracle banks of the 8 compared instances")
     with _pool() as pool:
         banks = _all_banks(cases, cfg, F.oracle_banks([c for c in cases if c["k"] in refs], cfg, pool))
-    _run_and_compare(cases, cfg, banks, refs, (8, 1, "pm1"), "cfg2")
+    _run_and_compare(cases, cfg, banks, refs, (8, 1, "pm1"), "8^3 x 64")
 
 
-def test_cfg3_full_length_tuned_launch():
-    cfg = F.CFG3
+def test_ea_mixed_x40_full_length_tuned_launch():
+    cfg = F.EA_MIXED
     golden, refs = F.load_golden(cfg)
     assert golden["sweeps"] == cfg["sweeps"] == 100_000 and len(refs) == 5
     cases = F.ea_cases(cfg)
     assert sorted({cases[k]["L"] for k in refs}) == [6, 8, 10, 12, 16]
-    announce("cfg3: oracle banks of the 5 compared instances")
+    announce("mixed sizes x 40: oracle banks of the 5 compared instances")
     with _pool() as pool:
         banks = _all_banks(cases, cfg, F.oracle_banks([c for c in cases if c["k"] in refs], cfg, pool))
     tuned = _tuned(cases, cfg)
-    _run_and_compare(cases, cfg, banks, refs, tuned, "cfg3 (autotuned)")
+    _run_and_compare(cases, cfg, banks, refs, tuned, "mixed sizes (autotuned)")
     if tuned != (0, 0, "auto"):
-        _run_and_compare(cases, cfg, banks, refs, (0, 0, "auto"), "cfg3 (automatic tiling)")
+        _run_and_compare(cases, cfg, banks, refs, (0, 0, "auto"), "mixed sizes (automatic tiling)")
 
 
-def test_cfg4_full_length_all_products():
-    cfg = F.CFG4
+def test_mult8x8_x64_full_length_all_products():
+    cfg = F.MULT8
     cases = F.fact_cases(cfg)
     assert len(cases) == 64 and len({c["C"] for c in cases}) == 64
-    announce("cfg4: oracle banks and 10^4-sweep oracle runs of all 64 products")
+    announce("8x8-bit multipliers x 64: oracle banks and 10^4-sweep oracle runs of all 64 products")
     t0 = time.perf_counter()
     with _pool() as pool:
         banks = F.oracle_banks(cases, cfg, pool)
         res = F.run_oracle(cases, cfg, banks, pool)
-    announce(f"cfg4: oracle {time.perf_counter() - t0:.1f} s, "
+    announce(f"8x8-bit multipliers x 64: oracle {time.perf_counter() - t0:.1f} s, "
              f"{sum(r['first_hit'] >= 0 for r in res)} of 64 reached the ground energy")
     for r in res:
         assert r["energy_mismatch"] == 0
@@ -125,5 +125,5 @@ def test_cfg4_full_length_all_products():
             B = inputs.bits_to_int(r["best_spins"], c["g"]["b_idx"])
             assert A * B == c["C"] and {A, B} == {c["p"], c["q"]}, (c["C"], A, B)
     tuned = _tuned(cases, cfg)
-    _run_and_compare(cases, cfg, banks, refs, tuned, "cfg4 (autotuned)")
+    _run_and_compare(cases, cfg, banks, refs, tuned, "8x8-bit multipliers (autotuned)")
     assert np.all([refs[k]["t"] == cfg["sweeps"] for k in refs])
