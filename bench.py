@@ -1120,7 +1120,8 @@ def main():
                vs_baseline=None, dtype="int8", data="synthetic",
                config=dict(workload=f"3D EA +-J L={L} ({n} spins) x {NI} instances, {R} replicas beta 0.2..3.0 "
                                     f"geometric, Metropolis, M={M}, proposals every 100 sweeps from {args.bank}-entry "
-                                    f"plain-PT banks on {n_prop} slots; {S} sweeps per step",
+                                    f"plain-PT banks on {n_prop} slots (bank energies computed once when the banks "
+                                    f"are installed, before the timed region); {S} sweeps per step",
                            instances=NI, L=L, replicas=R, sweeps_per_step=S, sweeps_per_swap=M, bank=args.bank,
                            tiling=dict(replicas_per_wg=G, replicas_per_thread=rpt, kernel=kern)),
                plain=plain, roofline=roof, cpu_baseline=cpu, mixed=mixed, factorization=fact,
