@@ -329,7 +329,7 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                                               : __builtin_amdgcn_exp2f(16.0f - y);
                         bool acc = (!gibbs && d <= 0) || X * (1.0f - MARGIN) >= uf + 1.0f;
                         const bool open = !acc && !(X * (1.0f + MARGIN) < uf);
-                        if (any_lane(open)) {
+                        if (__builtin_expect(any_lane(open), 0)) {
                             bool maybe = false;
                             uint32_t T = 0;
                             if (open) {
@@ -347,11 +347,11 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                                 }
                             }
                         }
-                        if (acc) {
-                            m_w[i] = (int8_t)(-m);
-                            dE += 2 * d;
-                            nf += 1;
-                        }
+                        // every lane with an item writes its spin back, so the
+                        // common path takes no branch
+                        m_w[i] = (int8_t)(acc ? -m : m);
+                        dE += acc ? 2 * d : 0;
+                        nf += acc ? 1 : 0;
                     };
                     if (nch == 1) decide(std::integral_constant<int, 1>{});
                     else decide(std::integral_constant<int, 2>{});
