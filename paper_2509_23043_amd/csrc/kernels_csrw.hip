@@ -325,8 +325,9 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                         // table would; the rest (about one uniform in 10^4, and a
                         // NaN X) read the slot's threshold.
                         const float uf = (float)ur, y = (float)d * cfl;
-                        const float X = gibbs ? 65536.0f * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(y))
-                                              : __builtin_amdgcn_exp2f(16.0f - y);
+                        // one exponential for either rule, no branch
+                        const float ex = __builtin_amdgcn_exp2f(gibbs ? y : 16.0f - y);
+                        const float X = gibbs ? 65536.0f * __builtin_amdgcn_rcpf(1.0f + ex) : ex;
                         bool acc = (!gibbs && d <= 0) || X * (1.0f - MARGIN) >= uf + 1.0f;
                         const bool open = !acc && !(X * (1.0f + MARGIN) < uf);
                         if (__builtin_expect(any_lane(open), 0)) {
