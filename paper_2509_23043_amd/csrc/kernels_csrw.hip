@@ -55,8 +55,9 @@ __host__ __device__ inline Off offsets(int n, int ncolors, int ipl, int chunks, 
     size_t o = 0;
     f.sp = o; o = align16(o + (size_t)G * SB);
     f.rnd = o; o = align16(o + (size_t)G * nr * 2);
-    f.bw = o; o = align16(o + (size_t)chunks * 64 * 16);
-    f.bj = o; o = align16(o + (size_t)chunks * 64 * 8);
+    // one chunk of padding: a group's second chunk is read whether or not it has one
+    f.bw = o; o = align16(o + (size_t)(chunks + 1) * 64 * 16);
+    f.bj = o; o = align16(o + (size_t)(chunks + 1) * 64 * 8);
     f.info = o; o = align16(o + nrec * 4);
     f.tab = o; o = align16(o + (size_t)G * stride * 4);
     f.toff = o; o = align16(o + (size_t)(G + 2) * 4);
@@ -251,9 +252,9 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
             // the first group's first two chunks, in flight while the uniforms are drawn
             int gcb = __builtin_amdgcn_readfirstlane(gcb_v);
             uint4 b0 = bw[(gcb >> 8) * 64 + lane];
-            uint4 b1 = (gcb & 255) > 1 ? bw[((gcb >> 8) + 1) * 64 + lane] : make_uint4(0u, 0u, 0u, 0u);
+            uint4 b1 = bw[((gcb >> 8) + 1) * 64 + lane];      // unused where the group has one chunk
             uint2 j0 = bj[(gcb >> 8) * 64 + lane];
-            uint2 j1 = (gcb & 255) > 1 ? bj[((gcb >> 8) + 1) * 64 + lane] : make_uint2(0u, 0u);
+            uint2 j1 = bj[((gcb >> 8) + 1) * 64 + lane];
             uint32_t inf = info[lane];
             // ---- the sweep's uniforms, staged in site order (at a cycle end
             // they were drawn while the slot waited for its partner) ----
@@ -274,9 +275,9 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                     if (g + 1 < ngr) {
                         gcb = __builtin_amdgcn_readlane(gcb_v, g + 1);
                         b0 = bw[(gcb >> 8) * 64 + lane];
-                        b1 = (gcb & 255) > 1 ? bw[((gcb >> 8) + 1) * 64 + lane] : make_uint4(0u, 0u, 0u, 0u);
+                        b1 = bw[((gcb >> 8) + 1) * 64 + lane];
                         j0 = bj[(gcb >> 8) * 64 + lane];
-                        j1 = (gcb & 255) > 1 ? bj[((gcb >> 8) + 1) * 64 + lane] : make_uint2(0u, 0u);
+                        j1 = bj[((gcb >> 8) + 1) * 64 + lane];
                         inf = info[(g + 1) * 64 + lane];
                     }
                     const int i = (int)(ci & 0xFFFu);
@@ -354,7 +355,7 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                         dE += acc ? 2 * d : 0;
                         nf += acc ? 1 : 0;
                     };
-                    if (nch == 1) decide(std::integral_constant<int, 1>{});
+                    if (__builtin_expect(nch == 1, 1)) decide(std::integral_constant<int, 1>{});
                     else decide(std::integral_constant<int, 2>{});
                 }
                 // the next class reads what this one wrote (in-order LDS within a wavefront)
