@@ -68,6 +68,14 @@ __host__ __device__ inline Off offsets(int n, int ncolors, int ipl, int chunks, 
     return f;
 }
 
+// a rank group's first two bond chunks and its site word, read one group ahead
+struct Rows {
+    uint4 b0, b1;
+    uint2 j0, j1;
+    uint32_t inf;
+    int gcb;
+};
+
 struct Rec {
     int E, slot;
     long long t, hit;
@@ -242,6 +250,14 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
         };
+        auto load_rows = [&](Rows &r, int g) {
+            r.gcb = __builtin_amdgcn_readlane(gcb_v, g);
+            r.b0 = bw[(r.gcb >> 8) * 64 + lane];
+            r.b1 = bw[((r.gcb >> 8) + 1) * 64 + lane];      // unused where the group has one chunk
+            r.j0 = bj[(r.gcb >> 8) * 64 + lane];
+            r.j1 = bj[((r.gcb >> 8) + 1) * 64 + lane];
+            r.inf = info[g * 64 + lane];
+        };
         bool drawn = false;
         for (uint64_t t = t0 + 1; t <= tend && !failed; ++t) {
             const bool ends = phase + 1 == (uint32_t)P.M;
@@ -249,13 +265,9 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                 u_base = cyc + 1;
                 u_vec = philox_v((uint32_t)(slot - 1) + u_i, u_base + u_c, 0, TAG_SWAP, P.k0, P.k1).v[0];
             }
-            // the first group's first two chunks, in flight while the uniforms are drawn
-            int gcb = __builtin_amdgcn_readfirstlane(gcb_v);
-            uint4 b0 = bw[(gcb >> 8) * 64 + lane];
-            uint4 b1 = bw[((gcb >> 8) + 1) * 64 + lane];      // unused where the group has one chunk
-            uint2 j0 = bj[(gcb >> 8) * 64 + lane];
-            uint2 j1 = bj[((gcb >> 8) + 1) * 64 + lane];
-            uint32_t inf = info[lane];
+            // the first group's rows, in flight while the uniforms are drawn
+            Rows ra, rb;
+            load_rows(ra, 0);
             // ---- the sweep's uniforms, staged in site order (at a cycle end
             // they were drawn while the slot waited for its partner) ----
             if (!drawn) draw(t);
@@ -264,103 +276,104 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
             // ---- the sweep: colour classes in order, item ranks lane + 64 k ----
             int8_t *m_w = sp + buf * SB;
             int dE = 0, nf = 0;
-            for (int c = 0; c < ncol; ++c) {
-                for (int k = 0; k < ipl; ++k) {
-                    const int g = c * ipl + k;
-                    const uint32_t ci = inf;
-                    const int cb = gcb >> 8, nch = gcb & 255;
-                    const uint32_t ws[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
-                    const uint32_t jz[4] = {j0.x, j0.y, j1.x, j1.y};
-                    // the next group's first chunks, in flight while this one is decided
-                    if (g + 1 < ngr) {
-                        gcb = __builtin_amdgcn_readlane(gcb_v, g + 1);
-                        b0 = bw[(gcb >> 8) * 64 + lane];
-                        b1 = bw[((gcb >> 8) + 1) * 64 + lane];
-                        j0 = bj[(gcb >> 8) * 64 + lane];
-                        j1 = bj[((gcb >> 8) + 1) * 64 + lane];
-                        inf = info[(g + 1) * 64 + lane];
+            // groups in pairs with two register sets, so that the rows read
+            // one group ahead never need copying
+            auto sweep_group = [&](const Rows &cur, Rows &nxt, int g) {
+                // this group's rows have arrived (read one group ago); waiting
+                // here keeps the compiler from waiting for the next group's
+                // rows below, after they are requested (lgkmcnt(0))
+                __builtin_amdgcn_s_waitcnt(0xc07f);
+                const uint32_t ci = cur.inf;
+                const int cb = cur.gcb >> 8, nch = cur.gcb & 255;
+                const uint32_t ws[8] = {cur.b0.x, cur.b0.y, cur.b0.z, cur.b0.w, cur.b1.x, cur.b1.y, cur.b1.z, cur.b1.w};
+                const uint32_t jz[4] = {cur.j0.x, cur.j0.y, cur.j1.x, cur.j1.y};
+                // the next group's first chunks, in flight while this one is decided
+                if (g + 1 < ngr) load_rows(nxt, g + 1);
+                const int i = (int)(ci & 0xFFFu);
+                // the item, with the reads of its first NC chunks issued
+                // before any is summed (one LDS round trip); a group takes
+                // one straight-line body by its chunk count, so no read is
+                // waited for at a branch
+                auto decide = [&](auto nc_const) {
+                    constexpr int NC = decltype(nc_const)::value;
+                    if (i == 0xFFF) return;
+                    const int m = m_w[i];
+                    const uint32_t ur = rnd_w[i], hs = ur << 16;
+                    int v[8 * NC];                      // 4 words of 2 neighbours per chunk
+#pragma unroll
+                    for (int q = 0; q < 4 * NC; ++q) {
+                        v[2 * q] = m_w[ws[q] & 0xFFFFu];
+                        v[2 * q + 1] = m_w[ws[q] >> 16];
                     }
-                    const int i = (int)(ci & 0xFFFu);
-                    // the item, with the reads of its first NC chunks issued
-                    // before any is summed (one LDS round trip); a group takes
-                    // one straight-line body by its chunk count, so no read is
-                    // waited for at a branch
-                    auto decide = [&](auto nc_const) {
-                        constexpr int NC = decltype(nc_const)::value;
-                        if (i == 0xFFF) return;
-                        const int m = m_w[i];
-                        const uint32_t ur = rnd_w[i], hs = ur << 16;
-                        int v[8 * NC];                      // 4 words of 2 neighbours per chunk
+                    // keep the scheduler from splitting the reads around a wait
+                    __builtin_amdgcn_sched_barrier(0);
+                    int f = (int)ci >> 16;
 #pragma unroll
-                        for (int q = 0; q < 4 * NC; ++q) {
-                            v[2 * q] = m_w[ws[q] & 0xFFFFu];
-                            v[2 * q + 1] = m_w[ws[q] >> 16];
+                    for (int q = 0; q < 2 * NC; ++q)
+                        f = __builtin_amdgcn_sdot4((int)pack4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]),
+                                                   (int)jz[q], f, false);
+                    // chunks past the second: the rare high-degree groups
+                    for (int j = 2; j < nch; ++j) {
+                        const uint4 wc = bw[(cb + j) * 64 + lane];
+                        const uint2 jc = bj[(cb + j) * 64 + lane];
+                        const uint32_t wj[4] = {wc.x, wc.y, wc.z, wc.w};
+                        int u[8];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            u[2 * q] = m_w[wj[q] & 0xFFFFu];
+                            u[2 * q + 1] = m_w[wj[q] >> 16];
                         }
-                        // keep the scheduler from splitting the reads around a wait
-                        __builtin_amdgcn_sched_barrier(0);
-                        int f = (int)ci >> 16;
-#pragma unroll
-                        for (int q = 0; q < 2 * NC; ++q)
-                            f = __builtin_amdgcn_sdot4((int)pack4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]),
-                                                       (int)jz[q], f, false);
-                        // chunks past the second: the rare high-degree groups
-                        for (int j = 2; j < nch; ++j) {
-                            const uint4 wc = bw[(cb + j) * 64 + lane];
-                            const uint2 jc = bj[(cb + j) * 64 + lane];
-                            const uint32_t wj[4] = {wc.x, wc.y, wc.z, wc.w};
-                            int u[8];
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                u[2 * q] = m_w[wj[q] & 0xFFFFu];
-                                u[2 * q + 1] = m_w[wj[q] >> 16];
-                            }
-                            f = __builtin_amdgcn_sdot4((int)pack4(u[0], u[1], u[2], u[3]), (int)jc.x, f, false);
-                            f = __builtin_amdgcn_sdot4((int)pack4(u[4], u[5], u[6], u[7]), (int)jc.y, f, false);
+                        f = __builtin_amdgcn_sdot4((int)pack4(u[0], u[1], u[2], u[3]), (int)jc.x, f, false);
+                        f = __builtin_amdgcn_sdot4((int)pack4(u[4], u[5], u[6], u[7]), (int)jc.y, f, false);
+                    }
+                    const int d = m * f;
+                    // The table's coarse test accepts iff floor(65536 p) > u_hi
+                    // and leaves u open iff floor(65536 p) == u_hi. X = 65536 p
+                    // in FP32 is within 3e-6 of the host's FP64 value wherever
+                    // X >= 1/2 (the exponent stays below 17), so X (1 - MARGIN)
+                    // >= u_hi + 1 accepts and X (1 + MARGIN) < u_hi rejects as the
+                    // table would; the rest (about one uniform in 10^4, and a
+                    // NaN X) read the slot's threshold.
+                    const float uf = (float)ur, y = (float)d * cfl;
+                    // one exponential for either rule, no branch
+                    const float ex = __builtin_amdgcn_exp2f(gibbs ? y : 16.0f - y);
+                    const float X = gibbs ? 65536.0f * __builtin_amdgcn_rcpf(1.0f + ex) : ex;
+                    bool acc = (!gibbs && d <= 0) || X * (1.0f - MARGIN) >= uf + 1.0f;
+                    const bool open = !acc && !(X * (1.0f + MARGIN) < uf);
+                    if (__builtin_expect(any_lane(open), 0)) {
+                        bool maybe = false;
+                        uint32_t T = 0;
+                        if (open) {
+                            T = tab_w[d];
+                            acc = coarse_accept(T, hs, maybe);
                         }
-                        const int d = m * f;
-                        // The table's coarse test accepts iff floor(65536 p) > u_hi
-                        // and leaves u open iff floor(65536 p) == u_hi. X = 65536 p
-                        // in FP32 is within 3e-6 of the host's FP64 value wherever
-                        // X >= 1/2 (the exponent stays below 17), so X (1 - MARGIN)
-                        // >= u_hi + 1 accepts and X (1 + MARGIN) < u_hi rejects as the
-                        // table would; the rest (about one uniform in 10^4, and a
-                        // NaN X) read the slot's threshold.
-                        const float uf = (float)ur, y = (float)d * cfl;
-                        // one exponential for either rule, no branch
-                        const float ex = __builtin_amdgcn_exp2f(gibbs ? y : 16.0f - y);
-                        const float X = gibbs ? 65536.0f * __builtin_amdgcn_rcpf(1.0f + ex) : ex;
-                        bool acc = (!gibbs && d <= 0) || X * (1.0f - MARGIN) >= uf + 1.0f;
-                        const bool open = !acc && !(X * (1.0f + MARGIN) < uf);
-                        if (__builtin_expect(any_lane(open), 0)) {
-                            bool maybe = false;
-                            uint32_t T = 0;
-                            if (open) {
-                                T = tab_w[d];
-                                acc = coarse_accept(T, hs, maybe);
-                            }
-                            if (any_lane(maybe)) {
-                                if (maybe) {
-                                    const P4 r2 = philox(opaque((uint32_t)(i >> 3)), (uint32_t)t, (uint32_t)slot,
-                                                         TAG_REFINE, P.k0, P.k1);
-                                    const int wq = (i & 7) >> 1;
-                                    const uint32_t wd = wq == 0 ? r2.v[0] : wq == 1 ? r2.v[1] : wq == 2 ? r2.v[2] : r2.v[3];
-                                    const uint32_t lo = ((i & 1) ? (wd >> 16) : wd) & 0xFFFFu;
-                                    acc = (T == ALWAYS) || ((hs | lo) < T);
-                                }
+                        if (any_lane(maybe)) {
+                            if (maybe) {
+                                const P4 r2 = philox(opaque((uint32_t)(i >> 3)), (uint32_t)t, (uint32_t)slot,
+                                                     TAG_REFINE, P.k0, P.k1);
+                                const int wq = (i & 7) >> 1;
+                                const uint32_t wd = wq == 0 ? r2.v[0] : wq == 1 ? r2.v[1] : wq == 2 ? r2.v[2] : r2.v[3];
+                                const uint32_t lo = ((i & 1) ? (wd >> 16) : wd) & 0xFFFFu;
+                                acc = (T == ALWAYS) || ((hs | lo) < T);
                             }
                         }
-                        // every lane with an item writes its spin back, so the
-                        // common path takes no branch
-                        m_w[i] = (int8_t)(acc ? -m : m);
-                        dE += acc ? 2 * d : 0;
-                        nf += acc ? 1 : 0;
-                    };
-                    if (__builtin_expect(nch == 1, 1)) decide(std::integral_constant<int, 1>{});
-                    else decide(std::integral_constant<int, 2>{});
-                }
-                // the next class reads what this one wrote (in-order LDS within a wavefront)
+                    }
+                    // every lane with an item writes its spin back, so the
+                    // common path takes no branch
+                    m_w[i] = (int8_t)(acc ? -m : m);
+                    dE += acc ? 2 * d : 0;
+                    nf += acc ? 1 : 0;
+                };
+                if (__builtin_expect(nch == 1, 1)) decide(std::integral_constant<int, 1>{});
+                else decide(std::integral_constant<int, 2>{});
+                // the next class reads what this one wrote (in-order LDS
+                // within a wavefront)
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
+            };
+            for (int g = 0; g < ngr; g += 2) {
+                sweep_group(ra, rb, g);
+                if (g + 1 < ngr) sweep_group(rb, ra, g + 1);
             }
             nflip += (unsigned)nf;
             E += wave_sum(dE);
