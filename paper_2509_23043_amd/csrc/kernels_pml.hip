@@ -406,7 +406,7 @@ __device__ __forceinline__ void pml_body(const ChunkArgs a, const int item)
                         uint32_t F = perm(pk_min_u16(pk_sub_sat_u16(T23, U23), ONE2),
                                           pk_min_u16(pk_sub_sat_u16(T01, U01), ONE2), 0x06040200u);
                         const uint32_t Z = pk_min_u16(pk_min_u16(T01 ^ U01, T23 ^ U23), ONE2);
-                        if (any_lane(Z != ONE2)) {
+                        if (__builtin_expect(any_lane(Z != ONE2), 0)) {
                             // exact test of the four sites: u = (upper << 16) | lower,
                             // the lower half from the refinement draw of the site's call
                             uint32_t Fx = 0;
