@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                         f = __builtin_amdgcn_sdot4((int)pack4(u[0], u[1], u[2], u[3]), (int)jc.x, f, false);
                         f = __builtin_amdgcn_sdot4((int)pack4(u[4], u[5], u[6], u[7]), (int)jc.y, f, false);
                     }
-                    const int d = m * f;
+                    const int d = __mul24(m, f);            // m = +-1, |f| <= 4096
                     // The table's coarse test accepts iff floor(65536 p) > u_hi
                     // and leaves u open iff floor(65536 p) == u_hi. X = 65536 p
                     // in FP32 is within 3e-6 of the host's FP64 value wherever
