@@ -48,7 +48,7 @@ struct Off {
 // n sites, ncolors classes of at most ipl * 64 sites, chunks bond chunks, G slots
 __host__ __device__ inline Off offsets(int n, int ncolors, int ipl, int chunks, int G, int stride, int tsw_entries)
 {
-    const int SB = (n + 15) & ~15, nr = (n + 7) & ~7;
+    const int SB = (n + 16) & ~15, nr = (n + 7) & ~7;     // spins, then at least one padding byte
     const int wpl = (n + 64 * 32 - 1) / (64 * 32);        // exchange words per lane
     const size_t nrec = (size_t)ncolors * 64 * ipl;
     Off f;
@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
         return;
     }
     const int ncol = I.ncolors, ipl = (I.maxcnt + 63) / 64, ngr = ncol * ipl;
-    const int SB = (n + 15) & ~15, nr = (n + 7) & ~7;
+    const int SB = (n + 16) & ~15, nr = (n + 7) & ~7;     // spins, then at least one padding byte
     const int spl = (n + 63) / 64;                            // sites per lane
     const int wpl = (spl + 31) / 32;                          // exchange words per lane
     const int NXW = 64 * wpl;                                 // words of a state, before the energy word
@@ -296,9 +296,13 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                 // waited for at a branch
                 auto decide = [&](auto nc_const) {
                     constexpr int NC = decltype(nc_const)::value;
-                    if (i == 0xFFF) return;
-                    const int m = m_w[i];
-                    const uint32_t ur = rnd_w[i], hs = ur << 16;
+                    // a lane without an item works on the padding byte n (its
+                    // bonds are site 0 with J = 0) and decides nothing, so the
+                    // lanes need no divergent region
+                    const bool has = i != 0xFFF;
+                    const int ii = has ? i : n;
+                    const int m = m_w[ii];
+                    const uint32_t ur = rnd_w[ii], hs = ur << 16;
                     int v[8 * NC];                      // 4 words of 2 neighbours per chunk
 #pragma unroll
                     for (int q = 0; q < 4 * NC; ++q) {
@@ -338,8 +342,8 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                     // one exponential for either rule, no branch
                     const float ex = __builtin_amdgcn_exp2f(gibbs ? y : 16.0f - y);
                     const float X = gibbs ? 65536.0f * __builtin_amdgcn_rcpf(1.0f + ex) : ex;
-                    bool acc = (!gibbs && d <= 0) || X * (1.0f - MARGIN) >= uf + 1.0f;
-                    const bool open = !acc && !(X * (1.0f + MARGIN) < uf);
+                    bool acc = has && ((!gibbs && d <= 0) || X * (1.0f - MARGIN) >= uf + 1.0f);
+                    const bool open = has && !acc && !(X * (1.0f + MARGIN) < uf);
                     if (__builtin_expect(any_lane(open), 0)) {
                         bool maybe = false;
                         uint32_t T = 0;
@@ -360,7 +364,7 @@ __global__ void __launch_bounds__(64 * csrw::MAXG) csrw_kernel(ChunkArgs a)
                     }
                     // every lane with an item writes its spin back, so the
                     // common path takes no branch
-                    m_w[i] = (int8_t)(acc ? -m : m);
+                    m_w[ii] = (int8_t)(acc ? -m : m);
                     dE += acc ? 2 * d : 0;
                     nf += acc ? 1 : 0;
                 };
