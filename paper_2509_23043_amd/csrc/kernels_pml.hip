@@ -388,7 +388,6 @@ __device__ __forceinline__ void pml_body(const ChunkArgs a, const int item)
                     uint32_t xp[NW], xm[NW];
                     rotate_row<L>(o, xp, xm);
                     const uint32_t S = sel_sites(p), Hp = sel_pair(p);
-                    bool wrote = false;
 #pragma unroll
                     for (int ch = 0; ch < NCH; ++ch) {
                         const int w0 = 2 * ch, w1 = 2 * ch + 1;
@@ -436,16 +435,14 @@ __device__ __forceinline__ void pml_body(const ChunkArgs a, const int item)
                                 F &= vm;
                             }
                         }
-                        if (F) wrote = true;
                         o[w0] ^= perm(0u, F, sel_flo(p));
                         o[w1] ^= perm(0u, F, sel_fhi(p));
                         nf += __builtin_popcount(F);
                         su = (int)__builtin_amdgcn_udot4(U, F, (uint32_t)su, false);
                     }
-                    if (wrote) {
-                        if constexpr (NW == 2) *(uint2 *)(bufs + a_me) = make_uint2(o[0], o[1]);
-                        else *(uint4 *)(bufs + a_me) = make_uint4(o[0], o[1], o[2], o[3]);
-                    }
+                    // the row goes back whether or not a site flipped: no branch
+                    if constexpr (NW == 2) *(uint2 *)(bufs + a_me) = make_uint2(o[0], o[1]);
+                    else *(uint4 *)(bufs + a_me) = make_uint4(o[0], o[1], o[2], o[3]);
                 }
                 // the next colour reads what this one wrote (in-order LDS within a wavefront)
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
